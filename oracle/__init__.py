@@ -1,0 +1,39 @@
+"""FP64 CPU oracle for batched state-vector simulation (test infrastructure).
+
+This package is test infrastructure. Only ``tests/``, the smoke check in
+``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` may
+import it. The product path (``paper_2509_25075_amd``) never imports, calls or
+links anything here, and this package never imports the product.
+
+It is a plain, slow, obviously correct NumPy complex128 simulator written
+from the textbook definitions of the operations:
+
+* gates: Pauli rotations R_P(t) = exp(-i t P / 2), Paulis, Hadamard, CNOT, CZ
+  (Nielsen & Chuang, *Quantum Computation and Quantum Information*, 2010,
+  §4.2 eqs. 4.4-4.6 and §4.3);
+* amplitude encoding |x> = x / ||x||_2 and basis-state (zero) initialisation
+  (Schuld & Petruccione, *Supervised Learning with Quantum Computers*, 2018,
+  §5.2);
+* data re-uploading of angle-encoded features (Perez-Salinas et al.,
+  *Quantum* 4, 226, 2020);
+* Pauli-Z expectation readout, and the fidelity of a quantum autoencoder whose
+  trash qubits are reset to |0> (Romero, Olson & Aspuru-Guzik,
+  *Quantum Sci. Technol.* 2, 045001, 2017);
+* gradients three ways: the adjoint (reverse state propagation) method
+  (Jones & Gacon, arXiv:2009.02823, §3), the parameter-shift rule
+  (Mitarai et al., *Phys. Rev. A* 98, 032309, 2018; Schuld et al.,
+  *Phys. Rev. A* 99, 032331, 2019, eq. 12) and central finite differences.
+
+Conventions: qubit q is bit q of the amplitude index (little-endian); states
+are arrays ``psi[b, i]`` of complex128 with i in [0, 2^n).
+"""
+
+from .statevector import (  # noqa: F401
+    gate_matrix, apply_1q, apply_cnot, apply_cz, apply_gate, gate_angles,
+    encode_amplitude, encode_zero, run_circuit, expz, fidelity_reset,
+    fidelity_reset_direct, reset_channel_fidelity_cotangents,
+)
+from .gradients import (  # noqa: F401
+    adjoint_vjp, param_shift_theta_jacobian, theta_to_param_grads,
+    finite_difference, loss_and_dexpz,
+)

@@ -1,0 +1,366 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+* hand-derived values from the textbook gate definitions (tests/golden);
+* closed forms (<Z> = cos theta after RY/RX, products of cosines, -sin theta);
+* brute-force 2^n x 2^n Kronecker products with scipy's matrix exponential
+  for n <= 6 (tests/_brute.py), covering every gate kind and qubit position;
+* invariants: unitarity, norm preservation, U then U^dagger = identity, the
+  CNOT ring as a permutation of basis states, fidelity in [0, 1] and = 1 for
+  a mirrored autoencoder without trash qubits;
+* the autoencoder's two-pass fidelity against its density-matrix definition;
+* gradients: adjoint = parameter shift (exact) = central finite differences.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle.gradients import observable_cotangent
+from oracle.statevector import circuit_unitary
+from workloads import circuits as C
+from workloads import data as Dt
+
+from _brute import circuit_full, gate_full, angle
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                   "hand_values.json")))
+OPS = C.OP
+
+
+def _one(op, q=0, n=1, theta=0.0, q1=-1):
+    g = np.array([(OPS[op], q, q1, -1, -1, -1, theta, 0)], dtype=C.GATE_DTYPE)
+    return C.Circuit(n, g, 0)
+
+
+def _run1(op, theta, psi):
+    c = _one(op, theta=theta)
+    return O.run_circuit(c, np.zeros(0), None, psi)
+
+
+# ---------------------------------------------------------------- hand values
+@pytest.mark.parametrize("key,op,start", [("rx_on_zero", "RX", "zero"),
+                                          ("ry_on_zero", "RY", "zero"),
+                                          ("rz_on_plus", "RZ", "plus")])
+def test_single_qubit_states_hand_values(key, op, start):
+    gv = GOLD[key]
+    psi = O.encode_zero(1, 1) if start == "zero" else \
+        np.array([[1, 1]], dtype=complex) / np.sqrt(2)
+    out = _run1(op, gv["theta"], psi)[0]
+    np.testing.assert_allclose(out.real, gv["re"], atol=1e-15)
+    np.testing.assert_allclose(out.imag, gv["im"], atol=1e-15)
+
+
+def test_basis_state_expz_bit_order():
+    gv = GOLD["basis5_n3_expz"]
+    x = np.zeros((1, 8))
+    x[0, gv["index"]] = 3.0  # unnormalised on purpose
+    z = O.expz(O.encode_amplitude(x, gv["n"]))
+    np.testing.assert_array_equal(z[0], gv["expz"])
+
+
+@pytest.mark.parametrize("key", ["cnot_ring_n3_on_1", "cnot_ring_n3_on_4"])
+def test_cnot_ring_permutation(key):
+    gv = GOLD[key]
+    n = gv["n"]
+    rows = [(OPS["CNOT"], i, (i + 1) % n, -1, -1, -1, 0.0, 0) for i in range(n)]
+    c = C.Circuit(n, np.array(rows, dtype=C.GATE_DTYPE), 0)
+    psi = np.zeros((1, 1 << n), dtype=complex)
+    psi[0, gv["input_index"]] = 1
+    out = O.run_circuit(c, np.zeros(0), None, psi)
+    expect = np.zeros(1 << n)
+    expect[gv["output_index"]] = 1
+    np.testing.assert_array_equal(out[0], expect)
+
+
+def test_cz_sign_pattern():
+    gv = GOLD["cz_sign_n3"]
+    psi = np.ones((1, 8), dtype=complex)
+    out = O.apply_cz(psi, gv["a"], gv["b"])
+    np.testing.assert_array_equal(out[0].real, gv["sign"])
+
+
+def test_bell_state():
+    gv = GOLD["bell"]
+    rows = [(OPS["H"], 0, -1, -1, -1, -1, 0.0, 0),
+            (OPS["CNOT"], 0, 1, -1, -1, -1, 0.0, 0)]
+    c = C.Circuit(2, np.array(rows, dtype=C.GATE_DTYPE), 0)
+    out = O.run_circuit(c, np.zeros(0), None, O.encode_zero(1, 2))
+    np.testing.assert_allclose(out[0].real, gv["re"], atol=1e-15)
+    np.testing.assert_allclose(out[0].imag, 0, atol=1e-15)
+    np.testing.assert_allclose(O.expz(out)[0], gv["expz"], atol=1e-15)
+
+
+# ---------------------------------------------------------------- closed forms
+@pytest.mark.parametrize("op", ["RX", "RY"])
+def test_expz_cos_theta(op):
+    th = np.linspace(-np.pi, np.pi, 17)
+    psi = O.encode_zero(th.size, 1)
+    g = np.array([(OPS[op], 0, -1, 0, -1, -1, 1.0, 0)], dtype=C.GATE_DTYPE)
+    c = C.Circuit(1, g, 1)
+    z = np.array([O.expz(O.run_circuit(c, np.array([t]), None, psi[:1]))[0, 0]
+                  for t in th])
+    np.testing.assert_allclose(z, np.cos(th), atol=1e-15)
+    # d<Z>/dtheta = -sin(theta), from the adjoint and from parameter shift
+    for t in th:
+        gth, _ = O.adjoint_vjp(c, np.array([t]), None, psi[:1],
+                               dexpz=np.ones((1, 1)))
+        np.testing.assert_allclose(gth[0, 0], -np.sin(t), atol=1e-14)
+
+
+def test_rz_leaves_z_unchanged_and_product_of_cosines():
+    gv = GOLD["ry_then_rx_expz"]
+    # angles through FP64 parameters (the descriptor's scale is float32)
+    P = np.array([gv["a"], 0.9, gv["b"]])
+    rows = [(OPS["RY"], 0, -1, 0, -1, -1, 1.0, 0),
+            (OPS["RZ"], 0, -1, 1, -1, -1, 1.0, 0),
+            (OPS["RX"], 0, -1, 2, -1, -1, 1.0, 0)]
+    # RZ after RY leaves <Z> = cos(a); RY then RX gives cos(a) cos(b).
+    c_rz = C.Circuit(1, np.array(rows[:2], dtype=C.GATE_DTYPE), 3)
+    z = O.expz(O.run_circuit(c_rz, P, None, O.encode_zero(1, 1)))
+    np.testing.assert_allclose(z[0, 0], np.cos(gv["a"]), atol=1e-15)
+    c = C.Circuit(1, np.array([rows[0], rows[2]], dtype=C.GATE_DTYPE), 3)
+    z = O.expz(O.run_circuit(c, P, None, O.encode_zero(1, 1)))
+    np.testing.assert_allclose(z[0, 0], gv["expz"], atol=1e-15)
+
+
+def test_product_circuit_expz_is_product_of_cosines(rng):
+    n = 5
+    a = rng.uniform(-np.pi, np.pi, n)
+    b = rng.uniform(-np.pi, np.pi, n)
+    rows = []
+    for q in range(n):
+        rows.append((OPS["RY"], q, -1, -1, -1, -1, a[q], 0))
+        rows.append((OPS["RX"], q, -1, -1, -1, -1, b[q], 0))
+    c = C.Circuit(n, np.array(rows, dtype=C.GATE_DTYPE), 0)
+    z = O.expz(O.run_circuit(c, np.zeros(0), None, O.encode_zero(1, n)))[0]
+    np.testing.assert_allclose(z, np.cos(a.astype(np.float32).astype(float)) *
+                               np.cos(b.astype(np.float32).astype(float)),
+                               atol=1e-14)
+
+
+def test_x_flips_only_its_qubit():
+    n = 4
+    for q in range(n):
+        c = _one("X", q=q, n=n)
+        z = O.expz(O.run_circuit(c, np.zeros(0), None, O.encode_zero(1, n)))[0]
+        expect = np.ones(n)
+        expect[q] = -1
+        np.testing.assert_array_equal(z, expect)
+
+
+# ---------------------------------------------------------------- encodings
+def test_amplitude_encoding_pads_and_normalises(rng):
+    x = rng.standard_normal((3, 5))
+    psi = O.encode_amplitude(x, 3)
+    np.testing.assert_allclose(np.linalg.norm(psi, axis=1), 1, atol=1e-15)
+    np.testing.assert_allclose(psi[:, :5].real * np.linalg.norm(x, axis=1)[:, None], x,
+                               atol=1e-14)
+    assert np.all(psi[:, 5:] == 0)
+    with pytest.raises(ValueError):
+        O.encode_amplitude(np.zeros((1, 4)), 2)
+    with pytest.raises(ValueError):
+        O.encode_amplitude(np.ones((1, 9)), 3)
+
+
+# ---------------------------------------------------------------- brute force
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
+def test_every_gate_kind_every_position_vs_kron(n, rng):
+    kinds = ["RX", "RY", "RZ", "X", "Y", "Z", "H"]
+    psi = rng.standard_normal((2, 1 << n)) + 1j * rng.standard_normal((2, 1 << n))
+    for k in kinds:
+        for q in range(n):
+            th = float(np.float32(rng.uniform(-4, 4)))
+            c = _one(k, q=q, n=n, theta=th)
+            U = gate_full(n, c.gates[0], th)
+            np.testing.assert_allclose(U.conj().T @ U, np.eye(1 << n), atol=1e-13)
+            out = O.run_circuit(c, np.zeros(0), None, psi)
+            np.testing.assert_allclose(out, psi @ U.T, atol=1e-13)
+    for k in ["CNOT", "CZ"]:
+        for a in range(n):
+            for b in range(n):
+                if a == b:
+                    continue
+                c = _one(k, q=a, n=n, q1=b)
+                U = gate_full(n, c.gates[0], 0.0)
+                out = O.run_circuit(c, np.zeros(0), None, psi)
+                np.testing.assert_allclose(out, psi @ U.T, atol=1e-13)
+
+
+@pytest.mark.parametrize("n,G", [(1, 12), (2, 30), (3, 40), (4, 60), (5, 80), (6, 90)])
+def test_random_circuits_vs_kron(n, G, rng):
+    c = C.random_circuit(n, G, rng, n_params=6, n_features=3)
+    B = 3
+    params = rng.uniform(-np.pi, np.pi, c.n_params)
+    feats = rng.uniform(-1, 1, (B, c.n_features))
+    x = rng.standard_normal((B, 1 << n))
+    psi0 = O.encode_amplitude(x, n)
+    out = O.run_circuit(c, params, feats, psi0)
+    for b in range(B):
+        U = circuit_full(c, params, feats[b])
+        np.testing.assert_allclose(U.conj().T @ U, np.eye(1 << n), atol=1e-12)
+        np.testing.assert_allclose(out[b], U @ psi0[b], atol=1e-12)
+        np.testing.assert_allclose(np.linalg.norm(out[b]), 1.0, atol=1e-13)
+
+
+def test_per_sample_params_vs_kron(rng):
+    n, B = 3, 4
+    c = C.hea_ry_rz_ring(n, 2)
+    params = rng.uniform(-np.pi, np.pi, (B, c.n_params))
+    psi0 = O.encode_amplitude(rng.standard_normal((B, 8)), n)
+    out = O.run_circuit(c, params, None, psi0)
+    for b in range(B):
+        np.testing.assert_allclose(out[b], circuit_full(c, params[b]) @ psi0[b],
+                                   atol=1e-12)
+
+
+def test_angle_rule_written_out():
+    # theta = scale (w f + bias), per field, against the brute helper's rule
+    g = np.array([(OPS["RY"], 0, -1, 1, 0, 2, 0.5, 0)], dtype=C.GATE_DTYPE)[0]
+    params = np.array([9.0, 2.0, -3.0])
+    feats = np.array([[0.25]])
+    th = O.gate_angles(g, params, feats, 1)[0]
+    assert th == pytest.approx(0.5 * (2.0 * 0.25 - 3.0), abs=0)
+    assert th == pytest.approx(angle(g, params, feats[0]), abs=0)
+
+
+# ---------------------------------------------------------------- invariants
+@pytest.mark.parametrize("key,B", [("c1", 8), ("c2", 4), ("c3", 16), ("c4", 2)])
+def test_workload_norm_and_inverse(key, B):
+    w = Dt.make_workload(key, B)
+    n = w.n_qubits
+    psi0 = O.encode_amplitude(w.x, n) if w.encoding == "amplitude" else \
+        O.encode_zero(B, n)
+    out = O.run_circuit(w.circuit, w.params, w.feats, psi0)
+    np.testing.assert_allclose(np.linalg.norm(out, axis=1), 1, atol=1e-12)
+    inv = C.inverse_structure(w.circuit)
+    back = O.run_circuit(inv, w.params, w.feats, out)
+    np.testing.assert_allclose(back, psi0, atol=1e-12)
+    z = O.expz(out)
+    assert np.all(np.abs(z) <= 1 + 1e-12)
+
+
+def test_inverse_structure_layer_ends():
+    c = C.ry_rz_chain(3, 2)
+    inv = C.inverse_structure(c)
+    assert c.layer_end == [8, 16]
+    assert inv.layer_end == [8, 16]
+
+
+# ---------------------------------------------------------------- fidelity
+@pytest.mark.parametrize("n,t", [(3, 1), (4, 2), (5, 2)])
+def test_fidelity_two_pass_equals_density_matrix_definition(n, t, rng):
+    enc = C.ry_rz_chain(n, 2)
+    B = 3
+    th = rng.uniform(-np.pi, np.pi, enc.n_params)
+    ph = rng.uniform(-np.pi, np.pi, enc.n_params)
+    x = O.encode_amplitude(rng.standard_normal((B, 1 << n)), n)
+    psi = O.run_circuit(enc, th, None, x)
+    chi = O.run_circuit(enc, ph, None, x)          # chi = V(phi)|x>
+    F, _ = O.fidelity_reset(psi, chi, t)
+    dec = C.inverse_structure(enc)                 # D = V(phi)^dagger
+    Fd = O.fidelity_reset_direct(x, enc, th, dec, ph, t)
+    np.testing.assert_allclose(F, Fd, atol=1e-12)
+    assert np.all((F >= -1e-12) & (F <= 1 + 1e-12))
+
+
+def test_fidelity_mirrored_without_trash_is_one(rng):
+    n = 4
+    enc = C.ry_rz_chain(n, 3)
+    th = rng.uniform(-np.pi, np.pi, enc.n_params)
+    x = O.encode_amplitude(rng.standard_normal((2, 16)), n)
+    psi = O.run_circuit(enc, th, None, x)
+    F, _ = O.fidelity_reset(psi, psi.copy(), 0)
+    np.testing.assert_allclose(F, 1.0, atol=1e-13)
+
+
+# ---------------------------------------------------------------- gradients
+def _expz_loss_setup(rng, n=3, G=30, B=3, F=2, per_sample=False):
+    c = C.random_circuit(n, G, rng, n_params=5, n_features=F)
+    params = rng.uniform(-np.pi, np.pi, (B, c.n_params) if per_sample else c.n_params)
+    feats = rng.uniform(-1, 1, (B, F))
+    psi0 = O.encode_amplitude(rng.standard_normal((B, 1 << n)), n)
+    wts = rng.uniform(-1, 1, (B, n))
+    return c, params, feats, psi0, wts
+
+
+@pytest.mark.parametrize("per_sample", [False, True])
+def test_adjoint_equals_param_shift_equals_fd(rng, per_sample):
+    c, params, feats, psi0, wts = _expz_loss_setup(rng, per_sample=per_sample)
+
+    def loss(p, f):
+        return float(np.sum(wts * O.expz(O.run_circuit(c, p, f, psi0))))
+
+    gth, _ = O.adjoint_vjp(c, params, feats, psi0, dexpz=wts)
+    dp, df = O.theta_to_param_grads(c, params, feats, gth)
+    J = O.param_shift_theta_jacobian(c, params, feats, psi0, O.expz)
+    gth_ps = np.einsum("bgk,bk->bg", J, wts)
+    np.testing.assert_allclose(gth, gth_ps, atol=1e-12)
+    dp_fd = O.finite_difference(lambda p: loss(p, feats), params.copy())
+    df_fd = O.finite_difference(lambda f: loss(params, f), feats.copy())
+    np.testing.assert_allclose(dp, dp_fd, atol=1e-8)
+    np.testing.assert_allclose(df, df_fd, atol=1e-8)
+
+
+def test_mse_loss_gradient_matches_fd(rng):
+    w = Dt.make_workload("c2", 3)
+    c = C.rxyz_cz_ring(4, 2)
+    params = w.params[:c.n_params].astype(np.float64)
+    psi0 = O.encode_amplitude(w.x[:, :16], 4)
+    y = w.labels
+
+    def loss(p):
+        return O.loss_and_dexpz("mse_z0", O.expz(O.run_circuit(c, p, None, psi0)), y)[0]
+
+    z = O.expz(O.run_circuit(c, params, None, psi0))
+    _, dz = O.loss_and_dexpz("mse_z0", z, y)
+    gth, _ = O.adjoint_vjp(c, params, None, psi0, dexpz=dz)
+    dp, _ = O.theta_to_param_grads(c, params, None, gth)
+    np.testing.assert_allclose(dp, O.finite_difference(loss, params.copy()), atol=1e-8)
+
+
+def test_fidelity_gradients_adjoint_shift_fd(rng):
+    n, t, B = 4, 2, 2
+    enc = C.ry_rz_chain(n, 2)
+    th = rng.uniform(-np.pi, np.pi, enc.n_params)
+    ph = rng.uniform(-np.pi, np.pi, enc.n_params)
+    x = O.encode_amplitude(rng.standard_normal((B, 16)), n)
+
+    def L(th_, ph_):
+        psi = O.run_circuit(enc, th_, None, x)
+        chi = O.run_circuit(enc, ph_, None, x)
+        return 1.0 - float(np.mean(O.fidelity_reset(psi, chi, t)[0]))
+
+    psi = O.run_circuit(enc, th, None, x)
+    chi = O.run_circuit(enc, ph, None, x)
+    F, cm = O.fidelity_reset(psi, chi, t)
+    dF = -np.ones(B) / B
+    lam, mu = O.reset_channel_fidelity_cotangents(psi, chi, cm, dF, t)
+    g1, _ = O.adjoint_vjp(enc, th, None, x, lam_final=lam)
+    g2, _ = O.adjoint_vjp(enc, ph, None, x, lam_final=mu)
+    d_th, _ = O.theta_to_param_grads(enc, th, None, g1)
+    d_ph, _ = O.theta_to_param_grads(enc, ph, None, g2)
+    np.testing.assert_allclose(d_th, O.finite_difference(lambda v: L(v, ph), th.copy()),
+                               atol=1e-8)
+    np.testing.assert_allclose(d_ph, O.finite_difference(lambda v: L(th, v), ph.copy()),
+                               atol=1e-8)
+    # parameter shift through F as an observable of psi (chi fixed)
+    J = O.param_shift_theta_jacobian(
+        enc, th, None, x, lambda p: O.fidelity_reset(p, chi, t)[0][:, None])
+    np.testing.assert_allclose(g1, J[:, :, 0] * dF[:, None], atol=1e-12)
+
+
+def test_observable_cotangent_is_diagonal_weighting(rng):
+    psi = O.encode_amplitude(rng.standard_normal((2, 8)), 3)
+    d = np.array([[1.0, 0.0, 0.0], [0.0, 0.0, 2.0]])
+    lam = observable_cotangent(psi, d)
+    # sample 0: Z_0 = diag(+1,-1,+1,-1,...); sample 1: 2 Z_2 = 2 diag(+,+,+,+,-,-,-,-)
+    np.testing.assert_allclose(lam[0], psi[0] * np.array([1, -1] * 4))
+    np.testing.assert_allclose(lam[1], psi[1] * 2 * np.array([1] * 4 + [-1] * 4))
+
+
+def test_unitary_helper_matches_kron(rng):
+    c = C.random_circuit(3, 20, rng, n_params=4)
+    p = rng.uniform(-np.pi, np.pi, c.n_params)
+    np.testing.assert_allclose(circuit_unitary(c, p), circuit_full(c, p), atol=1e-12)
