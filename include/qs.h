@@ -1,0 +1,237 @@
+/*
+ * qs.h -- C ABI of libqs, batched state-vector simulation of parameterised
+ * quantum circuits on AMD MI355X (gfx950), forward and adjoint gradient.
+ *
+ * Definitions the calls implement (standard sources, restated):
+ *   - Gates: Pauli rotations R_P(t) = exp(-i t P / 2) for P in {X, Y, Z}
+ *     (Nielsen & Chuang, Quantum Computation and Quantum Information, 2010,
+ *     sec. 4.2, eqs. 4.4-4.6); Paulis, Hadamard, CNOT and CZ (sec. 4.3).
+ *   - Qubit q is bit q of the amplitude index (little-endian).
+ *   - Amplitude encoding |x> = x / ||x||_2, zero-padded to 2^n (Schuld &
+ *     Petruccione, Supervised Learning with Quantum Computers, 2018, sec. 5.2).
+ *   - Readout <Z_q> = sum_i |psi_i|^2 (1 - 2 bit_q(i)).
+ *   - Adjoint gradient (Jones & Gacon, arXiv:2009.02823, sec. 3): with a state
+ *     cotangent lam (dL = 2 Re <lam|d psi>), dL/dtheta_g = Im <lam_g|P_g|psi_g>.
+ *
+ * Layouts. A batch of states is `[B][2^n]` complex numbers stored as
+ * interleaved (re, im) pairs of `float` (QS_C64) or `double` (QS_C128), row b
+ * contiguous, amplitude index i in logical order. Parameters and features use
+ * the real type of the state dtype: float for QS_C64, double for QS_C128.
+ *
+ * Ownership. Every pointer argument marked (device) is caller-owned device
+ * memory that must stay valid until the stream reaches the call; (host)
+ * pointers are read before the call returns. Input buffers must not alias
+ * output buffers, except `state`, which is in/out by design. The library owns
+ * only its plan cache (device copies of planned gate programs), released by
+ * qs_shutdown().
+ *
+ * Errors. Every call returns a qs_status; nothing throws across the ABI.
+ * Launch-side calls are asynchronous on the given stream (a hipStream_t
+ * passed as void*, NULL = the default stream). Shape and descriptor errors
+ * are detected on the host before anything is enqueued. NaN or Inf values in
+ * the inputs propagate into the outputs; they are not errors.
+ */
+#ifndef QS_H
+#define QS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+typedef enum qs_status {
+  QS_OK = 0,
+  QS_ERR_INVALID = -1,     /* bad descriptor, shape, pointer or flag        */
+  QS_ERR_UNSUPPORTED = -2, /* valid request this build does not implement   */
+  QS_ERR_WORKSPACE = -3,   /* workspace missing or smaller than required    */
+  QS_ERR_ZERO_NORM = -4,   /* amplitude input row with norm 0               */
+  QS_ERR_LAUNCH = -5,      /* a HIP runtime call or kernel launch failed    */
+  QS_ERR_NOMEM = -6        /* the plan cache could not allocate             */
+} qs_status;
+
+/* ------------------------------------------------------------- descriptor */
+/* Gate kinds (numbering is part of the descriptor format). */
+enum {
+  QS_OP_RX = 0, QS_OP_RY = 1, QS_OP_RZ = 2, /* R_P(theta), P = X, Y, Z      */
+  QS_OP_X = 3, QS_OP_Y = 4, QS_OP_Z = 5,    /* Paulis                        */
+  QS_OP_H = 6,                              /* Hadamard                      */
+  QS_OP_CNOT = 7,                           /* q0 = control, q1 = target     */
+  QS_OP_CZ = 8                              /* symmetric in q0, q1           */
+};
+
+/* One gate, 32 bytes. The angle of a rotation on sample b is
+ *   theta_b = scale * (w * f + bias),
+ *   w    = params[p_w]        (1 when p_w  < 0),
+ *   f    = feats[b][feat]     (1 when feat < 0),
+ *   bias = params[p_b]        (0 when p_b  < 0).
+ * With QS_FLAG_PER_SAMPLE_PARAMS, params is [B][n_params] and row b is used.
+ * Non-rotation gates ignore p_w, feat, p_b and scale. */
+typedef struct qs_gate {
+  int32_t op;
+  int32_t q0;
+  int32_t q1;     /* -1 for 1-qubit gates */
+  int32_t p_w;
+  int32_t feat;
+  int32_t p_b;
+  float scale;
+  int32_t flags;  /* reserved, must be 0 */
+} qs_gate;
+
+/* A circuit: `gates` is a host array of n_gates records. */
+typedef struct qs_circuit {
+  int32_t n_qubits;   /* 1 .. 30 */
+  int32_t n_gates;    /* >= 0    */
+  int32_t n_params;   /* >= 0; every p_w / p_b < n_params    */
+  int32_t n_features; /* >= 0; every feat < n_features       */
+  const qs_gate* gates;
+} qs_circuit;
+
+/* State dtypes. */
+enum { QS_C64 = 0, QS_C128 = 1 };
+/* Encodings for qs_encode. */
+enum { QS_ENC_AMPLITUDE = 0, QS_ENC_ZERO = 1 };
+
+/* Flags for qs_forward / qs_adjoint_backward / qs_workspace_size.
+ * The low byte selects the execution path. */
+enum {
+  QS_PATH_AUTO = 0,   /* register/LDS-resident engine when it fits, else HBM */
+  QS_PATH_FUSED = 1,  /* register/LDS-resident engine (n <= 14)              */
+  QS_PATH_PLAIN = 2,  /* one kernel launch per gate, state in HBM            */
+  QS_PATH_HBM = 3,    /* state in HBM, gates fused into dense k-qubit blocks
+                         applied with MFMA (reserved in this build)          */
+  QS_PATH_MASK = 0xff,
+  QS_FLAG_PER_SAMPLE_PARAMS = 0x100 /* params is [B][n_params]            */
+};
+
+/* ------------------------------------------------------------------ calls */
+
+/* Version of the library, major * 10000 + minor * 100 + patch. */
+int qs_version(void);
+
+/* Static text for a status code. Never NULL. */
+const char* qs_status_string(int status);
+
+/* Host only, never touches a GPU. Checks that the descriptor is well formed:
+ * 1 <= n_qubits <= 30, known op codes, qubits in range, distinct qubits for
+ * CNOT/CZ, q1 = -1 for 1-qubit gates, parameter and feature indices in range
+ * for rotations, flags = 0. Returns QS_OK or QS_ERR_INVALID. */
+int qs_validate(const qs_circuit* circuit);
+
+/* Encode a batch into states (qs_forward's input form).
+ *   enc      QS_ENC_AMPLITUDE: state[b] = pad(x[b]) / ||x[b]||_2, with the
+ *            squared norm accumulated in FP64 (D <= 2^n required);
+ *            QS_ENC_ZERO: state[b] = |0...0> (x, D, x_stride ignored).
+ *   dtype    QS_C64 or QS_C128.
+ *   x        (device) [B][x_stride] real inputs, first D used per row;
+ *            float32 when x_is_f64 == 0, float64 otherwise.
+ *   state    (device) [B][2^n] complex output.
+ *   bad_rows (device, optional) int32 counter; the number of zero-norm rows
+ *            is ADDED to it (those rows become NaN). The host cannot see this
+ *            without a sync, so the call itself returns QS_OK for them. */
+int qs_encode(int enc, int dtype, int n_qubits, int64_t B, int64_t D,
+              int x_is_f64, const void* x, int64_t x_stride, void* state,
+              int32_t* bad_rows, void* stream);
+
+/* Forward sweep: state[b] <- U_G(theta_G(b)) ... U_1(theta_1(b)) state[b].
+ *   params   (device) [n_params] or [B][n_params] (QS_FLAG_PER_SAMPLE_PARAMS)
+ *   feats    (device) [B][n_features] or NULL when n_features == 0
+ *   state    (device) [B][2^n] complex, in: encoded input, out: final state
+ *   expz     (device, optional) [B][n] double, receives <Z_q>_b summed in FP64
+ *   ckpt_gates (host, optional) n_ckpt strictly increasing gate counts in
+ *            (0, n_gates); after the first ckpt_gates[i] gates the state is
+ *            copied to ckpt + i * B * 2^n (complex elements)
+ *   ckpt     (device) [n_ckpt][B][2^n] complex, required when n_ckpt > 0
+ *   flags    path selection (QS_PATH_*) | QS_FLAG_PER_SAMPLE_PARAMS */
+int qs_forward(const qs_circuit* circuit, int dtype, int64_t B,
+               const void* params, const void* feats, void* state,
+               double* expz, const int32_t* ckpt_gates, int32_t n_ckpt,
+               void* ckpt, int flags, void* stream);
+
+/* Bytes of device workspace qs_adjoint_backward needs for this shape. */
+size_t qs_workspace_size(const qs_circuit* circuit, int dtype, int64_t B,
+                         int flags);
+
+/* Adjoint backward from the final state of qs_forward.
+ *   state    (device) [B][2^n] final state psi_G (read only)
+ *   dexpz    (device) [B][n] double dL/d<Z_q>_b, giving lam = sum_q dexpz Z_q psi_G
+ *   dstate   (device) [B][2^n] complex state cotangent lam (dL = 2Re<lam|dpsi>)
+ *            exactly one of dexpz / dstate is non-NULL
+ *   grad_params (device) [n_params] double, batch-summed in FP64; with
+ *            QS_FLAG_PER_SAMPLE_PARAMS [B][n_params]. Overwritten.
+ *   grad_feats  (device, optional) [B][n_features] double. Overwritten.
+ *   ckpt_gates / n_ckpt / ckpt  the checkpoints qs_forward stored (optional);
+ *            when given, psi is re-anchored to them on the way back
+ *   ws, ws_bytes  (device) workspace of qs_workspace_size() bytes */
+int qs_adjoint_backward(const qs_circuit* circuit, int dtype, int64_t B,
+                        const void* params, const void* feats,
+                        const void* state, const double* dexpz,
+                        const void* dstate, double* grad_params,
+                        double* grad_feats, const int32_t* ckpt_gates,
+                        int32_t n_ckpt, const void* ckpt, void* ws,
+                        size_t ws_bytes, int flags, void* stream);
+
+/* Readout alone: expz[b][q] = <Z_q>_b of state [B][2^n], FP64 sums. */
+int qs_expz(int dtype, int n_qubits, int64_t B, const void* state,
+            double* expz, void* stream);
+
+/* Autoencoder fidelity with the top n_trash qubits reset to |0> (Romero,
+ * Olson & Aspuru-Guzik, Quantum Sci. Technol. 2, 045001, 2017): with
+ * psi = U|x> and chi = V|x> (the decoder being V^dagger),
+ *   c_m = <chi_0|psi_m>,  F_b = sum_m |c_m|^2   (FP64),
+ * where psi_m is the slice of psi whose trash bits equal m and chi_0 the slice
+ * of chi whose trash bits are 0.
+ *   fid      (device) [B] double output
+ *   dfid     (device, optional) [B] double dL/dF_b; when given, the state
+ *            cotangents lam_psi = dfid_b sum_m c_m |m>|chi_0> and
+ *            lam_chi = dfid_b |0> sum_m conj(c_m) psi_m are written
+ *            (both [B][2^n] complex, device). */
+int qs_fidelity_reset(int dtype, int n_qubits, int n_trash, int64_t B,
+                      const void* psi, const void* chi, double* fid,
+                      const double* dfid, void* lam_psi, void* lam_chi,
+                      void* stream);
+
+/* What the planner decided for a circuit on the fused engine (host only).
+ * The forward and the adjoint may use different register tiles (both read
+ * and write states in logical order, so they need not agree). */
+typedef struct qs_plan_info {
+  int32_t path;              /* QS_PATH_FUSED or QS_PATH_PLAIN / QS_PATH_HBM */
+  int32_t log2_regs;         /* amplitudes per thread = 2^log2_regs          */
+  int32_t log2_threads;      /* threads per sample = 2^log2_threads          */
+  int32_t samples_per_block; /* samples per workgroup                        */
+  int32_t block_threads;     /* threads per workgroup                        */
+  int32_t n_segments;        /* register-resident segments                   */
+  int32_t n_remaps;          /* LDS remaps between segments (forward)        */
+  int32_t n_ops;             /* engine operations                            */
+  int64_t lds_bytes;         /* dynamic LDS per workgroup                    */
+  int32_t adj_log2_regs;     /* the adjoint's amplitudes-per-thread exponent */
+  int32_t adj_samples_per_block;
+  int32_t adj_block_threads;
+  int32_t reserved;
+} qs_plan_info;
+
+/* Fill `out` with the plan the engine would use (host only, no GPU). */
+int qs_plan_info_get(const qs_circuit* circuit, int dtype, int64_t B,
+                     int flags, qs_plan_info* out);
+
+/* Host only: export the fused engine's plan for inspection (tests, tools).
+ * Fills `info` like qs_plan_info_get; then, when the arrays are non-NULL,
+ * copies  ops [info->n_ops][4] int32 = (gate kind, physical position a,
+ * physical position b, descriptor gate index) in execution order,
+ * seg_begin [info->n_segments + 1] int32 op ranges, and
+ * seg_map [info->n_segments][16] uint8 = logical qubit at each physical bit
+ * position (positions below log2_regs are register bits). Returns
+ * QS_ERR_UNSUPPORTED when the circuit does not take the fused path. */
+int qs_plan_export(const qs_circuit* circuit, int dtype, int64_t B, int flags,
+                   qs_plan_info* info, int32_t* ops, int32_t* seg_begin,
+                   uint8_t* seg_map);
+
+/* Release the plan cache (device memory). Safe to call more than once. */
+void qs_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QS_H */

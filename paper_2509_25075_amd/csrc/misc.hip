@@ -1,0 +1,296 @@
+// Encoding, readout, fidelity and reduction kernels.
+//
+// Amplitude encoding |x> = x / ||x||_2 zero-padded to 2^n with the squared
+// norm summed in FP64 (Schuld & Petruccione 2018, sec. 5.2); Pauli-Z readout
+// <Z_q> = sum_i |psi_i|^2 (1 - 2 bit_q(i)) summed in FP64; autoencoder
+// fidelity with reset trash qubits F = sum_m |<chi_0|psi_m>|^2 (Romero, Olson
+// & Aspuru-Guzik 2017) and its state cotangents.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "qs_internal.h"
+
+namespace qs {
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  // sh: kBlock / 64 doubles
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+  return t;
+}
+
+template <typename real, typename xin>
+__global__ void __launch_bounds__(kBlock)
+encode_amplitude(int n, int64_t B, int64_t D, const xin* x, int64_t xs,
+                 real* state, int32_t* bad_rows) {
+  __shared__ double sh[kBlock / 64];
+  const int64_t b = blockIdx.x;
+  const int64_t N = 1ll << n;
+  const xin* row = x + b * xs;
+  double s = 0;
+  for (int64_t i = threadIdx.x; i < D; i += blockDim.x) {
+    double v = (double)row[i];
+    s += v * v;
+  }
+  s = block_sum(s, sh);
+  const bool zero = !(s > 0);
+  const double inv = zero ? NAN : 1.0 / sqrt(s);
+  real* out = state + 2 * b * N;
+  for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
+    double v = i < D ? (double)row[i] * inv : (zero ? NAN : 0.0);
+    out[2 * i] = (real)v;
+    out[2 * i + 1] = (real)(zero ? NAN : 0.0);
+  }
+  if (zero && threadIdx.x == 0 && bad_rows != nullptr) atomicAdd(bad_rows, 1);
+}
+
+template <typename real>
+__global__ void __launch_bounds__(kBlock)
+encode_zero(int n, int64_t total, real* state) {
+  const int64_t N = 1ll << n;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    state[2 * i] = (i & (N - 1)) == 0 ? (real)1 : (real)0;
+    state[2 * i + 1] = 0;
+  }
+}
+
+// <Z_q> for q < 32: grid (blocks_per_sample, B); partial sums in registers
+// (compile-time indexed), block sums, FP64 atomics into a zeroed expz.
+template <typename real>
+__global__ void __launch_bounds__(kBlock)
+expz_kernel(int n, int64_t B, const real* state, double* expz) {
+  __shared__ double sh[kBlock / 64];
+  const int64_t N = 1ll << n;
+  for (int64_t b = blockIdx.y; b < B; b += gridDim.y) {
+  const real* s = state + 2 * b * N;
+  double z[32];
+#pragma unroll
+  for (int q = 0; q < 32; ++q) z[q] = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double re = s[2 * i], im = s[2 * i + 1];
+    const double p = re * re + im * im;
+#pragma unroll
+    for (int q = 0; q < 32; ++q)
+      if (q < n) z[q] += ((i >> q) & 1) ? -p : p;
+  }
+#pragma unroll
+  for (int q = 0; q < 32; ++q) {
+    if (q < n) {
+      double t = block_sum(z[q], sh);
+      if (threadIdx.x == 0) atomicAdd(&expz[b * n + q], t);
+    }
+  }
+  }
+}
+
+template <typename real>
+__global__ void __launch_bounds__(kBlock)
+fidelity_kernel(int n, int nt, const real* psi, const real* chi, double* fid,
+                const double* dfid, real* lam_psi, real* lam_chi) {
+  __shared__ double sh[kBlock / 64];
+  __shared__ double cre[64], cim[64];
+  const int64_t b = blockIdx.x;
+  const int k = n - nt;
+  const int64_t K = 1ll << k, M = 1ll << nt, N = 1ll << n;
+  const real* p = psi + 2 * b * N;
+  const real* c = chi + 2 * b * N;  // chi_0 = first K amplitudes
+  double F = 0;
+  for (int64_t m = 0; m < M; ++m) {
+    double ar = 0, ai = 0;
+    for (int64_t j = threadIdx.x; j < K; j += blockDim.x) {
+      const double xr = c[2 * j], xi = c[2 * j + 1];
+      const double yr = p[2 * (m * K + j)], yi = p[2 * (m * K + j) + 1];
+      ar += xr * yr + xi * yi;  // conj(x) y
+      ai += xr * yi - xi * yr;
+    }
+    ar = block_sum(ar, sh);
+    ai = block_sum(ai, sh);
+    if (threadIdx.x == 0) {
+      cre[m] = ar;
+      cim[m] = ai;
+    }
+    F += ar * ar + ai * ai;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) fid[b] = F;
+  if (dfid == nullptr) return;
+  const double d = dfid[b];
+  real* lp = lam_psi + 2 * b * N;
+  real* lc = lam_chi + 2 * b * N;
+  for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
+    const int64_t m = i / K, j = i % K;
+    const double xr = c[2 * j], xi = c[2 * j + 1];
+    // lam_psi = d c_m chi0_j
+    lp[2 * i] = (real)(d * (cre[m] * xr - cim[m] * xi));
+    lp[2 * i + 1] = (real)(d * (cre[m] * xi + cim[m] * xr));
+    if (m == 0) {
+      // lam_chi_j = d sum_m conj(c_m) psi_{m j}
+      double sr = 0, si = 0;
+      for (int64_t mm = 0; mm < M; ++mm) {
+        const double yr = p[2 * (mm * K + j)], yi = p[2 * (mm * K + j) + 1];
+        sr += cre[mm] * yr + cim[mm] * yi;
+        si += cre[mm] * yi - cim[mm] * yr;
+      }
+      lc[2 * i] = (real)(d * sr);
+      lc[2 * i + 1] = (real)(d * si);
+    } else {
+      lc[2 * i] = 0;
+      lc[2 * i + 1] = 0;
+    }
+  }
+}
+
+// out[c] = sum_r partials[r][c] in FP64: one block per column, threads
+// stride over rows, then a block reduction.
+template <typename acc_t>
+__global__ void __launch_bounds__(kBlock)
+reduce_partials(const acc_t* partials, int64_t rows, int cols, double* out) {
+  __shared__ double sh[kBlock / 64];
+  const int c = blockIdx.x;
+  double s = 0;
+  for (int64_t r = threadIdx.x; r < rows; r += blockDim.x)
+    s += (double)partials[r * cols + c];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) out[c] = s;
+}
+
+__global__ void __launch_bounds__(kBlock) fill_f64(double* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+template <typename v2>
+__global__ void __launch_bounds__(kBlock)
+copy_state(const v2* src, v2* dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+unsigned grid_for(int64_t n) {
+  int64_t g = (n + kBlock - 1) / kBlock;
+  if (g > 65536) g = 65536;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+int ok() { return hipGetLastError() == hipSuccess ? QS_OK : QS_ERR_LAUNCH; }
+
+}  // namespace
+
+int launch_encode(int enc, int dtype, int n, int64_t B, int64_t D, int x_is_f64,
+                  const void* x, int64_t x_stride, void* state,
+                  int32_t* bad_rows, void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (B == 0) return QS_OK;
+  if (enc == QS_ENC_ZERO) {
+    const int64_t total = B << n;
+    if (dtype == QS_C64)
+      hipLaunchKernelGGL(encode_zero<float>, grid_for(total), kBlock, 0, st, n,
+                         total, (float*)state);
+    else
+      hipLaunchKernelGGL(encode_zero<double>, grid_for(total), kBlock, 0, st,
+                         n, total, (double*)state);
+    return ok();
+  }
+  dim3 g((unsigned)B);
+  if (dtype == QS_C64) {
+    if (x_is_f64)
+      hipLaunchKernelGGL((encode_amplitude<float, double>), g, kBlock, 0, st, n,
+                         B, D, (const double*)x, x_stride, (float*)state, bad_rows);
+    else
+      hipLaunchKernelGGL((encode_amplitude<float, float>), g, kBlock, 0, st, n,
+                         B, D, (const float*)x, x_stride, (float*)state, bad_rows);
+  } else {
+    if (x_is_f64)
+      hipLaunchKernelGGL((encode_amplitude<double, double>), g, kBlock, 0, st,
+                         n, B, D, (const double*)x, x_stride, (double*)state,
+                         bad_rows);
+    else
+      hipLaunchKernelGGL((encode_amplitude<double, float>), g, kBlock, 0, st, n,
+                         B, D, (const float*)x, x_stride, (double*)state,
+                         bad_rows);
+  }
+  return ok();
+}
+
+int launch_fill_f64(double* p, int64_t n, void* stream) {
+  if (n <= 0) return QS_OK;
+  hipLaunchKernelGGL(fill_f64, grid_for(n), kBlock, 0,
+                     static_cast<hipStream_t>(stream), p, n);
+  return ok();
+}
+
+int launch_expz(int dtype, int n, int64_t B, const void* state, double* expz,
+                void* stream) {
+  if (B == 0) return QS_OK;
+  int rc = launch_fill_f64(expz, B * n, stream);
+  if (rc != QS_OK) return rc;
+  const int64_t N = 1ll << n;
+  int64_t bx = (N + kBlock * 16 - 1) / (kBlock * 16);
+  if (bx > 4096) bx = 4096;
+  dim3 g((unsigned)bx, (unsigned)(B < 65535 ? B : 65535));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dtype == QS_C64)
+    hipLaunchKernelGGL(expz_kernel<float>, g, kBlock, 0, st, n, B,
+                       (const float*)state, expz);
+  else
+    hipLaunchKernelGGL(expz_kernel<double>, g, kBlock, 0, st, n, B,
+                       (const double*)state, expz);
+  return ok();
+}
+
+int launch_fidelity(int dtype, int n, int n_trash, int64_t B, const void* psi,
+                    const void* chi, double* fid, const double* dfid,
+                    void* lam_psi, void* lam_chi, void* stream) {
+  if (B == 0) return QS_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dtype == QS_C64)
+    hipLaunchKernelGGL(fidelity_kernel<float>, dim3((unsigned)B), kBlock, 0, st,
+                       n, n_trash, (const float*)psi, (const float*)chi, fid,
+                       dfid, (float*)lam_psi, (float*)lam_chi);
+  else
+    hipLaunchKernelGGL(fidelity_kernel<double>, dim3((unsigned)B), kBlock, 0,
+                       st, n, n_trash, (const double*)psi, (const double*)chi,
+                       fid, dfid, (double*)lam_psi, (double*)lam_chi);
+  return ok();
+}
+
+int launch_reduce_partials(int dtype, const void* partials, int64_t rows,
+                           int cols, double* out, void* stream) {
+  if (cols <= 0) return QS_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dtype == QS_C64)
+    hipLaunchKernelGGL(reduce_partials<float>, dim3((unsigned)cols), kBlock, 0, st,
+                       (const float*)partials, rows, cols, out);
+  else
+    hipLaunchKernelGGL(reduce_partials<double>, dim3((unsigned)cols), kBlock, 0, st,
+                       (const double*)partials, rows, cols, out);
+  return ok();
+}
+
+int launch_copy_state(int dtype, const void* src, void* dst, int64_t n_amp,
+                      void* stream) {
+  if (n_amp <= 0) return QS_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dtype == QS_C64)
+    hipLaunchKernelGGL(copy_state<float2>, grid_for(n_amp), kBlock, 0, st,
+                       (const float2*)src, (float2*)dst, n_amp);
+  else
+    hipLaunchKernelGGL(copy_state<double2>, grid_for(n_amp), kBlock, 0, st,
+                       (const double2*)src, (double2*)dst, n_amp);
+  return ok();
+}
+
+}  // namespace qs

@@ -1,0 +1,211 @@
+// Host planner for the register-resident engine.
+//
+// A sample's 2^n amplitudes are spread over 2^t threads holding 2^r
+// amplitudes each (n = r + t). A gate that mixes amplitude pairs (RX, RY, X,
+// Y, H, and the target of CNOT) can be applied without communication only
+// when its target qubit sits on a register bit; diagonal gates (RZ, Z, CZ)
+// and CNOT controls can sit anywhere. The planner cuts the gate list into
+// segments with one qubit placement each; between segments the engine
+// re-places the state through LDS (a "remap").
+//
+// Gates on disjoint qubits commute, so the planner list-schedules the gate
+// dependency DAG (only the order of gates sharing a qubit is kept): it runs
+// every ready gate the current placement can execute, and re-places only
+// when every ready gate mixes a thread-resident qubit. At a re-placement the
+// register bits receive the r qubits whose next pending pair-mixing gate is
+// soonest (ties: lower qubit). Checkpoint positions are scheduling barriers.
+#include <algorithm>
+#include <climits>
+#include <cstring>
+
+#include "qs_internal.h"
+
+namespace qs {
+
+namespace {
+
+int mixing_target(const qs_gate& g) {
+  switch (g.op) {
+    case QS_OP_RX: case QS_OP_RY: case QS_OP_X: case QS_OP_Y: case QS_OP_H:
+      return g.q0;
+    case QS_OP_CNOT:
+      return g.q1;
+    default:
+      return -1;  // RZ, Z, CZ are diagonal
+  }
+}
+
+struct Placement {
+  uint8_t phys2log[kMapStride];
+  uint8_t log2phys[32];
+};
+
+// Registers: the r qubits used soonest from gate g on. Threads: the rest,
+// ordered so that the lowest thread bits carry qubits with distinct q mod 5
+// (the LDS slot swizzle folds logical bits in groups of 5, so distinct
+// residues give distinct banks for lanes that differ in those bits).
+Placement choose(int n, int r, const std::vector<int>& next_use) {
+  std::vector<int> q(n);
+  for (int i = 0; i < n; ++i) q[i] = i;
+  std::stable_sort(q.begin(), q.end(), [&](int a, int b) {
+    return next_use[a] < next_use[b];
+  });
+  std::vector<int> regs(q.begin(), q.begin() + r);
+  std::sort(regs.begin(), regs.end());
+  std::vector<int> rest(q.begin() + r, q.end());
+  std::sort(rest.begin(), rest.end());
+  std::vector<int> thr;
+  bool used_res[5] = {false, false, false, false, false};
+  std::vector<bool> taken(rest.size(), false);
+  for (size_t pass = 0; pass < rest.size(); ++pass) {
+    int pick = -1;
+    for (size_t i = 0; i < rest.size(); ++i)
+      if (!taken[i] && !used_res[rest[i] % 5]) { pick = (int)i; break; }
+    if (pick < 0)
+      for (size_t i = 0; i < rest.size(); ++i)
+        if (!taken[i]) { pick = (int)i; break; }
+    taken[pick] = true;
+    used_res[rest[pick] % 5] = true;
+    thr.push_back(rest[pick]);
+    if (thr.size() % 5 == 0) std::fill(used_res, used_res + 5, false);
+  }
+  Placement p;
+  std::memset(&p, 0xff, sizeof(p));
+  for (int j = 0; j < r; ++j) p.phys2log[j] = (uint8_t)regs[j];
+  for (int i = 0; i < (int)thr.size(); ++i) p.phys2log[r + i] = (uint8_t)thr[i];
+  for (int i = 0; i < n; ++i) p.log2phys[p.phys2log[i]] = (uint8_t)i;
+  return p;
+}
+
+bool is_rotation(int op) {
+  return op == QS_OP_RX || op == QS_OP_RY || op == QS_OP_RZ;
+}
+
+}  // namespace
+
+SvPlan plan_sv(const qs_circuit& c, int r, bool per_sample_angles_all,
+               const int32_t* ckpt_gates, int n_ckpt) {
+  SvPlan P;
+  const int n = c.n_qubits, G = c.n_gates;
+  P.n = n;
+  P.r = r;
+  P.t = n - r;
+  P.n_gates = G;
+
+  // Epochs: checkpoint boundaries are scheduling barriers.
+  std::vector<int> bounds;
+  for (int i = 0; i < n_ckpt; ++i) bounds.push_back(ckpt_gates[i]);
+  bounds.push_back(G);
+
+  // Per-qubit gate sequences (the dependency DAG of the gate list: gates on
+  // disjoint qubits commute, so only the per-qubit order must be kept).
+  std::vector<std::vector<int>> seq(n);
+  for (int g = 0; g < G; ++g) {
+    seq[c.gates[g].q0].push_back(g);
+    if (c.gates[g].q1 >= 0) seq[c.gates[g].q1].push_back(g);
+  }
+  std::vector<size_t> head(n, 0);   // next unscheduled position per qubit
+  std::vector<char> done(G, 0);
+
+  auto ready = [&](int g) {
+    const qs_gate& x = c.gates[g];
+    if (seq[x.q0][head[x.q0]] != g) return false;
+    if (x.q1 >= 0 && seq[x.q1][head[x.q1]] != g) return false;
+    return true;
+  };
+  // Soonest pending pair-mixing use of each qubit, counted in gate order.
+  auto next_use_from_heads = [&]() {
+    std::vector<int> nu(n, INT_MAX);
+    for (int q = 0; q < n; ++q)
+      for (size_t i = head[q]; i < seq[q].size(); ++i) {
+        int g = seq[q][i];
+        if (mixing_target(c.gates[g]) == q) { nu[q] = g; break; }
+      }
+    return nu;
+  };
+
+  std::vector<SvOp> ops;
+  std::vector<int> op_gate;
+  Placement cur = choose(n, r, next_use_from_heads());
+  auto open_segment = [&](const Placement& pl) {
+    P.seg_begin.push_back((int32_t)ops.size());
+    P.seg_map.insert(P.seg_map.end(), pl.phys2log, pl.phys2log + kMapStride);
+    P.seg_ckpt.push_back(-1);
+  };
+  auto seg_empty = [&]() {
+    return P.seg_begin.back() == (int32_t)ops.size() && P.seg_ckpt.back() < 0;
+  };
+  open_segment(cur);
+  int lo = 0;
+  for (size_t ep = 0; ep < bounds.size(); ++ep) {
+    const int hi = bounds[ep];  // gates [lo, hi) form this epoch
+    int remaining = hi - lo;
+    while (remaining > 0) {
+      // Schedule every ready, executable gate of the epoch (lowest index
+      // first) until none is left.
+      bool progress = true;
+      while (progress) {
+        progress = false;
+        for (int g = lo; g < hi; ++g) {
+          if (done[g] || !ready(g)) continue;
+          const qs_gate& x = c.gates[g];
+          const int m = mixing_target(x);
+          if (m >= 0 && cur.log2phys[m] >= r) continue;
+          SvOp op;
+          op.kind = (uint8_t)x.op;
+          op.aux = 0;
+          op.gate = g;
+          op.a = cur.log2phys[x.q0];
+          op.b = x.q1 >= 0 ? cur.log2phys[x.q1] : 0;
+          ops.push_back(op);
+          done[g] = 1;
+          head[x.q0]++;
+          if (x.q1 >= 0) head[x.q1]++;
+          --remaining;
+          progress = true;
+        }
+      }
+      if (remaining == 0) break;
+      // Stuck: every ready gate mixes a thread-resident qubit. Re-place.
+      Placement nxt = choose(n, r, next_use_from_heads());
+      if (seg_empty())
+        std::memcpy(&P.seg_map[P.seg_map.size() - kMapStride], nxt.phys2log,
+                    kMapStride);
+      else
+        open_segment(nxt);
+      cur = nxt;
+    }
+    if (ep + 1 < bounds.size()) {  // checkpoint after the first hi gates
+      P.seg_ckpt.back() = (int32_t)ep;
+      open_segment(cur);
+    }
+    lo = hi;
+  }
+  P.seg_begin.push_back((int32_t)ops.size());
+
+  // Angle slots, indexed by op position: per-sample rotations get a slot.
+  P.angle_slot.assign(ops.size(), -1);
+  for (size_t o = 0; o < ops.size(); ++o) {
+    const qs_gate& gt = c.gates[ops[o].gate];
+    if (!is_rotation(gt.op)) continue;
+    bool per_sample = per_sample_angles_all
+                          ? (gt.p_w >= 0 || gt.p_b >= 0 || gt.feat >= 0)
+                          : (gt.feat >= 0);
+    if (per_sample) {
+      P.angle_slot[o] = (int)P.slot_gate.size();
+      P.slot_gate.push_back(ops[o].gate);
+      ops[o].aux = 1;
+    }
+  }
+  P.ops = std::move(ops);
+
+  int changes = 0;
+  for (int s = 1; s < P.nseg(); ++s)
+    if (std::memcmp(&P.seg_map[(s - 1) * kMapStride], &P.seg_map[s * kMapStride],
+                    kMapStride) != 0)
+      ++changes;
+  P.n_remaps = changes;
+  return P;
+}
+
+}  // namespace qs

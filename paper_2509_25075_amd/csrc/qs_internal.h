@@ -1,0 +1,136 @@
+// Internal declarations shared by the host API, the planner and the kernels.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "qs.h"
+
+namespace qs {
+
+// One operation of the register-resident engine. Positions are PHYSICAL bit
+// positions inside a sample's state: 0 .. r-1 are register bits (amplitude
+// index within a thread), r .. n-1 are thread bits (thread index within the
+// sample's thread group).
+//   kind  gate kind (QS_OP_*)
+//   a     target (1-qubit), control (CNOT), first qubit (CZ)
+//   b     target (CNOT), second qubit (CZ), unused otherwise
+//   aux   bit 0: the angle differs per sample (per-sample table slot)
+//   gate  index of the descriptor gate this op came from
+struct SvOp {
+  uint8_t kind, a, b, aux;
+  int32_t gate;
+};
+static_assert(sizeof(SvOp) == 8, "SvOp layout");
+
+constexpr int kMaxQubitsFused = 14;  // 2^14 complex64 = 128 KiB LDS staging
+constexpr int kMapStride = 16;       // bytes per segment mapping record
+
+// A planned gate program: a sequence of segments, each with a fixed
+// placement of the logical qubits onto physical bit positions, such that
+// every non-diagonal gate of the segment acts on a register-resident qubit.
+// Ops are the circuit's gates (one op per gate) in a dependency-respecting
+// order; op o applies gate ops[o].gate, and per-op tables use index o.
+struct SvPlan {
+  int n = 0, r = 0, t = 0;            // qubits, log2 regs, log2 threads/sample
+  int n_gates = 0;
+  std::vector<uint8_t> seg_map;       // [nseg][16]: physical pos -> logical q
+  std::vector<int32_t> seg_begin;     // [nseg + 1] op ranges
+  std::vector<int32_t> seg_ckpt;      // [nseg] checkpoint slot after segment
+  std::vector<SvOp> ops;
+  std::vector<int32_t> angle_slot;    // [n_ops] shared: -1, per-sample: slot
+  std::vector<int32_t> slot_gate;     // [n_slots] gate of a per-sample slot
+  int n_remaps = 0;
+  int nseg() const { return (int)seg_begin.size() - 1; }
+};
+
+// Plans `c` for 2^r amplitudes per thread. `per_sample_angles_all` marks every
+// rotation's angle per-sample (per-sample parameter sets); otherwise only
+// rotations with a feature are. Checkpoint boundaries force segment ends.
+SvPlan plan_sv(const qs_circuit& c, int r, bool per_sample_angles_all,
+               const int32_t* ckpt_gates, int n_ckpt);
+
+// Device copy of a plan plus its launch shape.
+struct SvDevPlan {
+  int n, r, t, nseg, n_gates, n_slots, n_params, n_features;
+  int n_remaps, n_ops;
+  uint8_t* seg_map;
+  int32_t* seg_begin;
+  int32_t* seg_ckpt;
+  SvOp* ops;
+  qs_gate* gates;
+  int32_t* angle_slot;
+  int32_t* slot_gate;
+};
+
+// Launch geometry of the engine for a plan.
+struct SvShape {
+  int r, t;                 // log2 regs, log2 threads per sample
+  int block_threads;        // threads per workgroup
+  int samples_per_block;
+  int64_t lds_bytes;
+};
+
+// Kernel launchers (defined in the .hip files).
+struct SvLaunch {
+  const SvDevPlan* p;
+  SvShape shape;
+  int64_t B;
+  int per_sample_params;
+  const void* params;
+  const void* feats;
+  void* state;
+  double* expz;
+  void* ckpt;
+  const double* dexpz;
+  const void* dstate;
+  void* ws_partials;        // [grid][n_params] shared-parameter partial sums
+                            // (float for complex64, double for complex128)
+  double* grad_params;
+  double* grad_feats;
+  void* stream;
+};
+int launch_sv_forward(int dtype, const SvLaunch& L);
+int launch_sv_adjoint(int dtype, const SvLaunch& L);
+
+int launch_encode(int enc, int dtype, int n, int64_t B, int64_t D,
+                  int x_is_f64, const void* x, int64_t x_stride, void* state,
+                  int32_t* bad_rows, void* stream);
+int launch_expz(int dtype, int n, int64_t B, const void* state, double* expz,
+                void* stream);
+int launch_fidelity(int dtype, int n, int n_trash, int64_t B, const void* psi,
+                    const void* chi, double* fid, const double* dfid,
+                    void* lam_psi, void* lam_chi, void* stream);
+int launch_reduce_partials(int dtype, const void* partials, int64_t rows,
+                           int cols, double* out, void* stream);
+int launch_fill_f64(double* p, int64_t n, void* stream);
+int launch_copy_state(int dtype, const void* src, void* dst, int64_t n_amp,
+                      void* stream);
+
+// Plain one-gate-per-launch path.
+struct PlainLaunch {
+  const qs_circuit* c;       // host descriptor
+  const qs_gate* d_gates;    // device copy
+  int dtype;
+  int64_t B;
+  int per_sample_params;
+  const void* params;
+  const void* feats;
+  void* state;
+  double* expz;
+  const int32_t* ckpt_gates;
+  int n_ckpt;
+  void* ckpt;
+  const double* dexpz;
+  const void* dstate;
+  double* grad_params;
+  double* grad_feats;
+  void* ws;                  // lam [B][2^n] + psi copy + gtheta [B][G]
+  void* stream;
+};
+size_t plain_workspace_bytes(const qs_circuit& c, int dtype, int64_t B);
+int run_plain_forward(const PlainLaunch& L);
+int run_plain_adjoint(const PlainLaunch& L);
+
+}  // namespace qs

@@ -1,0 +1,211 @@
+"""Torch-facing layer over the HIP library: device buffers, the autograd
+Function, and one training step of a workload.
+
+PyTorch supplies device memory and the stream; every step of the state
+simulation (encoding, gate sweep, readout, adjoint, fidelity) runs in
+libqs.so. The loss and its upstream gradient dL/d<Z> are the only arithmetic
+done in torch, on the GPU.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import torch
+
+from . import _native as N
+
+_DT = {
+    "c64": (N.QS_C64, torch.complex64, torch.float32),
+    "c128": (N.QS_C128, torch.complex128, torch.float64),
+}
+
+
+def require_gpu():
+    if not torch.cuda.is_available():
+        raise RuntimeError("paper_2509_25075_amd needs a ROCm GPU (no CPU fallback)")
+    N.lib()
+
+
+class Simulator:
+    """One circuit on one dtype: encode, forward, adjoint on device tensors."""
+
+    def __init__(self, circuit, dtype: str = "c64", flags: int = 0):
+        require_gpu()
+        self.circuit = circuit
+        self.h = N.CircuitHandle(circuit)
+        self.dtype = dtype
+        self.qs_dtype, self.cdtype, self.rdtype = _DT[dtype]
+        self.flags = flags
+        self.n = self.h.n_qubits
+
+    # -------------------------------------------------------------- states
+    def empty_state(self, B: int, device="cuda"):
+        return torch.empty((B, 1 << self.n), dtype=self.cdtype, device=device)
+
+    def encode_amplitude(self, x, out=None):
+        out = self.empty_state(x.shape[0], x.device) if out is None else out
+        N.qs_encode(N.QS_ENC_AMPLITUDE, self.qs_dtype, self.n, x, out)
+        return out
+
+    def zero_state(self, B: int, device="cuda", out=None):
+        out = self.empty_state(B, device) if out is None else out
+        N.qs_encode(N.QS_ENC_ZERO, self.qs_dtype, self.n, None, out)
+        return out
+
+    # ------------------------------------------------------------- sweeps
+    def forward(self, params, feats, state, want_expz=True, ckpt_gates=None,
+                ckpt=None, flags=None):
+        """In-place forward on ``state``; returns <Z> [B, n] (float64) or None."""
+        B = state.shape[0]
+        expz = torch.empty((B, self.n), dtype=torch.float64,
+                           device=state.device) if want_expz else None
+        N.qs_forward(self.h, self.qs_dtype, params, feats, state, expz,
+                     ckpt_gates, ckpt, self.flags if flags is None else flags)
+        return expz
+
+    def workspace(self, B: int, device="cuda", flags=None):
+        nbytes = N.qs_workspace_size(self.h, self.qs_dtype, B,
+                                     self.flags if flags is None else flags)
+        return torch.empty(max(nbytes, 8), dtype=torch.uint8, device=device)
+
+    def adjoint(self, params, feats, state, dexpz=None, dstate=None, ws=None,
+                ckpt_gates=None, ckpt=None, flags=None, want_feat_grad=True):
+        """Returns (grad_params float64, grad_feats float64 or None)."""
+        fl = self.flags if flags is None else flags
+        B = state.shape[0]
+        dev = state.device
+        per_sample = bool(fl & N.QS_FLAG_PER_SAMPLE_PARAMS)
+        gp = torch.empty((B, self.h.n_params) if per_sample else (self.h.n_params,),
+                         dtype=torch.float64, device=dev)
+        gf = None
+        if self.h.n_features and want_feat_grad:
+            gf = torch.empty((B, self.h.n_features), dtype=torch.float64, device=dev)
+        ws = self.workspace(B, dev, fl) if ws is None else ws
+        N.qs_adjoint_backward(self.h, self.qs_dtype, params, feats, state,
+                              dexpz=dexpz, dstate=dstate, grad_params=gp,
+                              grad_feats=gf, ckpt_gates=ckpt_gates, ckpt=ckpt,
+                              ws=ws, flags=fl)
+        return gp, gf
+
+    def plan_info(self, B: int, flags=None) -> dict:
+        return N.qs_plan_info_get(self.h, self.qs_dtype, B,
+                                  self.flags if flags is None else flags)
+
+
+class CircuitExpZ(torch.autograd.Function):
+    """<Z_q>_b of circuit(params, feats) applied to a fixed encoded state,
+    differentiable in params and feats through the library's adjoint."""
+
+    @staticmethod
+    def forward(ctx, params, feats, state0, sim: Simulator):
+        state = state0.clone()
+        expz = sim.forward(params.detach(), None if feats is None else feats.detach(),
+                           state)
+        ctx.sim = sim
+        ctx.has_feats = feats is not None
+        ctx.save_for_backward(params, feats if feats is not None else params, state)
+        return expz
+
+    @staticmethod
+    def backward(ctx, gexpz):
+        params, feats, state = ctx.saved_tensors
+        feats = feats if ctx.has_feats else None
+        gp, gf = ctx.sim.adjoint(params.detach(),
+                                 None if feats is None else feats.detach(), state,
+                                 dexpz=gexpz.contiguous().to(torch.float64))
+        gp = gp.to(params.dtype)
+        gf = None if gf is None else gf.to(feats.dtype)
+        return gp, gf, None, None
+
+
+def expz(params, feats, state0, sim: Simulator):
+    return CircuitExpZ.apply(params, feats, state0, sim)
+
+
+# ---------------------------------------------------------------- workloads
+@dataclass
+class DeviceWorkload:
+    """A workload's inputs resident on the GPU, plus preallocated buffers."""
+    w: object
+    sim: Simulator
+    sim_dec: Simulator | None
+    x: torch.Tensor | None
+    feats: torch.Tensor | None
+    params: torch.Tensor
+    params_dec: torch.Tensor | None
+    labels: torch.Tensor | None
+    weights: torch.Tensor | None
+    state: torch.Tensor
+    state_dec: torch.Tensor | None
+    ws: torch.Tensor
+    ws_dec: torch.Tensor | None
+    flags: int
+
+
+def to_device(w, flags: int = 0, device="cuda") -> DeviceWorkload:
+    sim = Simulator(w.circuit, w.dtype, flags)
+    rd = sim.rdtype
+    B = w.batch
+    t = lambda a, dt=rd: None if a is None else torch.as_tensor(a).to(device=device, dtype=dt).contiguous()
+    sim_dec = Simulator(w.decoder, w.dtype, flags) if w.decoder is not None else None
+    state = sim.empty_state(B, device)
+    return DeviceWorkload(
+        w=w, sim=sim, sim_dec=sim_dec, x=t(w.x), feats=t(w.feats),
+        params=t(w.params), params_dec=t(w.params_dec),
+        labels=t(w.labels, torch.float64), weights=t(w.weights, torch.float64),
+        state=state, state_dec=sim.empty_state(B, device) if sim_dec else None,
+        ws=sim.workspace(B, device, flags),
+        ws_dec=sim_dec.workspace(B, device, flags) if sim_dec else None,
+        flags=flags)
+
+
+def step(d: DeviceWorkload, backward: bool = True) -> dict:
+    """One pass of the whole path: encode, forward sweep, readout, loss,
+    adjoint backward. Returns the device tensors it produced."""
+    w, sim = d.w, d.sim
+    B = w.batch
+    if w.encoding == "amplitude":
+        sim.encode_amplitude(d.x, out=d.state)
+    else:
+        sim.zero_state(B, d.state.device, out=d.state)
+    out = {}
+    if w.loss == "fidelity_reset":
+        sim.encode_amplitude(d.x, out=d.state_dec)
+        sim.forward(d.params, d.feats, d.state, want_expz=False)
+        d.sim_dec.forward(d.params_dec, d.feats, d.state_dec, want_expz=False)
+        fid = torch.empty(B, dtype=torch.float64, device=d.state.device)
+        dfid = torch.full((B,), -1.0 / B, dtype=torch.float64, device=d.state.device)
+        lam_psi = torch.empty_like(d.state)
+        lam_chi = torch.empty_like(d.state)
+        N.qs_fidelity_reset(sim.qs_dtype, sim.n, w.n_trash, d.state, d.state_dec,
+                            fid, dfid if backward else None,
+                            lam_psi if backward else None,
+                            lam_chi if backward else None)
+        out["fid"] = fid
+        out["loss"] = 1.0 - fid.mean()
+        if backward:
+            out["grad_params"], _ = sim.adjoint(d.params, d.feats, d.state,
+                                                dstate=lam_psi, ws=d.ws)
+            out["grad_params_dec"], _ = d.sim_dec.adjoint(
+                d.params_dec, d.feats, d.state_dec, dstate=lam_chi, ws=d.ws_dec)
+        return out
+    z = sim.forward(d.params, d.feats, d.state, want_expz=True)
+    out["expz"] = z
+    if w.loss == "none" or not backward:
+        return out
+    if w.loss == "mse_z0":
+        r = z[:, 0] - d.labels
+        out["loss"] = (r * r).mean()
+        dz = torch.zeros_like(z)
+        dz[:, 0] = 2.0 * r / B
+    elif w.loss == "weighted_z":
+        out["loss"] = (z * d.weights[None, :]).sum()
+        dz = d.weights[None, :].expand_as(z).contiguous()
+    else:
+        raise ValueError(w.loss)
+    gp, gf = sim.adjoint(d.params, d.feats, d.state, dexpz=dz, ws=d.ws)
+    out["grad_params"] = gp
+    if gf is not None:
+        out["grad_feats"] = gf
+    return out

@@ -1,0 +1,163 @@
+"""Host-side tests of libqs.so that need no GPU: the library loads, exports
+every call include/qs.h declares, its descriptor constants match the
+workload generator's, descriptor validation rejects malformed input, and the
+planner's programs respect the circuit (same per-qubit gate order, every
+pair-mixing gate on a register-resident qubit)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2509_25075_amd import _native as N
+from workloads import circuits as C
+from workloads import data as Dt
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "qs.h")
+
+
+def _header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^[A-Za-z_][\w\s\*]*?\b(qs_\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_library_loads_and_exports_every_declared_call():
+    lib = N.lib()
+    names = _header_functions()
+    assert len(names) >= 12, names
+    for name in names:
+        assert hasattr(lib, name), f"libqs.so does not export {name}"
+    assert N.qs_version() == 10000
+
+
+def test_header_constants_match_descriptor_format():
+    txt = open(HEADER).read()
+    for name, val in C.OP.items():
+        m = re.search(rf"QS_OP_{name}\s*=\s*(\d+)", txt)
+        assert m and int(m.group(1)) == val, name
+    for const in ["QS_C64", "QS_C128", "QS_ENC_AMPLITUDE", "QS_ENC_ZERO",
+                  "QS_PATH_AUTO", "QS_PATH_FUSED", "QS_PATH_PLAIN", "QS_PATH_HBM"]:
+        m = re.search(rf"\b{const}\s*=\s*(\d+)", txt)
+        assert m and int(m.group(1)) == getattr(N, const), const
+    m = re.search(r"QS_FLAG_PER_SAMPLE_PARAMS\s*=\s*(0x[0-9a-f]+)", txt)
+    assert int(m.group(1), 16) == N.QS_FLAG_PER_SAMPLE_PARAMS
+    assert C.GATE_DTYPE == N.GATE_NP_DTYPE
+    assert C.GATE_DTYPE.itemsize == 32
+
+
+def test_status_strings():
+    for s in [0, -1, -2, -3, -4, -5, -6, 7]:
+        assert isinstance(N.status_string(s), str) and N.status_string(s)
+
+
+def _circ(n, rows, n_params=4, n_features=2):
+    return C.Circuit(n, np.array(rows, dtype=C.GATE_DTYPE), n_params, n_features)
+
+
+@pytest.mark.parametrize("rows,n,why", [
+    ([(0, 3, -1, 0, -1, -1, 1.0, 0)], 3, "qubit out of range"),
+    ([(0, -1, -1, 0, -1, -1, 1.0, 0)], 3, "negative qubit"),
+    ([(99, 0, -1, -1, -1, -1, 1.0, 0)], 3, "unknown op"),
+    ([(7, 1, 1, -1, -1, -1, 0.0, 0)], 3, "CNOT control = target"),
+    ([(8, 0, 5, -1, -1, -1, 0.0, 0)], 3, "CZ second qubit out of range"),
+    ([(0, 0, 1, 0, -1, -1, 1.0, 0)], 3, "1-qubit gate with q1"),
+    ([(1, 0, -1, 4, -1, -1, 1.0, 0)], 3, "weight index >= n_params"),
+    ([(1, 0, -1, -1, -1, 7, 1.0, 0)], 3, "bias index >= n_params"),
+    ([(2, 0, -1, -1, 2, -1, 1.0, 0)], 3, "feature index >= n_features"),
+    ([(2, 0, -1, -1, -1, -1, 1.0, 1)], 3, "nonzero flags"),
+    ([], 0, "zero qubits"),
+    ([], 31, "too many qubits"),
+])
+def test_validate_rejects(rows, n, why):
+    h = N.CircuitHandle(_circ(n, rows))
+    assert N.qs_validate(h) == N.QS_ERR_INVALID, why
+
+
+def test_validate_accepts_workloads_and_random():
+    for key in ["c1", "c2", "c3", "c4"]:
+        w = Dt.make_workload(key, 2)
+        assert N.qs_validate(N.CircuitHandle(w.circuit)) == N.QS_OK
+    rng = np.random.default_rng(0)
+    for n in range(1, 9):
+        c = C.random_circuit(n, 50, rng, n_params=5, n_features=3)
+        assert N.qs_validate(N.CircuitHandle(c)) == N.QS_OK
+    assert N.qs_validate(N.CircuitHandle(_circ(3, []))) == N.QS_OK
+
+
+MIXING = {C.OP[k] for k in ("RX", "RY", "X", "Y", "H")}
+
+
+def _check_plan(c, dtype, flags=0, B=8):
+    h = N.CircuitHandle(c)
+    info, ops, sb, sm = N.qs_plan_export(h, dtype, B, flags)
+    r = info["log2_regs"]
+    n = c.n_qubits
+    assert info["log2_regs"] + info["log2_threads"] == n
+    G = c.n_gates
+    # every gate exactly once
+    assert sorted(ops[:, 3].tolist()) == list(range(G))
+    # per-qubit order kept: any topological order of the dependency DAG
+    for q in range(n):
+        touch = [g for g in ops[:, 3] if c.gates[g]["q0"] == q or c.gates[g]["q1"] == q]
+        assert touch == sorted(touch)
+    assert sb[0] == 0 and sb[-1] == G and np.all(np.diff(sb) >= 0)
+    remaps = 0
+    for s in range(info["n_segments"]):
+        m = sm[s, :n]
+        assert sorted(m.tolist()) == list(range(n)), "placement is a permutation"
+        if s and not np.array_equal(sm[s - 1], sm[s]):
+            remaps += 1
+        for o in range(sb[s], sb[s + 1]):
+            kind, a, b, g = ops[o]
+            gate = c.gates[g]
+            assert kind == gate["op"]
+            assert m[a] == gate["q0"]
+            if gate["q1"] >= 0:
+                assert m[b] == gate["q1"]
+            if kind in MIXING:
+                assert a < r, "pair-mixing target on a register bit"
+            if kind == C.OP["CNOT"]:
+                assert b < r, "CNOT target on a register bit"
+    assert remaps == info["n_remaps"]
+    return info
+
+
+@pytest.mark.parametrize("key", ["c1", "c2", "c3", "c4"])
+def test_plans_of_workloads(key):
+    w = Dt.make_workload(key, 8)
+    dt = N.QS_C128 if w.dtype == "c128" else N.QS_C64
+    info = _check_plan(w.circuit, dt)
+    assert info["path"] == N.QS_PATH_FUSED
+    if key == "c2":
+        # one re-placement per layer: 8 layers of 10-qubit rotations, 5
+        # register qubits, commuting gates reordered across the CZ ring
+        assert info["n_remaps"] == 8
+
+
+@pytest.mark.parametrize("n", list(range(1, 15)))
+def test_plans_of_random_circuits(n):
+    rng = np.random.default_rng(n)
+    c = C.random_circuit(n, 120, rng, n_params=6, n_features=2)
+    for dt in (N.QS_C64, N.QS_C128):
+        if dt == N.QS_C128 and n > 13:
+            continue
+        _check_plan(c, dt)
+        _check_plan(c, dt, flags=N.QS_FLAG_PER_SAMPLE_PARAMS)
+
+
+def test_large_circuits_fall_back_to_plain_path():
+    c = C.hea_ry_rz_ring(16, 1)
+    info = N.qs_plan_info_get(N.CircuitHandle(c), N.QS_C64, 1)
+    assert info["path"] == N.QS_PATH_PLAIN
+
+
+def test_workspace_sizes():
+    w = Dt.make_workload("c2", 4096)
+    h = N.CircuitHandle(w.circuit)
+    fused = N.qs_workspace_size(h, N.QS_C64, 4096)
+    info = N.qs_plan_info_get(h, N.QS_C64, 4096)
+    blocks = -(-4096 // info["adj_samples_per_block"])
+    assert fused == blocks * w.circuit.n_params * 4
+    plain = N.qs_workspace_size(h, N.QS_C64, 4096, N.QS_PATH_PLAIN)
+    assert plain == 2 * 4096 * 1024 * 8 + 4096 * w.circuit.n_gates * 8
