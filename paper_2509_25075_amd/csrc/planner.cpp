@@ -208,4 +208,77 @@ SvPlan plan_sv(const qs_circuit& c, int r, bool per_sample_angles_all,
   return P;
 }
 
+std::vector<TiledEpoch> plan_tiled(const qs_circuit& c, int m, int low_keep,
+                                   const int32_t* ckpt_gates, int n_ckpt) {
+  const int n = c.n_qubits, G = c.n_gates;
+  if (m > n) m = n;
+  if (low_keep > m) low_keep = m;
+  std::vector<std::vector<int>> seq(n);
+  for (int g = 0; g < G; ++g) {
+    seq[c.gates[g].q0].push_back(g);
+    if (c.gates[g].q1 >= 0) seq[c.gates[g].q1].push_back(g);
+  }
+  std::vector<size_t> head(n, 0);
+  std::vector<char> done(G, 0);
+  auto ready = [&](int g) {
+    const qs_gate& x = c.gates[g];
+    if (seq[x.q0][head[x.q0]] != g) return false;
+    if (x.q1 >= 0 && seq[x.q1][head[x.q1]] != g) return false;
+    return true;
+  };
+  std::vector<int> bounds;
+  for (int i = 0; i < n_ckpt; ++i) bounds.push_back(ckpt_gates[i]);
+  bounds.push_back(G);
+
+  std::vector<TiledEpoch> out;
+  int lo = 0;
+  for (size_t ep = 0; ep < bounds.size(); ++ep) {
+    const int hi = bounds[ep];
+    int remaining = hi - lo;
+    while (remaining > 0) {
+      // Tile: the low_keep lowest qubits, then the qubits whose next
+      // unscheduled gate comes soonest.
+      std::vector<int> nxt(n, INT_MAX);
+      for (int q = 0; q < n; ++q)
+        if (head[q] < seq[q].size()) nxt[q] = seq[q][head[q]];
+      std::vector<int> cand;
+      for (int q = low_keep; q < n; ++q) cand.push_back(q);
+      std::stable_sort(cand.begin(), cand.end(),
+                       [&](int a, int b) { return nxt[a] < nxt[b]; });
+      std::vector<int> L;
+      for (int q = 0; q < low_keep; ++q) L.push_back(q);
+      for (int i = 0; (int)L.size() < m && i < (int)cand.size(); ++i)
+        L.push_back(cand[i]);
+      std::sort(L.begin(), L.end());
+      std::vector<int> local(n, -1);
+      for (int j = 0; j < (int)L.size(); ++j) local[L[j]] = j;
+      TiledEpoch e;
+      e.L = L;
+      bool progress = true;
+      while (progress) {
+        progress = false;
+        for (int g = lo; g < hi; ++g) {
+          if (done[g] || !ready(g)) continue;
+          const qs_gate& x = c.gates[g];
+          if (local[x.q0] < 0 || (x.q1 >= 0 && local[x.q1] < 0)) continue;
+          qs_gate y = x;
+          y.q0 = local[x.q0];
+          y.q1 = x.q1 >= 0 ? local[x.q1] : -1;
+          e.gates.push_back(y);
+          e.gate_index.push_back(g);
+          done[g] = 1;
+          head[x.q0]++;
+          if (x.q1 >= 0) head[x.q1]++;
+          --remaining;
+          progress = true;
+        }
+      }
+      out.push_back(std::move(e));
+    }
+    if (ep + 1 < bounds.size() && !out.empty()) out.back().ckpt_after = (int)ep;
+    lo = hi;
+  }
+  return out;
+}
+
 }  // namespace qs

@@ -51,6 +51,20 @@ struct SvPlan {
 SvPlan plan_sv(const qs_circuit& c, int r, bool per_sample_angles_all,
                const int32_t* ckpt_gates, int n_ckpt);
 
+// Large states: the gate list is cut into epochs; each epoch acts only on a
+// tile set L of m qubits (sorted; always containing the `low_keep` lowest
+// qubits so that a tile reads contiguous runs of 2^low_keep amplitudes), and
+// runs as the register engine on 2^(n-m) gathered m-qubit "samples" per
+// batch row.
+struct TiledEpoch {
+  std::vector<int> L;              // global qubit of each local bit
+  std::vector<qs_gate> gates;      // the epoch's gates, qubits renumbered local
+  std::vector<int> gate_index;     // descriptor index of each epoch gate
+  int ckpt_after = -1;             // checkpoint stored after this epoch
+};
+std::vector<TiledEpoch> plan_tiled(const qs_circuit& c, int m, int low_keep,
+                                   const int32_t* ckpt_gates, int n_ckpt);
+
 // Device copy of a plan plus its launch shape.
 struct SvDevPlan {
   int n, r, t, nseg, n_gates, n_slots, n_params, n_features;
@@ -89,6 +103,12 @@ struct SvLaunch {
                             // (float for complex64, double for complex128)
   double* grad_params;
   double* grad_feats;
+  // Tiled (gathered) operation on a larger state; ob = 0 for plain batches.
+  int n_tot = 0, ob = 0;
+  const uint8_t* tile_q = nullptr;   // device [n] global qubit per local bit
+  const uint8_t* outer_q = nullptr;  // device [ob] global qubit per outer bit
+  void* out_psi = nullptr;           // adjoint: final psi (may alias state)
+  void* out_lam = nullptr;           // adjoint: final lam (may alias dstate)
   void* stream;
 };
 int launch_sv_forward(int dtype, const SvLaunch& L);

@@ -334,7 +334,12 @@ struct Args {
   const int32_t* slot_gate;
   int n, t, nseg, n_gates, n_slots, n_params, n_feats, S;
   int per_sample_params;
-  int64_t B;
+  int64_t B;               // samples processed (tiled: batch rows << ob)
+  int n_tot, ob;           // tiled: qubits of the whole state, outer bits
+  const uint8_t* tile_q;   // tiled: [n] global qubit of each local bit
+  const uint8_t* outer_q;  // tiled: [ob] global qubit of each outer bit
+  real* out_psi;           // adjoint: store the final psi here (or null)
+  real* out_lam;           // adjoint: store the final lam here (or null)
   const real* params;
   const real* feats;
   real* state;
@@ -377,6 +382,9 @@ struct Ctx {
   const Args<real>& A;
   int tau, sl;       // thread within sample, sample within block
   int64_t b;         // global sample index
+  int64_t row;       // batch row of the sample (for parameters and features)
+  int64_t base;      // offset (complex elements) of the sample's amplitude 0
+  uint32_t dep_tau;  // tiled: global offset of this thread's low local bits
   bool active;
   v2* lds;           // this sample's state region
   uint32_t salt;     // per-sample slot salt
@@ -442,16 +450,27 @@ struct Ctx {
     read_mapped(x, to);
   }
 
+  // Global offset (complex elements) of local amplitude i = tau + x, x a
+  // multiple of T: the sample's base plus the local bits deposited onto the
+  // tile's qubits (identity when not tiled).
+  __device__ __forceinline__ int64_t addr(int x) const {
+    if (A.tile_q == nullptr) return base + tau + x;
+    int64_t d = dep_tau;
+    for (int j = A.t; j < A.n; ++j)
+      if ((x >> j) & 1) d |= 1ll << kc(A.tile_q)[j];
+    return base + d;
+  }
+
   // HBM (logical order) -> LDS -> registers under placement `map`.
   __device__ __forceinline__ void load_state(St<real, R>& x, const real* src,
                                              const QS_K uint8_t* map) {
     const int N = 1 << A.n, T = 1 << A.t;
     sample_sync(A.t);
-    const v2* s2 = reinterpret_cast<const v2*>(src) + (size_t)b * N;
+    const v2* s2 = reinterpret_cast<const v2*>(src);
     for (int i = tau; i < N; i += T) {
       v2 v;
       if (active) {
-        v = s2[i];
+        v = s2[addr(i - tau)];
       } else {
         v.x = 0;
         v.y = 0;
@@ -469,8 +488,8 @@ struct Ctx {
     write_mapped(x, map);
     sample_sync(A.t);
     if (active) {
-      v2* d2 = reinterpret_cast<v2*>(dst) + (size_t)b * N;
-      for (int i = tau; i < N; i += T) d2[i] = lds[swz((uint32_t)i) ^ salt];
+      v2* d2 = reinterpret_cast<v2*>(dst);
+      for (int i = tau; i < N; i += T) d2[addr(i - tau)] = lds[swz((uint32_t)i) ^ salt];
     }
   }
 
@@ -601,6 +620,21 @@ __device__ __forceinline__ void setup(Ctx<real, LR>& C, const Args<real>& A,
   C.sl = tid >> A.t;
   C.b = (int64_t)blockIdx.x * A.S + C.sl;
   C.active = C.b < A.B;
+  C.row = C.b >> A.ob;
+  if (A.tile_q == nullptr) {
+    C.base = C.b * (int64_t)N;
+    C.dep_tau = 0;
+  } else {
+    const int64_t outer = C.b & ((1ll << A.ob) - 1);
+    int64_t o = C.row << A.n_tot;
+    for (int k = 0; k < A.ob; ++k)
+      if ((outer >> k) & 1) o |= 1ll << kc(A.outer_q)[k];
+    C.base = o;
+    uint32_t d = 0;
+    for (int j = 0; j < A.t; ++j)
+      if ((C.tau >> j) & 1) d |= 1u << kc(A.tile_q)[j];
+    C.dep_tau = d;
+  }
   using v2 = typename V2<real>::T;
   v2* st = reinterpret_cast<v2*>(smem);
   C.lds = st + (size_t)C.sl * N;
@@ -629,7 +663,7 @@ __device__ __forceinline__ void setup(Ctx<real, LR>& C, const Args<real>& A,
     real c = 1, s = 0;
     if (bb < A.B) {
       qs_gate gt = kload(A.gates, kc(A.slot_gate)[slot]);
-      real th = theta_of(A, gt, bb);
+      real th = theta_of(A, gt, bb >> A.ob);
       fsincos(th * (real)0.5, &s, &c);
     }
     C.ang_ps[2 * (size_t)i] = c;
@@ -821,7 +855,7 @@ __global__ void __launch_bounds__(MAXT) sv_adjoint(Args<real> A) {
             const real w = gt.p_w >= 0 ? P[gt.p_w] : (real)1;
             if (A.per_sample_params) {
               if (leader) {
-                double* gp = A.grad_params + (size_t)C.b * A.n_params;
+                double* gp = A.grad_params + (size_t)C.row * A.n_params;
                 if (gt.p_w >= 0) atomicAdd(&gp[gt.p_w], (double)(gth * scale * f));
                 if (gt.p_b >= 0) atomicAdd(&gp[gt.p_b], (double)(gth * scale));
               }
@@ -852,6 +886,8 @@ __global__ void __launch_bounds__(MAXT) sv_adjoint(Args<real> A) {
       C.remap(lam, seg_map<real, LR>(A, s), seg_map<real, LR>(A, s - 1));
     }
   }
+  if (A.out_psi != nullptr) C.store_state(psi, A.out_psi, seg_map<real, LR>(A, 0));
+  if (A.out_lam != nullptr) C.store_state(lam, A.out_lam, seg_map<real, LR>(A, 0));
   __syncthreads();
   if (!A.per_sample_params)
     for (int i = threadIdx.x; i < A.n_params; i += blockDim.x)
@@ -859,7 +895,12 @@ __global__ void __launch_bounds__(MAXT) sv_adjoint(Args<real> A) {
   if (A.grad_feats != nullptr)
     for (int i = threadIdx.x; i < A.S * A.n_feats; i += blockDim.x) {
       const int64_t bb = (int64_t)blockIdx.x * A.S + i / A.n_feats;
-      if (bb < A.B) A.grad_feats[(size_t)bb * A.n_feats + i % A.n_feats] = C.facc[i];
+      if (bb >= A.B) continue;
+      double* dst = &A.grad_feats[(size_t)(bb >> A.ob) * A.n_feats + i % A.n_feats];
+      if (A.tile_q != nullptr)
+        atomicAdd(dst, (double)C.facc[i]);  // several tiles share a batch row
+      else
+        *dst = C.facc[i];
     }
 }
 
@@ -883,7 +924,13 @@ Args<real> make_args(const SvLaunch& L) {
   A.n_feats = p.n_features;
   A.S = L.shape.samples_per_block;
   A.per_sample_params = L.per_sample_params;
-  A.B = L.B;
+  A.B = L.B << L.ob;
+  A.n_tot = L.n_tot;
+  A.ob = L.ob;
+  A.tile_q = L.tile_q;
+  A.outer_q = L.outer_q;
+  A.out_psi = static_cast<real*>(L.out_psi);
+  A.out_lam = static_cast<real*>(L.out_lam);
   A.params = static_cast<const real*>(L.params);
   A.feats = static_cast<const real*>(L.feats);
   A.state = static_cast<real*>(L.state);
@@ -900,7 +947,7 @@ Args<real> make_args(const SvLaunch& L) {
 template <typename real, int LR, int MAXT>
 int launch_one(const SvLaunch& L, bool adjoint) {
   Args<real> A = make_args<real>(L);
-  const int64_t grid = (L.B + A.S - 1) / A.S;
+  const int64_t grid = (A.B + A.S - 1) / A.S;
   if (grid <= 0) return QS_OK;
   dim3 g((unsigned)grid), blk((unsigned)L.shape.block_threads);
   hipStream_t st = static_cast<hipStream_t>(L.stream);
