@@ -36,6 +36,9 @@ WORKLOAD_TEXT = {
           "decoder its inverse with separate params, 4 trash qubits reset, "
           "loss 1 - fidelity; complex64 forward + adjoint",
     "c1": "4 qubits, batch 64: 2 layers RY,RZ + ring CNOT; complex128 forward",
+    "c5b": "26 qubits, one complex64 state (512 MiB in HBM), 20 hardware-efficient "
+           "layers (RY,RZ + ring CNOT; 1560 gates), loss sum_q g_q <Z_q>; "
+           "forward + adjoint on the tiled large-state path",
 }
 # MI355X peaks (published): fp32 vector 157.3 TFLOP/s, HBM 8 TB/s.
 PEAK_FP32_TFLOPS = 157.3
@@ -109,7 +112,23 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB "
+                         "(5 launches) and exit: the known-size kernel whose "
+                         "FETCH_SIZE / WRITE_SIZE counters scale the engine's")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration << 18  # float32 elements
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_mib": args.copy_calibration,
+                          "bytes_read_per_launch": 4 * n,
+                          "bytes_written_per_launch": 4 * n}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "multi-GPU sharding is designed, not built", file=sys.stderr)
@@ -120,7 +139,8 @@ def main():
     from workloads import make_workload
 
     w = make_workload(args.workload)
-    d = sim.to_device(w, flags=1)  # fused engine
+    d = sim.to_device(w, flags=0)  # automatic: register/LDS engine, else tiled HBM
+    path_name = {1: "fused", 2: "plain", 3: "tiled_hbm"}[d.sim.plan_info(w.batch)["path"]]
     updates = w.updates_per_step()
     stream = torch.cuda.current_stream()
 
@@ -191,7 +211,7 @@ def main():
         "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}",
                    "batch": w.batch, "qubits": w.n_qubits,
                    "gates": w.circuit.n_gates + (w.decoder.n_gates if w.decoder else 0),
-                   "updates_per_step": updates, "path": "fused"},
+                   "updates_per_step": updates, "path": path_name},
         "roofline": None if achieved is None else {
             "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,

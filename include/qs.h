@@ -193,6 +193,48 @@ int qs_fidelity_reset(int dtype, int n_qubits, int n_trash, int64_t B,
                       const double* dfid, void* lam_psi, void* lam_chi,
                       void* stream);
 
+/* ------------------------------------------------------- uneven batches */
+/* Many circuits of uneven qubit count and depth in one persistent launch.
+ * Circuits are grouped into classes of identical structure (same gate list);
+ * class k has counts[k] circuits, each with its own parameter set and state.
+ * Device buffers are packed class after class, circuit-major inside a class:
+ *   states        [sum_k counts[k] * 2^n_k]   complex (c64 / c128)
+ *   x (encode)    [sum_k counts[k] * 2^n_k]   real, same offsets as states
+ *   params        [sum_k counts[k] * P_k]     real (P_k = n_params of class k)
+ *   expz, dexpz   [sum_k counts[k] * n_k]     double
+ *   grad_params   [sum_k counts[k] * P_k]     double (overwritten)
+ * Workgroups pull work items (a run of circuits of one class) from an atomic
+ * queue ordered longest first, so the uneven costs balance across the chip.
+ * Restrictions: no features; 5 <= n_k <= 14 for QS_C64, 4 <= n_k <= 13 for
+ * QS_C128. Calls on the same program must not overlap in time (they share
+ * the library-owned queue counter). */
+typedef struct qs_program {
+  int32_t n_classes;
+  const qs_circuit* circuits; /* [n_classes] (host) */
+  const int64_t* counts;      /* [n_classes] circuits per class (host) */
+} qs_program;
+
+/* Host only: offsets (in elements) of each class inside the packed buffers,
+ * and totals[3] = {state elements, parameter elements, expz elements}. Any
+ * output pointer may be NULL. */
+int qs_program_layout(const qs_program* prog, int64_t* state_off,
+                      int64_t* param_off, int64_t* expz_off, int64_t* totals);
+
+/* Amplitude-encode every circuit's input (x packed like states, real). */
+int qs_program_encode(const qs_program* prog, int dtype, const void* x,
+                      int x_is_f64, void* states, int32_t* bad_rows,
+                      void* stream);
+
+/* Forward sweep of every circuit in one persistent launch; expz optional. */
+int qs_program_forward(const qs_program* prog, int dtype, const void* params,
+                       void* states, double* expz, void* stream);
+
+/* Adjoint of every circuit in one persistent launch, from the final states
+ * and dL/d<Z> rows; per-circuit parameter gradients. */
+int qs_program_adjoint(const qs_program* prog, int dtype, const void* params,
+                       const void* states, const double* dexpz,
+                       double* grad_params, void* stream);
+
 /* What the planner decided for a circuit on the fused engine (host only).
  * The forward and the adjoint may use different register tiles (both read
  * and write states in logical order, so they need not agree). */
@@ -227,6 +269,30 @@ int qs_plan_info_get(const qs_circuit* circuit, int dtype, int64_t B,
 int qs_plan_export(const qs_circuit* circuit, int dtype, int64_t B, int flags,
                    qs_plan_info* info, int32_t* ops, int32_t* seg_begin,
                    uint8_t* seg_map);
+
+/* ------------------------------------------------------------- autotuner */
+typedef struct qs_tune_info {
+  int32_t path;           /* QS_PATH_FUSED or QS_PATH_HBM                    */
+  int32_t fwd_log2_regs;  /* chosen forward register tile (fused path)       */
+  int32_t adj_log2_regs;  /* chosen adjoint register tile (fused path)       */
+  int32_t tile_qubits;    /* chosen tile size (large-state path)             */
+  float fwd_ms;           /* best forward time measured                      */
+  float adj_ms;           /* best adjoint time measured                      */
+  int32_t n_candidates;   /* configurations timed                            */
+  int32_t reserved;
+} qs_tune_info;
+
+/* Time every feasible launch configuration of this circuit at batch size B
+ * (register tile per direction on the fused path, tile size on the
+ * large-state path) on library-allocated scratch buffers, synchronously on
+ * `stream`, and use the fastest for later calls with the same circuit, dtype,
+ * flags and a batch of the same power-of-two size class. When the environment
+ * variable QS_AUTOTUNE_CACHE names a file, the choice is appended to it and
+ * such files are read back at the first tuning lookup of a process. With
+ * QS_AUTOTUNE=1 a forward or adjoint call tunes itself on its first use.
+ * Allocates device memory: not to be called during a stream capture. */
+int qs_autotune(const qs_circuit* circuit, int dtype, int64_t B, int flags,
+                void* stream, qs_tune_info* out);
 
 /* Release the plan cache (device memory). Safe to call more than once. */
 void qs_shutdown(void);

@@ -54,6 +54,19 @@ class QsPlanInfo(ctypes.Structure):
                 ("adj_block_threads", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class QsProgram(ctypes.Structure):
+    _fields_ = [("n_classes", ctypes.c_int32),
+                ("circuits", ctypes.POINTER(QsCircuit)),
+                ("counts", ctypes.POINTER(ctypes.c_int64))]
+
+
+class QsTuneInfo(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int32), ("fwd_log2_regs", ctypes.c_int32),
+                ("adj_log2_regs", ctypes.c_int32), ("tile_qubits", ctypes.c_int32),
+                ("fwd_ms", ctypes.c_float), ("adj_ms", ctypes.c_float),
+                ("n_candidates", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class QsError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -96,6 +109,15 @@ def lib() -> ctypes.CDLL:
                                             ctypes.POINTER(QsPlanInfo)]),
         "qs_plan_export": (ctypes.c_int, [cp, ctypes.c_int, i64, ctypes.c_int,
                                           ctypes.POINTER(QsPlanInfo), vp, vp, vp]),
+        "qs_program_layout": (ctypes.c_int, [ctypes.POINTER(QsProgram), vp, vp, vp, vp]),
+        "qs_program_encode": (ctypes.c_int, [ctypes.POINTER(QsProgram), ctypes.c_int, vp,
+                                             ctypes.c_int, vp, vp, vp]),
+        "qs_program_forward": (ctypes.c_int, [ctypes.POINTER(QsProgram), ctypes.c_int, vp,
+                                              vp, vp, vp]),
+        "qs_program_adjoint": (ctypes.c_int, [ctypes.POINTER(QsProgram), ctypes.c_int, vp,
+                                              vp, vp, vp, vp]),
+        "qs_autotune": (ctypes.c_int, [cp, ctypes.c_int, i64, ctypes.c_int, vp,
+                                       ctypes.POINTER(QsTuneInfo)]),
         "qs_shutdown": (None, []),
     }
     for name, (res, args) in sig.items():
@@ -239,6 +261,55 @@ def qs_plan_export(h: CircuitHandle, dtype: int, B: int, flags: int = 0):
                                 ops.ctypes.data, sb.ctypes.data, sm.ctypes.data),
            "qs_plan_export")
     return ({k: getattr(info, k) for k, _ in QsPlanInfo._fields_}, ops, sb, sm)
+
+
+class ProgramHandle:
+    """An uneven batch in the C layout: classes (circuit, count)."""
+
+    def __init__(self, circuits, counts):
+        self.handles = [CircuitHandle(c) for c in circuits]
+        arr = (QsCircuit * len(circuits))(*[h.c for h in self.handles])
+        self._arr = arr
+        self._counts = (ctypes.c_int64 * len(counts))(*[int(v) for v in counts])
+        self.p = QsProgram(len(circuits), arr, self._counts)
+
+    @property
+    def ptr(self):
+        return ctypes.byref(self.p)
+
+    def layout(self):
+        k = self.p.n_classes
+        so, po, eo = (np.zeros(k, np.int64) for _ in range(3))
+        tot = np.zeros(3, np.int64)
+        _check(lib().qs_program_layout(self.ptr, so.ctypes.data, po.ctypes.data,
+                                       eo.ctypes.data, tot.ctypes.data), "qs_program_layout")
+        return so, po, eo, tot
+
+
+def qs_program_encode(ph: ProgramHandle, dtype: int, x, states, bad_rows=None, stream=None):
+    _check(lib().qs_program_encode(ph.ptr, dtype, _ptr(x), int(x.dtype.itemsize == 8),
+                                   _ptr(states), _ptr(bad_rows), _stream(stream)),
+           "qs_program_encode")
+
+
+def qs_program_forward(ph: ProgramHandle, dtype: int, params, states, expz=None,
+                       stream=None):
+    _check(lib().qs_program_forward(ph.ptr, dtype, _ptr(params), _ptr(states),
+                                    _ptr(expz), _stream(stream)), "qs_program_forward")
+
+
+def qs_program_adjoint(ph: ProgramHandle, dtype: int, params, states, dexpz,
+                       grad_params, stream=None):
+    _check(lib().qs_program_adjoint(ph.ptr, dtype, _ptr(params), _ptr(states),
+                                    _ptr(dexpz), _ptr(grad_params), _stream(stream)),
+           "qs_program_adjoint")
+
+
+def qs_autotune(h: CircuitHandle, dtype: int, B: int, flags: int = 0, stream=None) -> dict:
+    info = QsTuneInfo()
+    _check(lib().qs_autotune(h.ptr, dtype, B, flags, _stream(stream), ctypes.byref(info)),
+           "qs_autotune")
+    return {k: getattr(info, k) for k, _ in QsTuneInfo._fields_}
 
 
 def qs_shutdown():

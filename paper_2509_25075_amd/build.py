@@ -31,7 +31,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-result"]
 
-SOURCES = ["planner.cpp", "qs_api.cpp", "misc.hip", "plain.hip",
+SOURCES = ["planner.cpp", "qs_api.cpp", "prog_api.cpp", "misc.hip", "plain.hip",
            "sv_engine.hip"]
 
 

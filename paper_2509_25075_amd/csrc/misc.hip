@@ -53,6 +53,40 @@ encode_amplitude(int n, int64_t B, int64_t D, const xin* x, int64_t xs,
   if (zero && threadIdx.x == 0 && bad_rows != nullptr) atomicAdd(bad_rows, 1);
 }
 
+// Amplitude encoding of an uneven batch: one block per circuit; the class of
+// circuit `c` is found by binary search over the cumulative class counts.
+template <typename real, typename xin>
+__global__ void __launch_bounds__(kBlock)
+encode_program(int n_classes, const int64_t* cum, const int32_t* nq,
+               const int64_t* state_off, const xin* x, real* states,
+               int32_t* bad_rows) {
+  __shared__ double sh[kBlock / 64];
+  const int64_t c = blockIdx.x;
+  int lo = 0, hi = n_classes - 1;
+  while (lo < hi) {  // last class k with cum[k] <= c
+    const int mid = (lo + hi + 1) >> 1;
+    if (cum[mid] <= c) lo = mid; else hi = mid - 1;
+  }
+  const int n = nq[lo];
+  const int64_t N = 1ll << n;
+  const int64_t off = state_off[lo] + (c - cum[lo]) * N;
+  const xin* row = x + off;
+  double s = 0;
+  for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
+    const double v = (double)row[i];
+    s += v * v;
+  }
+  s = block_sum(s, sh);
+  const bool zero = !(s > 0);
+  const double inv = zero ? NAN : 1.0 / sqrt(s);
+  real* out = states + 2 * off;
+  for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
+    out[2 * i] = (real)((double)row[i] * inv);
+    out[2 * i + 1] = (real)(zero ? NAN : 0.0);
+  }
+  if (zero && threadIdx.x == 0 && bad_rows != nullptr) atomicAdd(bad_rows, 1);
+}
+
 template <typename real>
 __global__ void __launch_bounds__(kBlock)
 encode_zero(int n, int64_t total, real* state) {
@@ -155,14 +189,15 @@ fidelity_kernel(int n, int nt, const real* psi, const real* chi, double* fid,
 // stride over rows, then a block reduction.
 template <typename acc_t>
 __global__ void __launch_bounds__(kBlock)
-reduce_partials(const acc_t* partials, int64_t rows, int cols, double* out) {
+reduce_partials(const acc_t* partials, int64_t rows, int cols, double* out,
+                int accumulate) {
   __shared__ double sh[kBlock / 64];
   const int c = blockIdx.x;
   double s = 0;
   for (int64_t r = threadIdx.x; r < rows; r += blockDim.x)
     s += (double)partials[r * cols + c];
   s = block_sum(s, sh);
-  if (threadIdx.x == 0) out[c] = s;
+  if (threadIdx.x == 0) out[c] = accumulate ? out[c] + s : s;
 }
 
 __global__ void __launch_bounds__(kBlock) fill_f64(double* p, int64_t n) {
@@ -225,6 +260,31 @@ int launch_encode(int enc, int dtype, int n, int64_t B, int64_t D, int x_is_f64,
   return ok();
 }
 
+int launch_program_encode(int dtype, int n_classes, const int64_t* cum,
+                          const int32_t* nq, const int64_t* state_off,
+                          int64_t n_circuits, const void* x, int x_is_f64,
+                          void* states, int32_t* bad_rows, void* stream) {
+  if (n_circuits <= 0) return QS_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  dim3 g((unsigned)n_circuits);
+  if (dtype == QS_C64) {
+    if (x_is_f64)
+      hipLaunchKernelGGL((encode_program<float, double>), g, kBlock, 0, st, n_classes,
+                         cum, nq, state_off, (const double*)x, (float*)states, bad_rows);
+    else
+      hipLaunchKernelGGL((encode_program<float, float>), g, kBlock, 0, st, n_classes,
+                         cum, nq, state_off, (const float*)x, (float*)states, bad_rows);
+  } else {
+    if (x_is_f64)
+      hipLaunchKernelGGL((encode_program<double, double>), g, kBlock, 0, st, n_classes,
+                         cum, nq, state_off, (const double*)x, (double*)states, bad_rows);
+    else
+      hipLaunchKernelGGL((encode_program<double, float>), g, kBlock, 0, st, n_classes,
+                         cum, nq, state_off, (const float*)x, (double*)states, bad_rows);
+  }
+  return ok();
+}
+
 int launch_fill_f64(double* p, int64_t n, void* stream) {
   if (n <= 0) return QS_OK;
   hipLaunchKernelGGL(fill_f64, grid_for(n), kBlock, 0,
@@ -268,15 +328,15 @@ int launch_fidelity(int dtype, int n, int n_trash, int64_t B, const void* psi,
 }
 
 int launch_reduce_partials(int dtype, const void* partials, int64_t rows,
-                           int cols, double* out, void* stream) {
+                           int cols, double* out, int accumulate, void* stream) {
   if (cols <= 0) return QS_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (dtype == QS_C64)
     hipLaunchKernelGGL(reduce_partials<float>, dim3((unsigned)cols), kBlock, 0, st,
-                       (const float*)partials, rows, cols, out);
+                       (const float*)partials, rows, cols, out, accumulate);
   else
     hipLaunchKernelGGL(reduce_partials<double>, dim3((unsigned)cols), kBlock, 0, st,
-                       (const double*)partials, rows, cols, out);
+                       (const double*)partials, rows, cols, out, accumulate);
   return ok();
 }
 

@@ -319,6 +319,19 @@ int adjoint_t(const PlainLaunch& L) {
 
 }  // namespace
 
+int launch_obs_cot(int dtype, int n, int64_t B, const double* dexpz,
+                   const void* psi, void* lam, void* stream) {
+  const int64_t per = B << n;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dtype == QS_C64)
+    hipLaunchKernelGGL(plain_obs_cot<float>, grid1(per), kBlock, 0, st, n, B, dexpz,
+                       (const float*)psi, (float*)lam);
+  else
+    hipLaunchKernelGGL(plain_obs_cot<double>, grid1(per), kBlock, 0, st, n, B, dexpz,
+                       (const double*)psi, (double*)lam);
+  return ok();
+}
+
 size_t plain_workspace_bytes(const qs_circuit& c, int dtype, int64_t B) {
   const size_t real_sz = dtype == QS_C64 ? 4 : 8;
   const size_t per = (size_t)B << c.n_qubits;

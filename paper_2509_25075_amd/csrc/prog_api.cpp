@@ -1,0 +1,260 @@
+// Uneven batches: the qs_program_* calls. Classes of identically-structured
+// circuits are planned once (cached), cut into work items of S circuits
+// (S = 512 threads / threads per circuit), ordered longest first (cost
+// = circuits x 2^n x gates), and run by one persistent launch that pulls
+// items from an atomic queue.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "qs_internal.h"
+
+namespace qs {
+// Engine plans shared with the batched calls (qs_api.cpp).
+struct ProgEnginePlan {
+  SvDevPlan* dev;
+};
+ProgEnginePlan program_engine_plan(const qs_circuit& c, int r, int* rc);
+int64_t engine_lds_bytes(int dtype, int n, int S, int n_gates, int n_slots,
+                         int n_params, int n_feats, int block, bool ps);
+}  // namespace qs
+
+using namespace qs;
+
+namespace {
+
+constexpr int kBlock = 512;
+constexpr int64_t kMaxLds = 160 * 1024;
+
+struct ProgPlan {
+  ProgClass* d_classes = nullptr;
+  ProgItem* d_items = nullptr;
+  int n_items = 0;
+  int* d_counter = nullptr;
+  int grid = 0, r = 0;
+  int64_t lds = 0;
+  int64_t* d_cum = nullptr;
+  int32_t* d_nq = nullptr;
+  int64_t* d_state_off = nullptr;
+  int64_t n_circuits = 0;
+};
+
+std::mutex g_pmu;
+std::unordered_map<std::string, ProgPlan*> g_prog;
+
+int check_program(const qs_program* p, int dtype) {
+  if (!p || p->n_classes < 1 || !p->circuits || !p->counts) return QS_ERR_INVALID;
+  if (dtype != QS_C64 && dtype != QS_C128) return QS_ERR_INVALID;
+  const int nlo = dtype == QS_C64 ? 5 : 4, nhi = dtype == QS_C64 ? 14 : 13;
+  for (int k = 0; k < p->n_classes; ++k) {
+    if (p->counts[k] < 0) return QS_ERR_INVALID;
+    if (qs_validate(&p->circuits[k]) != QS_OK) return QS_ERR_INVALID;
+    if (p->circuits[k].n_features != 0) return QS_ERR_UNSUPPORTED;
+    if (p->circuits[k].n_qubits < nlo || p->circuits[k].n_qubits > nhi)
+      return QS_ERR_UNSUPPORTED;
+  }
+  return QS_OK;
+}
+
+void layout(const qs_program* p, std::vector<int64_t>& so, std::vector<int64_t>& po,
+            std::vector<int64_t>& eo, int64_t tot[3]) {
+  so.resize(p->n_classes);
+  po.resize(p->n_classes);
+  eo.resize(p->n_classes);
+  tot[0] = tot[1] = tot[2] = 0;
+  for (int k = 0; k < p->n_classes; ++k) {
+    const qs_circuit& c = p->circuits[k];
+    so[k] = tot[0];
+    po[k] = tot[1];
+    eo[k] = tot[2];
+    tot[0] += p->counts[k] << c.n_qubits;
+    tot[1] += p->counts[k] * c.n_params;
+    tot[2] += p->counts[k] * c.n_qubits;
+  }
+}
+
+template <typename T>
+bool up(T** d, const std::vector<T>& h) {
+  *d = nullptr;
+  const size_t bytes = sizeof(T) * (h.empty() ? 1 : h.size());
+  if (hipMalloc(reinterpret_cast<void**>(d), bytes) != hipSuccess) return false;
+  return h.empty() ||
+         hipMemcpy(*d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice) == hipSuccess;
+}
+
+ProgPlan* get_prog(const qs_program* p, int dtype, int* rc) {
+  int device = 0;
+  (void)hipGetDevice(&device);
+  std::string key;
+  int32_t hdr[3] = {p->n_classes, dtype, device};
+  key.append(reinterpret_cast<const char*>(hdr), sizeof(hdr));
+  for (int k = 0; k < p->n_classes; ++k) {
+    const qs_circuit& c = p->circuits[k];
+    int32_t ch[4] = {c.n_qubits, c.n_gates, c.n_params, c.n_features};
+    key.append(reinterpret_cast<const char*>(ch), sizeof(ch));
+    key.append(reinterpret_cast<const char*>(&p->counts[k]), sizeof(int64_t));
+    if (c.n_gates)
+      key.append(reinterpret_cast<const char*>(c.gates), sizeof(qs_gate) * c.n_gates);
+  }
+  {
+    std::lock_guard<std::mutex> lock(g_pmu);
+    auto it = g_prog.find(key);
+    if (it != g_prog.end()) return it->second;
+  }
+  const int r = dtype == QS_C64 ? 5 : 4;
+  std::vector<int64_t> so, po, eo;
+  int64_t tot[3];
+  layout(p, so, po, eo, tot);
+  std::vector<ProgClass> cls(p->n_classes);
+  std::vector<int64_t> cum(p->n_classes + 1, 0);
+  std::vector<int32_t> nq(p->n_classes);
+  struct Cand { ProgItem it; double cost; };
+  std::vector<Cand> items;
+  int64_t lds = 0;
+  for (int k = 0; k < p->n_classes; ++k) {
+    const qs_circuit& c = p->circuits[k];
+    ProgEnginePlan ep = program_engine_plan(c, r, rc);
+    if (!ep.dev) return nullptr;
+    ProgClass& d = cls[k];
+    std::memset(&d, 0, sizeof(d));
+    d.seg_map = ep.dev->seg_map;
+    d.seg_begin = ep.dev->seg_begin;
+    d.seg_ckpt = ep.dev->seg_ckpt;
+    d.ops = ep.dev->ops;
+    d.gates = ep.dev->gates;
+    d.angle_slot = ep.dev->angle_slot;
+    d.slot_gate = ep.dev->slot_gate;
+    d.n = c.n_qubits;
+    d.t = c.n_qubits - r;
+    d.nseg = ep.dev->nseg;
+    d.n_gates = c.n_gates;
+    d.n_slots = ep.dev->n_slots;
+    d.n_params = c.n_params;
+    d.S = kBlock >> d.t;
+    d.count = p->counts[k];
+    d.state_off = so[k];
+    d.param_off = po[k];
+    d.expz_off = eo[k];
+    lds = std::max(lds, engine_lds_bytes(dtype, d.n, d.S, c.n_gates, 0, c.n_params, 0,
+                                         kBlock, true));
+    cum[k + 1] = cum[k] + p->counts[k];
+    nq[k] = c.n_qubits;
+    for (int64_t f = 0; f < d.count; f += d.S) {
+      const int64_t m = std::min<int64_t>(d.S, d.count - f);
+      items.push_back({{k, (int32_t)f}, (double)m * (double)(1ll << d.n) *
+                                            (double)(c.n_gates > 0 ? c.n_gates : 1)});
+    }
+  }
+  if (lds > kMaxLds) {
+    *rc = QS_ERR_UNSUPPORTED;
+    return nullptr;
+  }
+  std::stable_sort(items.begin(), items.end(),
+                   [](const Cand& a, const Cand& b) { return a.cost > b.cost; });
+  std::vector<ProgItem> its;
+  for (const Cand& c : items) its.push_back(c.it);
+  ProgPlan* pp = new ProgPlan();
+  pp->n_items = (int)its.size();
+  pp->r = r;
+  pp->lds = lds;
+  pp->n_circuits = cum.back();
+  hipDeviceProp_t prop;
+  int cus = 256;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) cus = prop.multiProcessorCount;
+  const int per_cu = std::max<int>(1, std::min<int>(4, (int)(kMaxLds / std::max<int64_t>(lds, 1))));
+  pp->grid = std::max(1, std::min(pp->n_items, cus * per_cu));
+  std::vector<int32_t> zero(1, 0);
+  if (!up(&pp->d_classes, cls) || !up(&pp->d_items, its) || !up(&pp->d_counter, zero) ||
+      !up(&pp->d_cum, cum) || !up(&pp->d_nq, nq) || !up(&pp->d_state_off, so)) {
+    *rc = QS_ERR_NOMEM;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_pmu);
+  g_prog.emplace(key, pp);
+  return pp;
+}
+
+int run(const qs_program* p, int dtype, const void* params, void* states,
+        double* expz, const double* dexpz, double* grad, bool adjoint, void* stream) {
+  int rc = QS_OK;
+  ProgPlan* pp = get_prog(p, dtype, &rc);
+  if (!pp) return rc;
+  if (pp->n_items == 0) return QS_OK;
+  if (adjoint) {
+    int64_t tot[3];
+    std::vector<int64_t> so, po, eo;
+    layout(p, so, po, eo, tot);
+    if (tot[1] && (rc = launch_fill_f64(grad, tot[1], stream)) != QS_OK) return rc;
+  }
+  if ((rc = launch_zero_i32(pp->d_counter, stream)) != QS_OK) return rc;
+  ProgLaunch L{};
+  L.classes = pp->d_classes;
+  L.items = pp->d_items;
+  L.n_items = pp->n_items;
+  L.counter = pp->d_counter;
+  L.grid = pp->grid;
+  L.block = kBlock;
+  L.r = pp->r;
+  L.lds_bytes = pp->lds;
+  L.params = params;
+  L.states = states;
+  L.expz = expz;
+  L.dexpz = dexpz;
+  L.grad_params = grad;
+  L.stream = stream;
+  return launch_program(dtype, L, adjoint);
+}
+
+}  // namespace
+
+extern "C" {
+
+int qs_program_layout(const qs_program* p, int64_t* state_off, int64_t* param_off,
+                      int64_t* expz_off, int64_t* totals) {
+  if (!p || p->n_classes < 1 || !p->circuits || !p->counts) return QS_ERR_INVALID;
+  std::vector<int64_t> so, po, eo;
+  int64_t tot[3];
+  layout(p, so, po, eo, tot);
+  if (state_off) std::memcpy(state_off, so.data(), sizeof(int64_t) * so.size());
+  if (param_off) std::memcpy(param_off, po.data(), sizeof(int64_t) * po.size());
+  if (expz_off) std::memcpy(expz_off, eo.data(), sizeof(int64_t) * eo.size());
+  if (totals) std::memcpy(totals, tot, sizeof(tot));
+  return QS_OK;
+}
+
+int qs_program_encode(const qs_program* p, int dtype, const void* x, int x_is_f64,
+                      void* states, int32_t* bad_rows, void* stream) {
+  int rc = check_program(p, dtype);
+  if (rc != QS_OK) return rc;
+  if (!x || !states) return QS_ERR_INVALID;
+  ProgPlan* pp = get_prog(p, dtype, &rc);
+  if (!pp) return rc;
+  return launch_program_encode(dtype, p->n_classes, pp->d_cum, pp->d_nq,
+                               pp->d_state_off, pp->n_circuits, x, x_is_f64, states,
+                               bad_rows, stream);
+}
+
+int qs_program_forward(const qs_program* p, int dtype, const void* params,
+                       void* states, double* expz, void* stream) {
+  int rc = check_program(p, dtype);
+  if (rc != QS_OK) return rc;
+  if (!states || !params) return QS_ERR_INVALID;
+  return run(p, dtype, params, states, expz, nullptr, nullptr, false, stream);
+}
+
+int qs_program_adjoint(const qs_program* p, int dtype, const void* params,
+                       const void* states, const double* dexpz, double* grad_params,
+                       void* stream) {
+  int rc = check_program(p, dtype);
+  if (rc != QS_OK) return rc;
+  if (!states || !params || !dexpz || !grad_params) return QS_ERR_INVALID;
+  return run(p, dtype, params, const_cast<void*>(states), nullptr, dexpz, grad_params,
+             true, stream);
+}
+
+}  // extern "C"

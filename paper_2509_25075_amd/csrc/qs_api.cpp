@@ -1,7 +1,10 @@
 // C ABI entry points: validation, launch-shape choice, plan cache, dispatch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdio>
 #include <cstdlib>
+#include <functional>
 #include <cstring>
 #include <mutex>
 #include <unordered_map>
@@ -62,14 +65,83 @@ int env_int(const char* name, int dflt) {
   return v && *v ? std::atoi(v) : dflt;
 }
 
+// ------------------------------------------------------------- tuning table
+// Launch choices found by qs_autotune, keyed by (circuit, dtype, batch size
+// class, flags). Overrides set while tuning take precedence.
+struct TuneVal {
+  int fwd_r = 0, adj_r = 0, m = 0;
+};
+std::mutex g_tmu;
+std::mutex g_tune_run_mu;  // one tuning run at a time (overrides are global)
+std::unordered_map<std::string, TuneVal> g_tune;
+bool g_tune_loaded = false;
+int g_force_fwd_r = 0, g_force_adj_r = 0, g_force_m = 0;
+thread_local bool g_in_tune = false;  // calls made by the tuner itself
+
+int batch_class(int64_t B) {
+  int k = 0;
+  while ((1ll << k) < B) ++k;
+  return k;
+}
+
+std::string tune_key(const qs_circuit& c, int dtype, int64_t B, int flags) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void* p, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 1099511628211ull; }
+  };
+  int32_t hdr[7] = {c.n_qubits, c.n_gates, c.n_params, c.n_features, dtype,
+                    batch_class(B), flags};
+  mix(hdr, sizeof(hdr));
+  if (c.n_gates) mix(c.gates, sizeof(qs_gate) * c.n_gates);
+  char buf[32];
+  std::snprintf(buf, sizeof(buf), "%016llx", (unsigned long long)h);
+  return buf;
+}
+
+void load_tune_file_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("QS_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char key[64];
+  int fr, ar, m;
+  while (std::fscanf(f, "%63s %d %d %d", key, &fr, &ar, &m) == 4) {
+    TuneVal v;
+    v.fwd_r = fr;
+    v.adj_r = ar;
+    v.m = m;
+    g_tune[key] = v;
+  }
+  std::fclose(f);
+}
+
+bool tuned_lookup(const qs_circuit& c, int dtype, int64_t B, int flags, TuneVal* out) {
+  std::lock_guard<std::mutex> lock(g_tmu);
+  load_tune_file_locked();
+  if (g_tune.empty()) return false;
+  auto it = g_tune.find(tune_key(c, dtype, B, flags));
+  if (it == g_tune.end()) return false;
+  *out = it->second;
+  return true;
+}
+
 // Bytes of LDS the engine uses for a block of S samples.
+// `block` threads hold S samples of T = block / S threads each; gradient sums
+// take one slot per wave (shared parameters) and per wave of a sample
+// (features); per-sample parameter sets take none.
 int64_t lds_bytes(int dtype, int n, int S, int n_gates, int n_slots,
-                  int n_params, int n_feats) {
+                  int n_params, int n_feats, int block, bool ps) {
   const int64_t rs = dtype == QS_C64 ? 4 : 8;
+  const int64_t waves = (block + 63) / 64;
+  const int64_t T = block / (S > 0 ? S : 1);
+  const int64_t wps = T > 64 ? T / 64 : 1;
   int64_t b = (int64_t)S * (2 * rs << n);      // states
   b += 2 * rs * n_gates;                       // shared angle table
   b += 2 * rs * (int64_t)n_slots * S;          // per-sample angle table
-  b += rs * ((int64_t)n_params + (int64_t)S * n_feats);  // gradient accumulators
+  b += rs * ((ps ? 0 : waves * n_params) + (int64_t)S * wps * n_feats);
   return (b + 15) & ~15ll;
 }
 
@@ -79,7 +151,7 @@ int64_t lds_bytes(int dtype, int n, int S, int n_gates, int n_slots,
 // holds one state per thread group, the adjoint two (psi and lam), so the
 // adjoint prefers a narrower register tile.
 bool choose_shape(int dtype, const qs_circuit& c, int n_slots, int r_force,
-                  bool adjoint, SvShape* out) {
+                  bool adjoint, SvShape* out, bool ps = false) {
   const int n = c.n_qubits;
   if (n > kMaxQubitsFused) return false;
   static const int pref_c64_fwd[] = {5, 4, 3, 2, 1};
@@ -106,7 +178,7 @@ bool choose_shape(int dtype, const qs_circuit& c, int n_slots, int r_force,
     int S = block / T;
     // Shrink the block until the LDS fits.
     while (S > 1 && lds_bytes(dtype, n, S, c.n_gates, n_slots, c.n_params,
-                              c.n_features) > kMaxLds) {
+                              c.n_features, S * T, ps) > kMaxLds) {
       S >>= 1;
     }
     block = S * T;
@@ -115,7 +187,7 @@ bool choose_shape(int dtype, const qs_circuit& c, int n_slots, int r_force,
       block = 64;
     }
     const int64_t lds = lds_bytes(dtype, n, S, c.n_gates, n_slots, c.n_params,
-                                  c.n_features);
+                                  c.n_features, block, ps);
     if (lds > kMaxLds) continue;
     out->r = r;
     out->t = t;
@@ -239,19 +311,144 @@ qs_gate* get_dev_gates(const qs_circuit& c, int* rc) {
   return d;
 }
 
+// ------------------------------------------------------------ tiled plans
+// One engine plan per epoch and direction, plus the epoch's qubit maps.
+struct TiledEpochDev {
+  Entry* fwd = nullptr;
+  Entry* adj = nullptr;
+  SvShape fshape, ashape;
+  uint8_t* tile_q = nullptr;
+  uint8_t* outer_q = nullptr;
+  int ckpt_after = -1;
+  std::vector<qs_gate> gates;  // the epoch's local gate list (kept alive)
+};
+struct TiledEntry {
+  int m = 0;
+  std::vector<TiledEpochDev> epochs;
+};
+std::unordered_map<Key, TiledEntry*, KeyHash> g_tiled;
+
+int tile_qubits(int dtype, int n, int m_pref = 0) {
+  int m = env_int("QS_TILE_QUBITS", 0);
+  if (m == 0) m = g_force_m;
+  if (m == 0) m = m_pref;
+  if (m == 0) m = dtype == QS_C64 ? 13 : 12;
+  if (m > n) m = n;
+  if (m > kMaxQubitsFused) m = kMaxQubitsFused;
+  if (m < 3) m = n < 3 ? n : 3;
+  return m;
+}
+
+TiledEntry* get_tiled(const qs_circuit& c, int dtype, bool ps, const int32_t* ck,
+                      int n_ck, int m_pref, int* rc) {
+  int device = 0;
+  (void)hipGetDevice(&device);
+  const int m = tile_qubits(dtype, c.n_qubits, m_pref);
+  Key key = make_key(c, -100 - m - 32 * dtype, ps, ck, n_ck, device);
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_tiled.find(key);
+    if (it != g_tiled.end()) return it->second;
+  }
+  const int low_keep = m >= 6 ? 4 : (m >= 4 ? m - 2 : 0);
+  std::vector<TiledEpoch> eps = plan_tiled(c, m, low_keep, ck, n_ck);
+  TiledEntry* te = new TiledEntry();
+  te->m = m;
+  te->epochs.resize(eps.size());
+  for (size_t i = 0; i < eps.size(); ++i) {
+    TiledEpochDev& d = te->epochs[i];
+    d.gates = eps[i].gates;
+    d.ckpt_after = eps[i].ckpt_after;
+    qs_circuit sub{(int32_t)eps[i].L.size(), (int32_t)d.gates.size(), c.n_params,
+                   c.n_features, d.gates.empty() ? nullptr : d.gates.data()};
+    const int slots = [&] {
+      int k = 0;
+      for (const qs_gate& x : d.gates)
+        if (is_rotation(x.op) && (ps ? (x.p_w >= 0 || x.p_b >= 0 || x.feat >= 0) : x.feat >= 0)) ++k;
+      return k;
+    }();
+    if (!choose_shape(dtype, sub, slots, 0, false, &d.fshape, ps) ||
+        !choose_shape(dtype, sub, slots, 0, true, &d.ashape, ps)) {
+      *rc = QS_ERR_UNSUPPORTED;
+      return nullptr;
+    }
+    d.fwd = get_plan(sub, d.fshape.r, ps, nullptr, 0, rc);
+    d.adj = get_plan(sub, d.ashape.r, ps, nullptr, 0, rc);
+    if (!d.fwd || !d.adj) return nullptr;
+    std::vector<uint8_t> tq(eps[i].L.begin(), eps[i].L.end()), oq;
+    std::vector<char> in(c.n_qubits, 0);
+    for (int q : eps[i].L) in[q] = 1;
+    for (int q = 0; q < c.n_qubits; ++q)
+      if (!in[q]) oq.push_back((uint8_t)q);
+    if (!upload(&d.tile_q, tq.data(), tq.size()) || !upload(&d.outer_q, oq.data(), oq.size())) {
+      *rc = QS_ERR_NOMEM;
+      return nullptr;
+    }
+  }
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_tiled.emplace(std::move(key), te);
+  return te;
+}
+
+// Host-only view of the tiled plan: tile size, epochs, largest adjoint grid.
+struct TiledHostInfo {
+  int m = 0, n_epochs = 0;
+  int64_t max_grid = 1;
+  bool ok = true;
+};
+TiledHostInfo tiled_host_info(const qs_circuit& c, int dtype, int64_t B, bool ps,
+                              int m_pref) {
+  TiledHostInfo h;
+  h.m = tile_qubits(dtype, c.n_qubits, m_pref);
+  const int low_keep = h.m >= 6 ? 4 : (h.m >= 4 ? h.m - 2 : 0);
+  std::vector<TiledEpoch> eps = plan_tiled(c, h.m, low_keep, nullptr, 0);
+  h.n_epochs = (int)eps.size();
+  const int64_t samples = B << (c.n_qubits - h.m);
+  for (const TiledEpoch& e : eps) {
+    qs_circuit sub{(int32_t)e.L.size(), (int32_t)e.gates.size(), c.n_params,
+                   c.n_features, e.gates.empty() ? nullptr : e.gates.data()};
+    int slots = 0;
+    for (const qs_gate& x : e.gates)
+      if (is_rotation(x.op) && (ps ? (x.p_w >= 0 || x.p_b >= 0 || x.feat >= 0) : x.feat >= 0))
+        ++slots;
+    SvShape a;
+    if (!choose_shape(dtype, sub, slots, 0, true, &a, ps)) { h.ok = false; continue; }
+    const int64_t g = (samples + a.samples_per_block - 1) / a.samples_per_block;
+    if (g > h.max_grid) h.max_grid = g;
+  }
+  return h;
+}
+
+size_t tiled_ws_bytes(const qs_circuit& c, int dtype, int64_t B, bool ps, int m_pref,
+                      int* rc) {
+  TiledHostInfo h = tiled_host_info(c, dtype, B, ps, m_pref);
+  if (!h.ok) {
+    *rc = QS_ERR_UNSUPPORTED;
+    return 0;
+  }
+  const size_t cs = dtype == QS_C64 ? 8 : 16;
+  const size_t acc = dtype == QS_C64 ? 4 : 8;
+  const size_t st = ((size_t)B << c.n_qubits) * cs;
+  size_t part = ps ? 0 : (size_t)h.max_grid * (size_t)(c.n_params ? c.n_params : 1) * acc;
+  return 2 * st + ((part + 255) & ~(size_t)255);
+}
+
 int pick_path(const qs_circuit& c, int dtype, int flags, SvShape* shape,
-              int n_slots, bool adjoint) {
+              int n_slots, bool adjoint, int tuned_r = 0) {
   int path = flags & QS_PATH_MASK;
-  const int rf = env_int(adjoint ? "QS_ADJ_LOG2_REGS" : "QS_FWD_LOG2_REGS", 0);
+  int rf = env_int(adjoint ? "QS_ADJ_LOG2_REGS" : "QS_FWD_LOG2_REGS", 0);
+  if (rf == 0) rf = adjoint ? g_force_adj_r : g_force_fwd_r;
+  if (rf == 0) rf = tuned_r;
+  const bool ps = (flags & QS_FLAG_PER_SAMPLE_PARAMS) != 0;
   if (path == QS_PATH_AUTO) {
-    path = choose_shape(dtype, c, n_slots, rf, adjoint, shape) ? QS_PATH_FUSED
-                                                                : QS_PATH_PLAIN;
+    if (choose_shape(dtype, c, n_slots, rf, adjoint, shape, ps))
+      path = QS_PATH_FUSED;
+    else
+      path = c.n_qubits > kMaxQubitsFused ? QS_PATH_HBM : QS_PATH_PLAIN;
   } else if (path == QS_PATH_FUSED) {
-    if (!choose_shape(dtype, c, n_slots, rf, adjoint, shape)) return -QS_ERR_UNSUPPORTED;
-  } else if (path == QS_PATH_HBM) {
-    return -QS_ERR_UNSUPPORTED;
-  } else if (path != QS_PATH_PLAIN) {
-    return -QS_ERR_INVALID;
+    if (!choose_shape(dtype, c, n_slots, rf, adjoint, shape, ps)) return QS_ERR_UNSUPPORTED;
+  } else if (path != QS_PATH_PLAIN && path != QS_PATH_HBM) {
+    return QS_ERR_INVALID;
   }
   return path;
 }
@@ -277,9 +474,191 @@ size_t fused_ws_bytes(const qs_circuit& c, int dtype, const SvShape& s, int64_t 
   return (size_t)grid_of(s, B) * (size_t)(c.n_params ? c.n_params : 1) * acc;
 }
 
+bool tuned_for_call(const qs_circuit& c, int dtype, int64_t B, int flags, void* stream,
+                    TuneVal* out);
+
+}  // namespace
+
+namespace qs {
+struct ProgEnginePlan {
+  SvDevPlan* dev;
+};
+// Engine plan of one uneven-batch class: every rotation's angle is per circuit.
+ProgEnginePlan program_engine_plan(const qs_circuit& c, int r, int* rc) {
+  Entry* e = get_plan(c, r, true, nullptr, 0, rc);
+  return {e ? &e->dev : nullptr};
+}
+int64_t engine_lds_bytes(int dtype, int n, int S, int n_gates, int n_slots,
+                         int n_params, int n_feats, int block, bool ps) {
+  return lds_bytes(dtype, n, S, n_gates, n_slots, n_params, n_feats, block, ps);
+}
+}  // namespace qs
+
+namespace {
+
+float time_ms(hipStream_t st, const std::function<int()>& fn, int reps, int* rc) {
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    *rc = QS_ERR_LAUNCH;
+    return 0.f;
+  }
+  float best = 1e30f;
+  for (int i = 0; i <= reps; ++i) {  // first run warms plans and caches
+    (void)hipEventRecord(a, st);
+    int r = fn();
+    (void)hipEventRecord(b, st);
+    (void)hipEventSynchronize(b);
+    if (r != QS_OK) {
+      *rc = r;
+      best = 1e30f;
+      break;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    if (i > 0 && ms < best) best = ms;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return best;
+}
+
+struct Scratch {
+  std::vector<void*> ptrs;
+  void* get(size_t bytes) {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes ? bytes : 8) != hipSuccess) return nullptr;
+    (void)hipMemset(p, 0, bytes ? bytes : 8);
+    ptrs.push_back(p);
+    return p;
+  }
+  ~Scratch() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+};
+
+bool tuned_for_call(const qs_circuit& c, int dtype, int64_t B, int flags, void* stream,
+                    TuneVal* out) {
+  if (g_in_tune) return false;
+  if (tuned_lookup(c, dtype, B, flags, out)) return true;
+  if (env_int("QS_AUTOTUNE", 0) != 1) return false;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(static_cast<hipStream_t>(stream), &cs) == hipSuccess &&
+      cs != hipStreamCaptureStatusNone)
+    return false;
+  if (qs_autotune(&c, dtype, B, flags, stream, nullptr) != QS_OK) return false;
+  return tuned_lookup(c, dtype, B, flags, out);
+}
+
 }  // namespace
 
 extern "C" {
+
+int qs_autotune(const qs_circuit* c, int dtype, int64_t B, int flags, void* stream,
+                qs_tune_info* out) {
+  int rc = validate(c);
+  if (rc != QS_OK) return rc;
+  if ((dtype != QS_C64 && dtype != QS_C128) || B < 1) return QS_ERR_INVALID;
+  if (flags & ~(QS_PATH_MASK | QS_FLAG_PER_SAMPLE_PARAMS)) return QS_ERR_INVALID;
+  const bool ps = (flags & QS_FLAG_PER_SAMPLE_PARAMS) != 0;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  SvShape probe;
+  const int path = pick_path(*c, dtype, flags, &probe, count_slots(*c, ps), false);
+  if (path != QS_PATH_FUSED && path != QS_PATH_HBM) return QS_ERR_UNSUPPORTED;
+  const size_t rs = dtype == QS_C64 ? 4 : 8;
+  const int64_t per = B << c->n_qubits;
+  Scratch sc;
+  void* state = sc.get(2 * rs * per);
+  void* params = sc.get(rs * (size_t)(ps ? B : 1) * (c->n_params ? c->n_params : 1));
+  void* feats = sc.get(rs * (size_t)B * (c->n_features ? c->n_features : 1));
+  double* expz = static_cast<double*>(sc.get(sizeof(double) * B * c->n_qubits));
+  double* dexpz = static_cast<double*>(sc.get(sizeof(double) * B * c->n_qubits));
+  double* gp = static_cast<double*>(
+      sc.get(sizeof(double) * (size_t)(ps ? B : 1) * (c->n_params ? c->n_params : 1)));
+  double* gf = static_cast<double*>(sc.get(sizeof(double) * B * (c->n_features ? c->n_features : 1)));
+  if (!state || !params || !feats || !expz || !dexpz || !gp || !gf) return QS_ERR_NOMEM;
+  if ((rc = launch_encode(QS_ENC_ZERO, dtype, c->n_qubits, B, 0, 0, nullptr, 0, state,
+                          nullptr, stream)) != QS_OK)
+    return rc;
+  const void* fe = c->n_features ? feats : nullptr;
+  auto fwd = [&]() {
+    return qs_forward(c, dtype, B, params, fe, state, expz, nullptr, 0, nullptr, flags, stream);
+  };
+  auto adj = [&](void* ws, size_t wsb) {
+    return qs_adjoint_backward(c, dtype, B, params, fe, state, dexpz, nullptr, gp,
+                               c->n_features ? gf : nullptr, nullptr, 0, nullptr, ws, wsb,
+                               flags, stream);
+  };
+  TuneVal best;
+  qs_tune_info info;
+  std::memset(&info, 0, sizeof(info));
+  info.path = path;
+  float bf = 1e30f, ba = 1e30f;
+  std::lock_guard<std::mutex> tune_lock(g_tune_run_mu);
+  struct InTune {
+    InTune() { g_in_tune = true; }
+    ~InTune() { g_in_tune = false; }
+  } in_tune;
+  if (path == QS_PATH_FUSED) {
+    for (int r = 1; r <= 5; ++r) {
+      SvShape sh;
+      if (!choose_shape(dtype, *c, count_slots(*c, ps), r, false, &sh, ps) || sh.r != r) continue;
+      g_force_fwd_r = r;
+      const float ms = time_ms(st, fwd, 3, &rc);
+      g_force_fwd_r = 0;
+      info.n_candidates++;
+      if (rc != QS_OK) return rc;
+      if (ms < bf) { bf = ms; best.fwd_r = r; }
+    }
+    for (int r = 1; r <= 5; ++r) {
+      SvShape sh;
+      if (!choose_shape(dtype, *c, count_slots(*c, ps), r, true, &sh, ps) || sh.r != r) continue;
+      g_force_adj_r = r;
+      const size_t wsb = fused_ws_bytes(*c, dtype, sh, B, ps);
+      void* ws = sc.get(wsb);
+      if (!ws) { g_force_adj_r = 0; return QS_ERR_NOMEM; }
+      const float ms = time_ms(st, [&]() { return adj(ws, wsb); }, 3, &rc);
+      g_force_adj_r = 0;
+      info.n_candidates++;
+      if (rc != QS_OK) return rc;
+      if (ms < ba) { ba = ms; best.adj_r = r; }
+    }
+  } else {
+    const int hi = std::min(c->n_qubits, dtype == QS_C64 ? kMaxQubitsFused : 13);
+    float bt = 1e30f;
+    for (int m = std::max(6, hi - 3); m <= hi; ++m) {
+      g_force_m = m;
+      const size_t wsb = tiled_ws_bytes(*c, dtype, B, ps, m, &rc);
+      void* ws = rc == QS_OK ? sc.get(wsb) : nullptr;
+      if (!ws) { g_force_m = 0; rc = QS_OK; continue; }
+      const float mf = time_ms(st, fwd, 1, &rc);
+      const float ma = rc == QS_OK ? time_ms(st, [&]() { return adj(ws, wsb); }, 1, &rc) : 0.f;
+      g_force_m = 0;
+      info.n_candidates++;
+      if (rc != QS_OK) return rc;
+      if (mf + ma < bt) { bt = mf + ma; bf = mf; ba = ma; best.m = m; }
+    }
+  }
+  info.fwd_log2_regs = best.fwd_r;
+  info.adj_log2_regs = best.adj_r;
+  info.tile_qubits = best.m;
+  info.fwd_ms = bf;
+  info.adj_ms = ba;
+  {
+    std::lock_guard<std::mutex> lock(g_tmu);
+    load_tune_file_locked();
+    const std::string key = tune_key(*c, dtype, B, flags);
+    g_tune[key] = best;
+    const char* path_env = std::getenv("QS_AUTOTUNE_CACHE");
+    if (path_env && *path_env) {
+      if (FILE* f = std::fopen(path_env, "a")) {
+        std::fprintf(f, "%s %d %d %d\n", key.c_str(), best.fwd_r, best.adj_r, best.m);
+        std::fclose(f);
+      }
+    }
+  }
+  if (out) *out = info;
+  return QS_OK;
+}
 
 int qs_version(void) { return kVersion; }
 
@@ -328,9 +707,12 @@ int qs_forward(const qs_circuit* c, int dtype, int64_t B, const void* params,
   if (c->n_features > 0 && !feats) return QS_ERR_INVALID;
   if ((rc = check_ckpt(c, ckpt_gates, n_ckpt, ckpt)) != QS_OK) return rc;
   const bool ps = (flags & QS_FLAG_PER_SAMPLE_PARAMS) != 0;
+  TuneVal tv;
+  const bool tuned = tuned_for_call(*c, dtype, B, flags, stream, &tv);
   SvShape shape;
-  const int path = pick_path(*c, dtype, flags, &shape, count_slots(*c, ps), false);
-  if (path < 0) return -path;
+  const int path = pick_path(*c, dtype, flags, &shape, count_slots(*c, ps), false,
+                             tuned ? tv.fwd_r : 0);
+  if (path < 0) return path;
   if (path == QS_PATH_PLAIN) {
     PlainLaunch L{};
     L.c = c;
@@ -346,6 +728,35 @@ int qs_forward(const qs_circuit* c, int dtype, int64_t B, const void* params,
     L.ckpt = ckpt;
     L.stream = stream;
     return run_plain_forward(L);
+  }
+  if (path == QS_PATH_HBM) {
+    TiledEntry* te = get_tiled(*c, dtype, ps, ckpt_gates, n_ckpt, tuned ? tv.m : 0, &rc);
+    if (!te) return rc;
+    const int64_t per = B << c->n_qubits;  // complex elements per state batch
+    const size_t cs = dtype == QS_C64 ? 8 : 16;
+    for (const TiledEpochDev& d : te->epochs) {
+      SvLaunch L{};
+      L.p = &d.fwd->dev;
+      L.shape = d.fshape;
+      L.B = B;
+      L.per_sample_params = ps;
+      L.params = params;
+      L.feats = feats;
+      L.state = state;
+      L.n_tot = c->n_qubits;
+      L.ob = c->n_qubits - te->m;
+      L.tile_q = d.tile_q;
+      L.outer_q = d.outer_q;
+      L.stream = stream;
+      if ((rc = launch_sv_forward(dtype, L)) != QS_OK) return rc;
+      if (d.ckpt_after >= 0 && ckpt) {
+        rc = launch_copy_state(dtype, state,
+                               static_cast<char*>(ckpt) + cs * per * d.ckpt_after, per,
+                               stream);
+        if (rc != QS_OK) return rc;
+      }
+    }
+    return expz ? launch_expz(dtype, c->n_qubits, B, state, expz, stream) : QS_OK;
   }
   Entry* e = get_plan(*c, shape.r, ps, ckpt_gates, n_ckpt, &rc);
   if (!e) return rc;
@@ -366,10 +777,17 @@ int qs_forward(const qs_circuit* c, int dtype, int64_t B, const void* params,
 size_t qs_workspace_size(const qs_circuit* c, int dtype, int64_t B, int flags) {
   if (validate(c) != QS_OK || B < 0) return 0;
   const bool ps = (flags & QS_FLAG_PER_SAMPLE_PARAMS) != 0;
+  TuneVal tv;
+  const bool tuned = tuned_lookup(*c, dtype, B, flags, &tv);
   SvShape shape;
-  const int path = pick_path(*c, dtype, flags, &shape, count_slots(*c, ps), true);
+  const int path = pick_path(*c, dtype, flags, &shape, count_slots(*c, ps), true,
+                             tuned ? tv.adj_r : 0);
   if (path == QS_PATH_PLAIN) return plain_workspace_bytes(*c, dtype, B);
   if (path == QS_PATH_FUSED) return fused_ws_bytes(*c, dtype, shape, B, ps);
+  if (path == QS_PATH_HBM) {
+    int rc = QS_OK;
+    return tiled_ws_bytes(*c, dtype, B, ps, tuned ? tv.m : 0, &rc);
+  }
   return 0;
 }
 
@@ -395,12 +813,72 @@ int qs_adjoint_backward(const qs_circuit* c, int dtype, int64_t B,
   if (c->n_params > 0 && (!params || !grad_params)) return QS_ERR_INVALID;
   if (c->n_features > 0 && !feats) return QS_ERR_INVALID;
   if ((rc = check_ckpt(c, ckpt_gates, n_ckpt, ckpt)) != QS_OK) return rc;
+  TuneVal tv;
+  const bool tuned = tuned_for_call(*c, dtype, B, flags, stream, &tv);
   SvShape shape;
-  const int path = pick_path(*c, dtype, flags, &shape, count_slots(*c, ps), true);
-  if (path < 0) return -path;
+  const int path = pick_path(*c, dtype, flags, &shape, count_slots(*c, ps), true,
+                             tuned ? tv.adj_r : 0);
+  if (path < 0) return path;
+  const int m_pref = tuned ? tv.m : 0;
   const size_t need = path == QS_PATH_PLAIN ? plain_workspace_bytes(*c, dtype, B)
-                                            : fused_ws_bytes(*c, dtype, shape, B, ps);
+                     : path == QS_PATH_HBM ? tiled_ws_bytes(*c, dtype, B, ps, m_pref, &rc)
+                                           : fused_ws_bytes(*c, dtype, shape, B, ps);
+  if (rc != QS_OK) return rc;
   if (need > 0 && (!ws || ws_bytes < need)) return QS_ERR_WORKSPACE;
+  if (path == QS_PATH_HBM) {
+    TiledEntry* te = get_tiled(*c, dtype, ps, ckpt_gates, n_ckpt, m_pref, &rc);
+    if (!te) return rc;
+    const int64_t per = B << c->n_qubits;
+    const size_t cs = dtype == QS_C64 ? 8 : 16;
+    char* psi_w = static_cast<char*>(ws);
+    char* lam_w = psi_w + cs * per;
+    void* part = lam_w + cs * per;
+    if ((rc = launch_copy_state(dtype, state, psi_w, per, stream)) != QS_OK) return rc;
+    rc = dstate ? launch_copy_state(dtype, dstate, lam_w, per, stream)
+                : launch_obs_cot(dtype, c->n_qubits, B, dexpz, psi_w, lam_w, stream);
+    if (rc != QS_OK) return rc;
+    const int64_t gp_n = ps ? B * c->n_params : c->n_params;
+    if (c->n_params && (rc = launch_fill_f64(grad_params, gp_n, stream)) != QS_OK) return rc;
+    if (c->n_features && grad_feats &&
+        (rc = launch_fill_f64(grad_feats, B * c->n_features, stream)) != QS_OK)
+      return rc;
+    const int64_t samples = B << (c->n_qubits - te->m);
+    for (int i = (int)te->epochs.size() - 1; i >= 0; --i) {
+      const TiledEpochDev& d = te->epochs[i];
+      if (d.ckpt_after >= 0 && ckpt) {  // psi after this epoch = the checkpoint
+        rc = launch_copy_state(dtype,
+                               static_cast<const char*>(ckpt) + cs * per * d.ckpt_after,
+                               psi_w, per, stream);
+        if (rc != QS_OK) return rc;
+      }
+      SvLaunch L{};
+      L.p = &d.adj->dev;
+      L.shape = d.ashape;
+      L.B = B;
+      L.per_sample_params = ps;
+      L.params = params;
+      L.feats = feats;
+      L.state = psi_w;
+      L.dstate = lam_w;
+      L.out_psi = psi_w;
+      L.out_lam = lam_w;
+      L.ws_partials = part;
+      L.grad_params = grad_params;
+      L.grad_feats = c->n_features ? grad_feats : nullptr;
+      L.n_tot = c->n_qubits;
+      L.ob = c->n_qubits - te->m;
+      L.tile_q = d.tile_q;
+      L.outer_q = d.outer_q;
+      L.stream = stream;
+      if ((rc = launch_sv_adjoint(dtype, L)) != QS_OK) return rc;
+      if (!ps && c->n_params) {
+        const int64_t grid = (samples + d.ashape.samples_per_block - 1) / d.ashape.samples_per_block;
+        rc = launch_reduce_partials(dtype, part, grid, c->n_params, grad_params, 1, stream);
+        if (rc != QS_OK) return rc;
+      }
+    }
+    return QS_OK;
+  }
   if (path == QS_PATH_PLAIN) {
     qs_gate* dg = get_dev_gates(*c, &rc);
     if (!dg && c->n_gates) return rc;
@@ -447,7 +925,7 @@ int qs_adjoint_backward(const qs_circuit* c, int dtype, int64_t B,
   if ((rc = launch_sv_adjoint(dtype, L)) != QS_OK) return rc;
   if (!ps && c->n_params)
     rc = launch_reduce_partials(dtype, ws, grid_of(shape, B), c->n_params,
-                                grad_params, stream);
+                                grad_params, 0, stream);
   return rc;
 }
 
@@ -476,13 +954,24 @@ int qs_plan_info_get(const qs_circuit* c, int dtype, int64_t B, int flags,
   if (rc != QS_OK) return rc;
   if (!out || (dtype != QS_C64 && dtype != QS_C128)) return QS_ERR_INVALID;
   const bool ps = (flags & QS_FLAG_PER_SAMPLE_PARAMS) != 0;
+  TuneVal tv;
+  const bool tuned = tuned_lookup(*c, dtype, B, flags, &tv);
   SvShape shape, ashape;
-  const int path = pick_path(*c, dtype, flags, &shape, count_slots(*c, ps), false);
-  if (path < 0) return -path;
+  const int path = pick_path(*c, dtype, flags, &shape, count_slots(*c, ps), false,
+                             tuned ? tv.fwd_r : 0);
+  if (path < 0) return path;
   std::memset(out, 0, sizeof(*out));
   out->path = path;
+  if (path == QS_PATH_HBM) {
+    TiledHostInfo h = tiled_host_info(*c, dtype, B, ps, tuned ? tv.m : 0);
+    if (!h.ok) return QS_ERR_UNSUPPORTED;
+    out->n_segments = h.n_epochs;  // epochs
+    out->log2_threads = h.m;       // tile qubits
+    return QS_OK;
+  }
   if (path != QS_PATH_FUSED) return QS_OK;
-  if (pick_path(*c, dtype, flags, &ashape, count_slots(*c, ps), true) == QS_PATH_FUSED) {
+  if (pick_path(*c, dtype, flags, &ashape, count_slots(*c, ps), true,
+                tuned ? tv.adj_r : 0) == QS_PATH_FUSED) {
     out->adj_log2_regs = ashape.r;
     out->adj_samples_per_block = ashape.samples_per_block;
     out->adj_block_threads = ashape.block_threads;
@@ -507,7 +996,7 @@ int qs_plan_export(const qs_circuit* c, int dtype, int64_t B, int flags,
   if (rc != QS_OK) return rc;
   if (info->path != QS_PATH_FUSED) return QS_ERR_UNSUPPORTED;
   const bool ps = (flags & QS_FLAG_PER_SAMPLE_PARAMS) != 0;
-  SvPlan P = plan_sv(*c, info->log2_regs, ps, nullptr, 0);
+  SvPlan P = plan_sv(*c, info->log2_regs, ps, nullptr, 0);  // the forward plan
   if (ops)
     for (size_t o = 0; o < P.ops.size(); ++o) {
       ops[4 * o] = P.ops[o].kind;
@@ -530,6 +1019,14 @@ void qs_shutdown(void) {
   g_cache.clear();
   for (auto& kv : g_gate_cache) (void)hipFree(kv.second);
   g_gate_cache.clear();
+  for (auto& kv : g_tiled) {
+    for (auto& d : kv.second->epochs) {
+      (void)hipFree(d.tile_q);
+      (void)hipFree(d.outer_q);
+    }
+    delete kv.second;
+  }
+  g_tiled.clear();
 }
 
 }  // extern "C"

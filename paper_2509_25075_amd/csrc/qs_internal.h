@@ -123,10 +123,53 @@ int launch_fidelity(int dtype, int n, int n_trash, int64_t B, const void* psi,
                     const void* chi, double* fid, const double* dfid,
                     void* lam_psi, void* lam_chi, void* stream);
 int launch_reduce_partials(int dtype, const void* partials, int64_t rows,
-                           int cols, double* out, void* stream);
+                           int cols, double* out, int accumulate, void* stream);
+int launch_obs_cot(int dtype, int n, int64_t B, const double* dexpz,
+                   const void* psi, void* lam, void* stream);
 int launch_fill_f64(double* p, int64_t n, void* stream);
 int launch_copy_state(int dtype, const void* src, void* dst, int64_t n_amp,
                       void* stream);
+
+// Uneven batches: classes of identically-structured circuits, one parameter
+// set and one state per circuit, packed class after class.
+struct ProgClass {
+  const uint8_t* seg_map;
+  const int32_t* seg_begin;
+  const int32_t* seg_ckpt;
+  const SvOp* ops;
+  const qs_gate* gates;
+  const int32_t* angle_slot;
+  const int32_t* slot_gate;
+  int32_t n, t, nseg, n_gates, n_slots, n_params, S, pad;
+  int64_t count;       // circuits in the class
+  int64_t state_off;   // complex-element offset of the class's first state
+  int64_t param_off;   // element offset of the class's parameters [count][P]
+  int64_t expz_off;    // element offset of the class's <Z> rows [count][n]
+};
+struct ProgItem {
+  int32_t cls;
+  int32_t first;       // first circuit of the class in this work item
+};
+struct ProgLaunch {
+  const ProgClass* classes;  // device
+  const ProgItem* items;     // device, longest first
+  int n_items;
+  int* counter;              // device work-queue counter
+  int grid, block, r;
+  int64_t lds_bytes;
+  const void* params;
+  void* states;
+  double* expz;
+  const double* dexpz;
+  double* grad_params;
+  void* stream;
+};
+int launch_program(int dtype, const ProgLaunch& L, bool adjoint);
+int launch_zero_i32(int* p, void* stream);
+int launch_program_encode(int dtype, int n_classes, const int64_t* d_counts_cum,
+                          const int32_t* d_nq, const int64_t* d_state_off,
+                          int64_t n_circuits, const void* x, int x_is_f64,
+                          void* states, int32_t* bad_rows, void* stream);
 
 // Plain one-gate-per-launch path.
 struct PlainLaunch {

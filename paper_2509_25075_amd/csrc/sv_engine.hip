@@ -362,6 +362,21 @@ struct V2<double> { using T = double2; };
 __device__ __forceinline__ void fsincos(float x, float* s, float* c) { sincosf(x, s, c); }
 __device__ __forceinline__ void fsincos(double x, double* s, double* c) { sincos(x, s, c); }
 
+template <typename real>
+__device__ __forceinline__ const real* param_row(const Args<real>& A, int64_t b) {
+  return A.per_sample_params ? A.params + (size_t)b * A.n_params : A.params;
+}
+
+template <typename real>
+__device__ __forceinline__ real theta_of(const Args<real>& A, const qs_gate& g,
+                                         int64_t b) {
+  const real* P = param_row(A, b);
+  real w = g.p_w >= 0 ? P[g.p_w] : (real)1;
+  real f = g.feat >= 0 ? A.feats[(size_t)b * A.n_feats + g.feat] : (real)1;
+  real bias = g.p_b >= 0 ? P[g.p_b] : (real)0;
+  return (real)g.scale * (w * f + bias);
+}
+
 // Per-sample sync: a wave barrier when a sample lives in one wave,
 // otherwise a workgroup barrier (T is uniform over the workgroup).
 __device__ __forceinline__ void sample_sync(int t) {
@@ -375,7 +390,7 @@ __device__ __forceinline__ void sample_sync(int t) {
 }
 
 // The engine's per-thread context.
-template <typename real, int LR>
+template <typename real, int LR, bool FLY = false>
 struct Ctx {
   static constexpr int R = 1 << LR;
   using v2 = typename V2<real>::T;
@@ -390,8 +405,9 @@ struct Ctx {
   uint32_t salt;     // per-sample slot salt
   real* ang_sh;      // [G][2] shared (cos, sin) of theta/2
   real* ang_ps;      // [n_slots][S][2] per-sample
-  real* gacc;        // [n_params] shared-parameter gradient accumulators
-  real* facc;        // [S][n_feats] feature gradient accumulators
+  real* gacc;        // [waves][n_params] shared-parameter gradient sums
+  real* facc;        // [S * wps][n_feats] feature gradient sums
+  int wps;           // waves per sample (1 when a wave holds whole samples)
 
   __device__ Ctx(const Args<real>& a) : A(a) {}
 
@@ -494,8 +510,17 @@ struct Ctx {
   }
 
   // cos, sin of theta/2 for op number o (op o comes from gate o).
-  __device__ __forceinline__ void angle(int o, int aux, real& c, real& s) const {
-    if (aux & 1) {
+  __device__ __forceinline__ void angle(int o, const SvOp& op, real& c, real& s) const {
+    if constexpr (FLY) {
+      if (op.aux & 1) {
+        // per-sample angle computed in place (no per-sample table in LDS)
+        const qs_gate gt = kload(A.gates, op.gate);
+        const real th = active ? theta_of(A, gt, row) : (real)0;
+        fsincos(th * (real)0.5, &s, &c);
+        return;
+      }
+    }
+    if (op.aux & 1) {
       const int slot = kc(A.angle_slot)[o];
       const real* p = ang_ps + 2 * ((size_t)slot * A.S + sl);
       c = p[0];
@@ -595,30 +620,18 @@ struct Ctx {
   }
 };
 
-template <typename real>
-__device__ __forceinline__ const real* param_row(const Args<real>& A, int64_t b) {
-  return A.per_sample_params ? A.params + (size_t)b * A.n_params : A.params;
-}
-
-template <typename real>
-__device__ __forceinline__ real theta_of(const Args<real>& A, const qs_gate& g,
-                                         int64_t b) {
-  const real* P = param_row(A, b);
-  real w = g.p_w >= 0 ? P[g.p_w] : (real)1;
-  real f = g.feat >= 0 ? A.feats[(size_t)b * A.n_feats + g.feat] : (real)1;
-  real bias = g.p_b >= 0 ? P[g.p_b] : (real)0;
-  return (real)g.scale * (w * f + bias);
-}
-
 // Common prologue: LDS carve-up and angle tables.
-template <typename real, int LR>
-__device__ __forceinline__ void setup(Ctx<real, LR>& C, const Args<real>& A,
-                                      unsigned char* smem, bool adjoint) {
+// `blk` is the global index of the block's first sample. Gradient sums are
+// kept in per-wave LDS slots (each written by one lane of one wave) and added
+// in a fixed order at the end, so the adjoint is bitwise reproducible.
+template <typename real, int LR, bool FLY>
+__device__ __forceinline__ void setup(Ctx<real, LR, FLY>& C, const Args<real>& A,
+                                      unsigned char* smem, bool adjoint, int64_t blk) {
   const int tid = threadIdx.x;
   const int N = 1 << A.n;
   C.tau = tid & ((1 << A.t) - 1);
   C.sl = tid >> A.t;
-  C.b = (int64_t)blockIdx.x * A.S + C.sl;
+  C.b = blk + C.sl;
   C.active = C.b < A.B;
   C.row = C.b >> A.ob;
   if (A.tile_q == nullptr) {
@@ -642,8 +655,10 @@ __device__ __forceinline__ void setup(Ctx<real, LR>& C, const Args<real>& A,
   real* tail = reinterpret_cast<real*>(st + (size_t)A.S * N);
   C.ang_sh = tail;
   C.ang_ps = C.ang_sh + 2 * (size_t)A.n_gates;
-  C.gacc = C.ang_ps + 2 * (size_t)A.n_slots * A.S;
-  C.facc = C.gacc + A.n_params;
+  C.gacc = C.ang_ps + (FLY ? 0 : 2 * (size_t)A.n_slots * A.S);
+  C.wps = A.t > 6 ? (1 << (A.t - 6)) : 1;
+  const int waves = blockDim.x >> 6;
+  C.facc = C.gacc + (A.per_sample_params ? 0 : (size_t)waves * A.n_params);
 
   // Shared angles in op order (op o applies gate ops[o].gate).
   for (int o = tid; o < A.n_gates; o += blockDim.x) {
@@ -657,9 +672,9 @@ __device__ __forceinline__ void setup(Ctx<real, LR>& C, const Args<real>& A,
     C.ang_sh[2 * o] = c;
     C.ang_sh[2 * o + 1] = s;
   }
-  for (int i = tid; i < A.n_slots * A.S; i += blockDim.x) {
+  for (int i = tid; i < (FLY ? 0 : A.n_slots * A.S); i += blockDim.x) {
     const int slot = i / A.S, s_l = i % A.S;
-    const int64_t bb = (int64_t)blockIdx.x * A.S + s_l;
+    const int64_t bb = blk + s_l;
     real c = 1, s = 0;
     if (bb < A.B) {
       qs_gate gt = kload(A.gates, kc(A.slot_gate)[slot]);
@@ -670,8 +685,9 @@ __device__ __forceinline__ void setup(Ctx<real, LR>& C, const Args<real>& A,
     C.ang_ps[2 * (size_t)i + 1] = s;
   }
   if (adjoint) {
-    for (int i = tid; i < A.n_params; i += blockDim.x) C.gacc[i] = 0;
-    for (int i = tid; i < A.S * A.n_feats; i += blockDim.x) C.facc[i] = 0;
+    if (!A.per_sample_params)
+      for (int i = tid; i < waves * A.n_params; i += blockDim.x) C.gacc[i] = 0;
+    for (int i = tid; i < A.S * C.wps * A.n_feats; i += blockDim.x) C.facc[i] = 0;
   }
   __syncthreads();
 }
@@ -691,12 +707,12 @@ __device__ __forceinline__ bool map_changed(const Args<real>& A, int s) {
 }
 
 // ------------------------------------------------------------------ forward
-template <typename real, int LR, int MAXT>
-__global__ void __launch_bounds__(MAXT) sv_forward(Args<real> A) {
+template <typename real, int LR, bool FLY = false>
+__device__ __forceinline__ void forward_body(const Args<real>& A, unsigned char* smem,
+                                             int64_t blk) {
   constexpr int R = 1 << LR;
-  extern __shared__ __align__(16) unsigned char smem[];
-  Ctx<real, LR> C(A);
-  setup<real, LR>(C, A, smem, false);
+  Ctx<real, LR, FLY> C(A);
+  setup<real, LR, FLY>(C, A, smem, false, blk);
 
   St<real, R> x;
   C.load_state(x, A.state, seg_map<real, LR>(A, 0));
@@ -712,11 +728,11 @@ __global__ void __launch_bounds__(MAXT) sv_forward(Args<real> A) {
       // while op o is applied.
       SvOp cur = kload(A.ops, o);
       real c, sn;
-      C.angle(o, cur.aux, c, sn);
+      C.angle(o, cur, c, sn);
       for (; o < e; ++o) {
         const SvOp nxt = kload(A.ops, o + 1 < e ? o + 1 : o);
         real nc, ns;
-        C.angle(o + 1 < e ? o + 1 : o, nxt.aux, nc, ns);
+        C.angle(o + 1 < e ? o + 1 : o, nxt, nc, ns);
         C.apply(x, uni(cur.kind), uni(cur.a), uni(cur.b), c, sn);
         cur = nxt;
         c = nc;
@@ -773,12 +789,12 @@ __global__ void __launch_bounds__(MAXT) sv_forward(Args<real> A) {
 }
 
 // ------------------------------------------------------------------ adjoint
-template <typename real, int LR, int MAXT>
-__global__ void __launch_bounds__(MAXT) sv_adjoint(Args<real> A) {
+template <typename real, int LR, bool FLY = false>
+__device__ __forceinline__ void adjoint_body(const Args<real>& A, unsigned char* smem,
+                                             int64_t blk) {
   constexpr int R = 1 << LR;
-  extern __shared__ __align__(16) unsigned char smem[];
-  Ctx<real, LR> C(A);
-  setup<real, LR>(C, A, smem, true);
+  Ctx<real, LR, FLY> C(A);
+  setup<real, LR, FLY>(C, A, smem, true, blk);
   const int nseg = A.nseg;
   const QS_K uint8_t* last = seg_map<real, LR>(A, nseg - 1);
 
@@ -816,6 +832,7 @@ __global__ void __launch_bounds__(MAXT) sv_adjoint(Args<real> A) {
 
   const int Tw = (1 << A.t) < 64 ? (1 << A.t) : 64;
   const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
   const QS_K int32_t* seg_begin = kc(A.seg_begin);
   for (int s = nseg - 1; s >= 0; --s) {
     const int ck = kc(A.seg_ckpt)[s];
@@ -827,12 +844,12 @@ __global__ void __launch_bounds__(MAXT) sv_adjoint(Args<real> A) {
     if (o >= beg) {
       SvOp cur = kload(A.ops, o);
       real c, sn;
-      C.angle(o, cur.aux, c, sn);
+      C.angle(o, cur, c, sn);
       for (; o >= beg; --o) {
         const int on = o - 1 >= beg ? o - 1 : o;
         const SvOp nxt = kload(A.ops, on);
         real nc, ns;
-        C.angle(on, nxt.aux, nc, ns);
+        C.angle(on, nxt, nc, ns);
         const int kind = uni(cur.kind), a = uni(cur.a), bq = uni(cur.b);
         if (kind <= QS_OP_RZ) {
           const real part = C.grad_partial(kind, a, psi, lam);
@@ -842,15 +859,16 @@ __global__ void __launch_bounds__(MAXT) sv_adjoint(Args<real> A) {
             // shared parameters, no feature: dL/dP += scale sum_b dL/dtheta_b
             const real v = group_sum(part, 64);
             if (lane == 0) {
-              if (gt.p_w >= 0) atomicAdd(&C.gacc[gt.p_w], scale * v);
-              if (gt.p_b >= 0) atomicAdd(&C.gacc[gt.p_b], scale * v);
+              real* g = C.gacc + (size_t)wave * A.n_params;
+              if (gt.p_w >= 0) g[gt.p_w] += scale * v;
+              if (gt.p_b >= 0) g[gt.p_b] += scale * v;
             }
           } else {
             const real gth = group_sum(part, Tw);  // this sample (this wave's share)
             const bool leader = (C.tau & (Tw - 1)) == 0 && C.active;
-            const real* P = param_row(A, C.active ? C.b : 0);
+            const real* P = param_row(A, C.active ? C.row : 0);
             const real f = (gt.feat >= 0 && C.active)
-                               ? A.feats[(size_t)C.b * A.n_feats + gt.feat]
+                               ? A.feats[(size_t)C.row * A.n_feats + gt.feat]
                                : (real)1;
             const real w = gt.p_w >= 0 ? P[gt.p_w] : (real)1;
             if (A.per_sample_params) {
@@ -862,15 +880,16 @@ __global__ void __launch_bounds__(MAXT) sv_adjoint(Args<real> A) {
             } else {
               if (gt.p_w >= 0) {
                 const real v = group_sum(leader ? gth * scale * f : (real)0, 64);
-                if (lane == 0) atomicAdd(&C.gacc[gt.p_w], v);
+                if (lane == 0) C.gacc[(size_t)wave * A.n_params + gt.p_w] += v;
               }
               if (gt.p_b >= 0) {
                 const real v = group_sum(leader ? gth * scale : (real)0, 64);
-                if (lane == 0) atomicAdd(&C.gacc[gt.p_b], v);
+                if (lane == 0) C.gacc[(size_t)wave * A.n_params + gt.p_b] += v;
               }
             }
             if (gt.feat >= 0 && leader)
-              atomicAdd(&C.facc[C.sl * A.n_feats + gt.feat], gth * scale * w);
+              C.facc[((size_t)C.sl * C.wps + (C.tau >> 6)) * A.n_feats + gt.feat] +=
+                  gth * scale * w;
           }
           sn = -sn;  // inverse rotation
         }
@@ -889,20 +908,105 @@ __global__ void __launch_bounds__(MAXT) sv_adjoint(Args<real> A) {
   if (A.out_psi != nullptr) C.store_state(psi, A.out_psi, seg_map<real, LR>(A, 0));
   if (A.out_lam != nullptr) C.store_state(lam, A.out_lam, seg_map<real, LR>(A, 0));
   __syncthreads();
+  const int waves = blockDim.x >> 6;
   if (!A.per_sample_params)
-    for (int i = threadIdx.x; i < A.n_params; i += blockDim.x)
-      A.ws_partials[(size_t)blockIdx.x * A.n_params + i] = C.gacc[i];
+    for (int i = threadIdx.x; i < A.n_params; i += blockDim.x) {
+      real t = 0;
+      for (int w = 0; w < waves; ++w) t += C.gacc[(size_t)w * A.n_params + i];
+      A.ws_partials[(size_t)blockIdx.x * A.n_params + i] = t;
+    }
   if (A.grad_feats != nullptr)
     for (int i = threadIdx.x; i < A.S * A.n_feats; i += blockDim.x) {
-      const int64_t bb = (int64_t)blockIdx.x * A.S + i / A.n_feats;
+      const int sl = i / A.n_feats, f = i % A.n_feats;
+      const int64_t bb = blk + sl;
       if (bb >= A.B) continue;
-      double* dst = &A.grad_feats[(size_t)(bb >> A.ob) * A.n_feats + i % A.n_feats];
+      real t = 0;
+      for (int w = 0; w < C.wps; ++w) t += C.facc[((size_t)sl * C.wps + w) * A.n_feats + f];
+      double* dst = &A.grad_feats[(size_t)(bb >> A.ob) * A.n_feats + f];
       if (A.tile_q != nullptr)
-        atomicAdd(dst, (double)C.facc[i]);  // several tiles share a batch row
+        atomicAdd(dst, (double)t);  // several tiles share a batch row
       else
-        *dst = C.facc[i];
+        *dst = t;
     }
 }
+
+template <typename real, int LR, int MAXT>
+__global__ void __launch_bounds__(MAXT) sv_forward(Args<real> A) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  forward_body<real, LR>(A, smem, (int64_t)blockIdx.x * A.S);
+}
+
+template <typename real, int LR, int MAXT>
+__global__ void __launch_bounds__(MAXT) sv_adjoint(Args<real> A) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  adjoint_body<real, LR>(A, smem, (int64_t)blockIdx.x * A.S);
+}
+
+// Uneven batches in one persistent launch: workgroups pull work items (a
+// class of identically-structured circuits and a run of S of its circuits)
+// from an atomic counter until the queue is empty; items are ordered longest
+// first. Every workgroup runs the same engine as the batched kernels, with
+// per-circuit angles computed in place (no per-sample LDS table).
+template <typename real, int LR, int MAXT, bool ADJ>
+__global__ void __launch_bounds__(MAXT)
+sv_program(const ProgClass* classes, const ProgItem* items, int n_items,
+           int* counter, const real* params, real* states, double* expz,
+           const double* dexpz, double* grad_params) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int item_sh;
+  for (;;) {
+    if (threadIdx.x == 0) item_sh = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = item_sh;
+    __syncthreads();
+    if (it >= n_items) break;  // every wave of the workgroup sees the same it
+    const ProgItem w = kload(items, it);
+    const ProgClass cd = kload(classes, w.cls);
+    Args<real> A;
+    A.seg_map = cd.seg_map;
+    A.seg_begin = cd.seg_begin;
+    A.seg_ckpt = cd.seg_ckpt;
+    A.ops = cd.ops;
+    A.gates = cd.gates;
+    A.angle_slot = cd.angle_slot;
+    A.slot_gate = cd.slot_gate;
+    A.n = cd.n;
+    A.t = cd.t;
+    A.nseg = cd.nseg;
+    A.n_gates = cd.n_gates;
+    A.n_slots = cd.n_slots;
+    A.n_params = cd.n_params;
+    A.n_feats = 0;
+    A.S = cd.S;
+    A.per_sample_params = 1;
+    const int64_t left = cd.count - w.first;
+    A.B = left < cd.S ? left : cd.S;
+    A.n_tot = 0;
+    A.ob = 0;
+    A.tile_q = nullptr;
+    A.outer_q = nullptr;
+    A.out_psi = nullptr;
+    A.out_lam = nullptr;
+    const int64_t first = w.first;
+    A.params = params + cd.param_off + first * cd.n_params;
+    A.feats = nullptr;
+    A.state = states + 2 * (cd.state_off + (first << cd.n));
+    A.expz = expz ? expz + cd.expz_off + first * cd.n : nullptr;
+    A.ckpt = nullptr;
+    A.dexpz = dexpz ? dexpz + cd.expz_off + first * cd.n : nullptr;
+    A.dstate = nullptr;
+    A.ws_partials = nullptr;
+    A.grad_params = grad_params ? grad_params + cd.param_off + first * cd.n_params : nullptr;
+    A.grad_feats = nullptr;
+    if (ADJ)
+      adjoint_body<real, LR, true>(A, smem, 0);
+    else
+      forward_body<real, LR, true>(A, smem, 0);
+    __syncthreads();  // the next item reuses the LDS
+  }
+}
+
+__global__ void zero_i32(int* p) { *p = 0; }
 
 template <typename real>
 Args<real> make_args(const SvLaunch& L) {
@@ -997,7 +1101,40 @@ int dispatch(int dtype, const SvLaunch& L, bool adjoint) {
   }
 }
 
+
+template <typename real, int LR, int MAXT>
+int launch_prog(const ProgLaunch& L, bool adjoint) {
+  hipStream_t st = static_cast<hipStream_t>(L.stream);
+  auto kern = adjoint ? sv_program<real, LR, MAXT, true> : sv_program<real, LR, MAXT, false>;
+  if (L.lds_bytes > 65536 &&
+      hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)L.lds_bytes) != hipSuccess)
+    return QS_ERR_LAUNCH;
+  hipLaunchKernelGGL(kern, dim3((unsigned)L.grid), dim3((unsigned)L.block),
+                     (size_t)L.lds_bytes, st, L.classes, L.items, L.n_items, L.counter,
+                     static_cast<const real*>(L.params), static_cast<real*>(L.states),
+                     L.expz, L.dexpz, L.grad_params);
+  return hipGetLastError() == hipSuccess ? QS_OK : QS_ERR_LAUNCH;
+}
+
 }  // namespace
+
+int launch_program(int dtype, const ProgLaunch& L, bool adjoint) {
+  if (L.block != 512) return QS_ERR_UNSUPPORTED;
+  if (dtype == QS_C64) {
+    if (L.r == 5) return launch_prog<float, 5, 512>(L, adjoint);
+    if (L.r == 4) return launch_prog<float, 4, 512>(L, adjoint);
+    return QS_ERR_UNSUPPORTED;
+  }
+  if (L.r == 4) return launch_prog<double, 4, 512>(L, adjoint);
+  return QS_ERR_UNSUPPORTED;
+}
+
+int launch_zero_i32(int* p, void* stream) {
+  hipLaunchKernelGGL(zero_i32, dim3(1), dim3(1), 0, static_cast<hipStream_t>(stream), p);
+  return hipGetLastError() == hipSuccess ? QS_OK : QS_ERR_LAUNCH;
+}
 
 int launch_sv_forward(int dtype, const SvLaunch& L) { return dispatch(dtype, L, false); }
 int launch_sv_adjoint(int dtype, const SvLaunch& L) { return dispatch(dtype, L, true); }

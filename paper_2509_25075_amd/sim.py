@@ -209,3 +209,55 @@ def step(d: DeviceWorkload, backward: bool = True) -> dict:
     if gf is not None:
         out["grad_feats"] = gf
     return out
+
+
+# ------------------------------------------------------------- uneven batch
+class UnevenDevice:
+    """An uneven batch resident on the GPU: packed inputs, parameters, readout
+    weights, states, <Z> and gradient buffers; one step = program encode,
+    persistent forward (with FP64 readout), loss sum_q g_q <Z_q>, persistent
+    adjoint."""
+
+    def __init__(self, ub, dtype: str = "c64", device="cuda"):
+        require_gpu()
+        self.ub = ub
+        self.qs_dtype, self.cdtype, self.rdtype = _DT[dtype]
+        self.ph = N.ProgramHandle([c for (_, _, c, _) in ub.classes],
+                                  [len(idx) for (_, _, _, idx) in ub.classes])
+        so, po, eo, tot = self.ph.layout()
+        assert (so == ub.state_off).all() and (po == ub.param_off).all() \
+            and (eo == ub.expz_off).all()
+        self.x = torch.as_tensor(ub.x).to(device=device, dtype=self.rdtype)
+        self.params = torch.as_tensor(ub.params).to(device=device, dtype=self.rdtype)
+        self.weights = torch.as_tensor(ub.weights).to(device=device, dtype=torch.float64)
+        self.states = torch.empty(int(tot[0]), dtype=self.cdtype, device=device)
+        self.expz = torch.empty(int(tot[2]), dtype=torch.float64, device=device)
+        self.grad = torch.empty(int(tot[1]), dtype=torch.float64, device=device)
+
+    def step(self, backward: bool = True) -> dict:
+        N.qs_program_encode(self.ph, self.qs_dtype, self.x, self.states)
+        N.qs_program_forward(self.ph, self.qs_dtype, self.params, self.states, self.expz)
+        out = {"expz": self.expz, "loss": (self.expz * self.weights).sum()}
+        if backward:
+            N.qs_program_adjoint(self.ph, self.qs_dtype, self.params, self.states,
+                                 self.weights, self.grad)
+            out["grad_params"] = self.grad
+        return out
+
+
+class GraphStep:
+    """A whole step captured once in a HIP graph (torch.cuda.CUDAGraph) and
+    replayed. The first call runs the step eagerly so every plan is built and
+    uploaded before the capture; replays reuse the step's device buffers."""
+
+    def __init__(self, fn, warmup: int = 1):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.out = fn()
+
+    def replay(self):
+        self.graph.replay()
+        return self.out

@@ -21,7 +21,7 @@ if torch.cuda.is_available():
 
 TOL = {"c64": dict(z=1e-5, state=1e-5, grad=1e-4),
        "c128": dict(z=1e-10, state=1e-10, grad=1e-10)}
-PATHS = {"fused": 1, "plain": 2}
+PATHS = {"fused": 1, "plain": 2, "hbm": 3, "auto": 0}
 
 
 def _dev(a, dt):
@@ -115,7 +115,7 @@ def test_state_cotangent(n, path):
 def test_empty_circuit_and_single_gate():
     for rows in ([], [(C.OP["RY"], 0, -1, 0, -1, -1, 1.0, 0)]):
         c = C.Circuit(3, np.array(rows, dtype=C.GATE_DTYPE), 1)
-        for path in PATHS:
+        for path in ("fused", "plain"):
             _run_expz_case(c, "c64", path, 9, seed=1)
 
 
@@ -267,7 +267,7 @@ def test_zero_norm_rows_are_counted_and_nan():
 
 def test_zero_batch_is_a_no_op():
     c = C.hea_ry_rz_ring(4, 1)
-    for path in PATHS.values():
+    for path in (1, 2):
         s = sim.Simulator(c, "c64", path)
         st = s.empty_state(0)
         p = torch.zeros(c.n_params, device="cuda")
@@ -342,3 +342,238 @@ def test_autograd_function_matches_oracle():
     rp, rf = O.theta_to_param_grads(c, p64, f64, gth)
     np.testing.assert_allclose(params.grad.cpu().numpy(), rp, atol=1e-4)
     np.testing.assert_allclose(feats.grad.cpu().numpy(), rf, atol=1e-4)
+
+
+# ------------------------------------------------ large states: tiled path
+@pytest.fixture
+def tile_qubits(monkeypatch):
+    def set_m(m):
+        monkeypatch.setenv("QS_TILE_QUBITS", str(m))
+    return set_m
+
+
+@pytest.mark.parametrize("n,m", [(6, 4), (8, 5), (9, 6), (11, 7)])
+def test_tiled_path_random_circuits(n, m, tile_qubits):
+    tile_qubits(m)
+    rng = np.random.default_rng(500 + n)
+    c = C.random_circuit(n, 80, rng, n_params=6, n_features=2)
+    _run_expz_case(c, "c64", "hbm", 5, seed=n)
+    _run_expz_case(c, "c64", "hbm", 3, seed=n + 1, per_sample=True)
+    _run_expz_case(c, "c64", "hbm", 3, seed=n + 2, dstate_mode=True, amplitude=False)
+
+
+def test_tiled_path_c128(tile_qubits):
+    tile_qubits(5)
+    rng = np.random.default_rng(600)
+    c = C.random_circuit(8, 60, rng, n_params=5, n_features=2)
+    _run_expz_case(c, "c128", "hbm", 3, seed=3)
+
+
+@pytest.mark.parametrize("n", [15, 16])
+def test_large_state_auto_path(n):
+    rng = np.random.default_rng(700 + n)
+    c = C.random_circuit(n, 60, rng, n_params=6, n_features=1)
+    assert N.qs_plan_info_get(N.CircuitHandle(c), N.QS_C64, 2)["path"] == N.QS_PATH_HBM
+    _run_expz_case(c, "c64", "auto", 2, seed=n)
+
+
+def test_tiled_checkpoints(tile_qubits):
+    tile_qubits(6)
+    w = Dt.make_workload("c2", 3)
+    c = w.circuit
+    ck = c.layer_end[1:-1:3]
+    s = sim.Simulator(c, "c64", PATHS["hbm"])
+    st = s.encode_amplitude(_dev(w.x, torch.float32))
+    buf = torch.empty((len(ck),) + tuple(st.shape), dtype=st.dtype, device="cuda")
+    p = _dev(w.params, torch.float32)
+    s.forward(p, None, st, ckpt_gates=ck, ckpt=buf)
+    dz = torch.zeros(3, 10, dtype=torch.float64, device="cuda")
+    dz[:, 0] = 0.2
+    gp, _ = s.adjoint(p, None, st, dexpz=dz, ckpt_gates=ck, ckpt=buf)
+    torch.cuda.synchronize()
+    psi0 = O.encode_amplitude(w.x, 10)
+    for i, g in enumerate(ck):
+        ref = O.run_circuit(C.Circuit(10, c.gates[:g], c.n_params), w.params, None, psi0)
+        np.testing.assert_allclose(buf[i].cpu().numpy(), ref, atol=1e-5)
+    gth, _ = O.adjoint_vjp(c, w.params, None, psi0, dexpz=dz.cpu().numpy())
+    np.testing.assert_allclose(gp.cpu().numpy(),
+                               O.theta_to_param_grads(c, w.params, None, gth)[0], atol=1e-4)
+
+
+def _product_circuit(n, layers, rng):
+    """RY then RZ on every qubit, `layers` times, no entanglers: each qubit
+    evolves alone, so the oracle can check <Z_q> and its gradient qubit by
+    qubit at any n."""
+    b = C._Builder(n)
+    for _ in range(layers):
+        for q in range(n):
+            b.rot("RY", q, p_w=b.new_param())
+            b.rot("RZ", q, p_w=b.new_param())
+            b.rot("RX", q, p_w=b.new_param())
+    return b.build()
+
+
+@pytest.mark.parametrize("n", [20, 26])
+def test_full_size_product_state_closed_forms(n):
+    """Full-size large states on the tiled path: per-qubit closed forms for
+    <Z_q> and for dL/dP of L = sum_q g_q <Z_q>, computed by the oracle on each
+    qubit's own 1-qubit circuit."""
+    _announce(f"product state n={n}")
+    rng = np.random.default_rng(800 + n)
+    c = _product_circuit(n, 3, rng)
+    P = c.n_params
+    params = rng.uniform(-np.pi, np.pi, P).astype(np.float32)
+    g = rng.uniform(-1, 1, n)
+    s = sim.Simulator(c, "c64")
+    st = s.zero_state(1)
+    pt = _dev(params, torch.float32)
+    z = s.forward(pt, None, st)
+    gp, _ = s.adjoint(pt, None, st, dexpz=_dev(g[None, :], torch.float64))
+    torch.cuda.synchronize()
+    norm = float((st.abs().double() ** 2).sum().item())
+    assert abs(norm - 1.0) < 1e-5
+    z = z.cpu().numpy()[0]
+    gp = gp.cpu().numpy()
+    for q in range(n):
+        sel = [i for i, gt in enumerate(c.gates) if gt["q0"] == q]
+        g1 = c.gates[sel].copy()
+        g1["q0"] = 0
+        c1 = C.Circuit(1, g1, P)
+        psi = O.run_circuit(c1, params, None, O.encode_zero(1, 1))
+        assert abs(z[q] - O.expz(psi)[0, 0]) < 1e-5
+        gth, _ = O.adjoint_vjp(c1, params, None, O.encode_zero(1, 1),
+                               dexpz=np.array([[g[q]]]))
+        ref = O.theta_to_param_grads(c1, params, None, gth)[0]
+        idx = np.unique(g1["p_w"])
+        np.testing.assert_allclose(gp[idx], ref[idx], atol=1e-4)
+
+
+def test_full_size_26q_circuit_then_inverse_is_identity():
+    """The 26-qubit hardware-efficient circuit (20 layers, 1560 gates) followed
+    by its inverse returns |0...0> exactly (up to rounding), and the forward
+    alone preserves the norm."""
+    w = Dt.make_workload("c5b")
+    _announce("26-qubit U then U^dagger")
+    c = w.circuit
+    inv = C.inverse_structure(c)
+    s = sim.Simulator(c, "c64")
+    si = sim.Simulator(inv, "c64")
+    st = s.zero_state(1)
+    pt = _dev(w.params, torch.float32)
+    z = s.forward(pt, None, st)
+    torch.cuda.synchronize()
+    # In complex64 each rotation's cos and sin are rounded to float, so
+    # c^2 + s^2 = 1 + d with |d| <= 2 * 2^-23 (two roundings of 2^-24 each,
+    # doubled by squaring), and every rotation scales the whole norm by that
+    # factor. The drift is therefore bounded by n_rot * 2^-22 (systematic,
+    # growing linearly with depth); the random per-amplitude rounding adds only
+    # about sqrt(G) * 6e-8 on top.
+    n_rot = int(np.isin(c.gates["op"], list(C.ROTATIONS)).sum())
+    tol = n_rot * 2.0 ** -22
+    norm = float((st.abs().double() ** 2).sum().item())
+    assert abs(norm - 1.0) < tol, (norm, tol)
+    assert np.all(np.abs(z.cpu().numpy()) <= 1 + tol)
+    si.forward(pt, None, st, want_expz=False)
+    torch.cuda.synchronize()
+    a0 = st[0, 0].item()
+    # U^dagger repeats the norm drift with the same bound.
+    assert abs(a0 - 1.0) < 2 * tol + 1e-5, (a0, tol)
+
+
+# ------------------------------------------------------- uneven batches
+def _oracle_program_circuit(ub, k, j):
+    n, d, c, idx = ub.classes[k]
+    xs, ps, es = ub.circuit_slices(k, j)
+    x = ub.x[xs][None, :]
+    p = ub.params[ps]
+    g = ub.weights[es][None, :]
+    psi0 = O.encode_amplitude(x, n)
+    z = O.expz(O.run_circuit(c, p, None, psi0))
+    gth, _ = O.adjoint_vjp(c, p, None, psi0, dexpz=g)
+    return z[0], O.theta_to_param_grads(c, p, None, gth)[0]
+
+
+def test_uneven_batch_small_all_circuits():
+    ub = Dt.uneven_batch(90, seed=3, n_lo=5, n_hi=10, d_lo=1, d_hi=4)
+    _announce(f"uneven batch: {ub.n_circuits} circuits, {len(ub.classes)} classes")
+    dev = sim.UnevenDevice(ub)
+    out = dev.step()
+    torch.cuda.synchronize()
+    z = out["expz"].cpu().numpy()
+    gp = out["grad_params"].cpu().numpy()
+    for k, (n, d, c, idx) in enumerate(ub.classes):
+        for j in range(len(idx)):
+            zo, go = _oracle_program_circuit(ub, k, j)
+            _, ps, es = ub.circuit_slices(k, j)
+            np.testing.assert_allclose(z[es], zo, atol=1e-5)
+            np.testing.assert_allclose(gp[ps], go, atol=1e-4)
+
+
+def test_uneven_batch_full_size_sampled():
+    ub = Dt.uneven_batch()
+    _announce(f"uneven batch full: {ub.n_circuits} circuits, {len(ub.classes)} classes")
+    dev = sim.UnevenDevice(ub)
+    out = dev.step()
+    torch.cuda.synchronize()
+    z = out["expz"].cpu().numpy()
+    gp = out["grad_params"].cpu().numpy()
+    assert np.all(np.abs(z) <= 1 + 1e-5)
+    rng = np.random.default_rng(11)
+    picks = [(0, 0), (len(ub.classes) - 1, 0)] + \
+        [(int(k), 0) for k in rng.integers(0, len(ub.classes), 4)]
+    for k, j in picks:
+        zo, go = _oracle_program_circuit(ub, k, j)
+        _, ps, es = ub.circuit_slices(k, j)
+        np.testing.assert_allclose(z[es], zo, atol=1e-5)
+        g = gp[ps]
+        assert np.abs(g - go).max() < 1e-4 or \
+            np.linalg.norm(g - go) <= 1e-3 * np.linalg.norm(go)
+
+
+def test_graph_replay_matches_eager():
+    """A captured step replayed several times, with eager work in between,
+    reproduces the eager result every time (the batched and the uneven path)."""
+    w = Dt.make_workload("c2", 64)
+    d = sim.to_device(w)
+    eager = sim.step(d)
+    ref_z = eager["expz"].clone()
+    ref_g = eager["grad_params"].clone()
+    gs = sim.GraphStep(lambda: sim.step(d))
+    for rep in range(3):
+        out = gs.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out["expz"], ref_z), rep
+        assert torch.allclose(out["grad_params"], ref_g, rtol=0, atol=1e-12), rep
+        sim.step(d)  # eager work between replays
+        torch.cuda.synchronize()
+    ub = Dt.uneven_batch(60, seed=5, n_lo=5, n_hi=9, d_lo=1, d_hi=3)
+    dev = sim.UnevenDevice(ub)
+    e = dev.step()
+    rz, rg = e["expz"].clone(), e["grad_params"].clone()
+    gu = sim.GraphStep(lambda: dev.step())
+    for rep in range(3):
+        out = gu.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out["expz"], rz), rep
+        assert torch.allclose(out["grad_params"], rg, rtol=0, atol=1e-12), rep
+        dev.step()
+        torch.cuda.synchronize()
+
+
+# ------------------------------------------------------------- autotuner
+def test_autotune_picks_a_config_and_results_stay_exact(tmp_path, monkeypatch):
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("QS_AUTOTUNE_CACHE", str(cache))
+    w = Dt.make_workload("c2", 96)
+    s = sim.Simulator(w.circuit, "c64")
+    info = N.qs_autotune(s.h, s.qs_dtype, 96)
+    torch.cuda.synchronize()
+    assert info["path"] == N.QS_PATH_FUSED
+    assert info["fwd_log2_regs"] in (1, 2, 3, 4, 5) and info["adj_log2_regs"] in (1, 2, 3, 4, 5)
+    assert info["n_candidates"] >= 2 and info["fwd_ms"] > 0 and info["adj_ms"] > 0
+    line = cache.read_text().split()
+    assert int(line[1]) == info["fwd_log2_regs"] and int(line[2]) == info["adj_log2_regs"]
+    pi = s.plan_info(96)
+    assert pi["log2_regs"] == info["fwd_log2_regs"]
+    assert pi["adj_log2_regs"] == info["adj_log2_regs"]
+    test_workload_step_vs_oracle("c2", 96)  # the tuned configuration is exact too

@@ -146,10 +146,43 @@ def test_plans_of_random_circuits(n):
         _check_plan(c, dt, flags=N.QS_FLAG_PER_SAMPLE_PARAMS)
 
 
-def test_large_circuits_fall_back_to_plain_path():
+def test_large_circuits_take_the_tiled_path():
     c = C.hea_ry_rz_ring(16, 1)
     info = N.qs_plan_info_get(N.CircuitHandle(c), N.QS_C64, 1)
-    assert info["path"] == N.QS_PATH_PLAIN
+    assert info["path"] == N.QS_PATH_HBM
+    assert info["log2_threads"] == 13 and info["n_segments"] >= 2  # tile qubits, epochs
+    w = Dt.make_workload("c5b")
+    info = N.qs_plan_info_get(N.CircuitHandle(w.circuit), N.QS_C64, 1)
+    assert info["path"] == N.QS_PATH_HBM
+    # 20 hardware-efficient layers on 26 qubits in 13-qubit tiles
+    assert 40 <= info["n_segments"] <= 80
+    plain = N.qs_plan_info_get(N.CircuitHandle(c), N.QS_C64, 1, N.QS_PATH_PLAIN)
+    assert plain["path"] == N.QS_PATH_PLAIN
+
+
+def test_explicit_fused_path_refuses_states_that_do_not_fit():
+    """Asking for the register/LDS engine on a state it cannot hold is an
+    error, never a silent switch to another path."""
+    h = N.CircuitHandle(C.hea_ry_rz_ring(16, 1))
+    with pytest.raises(N.QsError) as e:
+        N.qs_plan_info_get(h, N.QS_C64, 1, N.QS_PATH_FUSED)
+    assert e.value.status == N.QS_ERR_UNSUPPORTED
+    with pytest.raises(N.QsError) as e:
+        N.qs_plan_info_get(h, N.QS_C64, 1, 7)  # no such path
+    assert e.value.status == N.QS_ERR_INVALID
+    assert N.qs_workspace_size(h, N.QS_C64, 1, N.QS_PATH_FUSED) == 0
+
+
+def test_program_layout_is_class_major():
+    ub = Dt.uneven_batch(50, seed=2, n_lo=5, n_hi=8, d_lo=1, d_hi=3)
+    ph = N.ProgramHandle([c for (_, _, c, _) in ub.classes],
+                         [len(i) for (_, _, _, i) in ub.classes])
+    so, po, eo, tot = ph.layout()
+    np.testing.assert_array_equal(so, ub.state_off)
+    np.testing.assert_array_equal(po, ub.param_off)
+    np.testing.assert_array_equal(eo, ub.expz_off)
+    assert tot[0] == ub.x.size and tot[1] == ub.params.size and tot[2] == ub.weights.size
+    assert sum(len(i) for (_, _, _, i) in ub.classes) == 50
 
 
 def test_workspace_sizes():

@@ -15,4 +15,5 @@ from .circuits import (  # noqa: F401
 from .data import (  # noqa: F401
     WORKLOADS, Workload, make_workload, amplitude_inputs, uniform_params,
     pm1_labels, uniform_features, upstream_weights, uneven_batch_spec,
+    UnevenBatch, uneven_batch,
 )

@@ -149,6 +149,74 @@ def make_workload(key: str, batch: int | None = None, seed: int = 0) -> Workload
     return fn(full if batch is None else batch, seed)
 
 
+@dataclass
+class UnevenBatch:
+    """Circuits of uneven qubit count and depth, grouped into classes of
+    identical structure and packed class after class (the layout of the
+    packed buffers of the library's uneven-batch calls).
+
+    classes[k] = (n, depth, circuit, idx) where idx are the original circuit
+    numbers of the class's circuits, in packed order. x, params and weights
+    are packed: x [sum 2^n] float32 (amplitude inputs, N(0,1)), params
+    [sum P] float32 (U(-pi, pi)), weights [sum n] float64 (g_q ~ U(-1, 1),
+    the loss sum_q g_q <Z_q> per circuit)."""
+    classes: list
+    x: np.ndarray
+    params: np.ndarray
+    weights: np.ndarray
+    state_off: np.ndarray
+    param_off: np.ndarray
+    expz_off: np.ndarray
+    n_circuits: int
+
+    def circuit_slices(self, k: int, j: int):
+        """Packed slices (x/state, params, expz) of circuit j of class k."""
+        n, _, c, _ = self.classes[k]
+        so = self.state_off[k] + (j << n)
+        po = self.param_off[k] + j * c.n_params
+        eo = self.expz_off[k] + j * n
+        return slice(so, so + (1 << n)), slice(po, po + c.n_params), slice(eo, eo + n)
+
+    def updates_per_step(self) -> int:
+        tot = 0
+        for n, d, c, idx in self.classes:
+            tot += 3 * len(idx) * (1 << n) * c.n_gates
+        return tot
+
+
+def uneven_batch(n_circuits: int = 10000, seed: int = 0, n_lo: int = 6,
+                 n_hi: int = 14, d_lo: int = 4, d_hi: int = 32) -> UnevenBatch:
+    """The uneven batch: n ~ U{n_lo..n_hi}, depth ~ U{d_lo..d_hi}
+    hardware-efficient layers (RY, RZ per qubit + ring CNOT), one amplitude
+    input, one parameter set and one readout-weight vector per circuit."""
+    n, d = uneven_batch_spec(n_circuits, seed, n_lo, n_hi, d_lo, d_hi)
+    keys = sorted(set(zip(n.tolist(), d.tolist())))
+    rng_x = _rng(seed, STREAM_X)
+    rng_p = _rng(seed, STREAM_P)
+    rng_w = _rng(seed, STREAM_Y)
+    # per-circuit draws in original circuit order, then packed by class
+    xs = [rng_x.standard_normal(1 << int(n[i])).astype(np.float32) for i in range(n_circuits)]
+    ps = [rng_p.uniform(-np.pi, np.pi, 2 * int(n[i]) * int(d[i])).astype(np.float32)
+          for i in range(n_circuits)]
+    ws = [rng_w.uniform(-1.0, 1.0, int(n[i])) for i in range(n_circuits)]
+    classes, X, P, W, so, po, eo = [], [], [], [], [], [], []
+    s_off = p_off = e_off = 0
+    for (nk, dk) in keys:
+        idx = np.nonzero((n == nk) & (d == dk))[0]
+        c = hea_ry_rz_ring(nk, dk, name=f"ryrz-ring n{nk} L{dk}")
+        classes.append((nk, dk, c, idx))
+        so.append(s_off); po.append(p_off); eo.append(e_off)
+        for i in idx:
+            X.append(xs[i]); P.append(ps[i]); W.append(ws[i])
+        s_off += len(idx) << nk
+        p_off += len(idx) * c.n_params
+        e_off += len(idx) * nk
+    return UnevenBatch(classes, np.concatenate(X), np.concatenate(P),
+                       np.concatenate(W), np.array(so, dtype=np.int64),
+                       np.array(po, dtype=np.int64), np.array(eo, dtype=np.int64),
+                       n_circuits)
+
+
 def uneven_batch_spec(n_circuits: int = 10000, seed: int = 0,
                       n_lo: int = 6, n_hi: int = 14, d_lo: int = 4,
                       d_hi: int = 32):
