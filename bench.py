@@ -112,6 +112,8 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (use the default register split)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB "
                          "(5 launches) and exit: the known-size kernel whose "
@@ -138,7 +140,24 @@ def main():
     from paper_2509_25075_amd import sim
     from workloads import make_workload
 
+    from paper_2509_25075_amd import _native as N
+
     w = make_workload(args.workload)
+    tuned = None
+    if not args.no_tune:
+        # The library's autotuner times the register-split candidates of each
+        # circuit at this batch size; later calls look the choice up.
+        tuned = {}
+        for name, c in (("circuit", w.circuit), ("decoder", w.decoder)):
+            if c is None:
+                continue
+            s0 = sim.Simulator(c, w.dtype)
+            if s0.plan_info(w.batch)["path"] not in (N.QS_PATH_FUSED, N.QS_PATH_HBM):
+                continue
+            t = N.qs_autotune(s0.h, s0.qs_dtype, w.batch, 0)
+            tuned[name] = {k: t[k] for k in ("fwd_log2_regs", "adj_log2_regs",
+                                             "tile_qubits")}
+        torch.cuda.synchronize()
     d = sim.to_device(w, flags=0)  # automatic: register/LDS engine, else tiled HBM
     path_name = {1: "fused", 2: "plain", 3: "tiled_hbm"}[d.sim.plan_info(w.batch)["path"]]
     updates = w.updates_per_step()
@@ -211,7 +230,7 @@ def main():
         "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}",
                    "batch": w.batch, "qubits": w.n_qubits,
                    "gates": w.circuit.n_gates + (w.decoder.n_gates if w.decoder else 0),
-                   "updates_per_step": updates, "path": path_name},
+                   "updates_per_step": updates, "path": path_name, "tuned": tuned},
         "roofline": None if achieved is None else {
             "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,

@@ -100,8 +100,8 @@ enum {
   QS_PATH_AUTO = 0,   /* register/LDS-resident engine when it fits, else HBM */
   QS_PATH_FUSED = 1,  /* register/LDS-resident engine (n <= 14)              */
   QS_PATH_PLAIN = 2,  /* one kernel launch per gate, state in HBM            */
-  QS_PATH_HBM = 3,    /* state in HBM, gates fused into dense k-qubit blocks
-                         applied with MFMA (reserved in this build)          */
+  QS_PATH_HBM = 3,    /* state in HBM, run as epochs of gathered m-qubit
+                         tiles through the register/LDS engine (n > 14)     */
   QS_PATH_MASK = 0xff,
   QS_FLAG_PER_SAMPLE_PARAMS = 0x100 /* params is [B][n_params]            */
 };
@@ -246,12 +246,14 @@ typedef struct qs_plan_info {
   int32_t block_threads;     /* threads per workgroup                        */
   int32_t n_segments;        /* register-resident segments                   */
   int32_t n_remaps;          /* LDS remaps between segments (forward)        */
-  int32_t n_ops;             /* engine operations                            */
+  int32_t n_ops;             /* gates as scheduled (qs_plan_export rows)     */
   int64_t lds_bytes;         /* dynamic LDS per workgroup                    */
   int32_t adj_log2_regs;     /* the adjoint's amplitudes-per-thread exponent */
   int32_t adj_samples_per_block;
   int32_t adj_block_threads;
-  int32_t reserved;
+  int32_t n_engine_ops;      /* engine operations after grouping gates into
+                                layer ops (fused single-qubit blocks on all
+                                register bits; CZ sets as one sign pattern) */
 } qs_plan_info;
 
 /* Fill `out` with the plan the engine would use (host only, no GPU). */

@@ -51,7 +51,7 @@ class QsPlanInfo(ctypes.Structure):
                 ("n_ops", ctypes.c_int32), ("lds_bytes", ctypes.c_int64),
                 ("adj_log2_regs", ctypes.c_int32),
                 ("adj_samples_per_block", ctypes.c_int32),
-                ("adj_block_threads", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("adj_block_threads", ctypes.c_int32), ("n_engine_ops", ctypes.c_int32)]
 
 
 class QsProgram(ctypes.Structure):

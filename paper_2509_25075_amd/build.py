@@ -31,8 +31,10 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-result"]
 
-SOURCES = ["planner.cpp", "qs_api.cpp", "prog_api.cpp", "misc.hip", "plain.hip",
-           "sv_engine.hip"]
+# Largest translation units first, so the parallel build ends soonest.
+SOURCES = ["sv_c64_adj.hip", "sv_c64_fwd.hip", "sv_c128.hip", "sv_prog.hip",
+           "sv_engine.hip", "planner.cpp", "qs_api.cpp", "prog_api.cpp", "misc.hip",
+           "plain.hip"]
 
 
 def _compile(src: str) -> str:

@@ -81,6 +81,120 @@ bool is_rotation(int op) {
   return op == QS_OP_RX || op == QS_OP_RY || op == QS_OP_RZ;
 }
 
+bool is_one_qubit(int op) { return op <= QS_OP_H; }
+
+// Regroups the single-gate ops of each segment into layer ops. Inside a
+// segment the placement is fixed, and only the order of gates sharing a
+// qubit matters. Alternately (a) every register bit takes the run of
+// single-qubit gates at the head of its qubit's pending list as one block,
+// and all blocks go into one L1Q op; (b) every other op whose qubits all have
+// it at the head of their pending lists is emitted, in the original order,
+// with consecutive CZs merged into one DIAG op. The earliest pending gate is
+// always at the head of its lists, so every round makes progress.
+void build_layers(SvPlan& P, const qs_circuit& c, bool per_sample_angles_all) {
+  const int r = P.r, R = 1 << r;
+  std::vector<SvOp> in = std::move(P.ops);
+  std::vector<int32_t> seg_in = P.seg_begin;
+  P.ops.clear();
+  P.exec.clear();
+  P.exec_seg.assign(1, 0);
+  auto per_sample = [&](const qs_gate& g) {
+    if (!is_rotation(g.op)) return false;
+    return per_sample_angles_all ? (g.p_w >= 0 || g.p_b >= 0 || g.feat >= 0)
+                                 : g.feat >= 0;
+  };
+  for (int s = 0; s + 1 < (int)seg_in.size(); ++s) {
+    const int beg = seg_in[s], end = seg_in[s + 1];
+    P.seg_begin[s] = (int32_t)P.ops.size();
+    std::vector<std::vector<int>> q(P.n);  // pending ops per physical position
+    std::vector<size_t> head(P.n, 0);
+    for (int o = beg; o < end; ++o) {
+      q[in[o].a].push_back(o);
+      if (in[o].kind == QS_OP_CNOT || in[o].kind == QS_OP_CZ) q[in[o].b].push_back(o);
+    }
+    auto at_head = [&](int pos, int o) {
+      return head[pos] < q[pos].size() && q[pos][head[pos]] == o;
+    };
+    auto is_u = [&](int o) { return is_one_qubit(in[o].kind) && in[o].a < r; };
+    std::vector<char> done(end - beg, 0);
+    int left = end - beg;
+    while (left > 0) {
+      // (a) one block per register bit
+      int32_t rec[kL1QWords];
+      for (int j = 0; j < kL1QWords; ++j) rec[j] = -1;
+      uint8_t mask = 0, ps = 0;
+      for (int j = 0; j < r; ++j) {
+        std::vector<int> gl;
+        while (head[j] < q[j].size() && is_u(q[j][head[j]])) {
+          const int o = q[j][head[j]++];
+          gl.push_back(in[o].gate);
+          done[o - beg] = 1;
+          --left;
+        }
+        if (gl.empty()) continue;
+        uint8_t bps = 0;
+        for (int g : gl) {
+          bps |= per_sample(c.gates[g]) ? 1 : 0;
+          P.exec.insert(P.exec.end(), {g, j, 0});
+        }
+        rec[j] = (int32_t)P.blk_fu.size();
+        P.blk_gates.insert(P.blk_gates.end(), gl.begin(), gl.end());
+        P.blk_begin.push_back((int32_t)P.blk_gates.size());
+        P.blk_fu.push_back(bps ? -1 : P.n_fu++);
+        mask |= (uint8_t)(1u << j);
+        ps |= bps;
+      }
+      if (mask) {
+        SvOp op{kOpL1Q, mask, 0, ps, (int32_t)(P.l1q.size() / kL1QWords)};
+        P.ops.push_back(op);
+        P.l1q.insert(P.l1q.end(), rec, rec + kL1QWords);
+      }
+      // (b) every other op that is ready, in order
+      bool progress = true;
+      int open_diag = -1;  // record index of the DIAG op being extended
+      while (progress) {
+        progress = false;
+        for (int o = beg; o < end; ++o) {
+          if (done[o - beg] || is_u(o)) continue;
+          const SvOp& x = in[o];
+          const bool two = x.kind == QS_OP_CNOT || x.kind == QS_OP_CZ;
+          if (!at_head(x.a, o) || (two && !at_head(x.b, o))) continue;
+          head[x.a]++;
+          if (two) head[x.b]++;
+          done[o - beg] = 1;
+          --left;
+          progress = true;
+          P.exec.insert(P.exec.end(), {x.gate, x.a, two ? x.b : 0});
+          if (x.kind != QS_OP_CZ) {
+            open_diag = -1;
+            SvOp y = x;
+            y.aux = per_sample(c.gates[x.gate]) ? 1 : 0;
+            P.ops.push_back(y);
+            continue;
+          }
+          if (open_diag < 0) {
+            open_diag = (int)(P.diag.size() / kDiagWords);
+            P.diag.resize(P.diag.size() + kDiagWords, 0u);
+            P.ops.push_back(SvOp{kOpDiag, 0, 0, 0, open_diag});
+          }
+          uint32_t* d = &P.diag[(size_t)open_diag * kDiagWords];
+          const int lo = x.a < x.b ? x.a : x.b, hi = x.a < x.b ? x.b : x.a;
+          if (hi < r) {
+            for (int k = 0; k < R; ++k)
+              if (((k >> lo) & 1) && ((k >> hi) & 1)) d[0] ^= 1u << k;
+          } else if (lo < r) {
+            d[2 + lo] ^= 1u << (hi - r);
+          } else {
+            d[7 + (lo - r)] ^= 1u << (hi - r);
+          }
+        }
+      }
+    }
+    P.exec_seg.push_back((int32_t)(P.exec.size() / 3));
+  }
+  P.seg_begin.back() = (int32_t)P.ops.size();
+}
+
 }  // namespace
 
 SvPlan plan_sv(const qs_circuit& c, int r, bool per_sample_angles_all,
@@ -183,21 +297,22 @@ SvPlan plan_sv(const qs_circuit& c, int r, bool per_sample_angles_all,
   }
   P.seg_begin.push_back((int32_t)ops.size());
 
-  // Angle slots, indexed by op position: per-sample rotations get a slot.
-  P.angle_slot.assign(ops.size(), -1);
-  for (size_t o = 0; o < ops.size(); ++o) {
-    const qs_gate& gt = c.gates[ops[o].gate];
+  // Angle slots, by gate: rotations whose angle differs per sample.
+  P.gate_slot.assign(G, -1);
+  for (int g = 0; g < G; ++g) {
+    const qs_gate& gt = c.gates[g];
     if (!is_rotation(gt.op)) continue;
     bool per_sample = per_sample_angles_all
                           ? (gt.p_w >= 0 || gt.p_b >= 0 || gt.feat >= 0)
                           : (gt.feat >= 0);
     if (per_sample) {
-      P.angle_slot[o] = (int)P.slot_gate.size();
-      P.slot_gate.push_back(ops[o].gate);
-      ops[o].aux = 1;
+      P.gate_slot[g] = (int)P.slot_gate.size();
+      P.slot_gate.push_back(g);
     }
   }
   P.ops = std::move(ops);
+  P.blk_begin.assign(1, 0);
+  build_layers(P, c, per_sample_angles_all);
 
   int changes = 0;
   for (int s = 1; s < P.nseg(); ++s)

@@ -20,8 +20,8 @@ struct ProgEnginePlan {
   SvDevPlan* dev;
 };
 ProgEnginePlan program_engine_plan(const qs_circuit& c, int r, int* rc);
-int64_t engine_lds_bytes(int dtype, int n, int S, int n_gates, int n_slots,
-                         int n_params, int n_feats, int block, bool ps);
+int64_t engine_lds_bytes(int dtype, const qs_circuit& c, int S, int n_slots, int block,
+                         bool ps, bool adjoint);
 }  // namespace qs
 
 using namespace qs;
@@ -127,8 +127,15 @@ ProgPlan* get_prog(const qs_program* p, int dtype, int* rc) {
     d.seg_ckpt = ep.dev->seg_ckpt;
     d.ops = ep.dev->ops;
     d.gates = ep.dev->gates;
-    d.angle_slot = ep.dev->angle_slot;
+    d.gate_slot = ep.dev->gate_slot;
     d.slot_gate = ep.dev->slot_gate;
+    d.l1q = ep.dev->l1q;
+    d.diag = ep.dev->diag;
+    d.blk_begin = ep.dev->blk_begin;
+    d.blk_gates = ep.dev->blk_gates;
+    d.blk_fu = ep.dev->blk_fu;
+    d.n_blocks = ep.dev->n_blocks;
+    d.n_fu = ep.dev->n_fu;
     d.n = c.n_qubits;
     d.t = c.n_qubits - r;
     d.nseg = ep.dev->nseg;
@@ -140,8 +147,7 @@ ProgPlan* get_prog(const qs_program* p, int dtype, int* rc) {
     d.state_off = so[k];
     d.param_off = po[k];
     d.expz_off = eo[k];
-    lds = std::max(lds, engine_lds_bytes(dtype, d.n, d.S, c.n_gates, 0, c.n_params, 0,
-                                         kBlock, true));
+    lds = std::max(lds, engine_lds_bytes(dtype, c, d.S, 0, kBlock, true, true));
     cum[k + 1] = cum[k] + p->counts[k];
     nq[k] = c.n_qubits;
     for (int64_t f = 0; f < d.count; f += d.S) {

@@ -132,16 +132,28 @@ bool tuned_lookup(const qs_circuit& c, int dtype, int64_t B, int flags, TuneVal*
 // `block` threads hold S samples of T = block / S threads each; gradient sums
 // take one slot per wave (shared parameters) and per wave of a sample
 // (features); per-sample parameter sets take none.
-int64_t lds_bytes(int dtype, int n, int S, int n_gates, int n_slots,
-                  int n_params, int n_feats, int block, bool ps) {
+int64_t lds_bytes(int dtype, const qs_circuit& c, int S, int n_slots, int block,
+                  bool ps, bool adjoint) {
   const int64_t rs = dtype == QS_C64 ? 4 : 8;
   const int64_t waves = (block + 63) / 64;
   const int64_t T = block / (S > 0 ? S : 1);
   const int64_t wps = T > 64 ? T / 64 : 1;
-  int64_t b = (int64_t)S * (2 * rs << n);      // states
-  b += 2 * rs * n_gates;                       // shared angle table
-  b += 2 * rs * (int64_t)n_slots * S;          // per-sample angle table
-  b += rs * ((ps ? 0 : waves * n_params) + (int64_t)S * wps * n_feats);
+  // Fused-matrix slots: one per block with shared angles, so at most one per
+  // single-qubit gate whose angle (if any) is shared.
+  int64_t n1q = 0;
+  for (int g = 0; g < c.n_gates; ++g) {
+    const qs_gate& x = c.gates[g];
+    if (x.op > QS_OP_H) continue;
+    const bool per_sample = is_rotation(x.op) &&
+                            (ps ? (x.p_w >= 0 || x.p_b >= 0 || x.feat >= 0) : x.feat >= 0);
+    n1q += per_sample ? 0 : 1;
+  }
+  int64_t b = (int64_t)S * (2 * rs << c.n_qubits);  // states
+  b += 2 * rs * c.n_gates;                          // shared angle table
+  b += 8 * rs * n1q;                                // fused block matrices
+  b += 2 * rs * (int64_t)n_slots * S;               // per-sample angle table
+  if (adjoint)                                      // gradient sums
+    b += rs * ((ps ? 0 : waves * c.n_params) + (int64_t)S * wps * c.n_features);
   return (b + 15) & ~15ll;
 }
 
@@ -177,8 +189,7 @@ bool choose_shape(int dtype, const qs_circuit& c, int n_slots, int r_force,
     if (block > maxT) block = maxT;
     int S = block / T;
     // Shrink the block until the LDS fits.
-    while (S > 1 && lds_bytes(dtype, n, S, c.n_gates, n_slots, c.n_params,
-                              c.n_features, S * T, ps) > kMaxLds) {
+    while (S > 1 && lds_bytes(dtype, c, S, n_slots, S * T, ps, adjoint) > kMaxLds) {
       S >>= 1;
     }
     block = S * T;
@@ -186,8 +197,7 @@ bool choose_shape(int dtype, const qs_circuit& c, int n_slots, int r_force,
       S = 64 / T;
       block = 64;
     }
-    const int64_t lds = lds_bytes(dtype, n, S, c.n_gates, n_slots, c.n_params,
-                                  c.n_features, block, ps);
+    const int64_t lds = lds_bytes(dtype, c, S, n_slots, block, ps, adjoint);
     if (lds > kMaxLds) continue;
     out->r = r;
     out->t = t;
@@ -248,8 +258,13 @@ void free_dev(SvDevPlan& d) {
   (void)hipFree(d.seg_ckpt);
   (void)hipFree(d.ops);
   (void)hipFree(d.gates);
-  (void)hipFree(d.angle_slot);
+  (void)hipFree(d.gate_slot);
   (void)hipFree(d.slot_gate);
+  (void)hipFree(d.l1q);
+  (void)hipFree(d.diag);
+  (void)hipFree(d.blk_begin);
+  (void)hipFree(d.blk_gates);
+  (void)hipFree(d.blk_fu);
 }
 
 // Plans on the host and uploads once per (circuit, r, flags, device). The
@@ -278,13 +293,20 @@ Entry* get_plan(const qs_circuit& c, int r, bool ps, const int32_t* ck, int n_ck
   d.n_features = c.n_features;
   d.n_remaps = P.n_remaps;
   d.n_ops = (int)P.ops.size();
+  d.n_blocks = P.n_blocks();
+  d.n_fu = P.n_fu;
   bool okk = upload(&d.seg_map, P.seg_map.data(), P.seg_map.size()) &&
              upload(&d.seg_begin, P.seg_begin.data(), P.seg_begin.size()) &&
              upload(&d.seg_ckpt, P.seg_ckpt.data(), P.seg_ckpt.size()) &&
              upload(&d.ops, P.ops.data(), P.ops.size()) &&
              upload(&d.gates, c.gates, (size_t)c.n_gates) &&
-             upload(&d.angle_slot, P.angle_slot.data(), P.angle_slot.size()) &&
-             upload(&d.slot_gate, P.slot_gate.data(), P.slot_gate.size());
+             upload(&d.gate_slot, P.gate_slot.data(), P.gate_slot.size()) &&
+             upload(&d.slot_gate, P.slot_gate.data(), P.slot_gate.size()) &&
+             upload(&d.l1q, P.l1q.data(), P.l1q.size()) &&
+             upload(&d.diag, P.diag.data(), P.diag.size()) &&
+             upload(&d.blk_begin, P.blk_begin.data(), P.blk_begin.size()) &&
+             upload(&d.blk_gates, P.blk_gates.data(), P.blk_gates.size()) &&
+             upload(&d.blk_fu, P.blk_fu.data(), P.blk_fu.size());
   if (!okk) {
     free_dev(d);
     delete e;
@@ -488,9 +510,9 @@ ProgEnginePlan program_engine_plan(const qs_circuit& c, int r, int* rc) {
   Entry* e = get_plan(c, r, true, nullptr, 0, rc);
   return {e ? &e->dev : nullptr};
 }
-int64_t engine_lds_bytes(int dtype, int n, int S, int n_gates, int n_slots,
-                         int n_params, int n_feats, int block, bool ps) {
-  return lds_bytes(dtype, n, S, n_gates, n_slots, n_params, n_feats, block, ps);
+int64_t engine_lds_bytes(int dtype, const qs_circuit& c, int S, int n_slots, int block,
+                         bool ps, bool adjoint) {
+  return lds_bytes(dtype, c, S, n_slots, block, ps, adjoint);
 }
 }  // namespace qs
 
@@ -983,7 +1005,8 @@ int qs_plan_info_get(const qs_circuit* c, int dtype, int64_t B, int flags,
   out->block_threads = shape.block_threads;
   out->n_segments = P.nseg();
   out->n_remaps = P.n_remaps;
-  out->n_ops = (int32_t)P.ops.size();
+  out->n_ops = (int32_t)(P.exec.size() / 3);
+  out->n_engine_ops = (int32_t)P.ops.size();
   out->lds_bytes = shape.lds_bytes;
   (void)B;
   return QS_OK;
@@ -998,14 +1021,15 @@ int qs_plan_export(const qs_circuit* c, int dtype, int64_t B, int flags,
   const bool ps = (flags & QS_FLAG_PER_SAMPLE_PARAMS) != 0;
   SvPlan P = plan_sv(*c, info->log2_regs, ps, nullptr, 0);  // the forward plan
   if (ops)
-    for (size_t o = 0; o < P.ops.size(); ++o) {
-      ops[4 * o] = P.ops[o].kind;
-      ops[4 * o + 1] = P.ops[o].a;
-      ops[4 * o + 2] = P.ops[o].b;
-      ops[4 * o + 3] = P.ops[o].gate;
+    for (size_t o = 0; o < P.exec.size() / 3; ++o) {
+      const int g = P.exec[3 * o];
+      ops[4 * o] = c->gates[g].op;
+      ops[4 * o + 1] = P.exec[3 * o + 1];
+      ops[4 * o + 2] = P.exec[3 * o + 2];
+      ops[4 * o + 3] = g;
     }
   if (seg_begin)
-    std::memcpy(seg_begin, P.seg_begin.data(), sizeof(int32_t) * P.seg_begin.size());
+    std::memcpy(seg_begin, P.exec_seg.data(), sizeof(int32_t) * P.exec_seg.size());
   if (seg_map) std::memcpy(seg_map, P.seg_map.data(), P.seg_map.size());
   return QS_OK;
 }

@@ -13,16 +13,30 @@ namespace qs {
 // positions inside a sample's state: 0 .. r-1 are register bits (amplitude
 // index within a thread), r .. n-1 are thread bits (thread index within the
 // sample's thread group).
-//   kind  gate kind (QS_OP_*)
-//   a     target (1-qubit), control (CNOT), first qubit (CZ)
-//   b     target (CNOT), second qubit (CZ), unused otherwise
-//   aux   bit 0: the angle differs per sample (per-sample table slot)
-//   gate  index of the descriptor gate this op came from
+//   kind  gate kind (QS_OP_*) or one of the layer kinds below
+//   a     target (1-qubit), control (CNOT); L1Q: mask of register bits used
+//   b     target (CNOT), unused otherwise
+//   aux   bit 0: some angle of the op differs per sample
+//   gate  descriptor gate of a single-gate op; record index of a layer op
 struct SvOp {
   uint8_t kind, a, b, aux;
   int32_t gate;
 };
 static_assert(sizeof(SvOp) == 8, "SvOp layout");
+
+// Layer ops. L1Q applies, on every register bit j at once, the product of a
+// run of consecutive single-qubit gates ("block") acting on the qubit held
+// there; its record is kL1QWords int32: the block id per register bit (-1:
+// none). DIAG applies a set of CZ gates as one sign pattern over the
+// amplitude index; its record is kDiagWords uint32:
+//   [0]      sign parity of register index k (bit k) from register-register CZs
+//   [1]      thread-bit mask of single thread-bit sign terms (Z on thread bits)
+//   [2 + j]  thread bits paired with register bit j (register-thread CZs)
+//   [7 + i]  higher thread bits paired with thread bit i (thread-thread CZs)
+constexpr uint8_t kOpL1Q = 16;
+constexpr uint8_t kOpDiag = 17;
+constexpr int kL1QWords = 8;
+constexpr int kDiagWords = 24;
 
 constexpr int kMaxQubitsFused = 14;  // 2^14 complex64 = 128 KiB LDS staging
 constexpr int kMapStride = 16;       // bytes per segment mapping record
@@ -30,8 +44,10 @@ constexpr int kMapStride = 16;       // bytes per segment mapping record
 // A planned gate program: a sequence of segments, each with a fixed
 // placement of the logical qubits onto physical bit positions, such that
 // every non-diagonal gate of the segment acts on a register-resident qubit.
-// Ops are the circuit's gates (one op per gate) in a dependency-respecting
-// order; op o applies gate ops[o].gate, and per-op tables use index o.
+// Within a segment the gates are grouped into layer ops (L1Q, DIAG) where
+// possible; the rest (CNOT, diagonal gates on thread bits) stay one op per
+// gate. `exec` lists every gate once in execution order with its physical
+// positions, for inspection.
 struct SvPlan {
   int n = 0, r = 0, t = 0;            // qubits, log2 regs, log2 threads/sample
   int n_gates = 0;
@@ -39,10 +55,20 @@ struct SvPlan {
   std::vector<int32_t> seg_begin;     // [nseg + 1] op ranges
   std::vector<int32_t> seg_ckpt;      // [nseg] checkpoint slot after segment
   std::vector<SvOp> ops;
-  std::vector<int32_t> angle_slot;    // [n_ops] shared: -1, per-sample: slot
+  std::vector<int32_t> gate_slot;     // [G] per-sample angle slot, or -1
   std::vector<int32_t> slot_gate;     // [n_slots] gate of a per-sample slot
+  std::vector<int32_t> l1q;           // [n_l1q][kL1QWords]
+  std::vector<uint32_t> diag;         // [n_diag][kDiagWords]
+  std::vector<int32_t> blk_begin;     // [n_blocks + 1] ranges of blk_gates
+  std::vector<int32_t> blk_gates;     // gates of each block, forward order
+  std::vector<int32_t> blk_fu;        // [n_blocks] slot of the block's fused matrix
+                                      // (angles shared), -1: built per sample
+  std::vector<int32_t> exec;          // [G][3] gate, physical a, physical b
+  std::vector<int32_t> exec_seg;      // [nseg + 1] ranges of exec rows
   int n_remaps = 0;
   int nseg() const { return (int)seg_begin.size() - 1; }
+  int n_fu = 0;                       // blocks with a fused-matrix slot
+  int n_blocks() const { return (int)blk_fu.size(); }
 };
 
 // Plans `c` for 2^r amplitudes per thread. `per_sample_angles_all` marks every
@@ -74,8 +100,14 @@ struct SvDevPlan {
   int32_t* seg_ckpt;
   SvOp* ops;
   qs_gate* gates;
-  int32_t* angle_slot;
+  int32_t* gate_slot;
   int32_t* slot_gate;
+  int32_t* l1q;
+  uint32_t* diag;
+  int32_t* blk_begin;
+  int32_t* blk_gates;
+  int32_t* blk_fu;
+  int n_blocks, n_fu;
 };
 
 // Launch geometry of the engine for a plan.
@@ -138,9 +170,14 @@ struct ProgClass {
   const int32_t* seg_ckpt;
   const SvOp* ops;
   const qs_gate* gates;
-  const int32_t* angle_slot;
+  const int32_t* gate_slot;
   const int32_t* slot_gate;
-  int32_t n, t, nseg, n_gates, n_slots, n_params, S, pad;
+  const int32_t* l1q;
+  const uint32_t* diag;
+  const int32_t* blk_begin;
+  const int32_t* blk_gates;
+  const int32_t* blk_fu;
+  int32_t n, t, nseg, n_gates, n_slots, n_params, S, n_blocks, n_fu, pad;
   int64_t count;       // circuits in the class
   int64_t state_off;   // complex-element offset of the class's first state
   int64_t param_off;   // element offset of the class's parameters [count][P]

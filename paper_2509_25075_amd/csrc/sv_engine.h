@@ -1,0 +1,1379 @@
+// Register-resident batched state-vector engine for gfx950 (forward and
+// adjoint): device code and launch templates, instantiated by the sv_*.hip
+// translation units (one per element type and direction, so that they build
+// in parallel).
+//
+// Layout. A sample's 2^n amplitudes live in the registers of T = 2^t
+// threads, R = 2^r amplitudes per thread (n = r + t). Physical index of
+// amplitude k of thread tau is k + R * tau, so physical bits 0..r-1 are
+// register bits and r..n-1 are thread bits. A segment of the planned gate
+// program fixes which logical qubit sits on which physical bit; every
+// pair-mixing gate of a segment targets a register bit, so it is applied
+// with no communication. Diagonal gates (RZ, Z, CZ) and CNOT controls on
+// thread bits use the lane's own bit. Between segments the state is written
+// to LDS in logical order and read back under the next placement (a remap).
+//
+// Layer ops. Runs of single-qubit gates on the qubit of each register bit
+// are multiplied into one 2x2 matrix per bit ("block"), and one L1Q op
+// applies the blocks of all register bits in straight-line code; a set of
+// CZ gates becomes one DIAG op, a per-thread sign mask over the register
+// index. The adjoint takes every rotation gradient of a block from the 2x2
+// correlation Q = sum psi lam^dagger on that bit at the block output, moved
+// back through the block gate by gate (Q <- G^dagger Q G).
+//
+// LDS slots are swizzled, slot(L) = L ^ fold5(L >> 5) ^ (per-sample salt),
+// which is linear over GF(2), so the address of amplitude k of a lane is
+// (per-lane part) XOR (uniform per-k part): one VALU op per access.
+//
+// Gates: R_P(t) = exp(-i t P / 2) (Nielsen & Chuang sec. 4.2); the adjoint
+// step computes dL/dtheta = Im <lam|P|psi> and un-applies the gate from psi
+// and lam (Jones & Gacon, arXiv:2009.02823, sec. 3).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "qs_internal.h"
+
+namespace qs {
+namespace {
+
+#define QS_AI __attribute__((always_inline))
+
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+// ------------------------------------------------------------------ wave ops
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  long long u = __double_as_longlong(v);
+  int lo = (int)(u & 0xffffffffll), hi = (int)(u >> 32);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) { return dpp_f32<CTRL>(v); }
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) { return dpp_f64<CTRL>(v); }
+
+// Sum over aligned groups of G lanes (G a power of two, 1..64, uniform);
+// every lane of a group receives the group's sum. Requires a full wave.
+template <typename real>
+__device__ __forceinline__ real group_sum(real v, int G) {
+  if (G >= 2) v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]  (lane ^ 1)
+  if (G >= 4) v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]  (lane ^ 2)
+  if (G >= 8) v += dpp<0x141>(v);  // row_half_mirror: the other quad of 8
+  if (G >= 16) v += dpp<0x140>(v); // row_mirror: the other 8 of a row
+  if (G >= 32) v += __shfl_xor(v, 16);
+  if (G >= 64) v += __shfl_xor(v, 32);
+  return v;
+}
+
+// Plan data is read-only for the whole launch: reading it through the
+// constant address space lets uniform indices become scalar loads.
+#define QS_K __attribute__((address_space(4)))
+template <typename T>
+__device__ __forceinline__ const QS_K T* kc(const T* p) {
+  return (const QS_K T*)p;
+}
+
+// Load a plan record (SvOp, qs_gate) word by word through the constant
+// address space.
+template <typename T>
+__device__ __forceinline__ T kload(const T* base, int i) {
+  static_assert(sizeof(T) % 4 == 0, "record of 32-bit words");
+  T out;
+  uint32_t* o = reinterpret_cast<uint32_t*>(&out);
+  const QS_K uint32_t* src = reinterpret_cast<const QS_K uint32_t*>(kc(base + i));
+#pragma unroll
+  for (int w = 0; w < (int)(sizeof(T) / 4); ++w) o[w] = src[w];
+  return out;
+}
+
+__device__ __forceinline__ int uni(int v) {
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Slot swizzle inside a sample's LDS region (in complex elements).
+__device__ __forceinline__ uint32_t swz(uint32_t L) {
+  return L ^ ((L >> 5) & 31u) ^ ((L >> 10) & 31u);
+}
+
+// --------------------------------------------------------------- state ops
+// Amplitudes of one thread: R-wide vector values (not arrays), so branches
+// that touch different elements can never be merged into a pointer select
+// that would push the state out of registers.
+template <typename real, int R>
+struct St {
+  typedef real V __attribute__((ext_vector_type(R)));
+  V re;
+  V im;
+};
+
+// Dispatch a uniform runtime position j in [0, LR) to a compile-time one.
+template <int LR, typename F>
+__device__ __forceinline__ void for_pos(int j, F&& f) {
+  if constexpr (LR > 0) { if (j == 0) { f(IC<0>{}); return; } }
+  if constexpr (LR > 1) { if (j == 1) { f(IC<1>{}); return; } }
+  if constexpr (LR > 2) { if (j == 2) { f(IC<2>{}); return; } }
+  if constexpr (LR > 3) { if (j == 3) { f(IC<3>{}); return; } }
+  if constexpr (LR > 4) { if (j == 4) { f(IC<4>{}); return; } }
+}
+
+// RX(theta) = [[c, -i s], [-i s, c]] on register bit J (s may carry the sign
+// of an inverse).
+template <int J, typename real, int R>
+__device__ __forceinline__ void g_rx(St<real, R>& x, real c, real s) {
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    if (k & (1 << J)) continue;
+    const int k1 = k | (1 << J);
+    real a0r = x.re[k], a0i = x.im[k], a1r = x.re[k1], a1i = x.im[k1];
+    x.re[k] = c * a0r + s * a1i;
+    x.im[k] = c * a0i - s * a1r;
+    x.re[k1] = c * a1r + s * a0i;
+    x.im[k1] = c * a1i - s * a0r;
+  }
+}
+// RY(theta) = [[c, -s], [s, c]].
+template <int J, typename real, int R>
+__device__ __forceinline__ void g_ry(St<real, R>& x, real c, real s) {
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    if (k & (1 << J)) continue;
+    const int k1 = k | (1 << J);
+    real a0r = x.re[k], a0i = x.im[k], a1r = x.re[k1], a1i = x.im[k1];
+    x.re[k] = c * a0r - s * a1r;
+    x.im[k] = c * a0i - s * a1i;
+    x.re[k1] = s * a0r + c * a1r;
+    x.im[k1] = s * a0i + c * a1i;
+  }
+}
+// RZ(theta) = diag(c - i s, c + i s) on register bit J.
+template <int J, typename real, int R>
+__device__ __forceinline__ void g_rz(St<real, R>& x, real c, real s) {
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const real sk = (k & (1 << J)) ? s : -s;  // phase c + i sk
+    real ar = x.re[k], ai = x.im[k];
+    x.re[k] = c * ar - sk * ai;
+    x.im[k] = c * ai + sk * ar;
+  }
+}
+// A lane-uniform phase c + i s on every amplitude (RZ on a thread bit).
+template <typename real, int R>
+__device__ __forceinline__ void g_phase_all(St<real, R>& x, real c, real s) {
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    real ar = x.re[k], ai = x.im[k];
+    x.re[k] = c * ar - s * ai;
+    x.im[k] = c * ai + s * ar;
+  }
+}
+template <int J, typename real, int R>
+__device__ __forceinline__ void g_x(St<real, R>& x) {
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    if (k & (1 << J)) continue;
+    const int k1 = k | (1 << J);
+    real tr = x.re[k], ti = x.im[k];
+    x.re[k] = x.re[k1];
+    x.im[k] = x.im[k1];
+    x.re[k1] = tr;
+    x.im[k1] = ti;
+  }
+}
+// Y = [[0, -i], [i, 0]]: (a0, a1) -> (-i a1, i a0).
+template <int J, typename real, int R>
+__device__ __forceinline__ void g_y(St<real, R>& x) {
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    if (k & (1 << J)) continue;
+    const int k1 = k | (1 << J);
+    real a0r = x.re[k], a0i = x.im[k], a1r = x.re[k1], a1i = x.im[k1];
+    x.re[k] = a1i;
+    x.im[k] = -a1r;
+    x.re[k1] = -a0i;
+    x.im[k1] = a0r;
+  }
+}
+template <int J, typename real, int R>
+__device__ __forceinline__ void g_z(St<real, R>& x) {
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    if (!(k & (1 << J))) continue;
+    x.re[k] = -x.re[k];
+    x.im[k] = -x.im[k];
+  }
+}
+template <int J, typename real, int R>
+__device__ __forceinline__ void g_h(St<real, R>& x) {
+  const real h = (real)0.70710678118654752440;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    if (k & (1 << J)) continue;
+    const int k1 = k | (1 << J);
+    real a0r = x.re[k], a0i = x.im[k], a1r = x.re[k1], a1i = x.im[k1];
+    x.re[k] = h * (a0r + a1r);
+    x.im[k] = h * (a0i + a1i);
+    x.re[k1] = h * (a0r - a1r);
+    x.im[k1] = h * (a0i - a1i);
+  }
+}
+// Negate every amplitude of lanes where `cond` holds.
+template <typename real, int R>
+__device__ __forceinline__ void g_neg_if(St<real, R>& x, bool cond) {
+  const real sg = cond ? (real)-1 : (real)1;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    x.re[k] *= sg;
+    x.im[k] *= sg;
+  }
+}
+// CZ between register bits A < B.
+template <int A, int B, typename real, int R>
+__device__ __forceinline__ void g_cz_rr(St<real, R>& x) {
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    if ((k & (1 << A)) && (k & (1 << B))) {
+      x.re[k] = -x.re[k];
+      x.im[k] = -x.im[k];
+    }
+  }
+}
+// CZ between register bit A and a thread bit whose value is `tb`.
+template <int A, typename real, int R>
+__device__ __forceinline__ void g_cz_rt(St<real, R>& x, bool tb) {
+  const real sg = tb ? (real)-1 : (real)1;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    if (k & (1 << A)) {
+      x.re[k] *= sg;
+      x.im[k] *= sg;
+    }
+  }
+}
+// CNOT, control register bit C, target register bit J.
+template <int C, int J, typename real, int R>
+__device__ __forceinline__ void g_cnot_rr(St<real, R>& x) {
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    if ((k & (1 << J)) || !(k & (1 << C))) continue;
+    const int k1 = k | (1 << J);
+    real tr = x.re[k], ti = x.im[k];
+    x.re[k] = x.re[k1];
+    x.im[k] = x.im[k1];
+    x.re[k1] = tr;
+    x.im[k1] = ti;
+  }
+}
+// CNOT, control on a thread bit (value tb), target register bit J.
+template <int J, typename real, int R>
+__device__ __forceinline__ void g_cnot_tr(St<real, R>& x, bool tb) {
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    if (k & (1 << J)) continue;
+    const int k1 = k | (1 << J);
+    real a0r = x.re[k], a0i = x.im[k], a1r = x.re[k1], a1i = x.im[k1];
+    x.re[k] = tb ? a1r : a0r;
+    x.im[k] = tb ? a1i : a0i;
+    x.re[k1] = tb ? a0r : a1r;
+    x.im[k1] = tb ? a0i : a1i;
+  }
+}
+
+// Per-thread partial sums of Im <lam|P|psi> for the rotation generators.
+template <int J, typename real, int R>
+__device__ __forceinline__ real gr_x(const St<real, R>& p, const St<real, R>& l) {
+  real acc = 0;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    if (k & (1 << J)) continue;
+    const int k1 = k | (1 << J);
+    // Im(conj(l0) p1 + conj(l1) p0)
+    acc += l.re[k] * p.im[k1] - l.im[k] * p.re[k1];
+    acc += l.re[k1] * p.im[k] - l.im[k1] * p.re[k];
+  }
+  return acc;
+}
+template <int J, typename real, int R>
+__device__ __forceinline__ real gr_y(const St<real, R>& p, const St<real, R>& l) {
+  real acc = 0;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    if (k & (1 << J)) continue;
+    const int k1 = k | (1 << J);
+    // Im(conj(l0)(-i p1) + conj(l1)(i p0)) = -Re(conj(l0) p1) + Re(conj(l1) p0)
+    acc += l.re[k1] * p.re[k] + l.im[k1] * p.im[k];
+    acc -= l.re[k] * p.re[k1] + l.im[k] * p.im[k1];
+  }
+  return acc;
+}
+template <int J, typename real, int R>
+__device__ __forceinline__ real gr_z(const St<real, R>& p, const St<real, R>& l) {
+  real acc = 0;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    real v = l.re[k] * p.im[k] - l.im[k] * p.re[k];  // Im(conj(l) p)
+    acc += (k & (1 << J)) ? -v : v;
+  }
+  return acc;
+}
+template <typename real, int R>
+__device__ __forceinline__ real gr_all(const St<real, R>& p, const St<real, R>& l) {
+  real acc = 0;
+#pragma unroll
+  for (int k = 0; k < R; ++k) acc += l.re[k] * p.im[k] - l.im[k] * p.re[k];
+  return acc;
+}
+
+// ------------------------------------------------------ 2x2 complex blocks
+// A single-qubit operator [[u00, u01], [u10, u11]] (real, imaginary parts).
+template <typename real>
+struct U2 {
+  real r00, i00, r01, i01, r10, i10, r11, i11;
+};
+
+template <typename real>
+__device__ __forceinline__ U2<real> u_mul(const U2<real>& a, const U2<real>& b) {
+  U2<real> c;
+  c.r00 = a.r00 * b.r00 - a.i00 * b.i00 + a.r01 * b.r10 - a.i01 * b.i10;
+  c.i00 = a.r00 * b.i00 + a.i00 * b.r00 + a.r01 * b.i10 + a.i01 * b.r10;
+  c.r01 = a.r00 * b.r01 - a.i00 * b.i01 + a.r01 * b.r11 - a.i01 * b.i11;
+  c.i01 = a.r00 * b.i01 + a.i00 * b.r01 + a.r01 * b.i11 + a.i01 * b.r11;
+  c.r10 = a.r10 * b.r00 - a.i10 * b.i00 + a.r11 * b.r10 - a.i11 * b.i10;
+  c.i10 = a.r10 * b.i00 + a.i10 * b.r00 + a.r11 * b.i10 + a.i11 * b.r10;
+  c.r11 = a.r10 * b.r01 - a.i10 * b.i01 + a.r11 * b.r11 - a.i11 * b.i11;
+  c.i11 = a.r10 * b.i01 + a.i10 * b.r01 + a.r11 * b.i11 + a.i11 * b.r11;
+  return c;
+}
+template <typename real>
+__device__ __forceinline__ U2<real> u_dag(const U2<real>& a) {
+  return U2<real>{a.r00, -a.i00, a.r10, -a.i10, a.r01, -a.i01, a.r11, -a.i11};
+}
+// The matrix of a single-qubit gate; rotations take (c, s) = cos, sin of
+// theta/2, so RX = [[c, -i s], [-i s, c]], RY = [[c, -s], [s, c]],
+// RZ = diag(c - i s, c + i s).
+template <typename real>
+__device__ __forceinline__ U2<real> gate_u(int kind, real c, real s) {
+  const real z = 0, o = 1, h = (real)0.70710678118654752440;
+  switch (kind) {
+    case QS_OP_RX: return U2<real>{c, z, z, -s, z, -s, c, z};
+    case QS_OP_RY: return U2<real>{c, z, -s, z, s, z, c, z};
+    case QS_OP_RZ: return U2<real>{c, -s, z, z, z, z, c, s};
+    case QS_OP_X: return U2<real>{z, z, o, z, o, z, z, z};
+    case QS_OP_Y: return U2<real>{z, z, z, -o, z, o, z, z};
+    case QS_OP_Z: return U2<real>{o, z, z, z, z, z, -o, z};
+    default: return U2<real>{h, z, h, z, h, z, -h, z};  // H
+  }
+}
+
+// x <- U x on register bit J.
+template <int J, typename real, int R>
+__device__ __forceinline__ void g_u(St<real, R>& x, const U2<real>& u) {
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    if (k & (1 << J)) continue;
+    const int k1 = k | (1 << J);
+    const real ar = x.re[k], ai = x.im[k], br = x.re[k1], bi = x.im[k1];
+    x.re[k] = u.r00 * ar - u.i00 * ai + u.r01 * br - u.i01 * bi;
+    x.im[k] = u.r00 * ai + u.i00 * ar + u.r01 * bi + u.i01 * br;
+    x.re[k1] = u.r10 * ar - u.i10 * ai + u.r11 * br - u.i11 * bi;
+    x.im[k1] = u.r10 * ai + u.i10 * ar + u.r11 * bi + u.i11 * br;
+  }
+}
+
+// Per-thread partial of Q = sum psi lam^dagger restricted to register bit J:
+// Q_ab = sum over the other index bits of psi_a conj(lam_b). For any
+// single-qubit generator P on that bit, Im <lam|P|psi> = Im Tr(P Q).
+template <int J, typename real, int R>
+__device__ __forceinline__ U2<real> q_part(const St<real, R>& p, const St<real, R>& l) {
+  U2<real> q{0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    if (k & (1 << J)) continue;
+    const int k1 = k | (1 << J);
+    const real p0r = p.re[k], p0i = p.im[k], p1r = p.re[k1], p1i = p.im[k1];
+    const real l0r = l.re[k], l0i = l.im[k], l1r = l.re[k1], l1i = l.im[k1];
+    q.r00 += p0r * l0r + p0i * l0i;
+    q.i00 += p0i * l0r - p0r * l0i;
+    q.r01 += p0r * l1r + p0i * l1i;
+    q.i01 += p0i * l1r - p0r * l1i;
+    q.r10 += p1r * l0r + p1i * l0i;
+    q.i10 += p1i * l0r - p1r * l0i;
+    q.r11 += p1r * l1r + p1i * l1i;
+    q.i11 += p1i * l1r - p1r * l1i;
+  }
+  return q;
+}
+
+// Im Tr(P Q) for the rotation generator P of `kind`.
+template <typename real>
+__device__ __forceinline__ real im_tr(int kind, const U2<real>& q) {
+  if (kind == QS_OP_RX) return q.i10 + q.i01;
+  if (kind == QS_OP_RY) return q.r01 - q.r10;
+  return q.i00 - q.i11;
+}
+
+// Q <- G^dagger Q G: the correlation moved from a gate's output to its
+// input. For a rotation G = c I - i s P this is
+// c^2 Q + s^2 P Q P + i c s (P Q - Q P), written out per generator.
+template <typename real>
+__device__ __forceinline__ U2<real> q_back(int kind, real c, real s, const U2<real>& q) {
+  const real cc = c * c, ss = s * s, cs = c * s;
+  U2<real> o;
+  if (kind == QS_OP_RX) {
+    // i cs (Q10 - Q01), i cs (Q11 - Q00), i cs (Q00 - Q11), i cs (Q01 - Q10)
+    o.r00 = cc * q.r00 + ss * q.r11 - cs * (q.i10 - q.i01);
+    o.i00 = cc * q.i00 + ss * q.i11 + cs * (q.r10 - q.r01);
+    o.r01 = cc * q.r01 + ss * q.r10 - cs * (q.i11 - q.i00);
+    o.i01 = cc * q.i01 + ss * q.i10 + cs * (q.r11 - q.r00);
+    o.r10 = cc * q.r10 + ss * q.r01 - cs * (q.i00 - q.i11);
+    o.i10 = cc * q.i10 + ss * q.i01 + cs * (q.r00 - q.r11);
+    o.r11 = cc * q.r11 + ss * q.r00 - cs * (q.i01 - q.i10);
+    o.i11 = cc * q.i11 + ss * q.i00 + cs * (q.r01 - q.r10);
+  } else if (kind == QS_OP_RY) {
+    o.r00 = cc * q.r00 + ss * q.r11 + cs * (q.r10 + q.r01);
+    o.i00 = cc * q.i00 + ss * q.i11 + cs * (q.i10 + q.i01);
+    o.r01 = cc * q.r01 - ss * q.r10 - cs * (q.r00 - q.r11);
+    o.i01 = cc * q.i01 - ss * q.i10 - cs * (q.i00 - q.i11);
+    o.r10 = cc * q.r10 - ss * q.r01 - cs * (q.r00 - q.r11);
+    o.i10 = cc * q.i10 - ss * q.i01 - cs * (q.i00 - q.i11);
+    o.r11 = cc * q.r11 + ss * q.r00 - cs * (q.r01 + q.r10);
+    o.i11 = cc * q.i11 + ss * q.i00 - cs * (q.i01 + q.i10);
+  } else if (kind == QS_OP_RZ) {
+    // diagonal entries scale by c^2 + s^2; Q01 by (c + i s)^2, Q10 by (c - i s)^2
+    const real n2 = cc + ss, a = cc - ss, b = 2 * cs;
+    o.r00 = n2 * q.r00;
+    o.i00 = n2 * q.i00;
+    o.r11 = n2 * q.r11;
+    o.i11 = n2 * q.i11;
+    o.r01 = a * q.r01 - b * q.i01;
+    o.i01 = a * q.i01 + b * q.r01;
+    o.r10 = a * q.r10 + b * q.i10;
+    o.i10 = a * q.i10 - b * q.r10;
+  } else {
+    const U2<real> g = gate_u<real>(kind, c, s);
+    o = u_mul(u_dag(g), u_mul(q, g));
+  }
+  return o;
+}
+
+__device__ __forceinline__ float flip_sign(float v, uint32_t bit) {
+  return __uint_as_float(__float_as_uint(v) ^ (bit << 31));
+}
+__device__ __forceinline__ double flip_sign(double v, uint32_t bit) {
+  return __longlong_as_double(__double_as_longlong(v) ^
+                              (long long)((unsigned long long)bit << 63));
+}
+
+template <int N, int I = 0, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(IC<I>{});
+    static_for<N, I + 1>(f);
+  }
+}
+
+// ------------------------------------------------------------- kernel args
+template <typename real>
+struct Args {
+  const uint8_t* seg_map;
+  const int32_t* seg_begin;
+  const int32_t* seg_ckpt;
+  const SvOp* ops;
+  const qs_gate* gates;
+  const int32_t* gate_slot;  // [G] per-sample angle slot or -1
+  const int32_t* slot_gate;
+  const int32_t* l1q;        // layer-op records
+  const uint32_t* diag;
+  const int32_t* blk_begin;  // fused single-qubit blocks
+  const int32_t* blk_gates;
+  const int32_t* blk_fu;
+  int n_blocks, n_fu;
+  int n, t, nseg, n_gates, n_slots, n_params, n_feats, S;
+  int per_sample_params;
+  int64_t B;               // samples processed (tiled: batch rows << ob)
+  int n_tot, ob;           // tiled: qubits of the whole state, outer bits
+  const uint8_t* tile_q;   // tiled: [n] global qubit of each local bit
+  const uint8_t* outer_q;  // tiled: [ob] global qubit of each outer bit
+  real* out_psi;           // adjoint: store the final psi here (or null)
+  real* out_lam;           // adjoint: store the final lam here (or null)
+  const real* params;
+  const real* feats;
+  real* state;
+  double* expz;
+  real* ckpt;
+  const double* dexpz;
+  const real* dstate;
+  real* ws_partials;
+  double* grad_params;
+  double* grad_feats;
+};
+
+template <typename real>
+struct V2;
+template <>
+struct V2<float> { using T = float2; };
+template <>
+struct V2<double> { using T = double2; };
+
+__device__ __forceinline__ void fsincos(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __forceinline__ void fsincos(double x, double* s, double* c) { sincos(x, s, c); }
+
+template <typename real>
+__device__ __forceinline__ const real* param_row(const Args<real>& A, int64_t b) {
+  return A.per_sample_params ? A.params + (size_t)b * A.n_params : A.params;
+}
+
+template <typename real>
+__device__ __forceinline__ real theta_of(const Args<real>& A, const qs_gate& g,
+                                         int64_t b) {
+  const real* P = param_row(A, b);
+  real w = g.p_w >= 0 ? P[g.p_w] : (real)1;
+  real f = g.feat >= 0 ? A.feats[(size_t)b * A.n_feats + g.feat] : (real)1;
+  real bias = g.p_b >= 0 ? P[g.p_b] : (real)0;
+  return (real)g.scale * (w * f + bias);
+}
+
+// Per-sample sync: a wave barrier when a sample lives in one wave,
+// otherwise a workgroup barrier (T is uniform over the workgroup).
+__device__ __forceinline__ void sample_sync(int t) {
+  if (t > 6) {
+    __syncthreads();
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+// The engine's per-thread context.
+template <typename real, int LR, bool FLY = false>
+struct Ctx {
+  static constexpr int R = 1 << LR;
+  using v2 = typename V2<real>::T;
+  const Args<real>& A;
+  int tau, sl;       // thread within sample, sample within block
+  int64_t b;         // global sample index
+  int64_t row;       // batch row of the sample (for parameters and features)
+  int64_t base;      // offset (complex elements) of the sample's amplitude 0
+  uint32_t dep_tau;  // tiled: global offset of this thread's low local bits
+  bool active;
+  v2* lds;           // this sample's state region
+  uint32_t salt;     // per-sample slot salt
+  real* ang_sh;      // [G][2] shared (cos, sin) of theta/2, by gate
+  real* ang_ps;      // [n_slots][S][2] per-sample
+  real* fu_sh;       // [n_fu][8] fused matrices of blocks with shared angles
+  real* gacc;        // [waves][n_params] shared-parameter gradient sums
+  real* facc;        // [S * wps][n_feats] feature gradient sums
+  int wps;           // waves per sample (1 when a wave holds whole samples)
+
+  __device__ Ctx(const Args<real>& a) : A(a) {}
+
+  __device__ __forceinline__ bool tbit(int p) const {
+    return (tau >> (p - LR)) & 1;
+  }
+
+  // Logical index bits of this thread's thread-bit part under placement s.
+  __device__ __forceinline__ uint32_t lane_part(const QS_K uint8_t* map) const {
+    uint32_t L = 0;
+    for (int i = 0; i < A.t; ++i)
+      if ((tau >> i) & 1) L |= 1u << map[LR + i];
+    return swz(L) ^ salt;
+  }
+
+  __device__ __forceinline__ void write_mapped(const St<real, R>& x,
+                                               const QS_K uint8_t* map) {
+    const uint32_t base = lane_part(map);
+    uint32_t m[LR > 0 ? LR : 1];
+#pragma unroll
+    for (int j = 0; j < LR; ++j) m[j] = swz(1u << uni(map[j]));
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      uint32_t off = 0;
+#pragma unroll
+      for (int j = 0; j < LR; ++j)
+        if (k & (1 << j)) off ^= m[j];
+      v2 v;
+      v.x = x.re[k];
+      v.y = x.im[k];
+      lds[base ^ off] = v;
+    }
+  }
+  __device__ __forceinline__ void read_mapped(St<real, R>& x,
+                                              const QS_K uint8_t* map) {
+    const uint32_t base = lane_part(map);
+    uint32_t m[LR > 0 ? LR : 1];
+#pragma unroll
+    for (int j = 0; j < LR; ++j) m[j] = swz(1u << uni(map[j]));
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      uint32_t off = 0;
+#pragma unroll
+      for (int j = 0; j < LR; ++j)
+        if (k & (1 << j)) off ^= m[j];
+      v2 v = lds[base ^ off];
+      x.re[k] = v.x;
+      x.im[k] = v.y;
+    }
+  }
+  __device__ __forceinline__ void remap(St<real, R>& x, const QS_K uint8_t* from,
+                                        const QS_K uint8_t* to) {
+    sample_sync(A.t);
+    write_mapped(x, from);
+    sample_sync(A.t);
+    read_mapped(x, to);
+  }
+
+  // Global offset (complex elements) of local amplitude i = tau + x, x a
+  // multiple of T: the sample's base plus the local bits deposited onto the
+  // tile's qubits (identity when not tiled).
+  __device__ __forceinline__ int64_t addr(int x) const {
+    if (A.tile_q == nullptr) return base + tau + x;
+    int64_t d = dep_tau;
+    for (int j = A.t; j < A.n; ++j)
+      if ((x >> j) & 1) d |= 1ll << kc(A.tile_q)[j];
+    return base + d;
+  }
+
+  // HBM (logical order) -> LDS -> registers under placement `map`.
+  __device__ __forceinline__ void load_state(St<real, R>& x, const real* src,
+                                             const QS_K uint8_t* map) {
+    const int N = 1 << A.n, T = 1 << A.t;
+    sample_sync(A.t);
+    const v2* s2 = reinterpret_cast<const v2*>(src);
+    for (int i = tau; i < N; i += T) {
+      v2 v;
+      if (active) {
+        v = s2[addr(i - tau)];
+      } else {
+        v.x = 0;
+        v.y = 0;
+      }
+      lds[swz((uint32_t)i) ^ salt] = v;
+    }
+    sample_sync(A.t);
+    read_mapped(x, map);
+  }
+  // Registers under `map` -> LDS -> HBM (logical order).
+  __device__ __forceinline__ void store_state(const St<real, R>& x, real* dst,
+                                              const QS_K uint8_t* map) {
+    const int N = 1 << A.n, T = 1 << A.t;
+    sample_sync(A.t);
+    write_mapped(x, map);
+    sample_sync(A.t);
+    if (active) {
+      v2* d2 = reinterpret_cast<v2*>(dst);
+      for (int i = tau; i < N; i += T) d2[addr(i - tau)] = lds[swz((uint32_t)i) ^ salt];
+    }
+  }
+
+  // cos, sin of theta/2 of rotation gate g (uniform g).
+  __device__ __forceinline__ void gate_cs(int g, real& c, real& s) const {
+    const int slot = kc(A.gate_slot)[g];
+    if (slot >= 0) {
+      if constexpr (FLY) {
+        // per-sample angle computed in place (no per-sample table in LDS)
+        const qs_gate gt = kload(A.gates, g);
+        const real th = active ? theta_of(A, gt, row) : (real)0;
+        fsincos(th * (real)0.5, &s, &c);
+      } else {
+        const real* p = ang_ps + 2 * ((size_t)slot * A.S + sl);
+        c = p[0];
+        s = p[1];
+      }
+    } else {
+      c = ang_sh[2 * g];
+      s = ang_sh[2 * g + 1];
+    }
+  }
+
+  // The product of block `bid`'s gates (first gate rightmost).
+  __device__ __forceinline__ U2<real> block_u(int bid) const {
+    const int fu = kc(A.blk_fu)[bid];
+    if (fu >= 0) {
+      const real* p = fu_sh + 8 * (size_t)fu;
+      return U2<real>{p[0], p[1], p[2], p[3], p[4], p[5], p[6], p[7]};
+    }
+    const int b0 = kc(A.blk_begin)[bid], b1 = kc(A.blk_begin)[bid + 1];
+    U2<real> u{1, 0, 0, 0, 0, 0, 1, 0};
+    for (int i = b0; i < b1; ++i) {
+      const int g = kc(A.blk_gates)[i];
+      const int kind = kload(A.gates, g).op;
+      real c = 1, s = 0;
+      if (kind <= QS_OP_RZ) gate_cs(g, c, s);
+      const U2<real> m = gate_u<real>(kind, c, s);
+      u = i == b0 ? m : u_mul(m, u);
+    }
+    return u;
+  }
+
+  // The block's matrix, the identity for bid < 0. Register bits without a
+  // block still get the (identity) update: a branch around the update would
+  // make the compiler copy the whole state at the join.
+  __device__ __forceinline__ U2<real> block_or_id(int bid) const {
+    if (bid < 0) return U2<real>{1, 0, 0, 0, 0, 0, 1, 0};
+    return block_u(bid);
+  }
+
+  // L1Q: each register bit's block (its inverse when `inv`).
+  __device__ __forceinline__ void apply_l1q(St<real, R>& x, int rec, bool inv) const {
+    const QS_K int32_t* r = kc(A.l1q) + (size_t)rec * kL1QWords;
+    static_for<LR>([&](auto J) QS_AI {
+      const U2<real> u = block_or_id(r[decltype(J)::value]);
+      g_u<decltype(J)::value>(x, inv ? u_dag(u) : u);
+    });
+  }
+
+  // DIAG: the sign (-1)^(sum over the CZ pairs of bit_a bit_b) of every
+  // amplitude, built per thread as a mask over its register index k.
+  __device__ __forceinline__ void apply_diag(St<real, R>& x, int rec) const {
+    const QS_K uint32_t* d = kc(A.diag) + (size_t)rec * kDiagWords;
+    const uint32_t tb = (uint32_t)tau;
+    uint32_t par = __builtin_popcount(tb & d[1]);
+    for (int i = 0; i < A.t; ++i)
+      if ((tb >> i) & 1) par += __builtin_popcount(tb & d[7 + i]);
+    uint32_t m = d[0] ^ ((par & 1) ? 0xffffffffu : 0u);
+    constexpr uint32_t pat[5] = {0xAAAAAAAAu, 0xCCCCCCCCu, 0xF0F0F0F0u, 0xFF00FF00u,
+                                 0xFFFF0000u};
+#pragma unroll
+    for (int j = 0; j < LR; ++j)
+      if (__builtin_popcount(tb & d[2 + j]) & 1) m ^= pat[j];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const uint32_t bit = (m >> k) & 1u;
+      x.re[k] = flip_sign(x.re[k], bit);
+      x.im[k] = flip_sign(x.im[k], bit);
+    }
+  }
+
+  // Adds this thread's partial dL/dtheta of rotation gate `gt` (gate index g)
+  // to the gradient sums: shared parameters through per-wave LDS slots,
+  // per-sample parameter sets with FP64 atomics, features per sample.
+  __device__ __forceinline__ void accum(const qs_gate& gt, real part, int lane, int wave,
+                                        int Tw) {
+    const real scale = (real)gt.scale;
+    if (!A.per_sample_params && gt.feat < 0) {
+      // shared parameters, no feature: dL/dP += scale sum_b dL/dtheta_b
+      const real v = group_sum(part, 64);
+      if (lane == 0) {
+        real* g = gacc + (size_t)wave * A.n_params;
+        if (gt.p_w >= 0) g[gt.p_w] += scale * v;
+        if (gt.p_b >= 0) g[gt.p_b] += scale * v;
+      }
+      return;
+    }
+    const real gth = group_sum(part, Tw);  // this sample (this wave's share)
+    const bool leader = (tau & (Tw - 1)) == 0 && active;
+    const real* P = param_row(A, active ? row : 0);
+    const real f = (gt.feat >= 0 && active) ? A.feats[(size_t)row * A.n_feats + gt.feat]
+                                             : (real)1;
+    const real w = gt.p_w >= 0 ? P[gt.p_w] : (real)1;
+    if (A.per_sample_params) {
+      if (leader) {
+        double* gp = A.grad_params + (size_t)row * A.n_params;
+        if (gt.p_w >= 0) atomicAdd(&gp[gt.p_w], (double)(gth * scale * f));
+        if (gt.p_b >= 0) atomicAdd(&gp[gt.p_b], (double)(gth * scale));
+      }
+    } else {
+      if (gt.p_w >= 0) {
+        const real v = group_sum(leader ? gth * scale * f : (real)0, 64);
+        if (lane == 0) gacc[(size_t)wave * A.n_params + gt.p_w] += v;
+      }
+      if (gt.p_b >= 0) {
+        const real v = group_sum(leader ? gth * scale : (real)0, 64);
+        if (lane == 0) gacc[(size_t)wave * A.n_params + gt.p_b] += v;
+      }
+    }
+    if (gt.feat >= 0 && leader)
+      facc[((size_t)sl * wps + (tau >> 6)) * A.n_feats + gt.feat] += gth * scale * w;
+  }
+
+  // Backward through an L1Q op: for each register bit's block, the
+  // gradients of its rotations from the correlation Q at the block output
+  // (moved back gate by gate), then psi and lam un-applied.
+  __device__ __forceinline__ void adjoint_l1q(St<real, R>& psi, St<real, R>& lam, int rec,
+                                              int lane, int wave, int Tw) {
+    const QS_K int32_t* r = kc(A.l1q) + (size_t)rec * kL1QWords;
+    static_for<LR>([&](auto J) QS_AI {
+      constexpr int j = decltype(J)::value;
+      const int bid = r[j];
+      if (bid >= 0) {  // reads psi and lam only: no state copies at the join
+        U2<real> q = q_part<j>(psi, lam);
+        const int b0 = kc(A.blk_begin)[bid], b1 = kc(A.blk_begin)[bid + 1];
+        for (int i = b1 - 1; i >= b0; --i) {
+          const int g = kc(A.blk_gates)[i];
+          const qs_gate gt = kload(A.gates, g);
+          real c = 1, sn = 0;
+          if (gt.op <= QS_OP_RZ) {
+            gate_cs(g, c, sn);
+            accum(gt, im_tr(gt.op, q), lane, wave, Tw);
+          }
+          if (i > b0) q = q_back(gt.op, c, sn, q);
+        }
+      }
+      const U2<real> ud = u_dag(block_or_id(bid));
+      g_u<j>(psi, ud);
+      g_u<j>(lam, ud);
+    });
+  }
+
+  // Apply op (its inverse when `inv`) to x. For rotations (c, s) are
+  // cos, sin of theta/2 already signed for the direction.
+  __device__ __forceinline__ void apply(St<real, R>& x, int kind, int a, int bq,
+                                        real c, real s) const {
+    switch (kind) {
+      case QS_OP_RX:
+        for_pos<LR>(a, [&](auto J) QS_AI { g_rx<decltype(J)::value>(x, c, s); });
+        break;
+      case QS_OP_RY:
+        for_pos<LR>(a, [&](auto J) QS_AI { g_ry<decltype(J)::value>(x, c, s); });
+        break;
+      case QS_OP_RZ:
+        if (a < LR)
+          for_pos<LR>(a, [&](auto J) QS_AI { g_rz<decltype(J)::value>(x, c, s); });
+        else
+          g_phase_all(x, c, tbit(a) ? s : -s);
+        break;
+      case QS_OP_X:
+        for_pos<LR>(a, [&](auto J) QS_AI { g_x<decltype(J)::value>(x); });
+        break;
+      case QS_OP_Y:
+        for_pos<LR>(a, [&](auto J) QS_AI { g_y<decltype(J)::value>(x); });
+        break;
+      case QS_OP_Z:
+        if (a < LR)
+          for_pos<LR>(a, [&](auto J) QS_AI { g_z<decltype(J)::value>(x); });
+        else
+          g_neg_if(x, tbit(a));
+        break;
+      case QS_OP_H:
+        for_pos<LR>(a, [&](auto J) QS_AI { g_h<decltype(J)::value>(x); });
+        break;
+      case QS_OP_CNOT:  // a = control, bq = target (register)
+        if (a < LR) {
+          for_pos<LR>(a, [&](auto C) QS_AI {
+            for_pos<LR>(bq, [&](auto J) QS_AI {
+              if constexpr (decltype(C)::value != decltype(J)::value)
+                g_cnot_rr<decltype(C)::value, decltype(J)::value>(x);
+            });
+          });
+        } else {
+          const bool tb = tbit(a);
+          for_pos<LR>(bq, [&](auto J) QS_AI { g_cnot_tr<decltype(J)::value>(x, tb); });
+        }
+        break;
+      case QS_OP_CZ: {
+        int lo = a < bq ? a : bq, hi = a < bq ? bq : a;
+        if (hi < LR) {
+          for_pos<LR>(lo, [&](auto A0) QS_AI {
+            for_pos<LR>(hi, [&](auto B0) QS_AI {
+              if constexpr (decltype(A0)::value < decltype(B0)::value)
+                g_cz_rr<decltype(A0)::value, decltype(B0)::value>(x);
+            });
+          });
+        } else if (lo < LR) {
+          const bool tb = tbit(hi);
+          for_pos<LR>(lo, [&](auto A0) QS_AI { g_cz_rt<decltype(A0)::value>(x, tb); });
+        } else {
+          g_neg_if(x, tbit(lo) && tbit(hi));
+        }
+        break;
+      }
+      default:
+        break;
+    }
+  }
+
+  __device__ __forceinline__ real grad_partial(int kind, int a,
+                                               const St<real, R>& p,
+                                               const St<real, R>& l) const {
+    real v = 0;
+    switch (kind) {
+      case QS_OP_RX:
+        for_pos<LR>(a, [&](auto J) QS_AI { v = gr_x<decltype(J)::value>(p, l); });
+        break;
+      case QS_OP_RY:
+        for_pos<LR>(a, [&](auto J) QS_AI { v = gr_y<decltype(J)::value>(p, l); });
+        break;
+      default:  // RZ
+        if (a < LR)
+          for_pos<LR>(a, [&](auto J) QS_AI { v = gr_z<decltype(J)::value>(p, l); });
+        else
+          v = tbit(a) ? -gr_all(p, l) : gr_all(p, l);
+        break;
+    }
+    return v;
+  }
+};
+
+// Common prologue: LDS carve-up and angle tables.
+// `blk` is the global index of the block's first sample. Gradient sums are
+// kept in per-wave LDS slots (each written by one lane of one wave) and added
+// in a fixed order at the end, so the adjoint is bitwise reproducible.
+template <typename real, int LR, bool FLY>
+__device__ __forceinline__ void setup(Ctx<real, LR, FLY>& C, const Args<real>& A,
+                                      unsigned char* smem, bool adjoint, int64_t blk) {
+  const int tid = threadIdx.x;
+  const int N = 1 << A.n;
+  C.tau = tid & ((1 << A.t) - 1);
+  C.sl = tid >> A.t;
+  C.b = blk + C.sl;
+  C.active = C.b < A.B;
+  C.row = C.b >> A.ob;
+  if (A.tile_q == nullptr) {
+    C.base = C.b * (int64_t)N;
+    C.dep_tau = 0;
+  } else {
+    const int64_t outer = C.b & ((1ll << A.ob) - 1);
+    int64_t o = C.row << A.n_tot;
+    for (int k = 0; k < A.ob; ++k)
+      if ((outer >> k) & 1) o |= 1ll << kc(A.outer_q)[k];
+    C.base = o;
+    uint32_t d = 0;
+    for (int j = 0; j < A.t; ++j)
+      if ((C.tau >> j) & 1) d |= 1u << kc(A.tile_q)[j];
+    C.dep_tau = d;
+  }
+  using v2 = typename V2<real>::T;
+  v2* st = reinterpret_cast<v2*>(smem);
+  C.lds = st + (size_t)C.sl * N;
+  C.salt = ((uint32_t)C.sl << A.t) & 31u & (uint32_t)(N - 1);
+  real* tail = reinterpret_cast<real*>(st + (size_t)A.S * N);
+  C.ang_sh = tail;
+  C.ang_ps = C.ang_sh + 2 * (size_t)A.n_gates;
+  C.fu_sh = C.ang_ps + (FLY ? 0 : 2 * (size_t)A.n_slots * A.S);
+  C.gacc = C.fu_sh + 8 * (size_t)A.n_fu;
+  C.wps = A.t > 6 ? (1 << (A.t - 6)) : 1;
+  const int waves = blockDim.x >> 6;
+  C.facc = C.gacc + (A.per_sample_params ? 0 : (size_t)waves * A.n_params);
+
+  // Shared angles, by gate.
+  for (int g = tid; g < A.n_gates; g += blockDim.x) {
+    const qs_gate gt = A.gates[g];
+    real c = 1, s = 0;
+    if (gt.op <= QS_OP_RZ && A.gate_slot[g] < 0) {
+      real th = theta_of(A, gt, 0);  // shared: no feature, shared params
+      fsincos(th * (real)0.5, &s, &c);
+    }
+    C.ang_sh[2 * g] = c;
+    C.ang_sh[2 * g + 1] = s;
+  }
+  for (int i = tid; i < (FLY ? 0 : A.n_slots * A.S); i += blockDim.x) {
+    const int slot = i / A.S, s_l = i % A.S;
+    const int64_t bb = blk + s_l;
+    real c = 1, s = 0;
+    if (bb < A.B) {
+      qs_gate gt = kload(A.gates, kc(A.slot_gate)[slot]);
+      real th = theta_of(A, gt, bb >> A.ob);
+      fsincos(th * (real)0.5, &s, &c);
+    }
+    C.ang_ps[2 * (size_t)i] = c;
+    C.ang_ps[2 * (size_t)i + 1] = s;
+  }
+  if (adjoint) {
+    if (!A.per_sample_params)
+      for (int i = tid; i < waves * A.n_params; i += blockDim.x) C.gacc[i] = 0;
+    for (int i = tid; i < A.S * C.wps * A.n_feats; i += blockDim.x) C.facc[i] = 0;
+  }
+  __syncthreads();
+  // Fused matrices of the blocks whose angles are shared.
+  for (int bid = tid; bid < A.n_blocks; bid += blockDim.x) {
+    const int fu = A.blk_fu[bid];
+    if (fu < 0) continue;
+    U2<real> u{1, 0, 0, 0, 0, 0, 1, 0};
+    for (int i = A.blk_begin[bid]; i < A.blk_begin[bid + 1]; ++i) {
+      const int g = A.blk_gates[i];
+      u = u_mul(gate_u<real>(A.gates[g].op, C.ang_sh[2 * g], C.ang_sh[2 * g + 1]), u);
+    }
+    real* f = C.fu_sh + 8 * (size_t)fu;
+    f[0] = u.r00; f[1] = u.i00; f[2] = u.r01; f[3] = u.i01;
+    f[4] = u.r10; f[5] = u.i10; f[6] = u.r11; f[7] = u.i11;
+  }
+  __syncthreads();
+}
+
+template <typename real, int LR>
+__device__ __forceinline__ const QS_K uint8_t* seg_map(const Args<real>& A, int s) {
+  return kc(A.seg_map) + (size_t)s * kMapStride;
+}
+template <typename real>
+__device__ __forceinline__ bool map_changed(const Args<real>& A, int s) {
+  const QS_K uint32_t* m = reinterpret_cast<const QS_K uint32_t*>(kc(A.seg_map));
+  bool ch = false;
+#pragma unroll
+  for (int w = 0; w < kMapStride / 4; ++w)
+    ch |= m[(size_t)(s - 1) * (kMapStride / 4) + w] != m[(size_t)s * (kMapStride / 4) + w];
+  return ch;
+}
+
+// ------------------------------------------------------------------ forward
+template <typename real, int LR, bool FLY = false>
+__device__ __forceinline__ void forward_body(const Args<real>& A, unsigned char* smem,
+                                             int64_t blk) {
+  constexpr int R = 1 << LR;
+  Ctx<real, LR, FLY> C(A);
+  setup<real, LR, FLY>(C, A, smem, false, blk);
+
+  St<real, R> x;
+  C.load_state(x, A.state, seg_map<real, LR>(A, 0));
+  const int nseg = A.nseg;
+  const QS_K int32_t* seg_begin = kc(A.seg_begin);
+  for (int s = 0; s < nseg; ++s) {
+    if (s > 0 && map_changed(A, s))
+      C.remap(x, seg_map<real, LR>(A, s - 1), seg_map<real, LR>(A, s));
+    const int e = seg_begin[s + 1];
+    for (int o = seg_begin[s]; o < e; ++o) {
+      const SvOp cur = kload(A.ops, o);
+      const int kind = uni(cur.kind);
+      if (kind == kOpL1Q) {
+        C.apply_l1q(x, cur.gate, false);
+      } else if (kind == kOpDiag) {
+        C.apply_diag(x, cur.gate);
+      } else {
+        real c = 1, sn = 0;
+        if (kind <= QS_OP_RZ) C.gate_cs(cur.gate, c, sn);
+        C.apply(x, kind, uni(cur.a), uni(cur.b), c, sn);
+      }
+    }
+    const int ck = kc(A.seg_ckpt)[s];
+    if (ck >= 0 && A.ckpt != nullptr)
+      C.store_state(x, A.ckpt + (size_t)ck * A.B * (2ull << A.n),
+                    seg_map<real, LR>(A, s));
+  }
+  const QS_K uint8_t* last = seg_map<real, LR>(A, nseg - 1);
+  C.store_state(x, A.state, last);
+
+  if (A.expz != nullptr) {
+    // <Z_q> partials in FP64, reduced over the sample's threads.
+    const int Tw = (1 << A.t) < 64 ? (1 << A.t) : 64;
+    const int nw = (1 << A.t) / Tw;  // waves per sample
+    double* red = reinterpret_cast<double*>(C.lds);
+    sample_sync(A.t);
+    double tot = 0;
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+      tot += (double)x.re[k] * x.re[k] + (double)x.im[k] * x.im[k];
+    const int wave_in_sample = C.tau / Tw;
+    for (int q = 0; q < A.n; ++q) {
+      int p = 0;
+      for (int i = 0; i < A.n; ++i)
+        if (last[i] == q) p = i;
+      p = uni(p);
+      double z = 0;
+      if (p < LR) {
+        for_pos<LR>(p, [&](auto J) QS_AI {
+#pragma unroll
+          for (int k = 0; k < R; ++k) {
+            double pr = (double)x.re[k] * x.re[k] + (double)x.im[k] * x.im[k];
+            z += (k & (1 << decltype(J)::value)) ? -pr : pr;
+          }
+        });
+      } else {
+        z = C.tbit(p) ? -tot : tot;
+      }
+      z = group_sum(z, Tw);
+      if ((C.tau & (Tw - 1)) == 0) red[(size_t)wave_in_sample * A.n + q] = z;
+    }
+    sample_sync(A.t);
+    if (C.active)
+      for (int q = C.tau; q < A.n; q += (1 << A.t)) {
+        double z = 0;
+        for (int w = 0; w < nw; ++w) z += red[(size_t)w * A.n + q];
+        A.expz[(size_t)C.b * A.n + q] = z;
+      }
+  }
+}
+
+// ------------------------------------------------------------------ adjoint
+template <typename real, int LR, bool FLY = false>
+__device__ __forceinline__ void adjoint_body(const Args<real>& A, unsigned char* smem,
+                                             int64_t blk) {
+  constexpr int R = 1 << LR;
+  Ctx<real, LR, FLY> C(A);
+  setup<real, LR, FLY>(C, A, smem, true, blk);
+  const int nseg = A.nseg;
+  const QS_K uint8_t* last = seg_map<real, LR>(A, nseg - 1);
+
+  St<real, R> psi, lam;
+  C.load_state(psi, A.state, last);
+  if (A.dstate != nullptr) {
+    C.load_state(lam, A.dstate, last);
+  } else {
+    // lam = sum_q g_q Z_q psi: coefficient of amplitude with logical index L
+    // is sum_q g_q - 2 sum_{q : bit q of L = 1} g_q.
+    double base = 0;
+    double w[LR > 0 ? LR : 1];
+#pragma unroll
+    for (int j = 0; j < LR; ++j) w[j] = 0;
+    if (C.active) {
+      const double* g = A.dexpz + (size_t)C.b * A.n;
+      for (int p = 0; p < A.n; ++p) {
+        const double gq = g[last[p]];
+        base += gq;
+        if (p >= LR && C.tbit(p)) base -= 2 * gq;
+      }
+#pragma unroll
+      for (int j = 0; j < LR; ++j) w[j] = 2 * g[last[j]];
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      double cf = C.active ? base : 0.0;
+#pragma unroll
+      for (int j = 0; j < LR; ++j)
+        if (k & (1 << j)) cf -= w[j];
+      lam.re[k] = (real)cf * psi.re[k];
+      lam.im[k] = (real)cf * psi.im[k];
+    }
+  }
+
+  const int Tw = (1 << A.t) < 64 ? (1 << A.t) : 64;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const QS_K int32_t* seg_begin = kc(A.seg_begin);
+  for (int s = nseg - 1; s >= 0; --s) {
+    const int ck = kc(A.seg_ckpt)[s];
+    if (ck >= 0 && A.ckpt != nullptr)  // re-anchor psi to the stored state
+      C.load_state(psi, A.ckpt + (size_t)ck * A.B * (2ull << A.n),
+                   seg_map<real, LR>(A, s));
+    const int beg = seg_begin[s];
+    for (int o = seg_begin[s + 1] - 1; o >= beg; --o) {
+      const SvOp cur = kload(A.ops, o);
+      const int kind = uni(cur.kind), a = uni(cur.a), bq = uni(cur.b);
+      if (kind == kOpL1Q) {
+        C.adjoint_l1q(psi, lam, cur.gate, lane, wave, Tw);
+        continue;
+      }
+      if (kind == kOpDiag) {  // its own inverse
+        C.apply_diag(psi, cur.gate);
+        C.apply_diag(lam, cur.gate);
+        continue;
+      }
+      real c = 1, sn = 0;
+      if (kind <= QS_OP_RZ) {
+        C.gate_cs(cur.gate, c, sn);
+        const qs_gate gt = kload(A.gates, cur.gate);
+        C.accum(gt, C.grad_partial(kind, a, psi, lam), lane, wave, Tw);
+        sn = -sn;  // inverse rotation
+      }
+      C.apply(psi, kind, a, bq, c, sn);
+      C.apply(lam, kind, a, bq, c, sn);
+    }
+    if (s > 0 && map_changed(A, s)) {
+      C.remap(psi, seg_map<real, LR>(A, s), seg_map<real, LR>(A, s - 1));
+      C.remap(lam, seg_map<real, LR>(A, s), seg_map<real, LR>(A, s - 1));
+    }
+  }
+  if (A.out_psi != nullptr) C.store_state(psi, A.out_psi, seg_map<real, LR>(A, 0));
+  if (A.out_lam != nullptr) C.store_state(lam, A.out_lam, seg_map<real, LR>(A, 0));
+  __syncthreads();
+  const int waves = blockDim.x >> 6;
+  if (!A.per_sample_params)
+    for (int i = threadIdx.x; i < A.n_params; i += blockDim.x) {
+      real t = 0;
+      for (int w = 0; w < waves; ++w) t += C.gacc[(size_t)w * A.n_params + i];
+      A.ws_partials[(size_t)blockIdx.x * A.n_params + i] = t;
+    }
+  if (A.grad_feats != nullptr)
+    for (int i = threadIdx.x; i < A.S * A.n_feats; i += blockDim.x) {
+      const int sl = i / A.n_feats, f = i % A.n_feats;
+      const int64_t bb = blk + sl;
+      if (bb >= A.B) continue;
+      real t = 0;
+      for (int w = 0; w < C.wps; ++w) t += C.facc[((size_t)sl * C.wps + w) * A.n_feats + f];
+      double* dst = &A.grad_feats[(size_t)(bb >> A.ob) * A.n_feats + f];
+      if (A.tile_q != nullptr)
+        atomicAdd(dst, (double)t);  // several tiles share a batch row
+      else
+        *dst = t;
+    }
+}
+
+template <typename real, int LR, int MAXT>
+__global__ void __launch_bounds__(MAXT) sv_forward(Args<real> A) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  forward_body<real, LR>(A, smem, (int64_t)blockIdx.x * A.S);
+}
+
+template <typename real, int LR, int MAXT>
+__global__ void __launch_bounds__(MAXT) sv_adjoint(Args<real> A) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  adjoint_body<real, LR>(A, smem, (int64_t)blockIdx.x * A.S);
+}
+
+// Uneven batches in one persistent launch: workgroups pull work items (a
+// class of identically-structured circuits and a run of S of its circuits)
+// from an atomic counter until the queue is empty; items are ordered longest
+// first. Every workgroup runs the same engine as the batched kernels, with
+// per-circuit angles computed in place (no per-sample LDS table).
+template <typename real, int LR, int MAXT, bool ADJ>
+__global__ void __launch_bounds__(MAXT)
+sv_program(const ProgClass* classes, const ProgItem* items, int n_items,
+           int* counter, const real* params, real* states, double* expz,
+           const double* dexpz, double* grad_params) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int item_sh;
+  for (;;) {
+    if (threadIdx.x == 0) item_sh = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = item_sh;
+    __syncthreads();
+    if (it >= n_items) break;  // every wave of the workgroup sees the same it
+    const ProgItem w = kload(items, it);
+    const ProgClass cd = kload(classes, w.cls);
+    Args<real> A;
+    A.seg_map = cd.seg_map;
+    A.seg_begin = cd.seg_begin;
+    A.seg_ckpt = cd.seg_ckpt;
+    A.ops = cd.ops;
+    A.gates = cd.gates;
+    A.gate_slot = cd.gate_slot;
+    A.slot_gate = cd.slot_gate;
+    A.l1q = cd.l1q;
+    A.diag = cd.diag;
+    A.blk_begin = cd.blk_begin;
+    A.blk_gates = cd.blk_gates;
+    A.blk_fu = cd.blk_fu;
+    A.n_blocks = cd.n_blocks;
+    A.n_fu = cd.n_fu;
+    A.n = cd.n;
+    A.t = cd.t;
+    A.nseg = cd.nseg;
+    A.n_gates = cd.n_gates;
+    A.n_slots = cd.n_slots;
+    A.n_params = cd.n_params;
+    A.n_feats = 0;
+    A.S = cd.S;
+    A.per_sample_params = 1;
+    const int64_t left = cd.count - w.first;
+    A.B = left < cd.S ? left : cd.S;
+    A.n_tot = 0;
+    A.ob = 0;
+    A.tile_q = nullptr;
+    A.outer_q = nullptr;
+    A.out_psi = nullptr;
+    A.out_lam = nullptr;
+    const int64_t first = w.first;
+    A.params = params + cd.param_off + first * cd.n_params;
+    A.feats = nullptr;
+    A.state = states + 2 * (cd.state_off + (first << cd.n));
+    A.expz = expz ? expz + cd.expz_off + first * cd.n : nullptr;
+    A.ckpt = nullptr;
+    A.dexpz = dexpz ? dexpz + cd.expz_off + first * cd.n : nullptr;
+    A.dstate = nullptr;
+    A.ws_partials = nullptr;
+    A.grad_params = grad_params ? grad_params + cd.param_off + first * cd.n_params : nullptr;
+    A.grad_feats = nullptr;
+    if (ADJ)
+      adjoint_body<real, LR, true>(A, smem, 0);
+    else
+      forward_body<real, LR, true>(A, smem, 0);
+    __syncthreads();  // the next item reuses the LDS
+  }
+}
+
+
+template <typename real>
+Args<real> make_args(const SvLaunch& L) {
+  const SvDevPlan& p = *L.p;
+  Args<real> A;
+  A.seg_map = p.seg_map;
+  A.seg_begin = p.seg_begin;
+  A.seg_ckpt = p.seg_ckpt;
+  A.ops = p.ops;
+  A.gates = p.gates;
+  A.gate_slot = p.gate_slot;
+  A.slot_gate = p.slot_gate;
+  A.l1q = p.l1q;
+  A.diag = p.diag;
+  A.blk_begin = p.blk_begin;
+  A.blk_gates = p.blk_gates;
+  A.blk_fu = p.blk_fu;
+  A.n_blocks = p.n_blocks;
+  A.n_fu = p.n_fu;
+  A.n = p.n;
+  A.t = p.t;
+  A.nseg = p.nseg;
+  A.n_gates = p.n_gates;
+  A.n_slots = p.n_slots;
+  A.n_params = p.n_params;
+  A.n_feats = p.n_features;
+  A.S = L.shape.samples_per_block;
+  A.per_sample_params = L.per_sample_params;
+  A.B = L.B << L.ob;
+  A.n_tot = L.n_tot;
+  A.ob = L.ob;
+  A.tile_q = L.tile_q;
+  A.outer_q = L.outer_q;
+  A.out_psi = static_cast<real*>(L.out_psi);
+  A.out_lam = static_cast<real*>(L.out_lam);
+  A.params = static_cast<const real*>(L.params);
+  A.feats = static_cast<const real*>(L.feats);
+  A.state = static_cast<real*>(L.state);
+  A.expz = L.expz;
+  A.ckpt = static_cast<real*>(L.ckpt);
+  A.dexpz = L.dexpz;
+  A.dstate = static_cast<const real*>(L.dstate);
+  A.ws_partials = static_cast<real*>(L.ws_partials);
+  A.grad_params = L.grad_params;
+  A.grad_feats = L.grad_feats;
+  return A;
+}
+
+template <typename real, int LR, int MAXT, bool ADJ>
+int launch_one(const SvLaunch& L) {
+  Args<real> A = make_args<real>(L);
+  const int64_t grid = (A.B + A.S - 1) / A.S;
+  if (grid <= 0) return QS_OK;
+  dim3 g((unsigned)grid), blk((unsigned)L.shape.block_threads);
+  hipStream_t st = static_cast<hipStream_t>(L.stream);
+  // Only the kernel of this direction is instantiated.
+  auto kern = [] {
+    if constexpr (ADJ)
+      return sv_adjoint<real, LR, MAXT>;
+    else
+      return sv_forward<real, LR, MAXT>;
+  }();
+  if (L.shape.lds_bytes > 65536) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)L.shape.lds_bytes) != hipSuccess)
+      return QS_ERR_LAUNCH;
+  }
+  hipLaunchKernelGGL(kern, g, blk, (size_t)L.shape.lds_bytes, st, A);
+  return hipGetLastError() == hipSuccess ? QS_OK : QS_ERR_LAUNCH;
+}
+
+template <typename real, int LR, int MAXT>
+int launch_prog(const ProgLaunch& L, bool adjoint) {
+  hipStream_t st = static_cast<hipStream_t>(L.stream);
+  auto kern = adjoint ? sv_program<real, LR, MAXT, true> : sv_program<real, LR, MAXT, false>;
+  if (L.lds_bytes > 65536 &&
+      hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)L.lds_bytes) != hipSuccess)
+    return QS_ERR_LAUNCH;
+  hipLaunchKernelGGL(kern, dim3((unsigned)L.grid), dim3((unsigned)L.block),
+                     (size_t)L.lds_bytes, st, L.classes, L.items, L.n_items, L.counter,
+                     static_cast<const real*>(L.params), static_cast<real*>(L.states),
+                     L.expz, L.dexpz, L.grad_params);
+  return hipGetLastError() == hipSuccess ? QS_OK : QS_ERR_LAUNCH;
+}
+
+}  // namespace
+
+// Per-(element type, direction) dispatchers over the register exponent r.
+int sv_c64_forward(const SvLaunch& L);
+int sv_c64_adjoint(const SvLaunch& L);
+int sv_c128_forward(const SvLaunch& L);
+int sv_c128_adjoint(const SvLaunch& L);
+
+}  // namespace qs

@@ -1,0 +1,17 @@
+// Persistent uneven-batch instantiations of the register engine.
+#include "sv_engine.h"
+
+namespace qs {
+
+int launch_program(int dtype, const ProgLaunch& L, bool adjoint) {
+  if (L.block != 512) return QS_ERR_UNSUPPORTED;
+  if (dtype == QS_C64) {
+    if (L.r == 5) return launch_prog<float, 5, 512>(L, adjoint);
+    if (L.r == 4) return launch_prog<float, 4, 512>(L, adjoint);
+    return QS_ERR_UNSUPPORTED;
+  }
+  if (L.r == 4) return launch_prog<double, 4, 512>(L, adjoint);
+  return QS_ERR_UNSUPPORTED;
+}
+
+}  // namespace qs

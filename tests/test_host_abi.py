@@ -129,10 +129,14 @@ def test_plans_of_workloads(key):
     dt = N.QS_C128 if w.dtype == "c128" else N.QS_C64
     info = _check_plan(w.circuit, dt)
     assert info["path"] == N.QS_PATH_FUSED
+    assert info["n_engine_ops"] <= info["n_ops"]
     if key == "c2":
         # one re-placement per layer: 8 layers of 10-qubit rotations, 5
         # register qubits, commuting gates reordered across the CZ ring
         assert info["n_remaps"] == 8
+        # layer ops: per layer the 30 rotations become two fused-block ops
+        # (5 register bits each) and the 10 CZs at most two sign-pattern ops
+        assert info["n_engine_ops"] <= 4 * 8
 
 
 @pytest.mark.parametrize("n", list(range(1, 15)))
