@@ -402,14 +402,23 @@ __device__ __forceinline__ U2<real> q_part(const St<real, R>& p, const St<real, 
     const int k1 = k | (1 << J);
     const real p0r = p.re[k], p0i = p.im[k], p1r = p.re[k1], p1i = p.im[k1];
     const real l0r = l.re[k], l0i = l.im[k], l1r = l.re[k1], l1i = l.im[k1];
-    q.r00 += p0r * l0r + p0i * l0i;
-    q.i00 += p0i * l0r - p0r * l0i;
-    q.r01 += p0r * l1r + p0i * l1i;
-    q.i01 += p0i * l1r - p0r * l1i;
-    q.r10 += p1r * l0r + p1i * l0i;
-    q.i10 += p1i * l0r - p1r * l0i;
-    q.r11 += p1r * l1r + p1i * l1i;
-    q.i11 += p1i * l1r - p1r * l1i;
+    // one fused multiply-add per product into the running sums
+    q.r00 = p0r * l0r + q.r00;
+    q.r00 = p0i * l0i + q.r00;
+    q.i00 = p0i * l0r + q.i00;
+    q.i00 = -p0r * l0i + q.i00;
+    q.r01 = p0r * l1r + q.r01;
+    q.r01 = p0i * l1i + q.r01;
+    q.i01 = p0i * l1r + q.i01;
+    q.i01 = -p0r * l1i + q.i01;
+    q.r10 = p1r * l0r + q.r10;
+    q.r10 = p1i * l0i + q.r10;
+    q.i10 = p1i * l0r + q.i10;
+    q.i10 = -p1r * l0i + q.i10;
+    q.r11 = p1r * l1r + q.r11;
+    q.r11 = p1i * l1i + q.r11;
+    q.i11 = p1i * l1r + q.i11;
+    q.i11 = -p1r * l1i + q.i11;
   }
   return q;
 }
@@ -633,46 +642,79 @@ struct Ctx {
     read_mapped(x, to);
   }
 
-  // Global offset (complex elements) of local amplitude i = tau + x, x a
-  // multiple of T: the sample's base plus the local bits deposited onto the
-  // tile's qubits (identity when not tiled).
-  __device__ __forceinline__ int64_t addr(int x) const {
-    if (A.tile_q == nullptr) return base + tau + x;
-    int64_t d = dep_tau;
-    for (int j = A.t; j < A.n; ++j)
-      if ((x >> j) & 1) d |= 1ll << kc(A.tile_q)[j];
-    return base + d;
+  // HBM offsets of the R amplitudes this thread moves between HBM and LDS:
+  // element u (local index tau + u T) sits at a0 + sum of off[j] over the set
+  // bits j of u. Batched: off[j] = T << j. Tiled: local bit t + j is the
+  // tile's global qubit tile_q[t + j].
+  __device__ __forceinline__ int64_t hbm_a0() const {
+    return A.tile_q == nullptr ? base + tau : base + dep_tau;
+  }
+  __device__ __forceinline__ void hbm_offsets(int64_t* off) const {
+#pragma unroll
+    for (int j = 0; j < LR; ++j)
+      off[j] = A.tile_q == nullptr ? ((int64_t)1 << (A.t + j))
+                                   : ((int64_t)1 << kc(A.tile_q)[A.t + j]);
   }
 
-  // HBM (logical order) -> LDS -> registers under placement `map`.
+  // HBM (logical order) -> LDS -> registers under placement `map`. All R
+  // loads of a thread are issued before the first wait.
   __device__ __forceinline__ void load_state(St<real, R>& x, const real* src,
                                              const QS_K uint8_t* map) {
-    const int N = 1 << A.n, T = 1 << A.t;
-    sample_sync(A.t);
     const v2* s2 = reinterpret_cast<const v2*>(src);
-    for (int i = tau; i < N; i += T) {
+    int64_t off[LR > 0 ? LR : 1];
+    hbm_offsets(off);
+    const int64_t a0 = hbm_a0();
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      int64_t o = 0;
+#pragma unroll
+      for (int j = 0; j < LR; ++j)
+        if (u & (1 << j)) o += off[j];
       v2 v;
-      if (active) {
-        v = s2[addr(i - tau)];
-      } else {
-        v.x = 0;
-        v.y = 0;
-      }
-      lds[swz((uint32_t)i) ^ salt] = v;
+      v.x = 0;
+      v.y = 0;
+      if (active) v = s2[a0 + o];
+      x.re[u] = v.x;  // staging only: read_mapped below sets the placement
+      x.im[u] = v.y;
+    }
+    sample_sync(A.t);
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      v2 v;
+      v.x = x.re[u];
+      v.y = x.im[u];
+      lds[swz((uint32_t)(tau + (u << A.t))) ^ salt] = v;
     }
     sample_sync(A.t);
     read_mapped(x, map);
   }
-  // Registers under `map` -> LDS -> HBM (logical order).
+  // Registers under `map` -> LDS -> HBM (logical order), in runs of 8.
   __device__ __forceinline__ void store_state(const St<real, R>& x, real* dst,
                                               const QS_K uint8_t* map) {
-    const int N = 1 << A.n, T = 1 << A.t;
     sample_sync(A.t);
     write_mapped(x, map);
     sample_sync(A.t);
-    if (active) {
-      v2* d2 = reinterpret_cast<v2*>(dst);
-      for (int i = tau; i < N; i += T) d2[addr(i - tau)] = lds[swz((uint32_t)i) ^ salt];
+    if (!active) return;
+    v2* d2 = reinterpret_cast<v2*>(dst);
+    int64_t off[LR > 0 ? LR : 1];
+    hbm_offsets(off);
+    const int64_t a0 = hbm_a0();
+    constexpr int W = R < 8 ? R : 8;
+#pragma unroll
+    for (int u0 = 0; u0 < R; u0 += W) {
+      v2 v[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w)
+        v[w] = lds[swz((uint32_t)(tau + ((u0 + w) << A.t))) ^ salt];
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const int u = u0 + w;
+        int64_t o = 0;
+#pragma unroll
+        for (int j = 0; j < LR; ++j)
+          if (u & (1 << j)) o += off[j];
+        d2[a0 + o] = v[w];
+      }
     }
   }
 
@@ -1058,25 +1100,33 @@ __device__ __forceinline__ void forward_body(const Args<real>& A, unsigned char*
     const int nw = (1 << A.t) / Tw;  // waves per sample
     double* red = reinterpret_cast<double*>(C.lds);
     sample_sync(A.t);
+    // tot = sum_k |x_k|^2 and hi[j] = the part with register bit j set, so a
+    // register-bit qubit reads tot - 2 hi[j] and a thread-bit one +-tot.
     double tot = 0;
+    double hi[LR > 0 ? LR : 1];
 #pragma unroll
-    for (int k = 0; k < R; ++k)
-      tot += (double)x.re[k] * x.re[k] + (double)x.im[k] * x.im[k];
+    for (int j = 0; j < LR; ++j) hi[j] = 0;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const double pk = (double)x.re[k] * x.re[k] + (double)x.im[k] * x.im[k];
+      tot += pk;
+#pragma unroll
+      for (int j = 0; j < LR; ++j)
+        if (k & (1 << j)) hi[j] += pk;
+    }
     const int wave_in_sample = C.tau / Tw;
     for (int q = 0; q < A.n; ++q) {
       int p = 0;
       for (int i = 0; i < A.n; ++i)
         if (last[i] == q) p = i;
       p = uni(p);
-      double z = 0;
+      double z;
       if (p < LR) {
-        for_pos<LR>(p, [&](auto J) QS_AI {
+        double h = hi[0];
 #pragma unroll
-          for (int k = 0; k < R; ++k) {
-            double pr = (double)x.re[k] * x.re[k] + (double)x.im[k] * x.im[k];
-            z += (k & (1 << decltype(J)::value)) ? -pr : pr;
-          }
-        });
+        for (int j = 1; j < LR; ++j)
+          if (p == j) h = hi[j];
+        z = tot - 2 * h;
       } else {
         z = C.tbit(p) ? -tot : tot;
       }
