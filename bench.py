@@ -51,6 +51,39 @@ FLOPS_ROT_FWD = 6
 FLOPS_ROT_ADJ = 16
 
 
+# Sources that decide what the adjoint kernel does; the measured HBM traffic
+# in profiles/ is only reported while their hash matches the one recorded
+# with the counters.
+KERNEL_SOURCES = ["paper_2509_25075_amd/csrc/sv_engine.h",
+                  "paper_2509_25075_amd/csrc/sv_c64_adj.hip",
+                  "paper_2509_25075_amd/csrc/qs_internal.h",
+                  "paper_2509_25075_amd/csrc/planner.cpp",
+                  "include/qs.h"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the adjoint kernel from the FETCH_SIZE /
+    WRITE_SIZE counters recorded under profiles/ (scaled by a plain copy of
+    known size), or None when absent or taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"sv_adjoint_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_sha256") != kernel_source_hash():
+        return None
+    return d["bytes_per_launch"]
+
+
 def _rotations(circuit):
     import numpy as np
     return int(np.isin(circuit.gates["op"], (0, 1, 2)).sum())
@@ -112,6 +145,8 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--source-hash", action="store_true",
+                    help="print the hash of the adjoint kernel's sources and exit")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (use the default register split)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -119,6 +154,9 @@ def main():
                          "(5 launches) and exit: the known-size kernel whose "
                          "FETCH_SIZE / WRITE_SIZE counters scale the engine's")
     args = ap.parse_args()
+    if args.source_hash:
+        print(kernel_source_hash())
+        return
     if args.copy_calibration:
         import torch
         n = args.copy_calibration << 18  # float32 elements
@@ -234,7 +272,7 @@ def main():
         "roofline": None if achieved is None else {
             "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": None, "kernel": "sv_adjoint",
+            "traffic": measured_traffic(args.workload), "kernel": "sv_adjoint",
             "kernel_ms": adj_ms / 1.0, "launches_per_step": n_adj_per_step,
             "algorithmic_flops_per_launch": flops_adj},
         "cpu_baseline": cpu,

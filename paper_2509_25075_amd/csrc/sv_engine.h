@@ -423,6 +423,48 @@ __device__ __forceinline__ U2<real> q_part(const St<real, R>& p, const St<real, 
   return q;
 }
 
+// One pass over the pairs of register bit J: the correlation Q of the
+// incoming psi and lam (as q_part), and psi <- V psi, lam <- V lam. Each
+// pair's old values die as soon as its new values exist, so the pass needs
+// no second copy of either state.
+template <int J, typename real, int R>
+__device__ __forceinline__ U2<real> q_and_apply(St<real, R>& p, St<real, R>& l,
+                                                const U2<real>& v) {
+  U2<real> q{0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    if (k & (1 << J)) continue;
+    const int k1 = k | (1 << J);
+    const real p0r = p.re[k], p0i = p.im[k], p1r = p.re[k1], p1i = p.im[k1];
+    const real l0r = l.re[k], l0i = l.im[k], l1r = l.re[k1], l1i = l.im[k1];
+    q.r00 = p0r * l0r + q.r00;
+    q.r00 = p0i * l0i + q.r00;
+    q.i00 = p0i * l0r + q.i00;
+    q.i00 = -p0r * l0i + q.i00;
+    q.r01 = p0r * l1r + q.r01;
+    q.r01 = p0i * l1i + q.r01;
+    q.i01 = p0i * l1r + q.i01;
+    q.i01 = -p0r * l1i + q.i01;
+    q.r10 = p1r * l0r + q.r10;
+    q.r10 = p1i * l0i + q.r10;
+    q.i10 = p1i * l0r + q.i10;
+    q.i10 = -p1r * l0i + q.i10;
+    q.r11 = p1r * l1r + q.r11;
+    q.r11 = p1i * l1i + q.r11;
+    q.i11 = p1i * l1r + q.i11;
+    q.i11 = -p1r * l1i + q.i11;
+    p.re[k] = v.r00 * p0r - v.i00 * p0i + v.r01 * p1r - v.i01 * p1i;
+    p.im[k] = v.r00 * p0i + v.i00 * p0r + v.r01 * p1i + v.i01 * p1r;
+    p.re[k1] = v.r10 * p0r - v.i10 * p0i + v.r11 * p1r - v.i11 * p1i;
+    p.im[k1] = v.r10 * p0i + v.i10 * p0r + v.r11 * p1i + v.i11 * p1r;
+    l.re[k] = v.r00 * l0r - v.i00 * l0i + v.r01 * l1r - v.i01 * l1i;
+    l.im[k] = v.r00 * l0i + v.i00 * l0r + v.r01 * l1i + v.i01 * l1r;
+    l.re[k1] = v.r10 * l0r - v.i10 * l0i + v.r11 * l1r - v.i11 * l1i;
+    l.im[k1] = v.r10 * l0i + v.i10 * l0r + v.r11 * l1i + v.i11 * l1r;
+  }
+  return q;
+}
+
 // Im Tr(P Q) for the rotation generator P of `kind`.
 template <typename real>
 __device__ __forceinline__ real im_tr(int kind, const U2<real>& q) {
@@ -777,7 +819,7 @@ struct Ctx {
 
   // DIAG: the sign (-1)^(sum over the CZ pairs of bit_a bit_b) of every
   // amplitude, built per thread as a mask over its register index k.
-  __device__ __forceinline__ void apply_diag(St<real, R>& x, int rec) const {
+  __device__ __forceinline__ uint32_t diag_mask(int rec) const {
     const QS_K uint32_t* d = kc(A.diag) + (size_t)rec * kDiagWords;
     const uint32_t tb = (uint32_t)tau;
     uint32_t par = __builtin_popcount(tb & d[1]);
@@ -789,6 +831,10 @@ struct Ctx {
 #pragma unroll
     for (int j = 0; j < LR; ++j)
       if (__builtin_popcount(tb & d[2 + j]) & 1) m ^= pat[j];
+    return m;
+  }
+  __device__ __forceinline__ void apply_diag(St<real, R>& x, int rec) const {
+    const uint32_t m = diag_mask(rec);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const uint32_t bit = (m >> k) & 1u;
@@ -796,10 +842,12 @@ struct Ctx {
       x.im[k] = flip_sign(x.im[k], bit);
     }
   }
-
   // Adds this thread's partial dL/dtheta of rotation gate `gt` (gate index g)
   // to the gradient sums: shared parameters through per-wave LDS slots,
-  // per-sample parameter sets with FP64 atomics, features per sample.
+  // per-sample parameter sets with FP64 atomics, features per sample. Each
+  // LDS slot has a single writer (one lane of one wave), so its LDS atomic
+  // adds (which need no wait) happen in program order: the sums stay
+  // bitwise reproducible.
   __device__ __forceinline__ void accum(const qs_gate& gt, real part, int lane, int wave,
                                         int Tw) {
     const real scale = (real)gt.scale;
@@ -808,8 +856,8 @@ struct Ctx {
       const real v = group_sum(part, 64);
       if (lane == 0) {
         real* g = gacc + (size_t)wave * A.n_params;
-        if (gt.p_w >= 0) g[gt.p_w] += scale * v;
-        if (gt.p_b >= 0) g[gt.p_b] += scale * v;
+        if (gt.p_w >= 0) atomicAdd(&g[gt.p_w], scale * v);
+        if (gt.p_b >= 0) atomicAdd(&g[gt.p_b], scale * v);
       }
       return;
     }
@@ -828,15 +876,16 @@ struct Ctx {
     } else {
       if (gt.p_w >= 0) {
         const real v = group_sum(leader ? gth * scale * f : (real)0, 64);
-        if (lane == 0) gacc[(size_t)wave * A.n_params + gt.p_w] += v;
+        if (lane == 0) atomicAdd(&gacc[(size_t)wave * A.n_params + gt.p_w], v);
       }
       if (gt.p_b >= 0) {
         const real v = group_sum(leader ? gth * scale : (real)0, 64);
-        if (lane == 0) gacc[(size_t)wave * A.n_params + gt.p_b] += v;
+        if (lane == 0) atomicAdd(&gacc[(size_t)wave * A.n_params + gt.p_b], v);
       }
     }
     if (gt.feat >= 0 && leader)
-      facc[((size_t)sl * wps + (tau >> 6)) * A.n_feats + gt.feat] += gth * scale * w;
+      atomicAdd(&facc[((size_t)sl * wps + (tau >> 6)) * A.n_feats + gt.feat],
+                gth * scale * w);
   }
 
   // Backward through an L1Q op: for each register bit's block, the
@@ -848,8 +897,8 @@ struct Ctx {
     static_for<LR>([&](auto J) QS_AI {
       constexpr int j = decltype(J)::value;
       const int bid = r[j];
-      if (bid >= 0) {  // reads psi and lam only: no state copies at the join
-        U2<real> q = q_part<j>(psi, lam);
+      U2<real> q = q_and_apply<j>(psi, lam, u_dag(block_or_id(bid)));
+      if (bid >= 0) {  // Q only: no state copies at the join
         const int b0 = kc(A.blk_begin)[bid], b1 = kc(A.blk_begin)[bid + 1];
         for (int i = b1 - 1; i >= b0; --i) {
           const int g = kc(A.blk_gates)[i];
@@ -862,9 +911,6 @@ struct Ctx {
           if (i > b0) q = q_back(gt.op, c, sn, q);
         }
       }
-      const U2<real> ud = u_dag(block_or_id(bid));
-      g_u<j>(psi, ud);
-      g_u<j>(lam, ud);
     });
   }
 
