@@ -1,16 +1,19 @@
 """Benchmark: forward + adjoint gate-amplitude updates per second.
 
 One step = the whole path over one batch with inputs resident in HBM:
-amplitude/angle encoding, forward gate sweep with FP64 Pauli-Z readout, the
-loss and dL/d<Z> in torch, and the adjoint backward (FP64 batch-summed
-parameter gradients). Work per step = 3 * B * 2^n * G gate-amplitude updates.
+amplitude/angle encoding, forward gate sweep with FP64 Pauli-Z (or fidelity)
+readout, the loss and its upstream gradient in torch, and the adjoint
+backward (FP64 batch-summed parameter gradients). Work per step =
+3 * B * 2^n * G gate-amplitude updates (forward sweep, then uncompute and
+propagate in the backward).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
 
-Prints ONE JSON line. Alongside the fused path it times the plain path (one
-kernel launch per gate, states in HBM) on the same inputs, the dominant
-kernel's duration with HIP events on the launch stream, and the FP64 CPU
-oracle on a bounded sample of the batch (the ``cpu_baseline`` leg).
+Prints ONE JSON line. The default workload is the 10-qubit x 4096 batch
+(c2). Alongside the fused path it times the plain path (one kernel launch per
+gate, states in HBM) on the same inputs, the dominant kernel's duration with
+HIP events on the launch stream, and the FP64 CPU oracle on a bounded sample
+of the batch (the ``cpu_baseline`` leg, c2 only).
 """
 
 from __future__ import annotations
@@ -27,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fwd+adjoint gate-amp updates/s, 10q×4096 batch; % LDS/HBM roofline vs plain"
 WORKLOAD_TEXT = {
+    "c1": "4 qubits, batch 64: 2 layers RY,RZ + ring CNOT; complex128 forward",
     "c2": "10 qubits, batch 4096: amplitude-encoded N(0,1) 1024-dim inputs; "
           "8 layers of RX,RY,RZ per qubit + CZ ring (240 params); "
           "MSE(<Z_0>, +-1 labels); complex64 forward + adjoint",
@@ -35,13 +39,21 @@ WORKLOAD_TEXT = {
     "c4": "12 qubits, batch 1024: 6-layer RY/RZ + CNOT-chain encoder, "
           "decoder its inverse with separate params, 4 trash qubits reset, "
           "loss 1 - fidelity; complex64 forward + adjoint",
-    "c1": "4 qubits, batch 64: 2 layers RY,RZ + ring CNOT; complex128 forward",
+    "c5a": "10000 independent circuits, n ~ U{6..14}, depth ~ U{4..32} "
+           "hardware-efficient layers (RY,RZ + ring CNOT), one amplitude-encoded "
+           "N(0,1) input each, loss sum_q g_q <Z_q>; one persistent launch per "
+           "direction; complex64 forward + adjoint",
     "c5b": "26 qubits, one complex64 state (512 MiB in HBM), 20 hardware-efficient "
-           "layers (RY,RZ + ring CNOT; 1560 gates), loss sum_q g_q <Z_q>; "
-           "forward + adjoint on the tiled large-state path",
+           "layers (RY,RZ + ring CNOT; 1560 gates), loss sum_q g_q <Z_q>, state "
+           "checkpoints every 4 layers; forward + adjoint on the tiled large-state "
+           "path",
 }
-# MI355X peaks (published): fp32 vector 157.3 TFLOP/s, HBM 8 TB/s.
+# MI355X published peaks: fp32 vector 157.3 TFLOP/s, HBM 8 TB/s.
 PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBPS = 8000.0
+# LDS: 128 B per clock per CU (the CDNA figure; not re-measured here) x 256
+# CUs x 2.4 GHz. Used only for the pass-equivalent context figure.
+LDS_TBPS_ASSUMED = 78.6
 
 # Algorithmic flops per amplitude of one gate: a Pauli rotation applied to a
 # complex amplitude costs 6 real flops (each output component is two real
@@ -49,7 +61,6 @@ PEAK_FP32_TFLOPS = 157.3
 # forms Im<lam|P|psi> (4). CNOT, CZ, X, Y, Z, H: counted as 0.
 FLOPS_ROT_FWD = 6
 FLOPS_ROT_ADJ = 16
-
 
 # Sources that decide what the adjoint kernel does; the measured HBM traffic
 # in profiles/ is only reported while their hash matches the one recorded
@@ -89,50 +100,115 @@ def _rotations(circuit):
     return int(np.isin(circuit.gates["op"], (0, 1, 2)).sum())
 
 
-def cpu_baseline(key: str, rows: int) -> dict:
-    """The FP64 oracle, as it stands, on `rows` rows of the workload, one
-    host thread (subprocess with BLAS/OpenMP pinned to 1 thread)."""
-    code = f"""
+# ------------------------------------------------------------ CPU baseline
+_CPU_WORKER = """
 import json, sys, time
-sys.path.insert(0, {ROOT!r})
+sys.path.insert(0, {root!r})
 import numpy as np
 import oracle as O
 from workloads import make_workload
 w = make_workload({key!r}, {rows})
+k, W = {part}, {parts}
+sl = slice(k, None, W)
+x = w.x[sl] if w.x is not None else None
+feats = w.feats[sl] if w.feats is not None else None
+labels = w.labels[sl] if w.labels is not None else None
+B = len(range(*sl.indices(w.batch)))
 t0 = time.perf_counter()
-feats = w.feats
 if w.encoding == "amplitude":
-    psi0 = O.encode_amplitude(w.x, w.n_qubits)
+    psi0 = O.encode_amplitude(x, w.n_qubits)
 else:
-    psi0 = O.encode_zero(w.batch, w.n_qubits)
+    psi0 = O.encode_zero(B, w.n_qubits)
 if w.loss == "fidelity_reset":
     psi = O.run_circuit(w.circuit, w.params, None, psi0)
     chi = O.run_circuit(w.decoder, w.params_dec, None, psi0)
     F, c = O.fidelity_reset(psi, chi, w.n_trash)
-    dF = -np.ones(w.batch) / w.batch
+    dF = -np.ones(B) / B
     lam, mu = O.reset_channel_fidelity_cotangents(psi, chi, c, dF, w.n_trash)
-    g1, _ = O.adjoint_vjp(w.circuit, w.params, None, psi0, lam_final=lam)
-    g2, _ = O.adjoint_vjp(w.decoder, w.params_dec, None, psi0, lam_final=mu)
+    O.adjoint_vjp(w.circuit, w.params, None, psi0, lam_final=lam)
+    O.adjoint_vjp(w.decoder, w.params_dec, None, psi0, lam_final=mu)
 else:
     z = O.expz(O.run_circuit(w.circuit, w.params, feats, psi0))
     if w.loss != "none":
-        L, dz = O.loss_and_dexpz(w.loss, z, w.labels, w.weights)
+        L, dz = O.loss_and_dexpz(w.loss, z, labels, w.weights)
         gth, _ = O.adjoint_vjp(w.circuit, w.params, feats, psi0, dexpz=dz)
         O.theta_to_param_grads(w.circuit, w.params, feats, gth)
 dt = time.perf_counter() - t0
-print(json.dumps({{"seconds": dt, "updates": w.updates_per_step()}}))
+G = w.circuit.n_gates + (w.decoder.n_gates if w.decoder else 0)
+passes = 1 if w.loss == "none" else 3
+print(json.dumps({{"seconds": dt, "updates": passes * B * (1 << w.n_qubits) * G}}))
 """
+
+
+def cpu_baseline(key: str, rows_per_worker: int) -> dict:
+    """The FP64 oracle, as it stands, on a bounded sample of the workload:
+    one process per available host core (at most 16), each with one
+    BLAS/OpenMP thread, each on its own rows of the sample."""
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    rows = rows_per_worker * workers
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1",
                MKL_NUM_THREADS="1", NUMEXPR_NUM_THREADS="1")
-    out = subprocess.run([sys.executable, "-c", code], capture_output=True,
-                         text=True, env=env, timeout=600)
-    if out.returncode != 0:
-        raise RuntimeError(out.stderr)
-    r = json.loads(out.stdout.strip().splitlines()[-1])
-    return {"value": r["updates"] / r["seconds"], "unit": "gate-amp updates/s",
-            "cores": 1, "kind": "oracle",
-            "sample": f"{rows} rows of the batch, forward + adjoint, "
-                      f"{r['seconds']:.1f} s on 1 host thread"}
+    procs = [subprocess.Popen([sys.executable, "-c", _CPU_WORKER.format(
+        root=ROOT, key=key, rows=rows, part=k, parts=workers)],
+        stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env)
+        for k in range(workers)]
+    res = []
+    for p in procs:
+        out, err = p.communicate(timeout=900)
+        if p.returncode != 0:
+            raise RuntimeError(err)
+        res.append(json.loads(out.strip().splitlines()[-1]))
+    wall = max(r["seconds"] for r in res)
+    updates = sum(r["updates"] for r in res)
+    return {"value": updates / wall, "unit": "gate-amp updates/s",
+            "cores": workers, "kind": "oracle",
+            "sample": f"{rows} rows of the batch ({rows_per_worker} per process, "
+                      f"{workers} processes x 1 thread), forward + adjoint, "
+                      f"{wall:.1f} s wall"}
+
+
+# ---------------------------------------------------------------- timing
+class AdjointTimer:
+    """HIP events around every call of the dominant library call (the
+    adjoint) on the launch stream during the timed region."""
+
+    def __init__(self, torch, stream):
+        self.torch, self.stream, self.ev, self.on = torch, stream, [], False
+
+    def wrap(self, fn):
+        def timed(*a, **k):
+            if not self.on:
+                return fn(*a, **k)
+            e0 = self.torch.cuda.Event(enable_timing=True)
+            e1 = self.torch.cuda.Event(enable_timing=True)
+            e0.record(self.stream)
+            r = fn(*a, **k)
+            e1.record(self.stream)
+            self.ev.append((e0, e1))
+            return r
+        return timed
+
+    def mean_ms(self):
+        return sum(a.elapsed_time(b) for a, b in self.ev) / max(1, len(self.ev))
+
+
+def timed_loop(torch, stream, step, steps, warmup, timer):
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    timer.on = True
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    wall0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    timer.on = False
+    return t0.elapsed_time(t1) / steps, wall
 
 
 def main():
@@ -142,23 +218,33 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--plain-steps", type=int, default=5)
-    ap.add_argument("--cpu-rows", type=int, default=384)
+    ap.add_argument("--cpu-rows", type=int, default=256,
+                    help="oracle rows per host process for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--source-hash", action="store_true",
-                    help="print the hash of the adjoint kernel's sources and exit")
-    ap.add_argument("--no-tune", action="store_true",
-                    help="skip the autotuner (use the default register split)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB "
                          "(5 launches) and exit: the known-size kernel whose "
                          "FETCH_SIZE / WRITE_SIZE counters scale the engine's")
+    ap.add_argument("--source-hash", action="store_true",
+                    help="print the hash of the adjoint kernel's sources and exit")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (use the default register split)")
     args = ap.parse_args()
     if args.source_hash:
         print(kernel_source_hash())
         return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "multi-GPU sharding is designed, not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2509_25075_amd import sim
+    from paper_2509_25075_amd import _native as N
+    from workloads import make_workload, uneven_batch
+
     if args.copy_calibration:
-        import torch
         n = args.copy_calibration << 18  # float32 elements
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -169,116 +255,120 @@ def main():
                           "bytes_read_per_launch": 4 * n,
                           "bytes_written_per_launch": 4 * n}))
         return
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding is designed, not built", file=sys.stderr)
-        sys.exit(2)
 
-    import torch
-    from paper_2509_25075_amd import sim
-    from workloads import make_workload
-
-    from paper_2509_25075_amd import _native as N
-
-    w = make_workload(args.workload)
-    tuned = None
-    if not args.no_tune:
-        # The library's autotuner times the register-split candidates of each
-        # circuit at this batch size; later calls look the choice up.
-        tuned = {}
-        for name, c in (("circuit", w.circuit), ("decoder", w.decoder)):
-            if c is None:
-                continue
-            s0 = sim.Simulator(c, w.dtype)
-            if s0.plan_info(w.batch)["path"] not in (N.QS_PATH_FUSED, N.QS_PATH_HBM):
-                continue
-            t = N.qs_autotune(s0.h, s0.qs_dtype, w.batch, 0)
-            tuned[name] = {k: t[k] for k in ("fwd_log2_regs", "adj_log2_regs",
-                                             "tile_qubits")}
-        torch.cuda.synchronize()
-    d = sim.to_device(w, flags=0)  # automatic: register/LDS engine, else tiled HBM
-    path_name = {1: "fused", 2: "plain", 3: "tiled_hbm"}[d.sim.plan_info(w.batch)["path"]]
-    updates = w.updates_per_step()
     stream = torch.cuda.current_stream()
-
-    # dominant-kernel events: the adjoint call (one engine launch + a small
-    # FP64 reduction of per-block partials) on the launch stream
-    adj_events = []
-    orig_adjoint = sim.Simulator.adjoint
-
-    def timed_adjoint(self, *a, **k):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        r = orig_adjoint(self, *a, **k)
-        e1.record(stream)
-        adj_events.append((e0, e1))
-        return r
-
-    for _ in range(args.warmup):
-        sim.step(d)
-    torch.cuda.synchronize()
-    sim.Simulator.adjoint = timed_adjoint
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0.record(stream)
-    wall0 = time.perf_counter()
-    for _ in range(args.steps):
-        sim.step(d)
-    t1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    sim.Simulator.adjoint = orig_adjoint
-    ms = t0.elapsed_time(t1) / args.steps
-    value = updates / (ms * 1e-3)
-    adj_ms = sum(a.elapsed_time(b) for a, b in adj_events) / max(1, len(adj_events))
-    n_adj_per_step = max(1, len(adj_events) // args.steps)
-
-    rot = _rotations(w.circuit) + (_rotations(w.decoder) if w.decoder else 0)
-    flops_adj = FLOPS_ROT_ADJ * (rot // (2 if w.decoder else 1)) * (1 << w.n_qubits) * w.batch
-    achieved = flops_adj / (adj_ms * 1e-3) / 1e12 if w.loss != "none" else None
-
+    timer = AdjointTimer(torch, stream)
+    key = args.workload
     plain = None
-    if not args.no_plain and w.loss != "none":
-        dp = sim.to_device(w, flags=2)
-        sim.step(dp)
-        torch.cuda.synchronize()
-        p0 = torch.cuda.Event(enable_timing=True)
-        p1 = torch.cuda.Event(enable_timing=True)
-        p0.record(stream)
-        for _ in range(args.plain_steps):
+    extra = {}
+
+    if key == "c5a":
+        ub = uneven_batch()
+        dev = sim.UnevenDevice(ub)
+        updates = ub.updates_per_step()
+        N.qs_program_adjoint = timer.wrap(N.qs_program_adjoint)
+        ms, wall = timed_loop(torch, stream, dev.step, args.steps, args.warmup, timer)
+        rot_amp = sum(len(idx) * (1 << n) * _rotations(c) for n, _, c, idx in ub.classes)
+        flops_adj = FLOPS_ROT_ADJ * rot_amp
+        adj_ms = timer.mean_ms()
+        roof = {"bound": "alu", "achieved": flops_adj / (adj_ms * 1e-3) / 1e12,
+                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "traffic": None,
+                "kernel": "sv_program (adjoint)", "kernel_ms": adj_ms,
+                "launches_per_step": 1, "algorithmic_flops_per_launch": flops_adj}
+        roof["frac"] = roof["achieved"] / roof["peak"]
+        cfg = {"workload": f"c5a: {WORKLOAD_TEXT[key]}", "circuits": ub.n_circuits,
+               "classes": len(ub.classes), "updates_per_step": updates,
+               "path": "persistent"}
+        dtype = "fp32"
+    else:
+        w = make_workload(key)
+        tuned = None
+        if not args.no_tune:
+            # The library's autotuner times the register-split candidates of
+            # each circuit at this batch size; later calls look the choice up.
+            tuned = {}
+            for name, c in (("circuit", w.circuit), ("decoder", w.decoder)):
+                if c is None:
+                    continue
+                s0 = sim.Simulator(c, w.dtype)
+                if s0.plan_info(w.batch)["path"] not in (N.QS_PATH_FUSED, N.QS_PATH_HBM):
+                    continue
+                t = N.qs_autotune(s0.h, s0.qs_dtype, w.batch, 0)
+                tuned[name] = {k: t[k] for k in ("fwd_log2_regs", "adj_log2_regs",
+                                                 "tile_qubits")}
+            torch.cuda.synchronize()
+        ck = 4 if key == "c5b" else 0
+        # automatic path: register/LDS engine when it fits, else tiled HBM
+        d = sim.to_device(w, flags=0, ckpt_every_layers=ck)
+        path = {1: "fused", 2: "plain", 3: "tiled_hbm"}[d.sim.plan_info(w.batch)["path"]]
+        updates = w.updates_per_step()
+        sim.Simulator.adjoint = timer.wrap(sim.Simulator.adjoint)
+        ms, wall = timed_loop(torch, stream, lambda: sim.step(d), args.steps,
+                              args.warmup, timer)
+        adj_ms = timer.mean_ms()
+        n_adj = max(1, len(timer.ev) // args.steps)
+        rot = _rotations(w.circuit)
+        amps = (1 << w.n_qubits) * w.batch
+        if w.loss == "none":
+            roof = None
+        elif path == "tiled_hbm":
+            # Each epoch's adjoint launch reads psi and lam and writes them
+            # back (4 x 8 B per amplitude); the timed call runs all epochs.
+            n_ep = d.sim.plan_info(w.batch)["n_segments"]
+            bytes_call = n_ep * 4 * 8 * amps
+            roof = {"bound": "hbm", "achieved": bytes_call / (adj_ms * 1e-3) / 1e9,
+                    "peak": PEAK_HBM_GBPS, "unit": "GB/s", "traffic": None,
+                    "kernel": "sv_adjoint (tiled epochs)", "kernel_ms": adj_ms,
+                    "launches_per_step": n_ep, "algorithmic_bytes_per_call": bytes_call}
+        else:
+            flops_adj = FLOPS_ROT_ADJ * rot * amps
+            roof = {"bound": "alu", "achieved": flops_adj / (adj_ms * 1e-3) / 1e12,
+                    "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                    "traffic": measured_traffic(key), "kernel": "sv_adjoint",
+                    "kernel_ms": adj_ms, "launches_per_step": n_adj,
+                    "algorithmic_flops_per_launch": flops_adj}
+        if roof is not None:
+            roof["frac"] = roof["achieved"] / roof["peak"]
+        if not args.no_plain and w.loss != "none" and path == "fused":
+            dp = sim.to_device(w, flags=N.QS_PATH_PLAIN)
             sim.step(dp)
-        p1.record(stream)
-        torch.cuda.synchronize()
-        pms = p0.elapsed_time(p1) / args.plain_steps
-        plain = {"value": updates / (pms * 1e-3), "ms_per_step": pms}
-        del dp
+            torch.cuda.synchronize()
+            p0 = torch.cuda.Event(enable_timing=True)
+            p1 = torch.cuda.Event(enable_timing=True)
+            p0.record(stream)
+            for _ in range(args.plain_steps):
+                sim.step(dp)
+            p1.record(stream)
+            torch.cuda.synchronize()
+            pms = p0.elapsed_time(p1) / args.plain_steps
+            plain = {"value": updates / (pms * 1e-3), "ms_per_step": pms}
+            del dp
+        cfg = {"workload": f"{key}: {WORKLOAD_TEXT[key]}", "batch": w.batch,
+               "qubits": w.n_qubits,
+               "gates": w.circuit.n_gates + (w.decoder.n_gates if w.decoder else 0),
+               "updates_per_step": updates, "path": path, "tuned": tuned}
+        if d.ckpt_gates:
+            cfg["checkpoints_after_gates"] = d.ckpt_gates
+        dtype = "fp32" if w.dtype == "c64" else "fp64"
+        if path == "fused":
+            # context: updates/s x 16 B (one LDS round trip per gate-amplitude
+            # in complex64) over the LDS peak; above 1 means gates applied from
+            # registers without an LDS pass each.
+            extra["pass_equivalent_lds_frac"] = (updates / (ms * 1e-3)) * 16 / (
+                LDS_TBPS_ASSUMED * 1e12)
 
+    value = updates / (ms * 1e-3)
     cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.workload, min(args.cpu_rows, w.batch))
-
+    if not args.no_cpu_baseline and key == "c2":
+        cpu = cpu_baseline(key, args.cpu_rows)
     rec = {
         "metric": METRIC, "value": value, "unit": "gate-amp updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "fp32" if w.dtype == "c64" else "fp64",
-        "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}",
-                   "batch": w.batch, "qubits": w.n_qubits,
-                   "gates": w.circuit.n_gates + (w.decoder.n_gates if w.decoder else 0),
-                   "updates_per_step": updates, "path": path_name, "tuned": tuned},
-        "roofline": None if achieved is None else {
-            "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": measured_traffic(args.workload), "kernel": "sv_adjoint",
-            "kernel_ms": adj_ms / 1.0, "launches_per_step": n_adj_per_step,
-            "algorithmic_flops_per_launch": flops_adj},
-        "cpu_baseline": cpu,
-        "plain": plain,
+        "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+        "config": cfg, "roofline": roof, "cpu_baseline": cpu, "plain": plain,
         "speedup_vs_plain": None if plain is None else value / plain["value"],
-        "wall_s": wall,
+        "wall_s": wall, **extra,
     }
     print(json.dumps(rec))
 

@@ -101,6 +101,14 @@ __device__ __forceinline__ int uni(int v) {
   return __builtin_amdgcn_readfirstlane(v);
 }
 
+// A copy of v the compiler cannot see through: per-lane address tables
+// derived from it are then recomputed at each use instead of being kept
+// live (and spilled) across the whole kernel.
+__device__ __forceinline__ uint32_t opaque(uint32_t v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 // Slot swizzle inside a sample's LDS region (in complex elements).
 __device__ __forceinline__ uint32_t swz(uint32_t L) {
   return L ^ ((L >> 5) & 31u) ^ ((L >> 10) & 31u);
@@ -635,9 +643,10 @@ struct Ctx {
 
   // Logical index bits of this thread's thread-bit part under placement s.
   __device__ __forceinline__ uint32_t lane_part(const QS_K uint8_t* map) const {
+    const uint32_t tb = opaque((uint32_t)tau);
     uint32_t L = 0;
     for (int i = 0; i < A.t; ++i)
-      if ((tau >> i) & 1) L |= 1u << map[LR + i];
+      if ((tb >> i) & 1) L |= 1u << map[LR + i];
     return swz(L) ^ salt;
   }
 
@@ -720,12 +729,13 @@ struct Ctx {
       x.im[u] = v.y;
     }
     sample_sync(A.t);
+    const uint32_t tb = opaque((uint32_t)tau);
 #pragma unroll
     for (int u = 0; u < R; ++u) {
       v2 v;
       v.x = x.re[u];
       v.y = x.im[u];
-      lds[swz((uint32_t)(tau + (u << A.t))) ^ salt] = v;
+      lds[swz(tb + ((uint32_t)u << A.t)) ^ salt] = v;
     }
     sample_sync(A.t);
     read_mapped(x, map);
@@ -742,12 +752,13 @@ struct Ctx {
     hbm_offsets(off);
     const int64_t a0 = hbm_a0();
     constexpr int W = R < 8 ? R : 8;
+    const uint32_t tb = opaque((uint32_t)tau);
 #pragma unroll
     for (int u0 = 0; u0 < R; u0 += W) {
       v2 v[W];
 #pragma unroll
       for (int w = 0; w < W; ++w)
-        v[w] = lds[swz((uint32_t)(tau + ((u0 + w) << A.t))) ^ salt];
+        v[w] = lds[swz(tb + ((uint32_t)(u0 + w) << A.t)) ^ salt];
 #pragma unroll
       for (int w = 0; w < W; ++w) {
         const int u = u0 + w;

@@ -141,15 +141,27 @@ class DeviceWorkload:
     ws: torch.Tensor
     ws_dec: torch.Tensor | None
     flags: int
+    ckpt_gates: list | None = None   # gate counts after which psi is stored
+    ckpt: torch.Tensor | None = None  # [n_ckpt, B, 2^n] stored states
 
 
-def to_device(w, flags: int = 0, device="cuda") -> DeviceWorkload:
+def to_device(w, flags: int = 0, device="cuda", ckpt_every_layers: int = 0) -> DeviceWorkload:
     sim = Simulator(w.circuit, w.dtype, flags)
     rd = sim.rdtype
     B = w.batch
     t = lambda a, dt=rd: None if a is None else torch.as_tensor(a).to(device=device, dtype=dt).contiguous()
     sim_dec = Simulator(w.decoder, w.dtype, flags) if w.decoder is not None else None
     state = sim.empty_state(B, device)
+    ckpt_gates, ckpt = None, None
+    if ckpt_every_layers and w.decoder is None:
+        ends = w.circuit.layer_end
+        ckpt_gates = [ends[l - 1] for l in range(ckpt_every_layers, len(ends),
+                                                 ckpt_every_layers)]
+        if ckpt_gates:
+            ckpt = torch.empty((len(ckpt_gates), B, 1 << w.n_qubits),
+                               dtype=sim.cdtype, device=device)
+        else:
+            ckpt_gates = None
     return DeviceWorkload(
         w=w, sim=sim, sim_dec=sim_dec, x=t(w.x), feats=t(w.feats),
         params=t(w.params), params_dec=t(w.params_dec),
@@ -157,7 +169,7 @@ def to_device(w, flags: int = 0, device="cuda") -> DeviceWorkload:
         state=state, state_dec=sim.empty_state(B, device) if sim_dec else None,
         ws=sim.workspace(B, device, flags),
         ws_dec=sim_dec.workspace(B, device, flags) if sim_dec else None,
-        flags=flags)
+        flags=flags, ckpt_gates=ckpt_gates, ckpt=ckpt)
 
 
 def step(d: DeviceWorkload, backward: bool = True) -> dict:
@@ -190,7 +202,8 @@ def step(d: DeviceWorkload, backward: bool = True) -> dict:
             out["grad_params_dec"], _ = d.sim_dec.adjoint(
                 d.params_dec, d.feats, d.state_dec, dstate=lam_chi, ws=d.ws_dec)
         return out
-    z = sim.forward(d.params, d.feats, d.state, want_expz=True)
+    z = sim.forward(d.params, d.feats, d.state, want_expz=True,
+                    ckpt_gates=d.ckpt_gates, ckpt=d.ckpt)
     out["expz"] = z
     if w.loss == "none" or not backward:
         return out
@@ -204,7 +217,8 @@ def step(d: DeviceWorkload, backward: bool = True) -> dict:
         dz = d.weights[None, :].expand_as(z).contiguous()
     else:
         raise ValueError(w.loss)
-    gp, gf = sim.adjoint(d.params, d.feats, d.state, dexpz=dz, ws=d.ws)
+    gp, gf = sim.adjoint(d.params, d.feats, d.state, dexpz=dz, ws=d.ws,
+                         ckpt_gates=d.ckpt_gates, ckpt=d.ckpt)
     out["grad_params"] = gp
     if gf is not None:
         out["grad_feats"] = gf
