@@ -14,6 +14,12 @@
 // when every ready gate mixes a thread-resident qubit. At a re-placement the
 // register bits receive the r qubits whose next pending pair-mixing gate is
 // soonest (ties: lower qubit). Checkpoint positions are scheduling barriers.
+//
+// CNOTs are never applied as engine ops. A CNOT maps the amplitude index
+// x -> x ^ (x_c << t), a linear map over GF(2); so is the LDS slot of a remap.
+// Every ready CNOT is therefore folded, at the next re-placement, into the
+// write addresses of the closing segment: its write masks are the closing
+// placement's unit vectors mapped through the folded CNOTs (in order).
 #include <algorithm>
 #include <climits>
 #include <cstring>
@@ -28,11 +34,14 @@ int mixing_target(const qs_gate& g) {
   switch (g.op) {
     case QS_OP_RX: case QS_OP_RY: case QS_OP_X: case QS_OP_Y: case QS_OP_H:
       return g.q0;
-    case QS_OP_CNOT:
-      return g.q1;
     default:
-      return -1;  // RZ, Z, CZ are diagonal
+      return -1;  // RZ, Z, CZ are diagonal; CNOTs are folded into remaps
   }
+}
+
+// x -> x ^ (bit c of x) << t on a logical index mask.
+uint16_t apply_cnot(uint16_t x, int c, int t) {
+  return (uint16_t)(x ^ (((x >> c) & 1u) << t));
 }
 
 struct Placement {
@@ -190,6 +199,7 @@ void build_layers(SvPlan& P, const qs_circuit& c, bool per_sample_angles_all) {
         }
       }
     }
+    for (int g : P.seg_folded[s]) P.exec.insert(P.exec.end(), {g, -1, -1});
     P.exec_seg.push_back((int32_t)(P.exec.size() / 3));
   }
   P.seg_begin.back() = (int32_t)P.ops.size();
@@ -245,9 +255,29 @@ SvPlan plan_sv(const qs_circuit& c, int r, bool per_sample_angles_all,
     P.seg_begin.push_back((int32_t)ops.size());
     P.seg_map.insert(P.seg_map.end(), pl.phys2log, pl.phys2log + kMapStride);
     P.seg_ckpt.push_back(-1);
+    P.seg_folded.emplace_back();
   };
   auto seg_empty = [&]() {
-    return P.seg_begin.back() == (int32_t)ops.size() && P.seg_ckpt.back() < 0;
+    return P.seg_begin.back() == (int32_t)ops.size() && P.seg_ckpt.back() < 0 &&
+           P.seg_folded.back().empty();
+  };
+  // Folds every ready CNOT of [lo, hi) (repeatedly: a chain folds whole) into
+  // the current segment's closing remap.
+  auto fold_cnots = [&](int lo, int hi, int& remaining) {
+    bool any = false, more = true;
+    while (more) {
+      more = false;
+      for (int g = lo; g < hi; ++g) {
+        if (done[g] || c.gates[g].op != QS_OP_CNOT || !ready(g)) continue;
+        P.seg_folded.back().push_back(g);
+        done[g] = 1;
+        head[c.gates[g].q0]++;
+        head[c.gates[g].q1]++;
+        --remaining;
+        more = any = true;
+      }
+    }
+    return any;
   };
   open_segment(cur);
   int lo = 0;
@@ -263,6 +293,7 @@ SvPlan plan_sv(const qs_circuit& c, int r, bool per_sample_angles_all,
         for (int g = lo; g < hi; ++g) {
           if (done[g] || !ready(g)) continue;
           const qs_gate& x = c.gates[g];
+          if (x.op == QS_OP_CNOT) continue;  // folded at the next remap
           const int m = mixing_target(x);
           if (m >= 0 && cur.log2phys[m] >= r) continue;
           SvOp op;
@@ -279,8 +310,16 @@ SvPlan plan_sv(const qs_circuit& c, int r, bool per_sample_angles_all,
           progress = true;
         }
       }
-      if (remaining == 0) break;
-      // Stuck: every ready gate mixes a thread-resident qubit. Re-place.
+      // Stuck: every ready gate mixes a thread-resident qubit or is a
+      // CNOT. Fold the ready CNOTs into this segment's closing remap and
+      // re-place (an epoch ending in CNOTs gets a remap to the same
+      // placement, so every checkpoint and the last segment end in a plain
+      // placement).
+      const bool folded = remaining > 0 && fold_cnots(lo, hi, remaining);
+      if (remaining == 0) {
+        if (folded) open_segment(cur);
+        break;
+      }
       Placement nxt = choose(n, r, next_use_from_heads());
       if (seg_empty())
         std::memcpy(&P.seg_map[P.seg_map.size() - kMapStride], nxt.phys2log,
@@ -314,10 +353,24 @@ SvPlan plan_sv(const qs_circuit& c, int r, bool per_sample_angles_all,
   P.blk_begin.assign(1, 0);
   build_layers(P, c, per_sample_angles_all);
 
+  // Read masks (a segment's placement) and write masks (its placement mapped
+  // through the CNOTs folded at its end).
+  const int nseg = P.nseg();
+  P.seg_lay.assign((size_t)nseg * kLayWords, 0);
+  for (int s = 0; s < nseg; ++s) {
+    uint16_t* rd = &P.seg_lay[(size_t)s * kLayWords];
+    uint16_t* wr = rd + kMapStride;
+    for (int p = 0; p < n; ++p) {
+      uint16_t v = (uint16_t)(1u << P.seg_map[(size_t)s * kMapStride + p]);
+      rd[p] = v;
+      for (int g : P.seg_folded[s]) v = apply_cnot(v, c.gates[g].q0, c.gates[g].q1);
+      wr[p] = v;
+    }
+  }
   int changes = 0;
-  for (int s = 1; s < P.nseg(); ++s)
-    if (std::memcmp(&P.seg_map[(s - 1) * kMapStride], &P.seg_map[s * kMapStride],
-                    kMapStride) != 0)
+  for (int s = 1; s < nseg; ++s)
+    if (std::memcmp(&P.seg_lay[(size_t)(s - 1) * kLayWords + kMapStride],
+                    &P.seg_lay[(size_t)s * kLayWords], kMapStride * 2) != 0)
       ++changes;
   P.n_remaps = changes;
   return P;

@@ -123,6 +123,7 @@ ProgPlan* get_prog(const qs_program* p, int dtype, int* rc) {
     ProgClass& d = cls[k];
     std::memset(&d, 0, sizeof(d));
     d.seg_map = ep.dev->seg_map;
+    d.seg_lay = ep.dev->seg_lay;
     d.seg_begin = ep.dev->seg_begin;
     d.seg_ckpt = ep.dev->seg_ckpt;
     d.ops = ep.dev->ops;

@@ -254,6 +254,7 @@ bool upload(T** dst, const T* src, size_t n) {
 
 void free_dev(SvDevPlan& d) {
   (void)hipFree(d.seg_map);
+  (void)hipFree(d.seg_lay);
   (void)hipFree(d.seg_begin);
   (void)hipFree(d.seg_ckpt);
   (void)hipFree(d.ops);
@@ -296,6 +297,7 @@ Entry* get_plan(const qs_circuit& c, int r, bool ps, const int32_t* ck, int n_ck
   d.n_blocks = P.n_blocks();
   d.n_fu = P.n_fu;
   bool okk = upload(&d.seg_map, P.seg_map.data(), P.seg_map.size()) &&
+             upload(&d.seg_lay, P.seg_lay.data(), P.seg_lay.size()) &&
              upload(&d.seg_begin, P.seg_begin.data(), P.seg_begin.size()) &&
              upload(&d.seg_ckpt, P.seg_ckpt.data(), P.seg_ckpt.size()) &&
              upload(&d.ops, P.ops.data(), P.ops.size()) &&

@@ -40,18 +40,25 @@ constexpr int kDiagWords = 24;
 
 constexpr int kMaxQubitsFused = 14;  // 2^14 complex64 = 128 KiB LDS staging
 constexpr int kMapStride = 16;       // bytes per segment mapping record
+constexpr int kLayWords = 32;        // uint16 per segment layout record
 
 // A planned gate program: a sequence of segments, each with a fixed
 // placement of the logical qubits onto physical bit positions, such that
 // every non-diagonal gate of the segment acts on a register-resident qubit.
 // Within a segment the gates are grouped into layer ops (L1Q, DIAG) where
-// possible; the rest (CNOT, diagonal gates on thread bits) stay one op per
-// gate. `exec` lists every gate once in execution order with its physical
-// positions, for inspection.
+// possible; the rest (diagonal gates on thread bits) stay one op per gate.
+// CNOTs are folded into the remap that closes their segment. `exec` lists
+// every gate once in execution order with its physical positions (-1, -1 for
+// a folded CNOT, listed after its segment's ops), for inspection.
 struct SvPlan {
   int n = 0, r = 0, t = 0;            // qubits, log2 regs, log2 threads/sample
   int n_gates = 0;
   std::vector<uint8_t> seg_map;       // [nseg][16]: physical pos -> logical q
+  // [nseg][32]: logical index mask of each physical bit when the segment's
+  // state is read from LDS (first 16: 1 << seg_map) and when it is written
+  // at its end (last 16: mapped through the CNOTs folded there).
+  std::vector<uint16_t> seg_lay;
+  std::vector<std::vector<int>> seg_folded;  // CNOT gates folded at each end
   std::vector<int32_t> seg_begin;     // [nseg + 1] op ranges
   std::vector<int32_t> seg_ckpt;      // [nseg] checkpoint slot after segment
   std::vector<SvOp> ops;
@@ -96,6 +103,7 @@ struct SvDevPlan {
   int n, r, t, nseg, n_gates, n_slots, n_params, n_features;
   int n_remaps, n_ops;
   uint8_t* seg_map;
+  uint16_t* seg_lay;
   int32_t* seg_begin;
   int32_t* seg_ckpt;
   SvOp* ops;
@@ -166,6 +174,7 @@ int launch_copy_state(int dtype, const void* src, void* dst, int64_t n_amp,
 // set and one state per circuit, packed class after class.
 struct ProgClass {
   const uint8_t* seg_map;
+  const uint16_t* seg_lay;
   const int32_t* seg_begin;
   const int32_t* seg_ckpt;
   const SvOp* ops;

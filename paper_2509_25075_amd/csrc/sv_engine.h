@@ -545,6 +545,7 @@ __device__ __forceinline__ void static_for(F&& f) {
 template <typename real>
 struct Args {
   const uint8_t* seg_map;
+  const uint16_t* seg_lay;   // [nseg][32] read / write layouts
   const int32_t* seg_begin;
   const int32_t* seg_ckpt;
   const SvOp* ops;
@@ -641,21 +642,23 @@ struct Ctx {
     return (tau >> (p - LR)) & 1;
   }
 
-  // Logical index bits of this thread's thread-bit part under placement s.
-  __device__ __forceinline__ uint32_t lane_part(const QS_K uint8_t* map) const {
+  // A layout `lay` gives, for each physical bit, the logical index mask it
+  // contributes (a placement: one bit each; after folded CNOTs: any GF(2)
+  // combination). Logical index bits of this thread's thread-bit part:
+  __device__ __forceinline__ uint32_t lane_part(const QS_K uint16_t* lay) const {
     const uint32_t tb = opaque((uint32_t)tau);
     uint32_t L = 0;
     for (int i = 0; i < A.t; ++i)
-      if ((tb >> i) & 1) L |= 1u << map[LR + i];
+      if ((tb >> i) & 1) L ^= lay[LR + i];
     return swz(L) ^ salt;
   }
 
   __device__ __forceinline__ void write_mapped(const St<real, R>& x,
-                                               const QS_K uint8_t* map) {
-    const uint32_t base = lane_part(map);
+                                               const QS_K uint16_t* lay) {
+    const uint32_t base = lane_part(lay);
     uint32_t m[LR > 0 ? LR : 1];
 #pragma unroll
-    for (int j = 0; j < LR; ++j) m[j] = swz(1u << uni(map[j]));
+    for (int j = 0; j < LR; ++j) m[j] = swz(uni(lay[j]));
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       uint32_t off = 0;
@@ -669,11 +672,11 @@ struct Ctx {
     }
   }
   __device__ __forceinline__ void read_mapped(St<real, R>& x,
-                                              const QS_K uint8_t* map) {
-    const uint32_t base = lane_part(map);
+                                              const QS_K uint16_t* lay) {
+    const uint32_t base = lane_part(lay);
     uint32_t m[LR > 0 ? LR : 1];
 #pragma unroll
-    for (int j = 0; j < LR; ++j) m[j] = swz(1u << uni(map[j]));
+    for (int j = 0; j < LR; ++j) m[j] = swz(uni(lay[j]));
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       uint32_t off = 0;
@@ -685,8 +688,8 @@ struct Ctx {
       x.im[k] = v.y;
     }
   }
-  __device__ __forceinline__ void remap(St<real, R>& x, const QS_K uint8_t* from,
-                                        const QS_K uint8_t* to) {
+  __device__ __forceinline__ void remap(St<real, R>& x, const QS_K uint16_t* from,
+                                        const QS_K uint16_t* to) {
     sample_sync(A.t);
     write_mapped(x, from);
     sample_sync(A.t);
@@ -710,7 +713,7 @@ struct Ctx {
   // HBM (logical order) -> LDS -> registers under placement `map`. All R
   // loads of a thread are issued before the first wait.
   __device__ __forceinline__ void load_state(St<real, R>& x, const real* src,
-                                             const QS_K uint8_t* map) {
+                                             const QS_K uint16_t* map) {
     const v2* s2 = reinterpret_cast<const v2*>(src);
     int64_t off[LR > 0 ? LR : 1];
     hbm_offsets(off);
@@ -742,7 +745,7 @@ struct Ctx {
   }
   // Registers under `map` -> LDS -> HBM (logical order), in runs of 8.
   __device__ __forceinline__ void store_state(const St<real, R>& x, real* dst,
-                                              const QS_K uint8_t* map) {
+                                              const QS_K uint16_t* map) {
     sample_sync(A.t);
     write_mapped(x, map);
     sample_sync(A.t);
@@ -1104,13 +1107,25 @@ template <typename real, int LR>
 __device__ __forceinline__ const QS_K uint8_t* seg_map(const Args<real>& A, int s) {
   return kc(A.seg_map) + (size_t)s * kMapStride;
 }
+// Layout of segment s when its state is read in (rlay) and written out at its
+// end (wlay: includes the CNOTs folded there).
+template <typename real>
+__device__ __forceinline__ const QS_K uint16_t* rlay(const Args<real>& A, int s) {
+  return kc(A.seg_lay) + (size_t)s * kLayWords;
+}
+template <typename real>
+__device__ __forceinline__ const QS_K uint16_t* wlay(const Args<real>& A, int s) {
+  return kc(A.seg_lay) + (size_t)s * kLayWords + kMapStride;
+}
+// A remap is needed between segments s - 1 and s unless the end layout of
+// s - 1 is the start layout of s.
 template <typename real>
 __device__ __forceinline__ bool map_changed(const Args<real>& A, int s) {
-  const QS_K uint32_t* m = reinterpret_cast<const QS_K uint32_t*>(kc(A.seg_map));
+  const QS_K uint32_t* a = reinterpret_cast<const QS_K uint32_t*>(wlay(A, s - 1));
+  const QS_K uint32_t* b = reinterpret_cast<const QS_K uint32_t*>(rlay(A, s));
   bool ch = false;
 #pragma unroll
-  for (int w = 0; w < kMapStride / 4; ++w)
-    ch |= m[(size_t)(s - 1) * (kMapStride / 4) + w] != m[(size_t)s * (kMapStride / 4) + w];
+  for (int w = 0; w < kMapStride / 2; ++w) ch |= a[w] != b[w];
   return ch;
 }
 
@@ -1123,12 +1138,12 @@ __device__ __forceinline__ void forward_body(const Args<real>& A, unsigned char*
   setup<real, LR, FLY>(C, A, smem, false, blk);
 
   St<real, R> x;
-  C.load_state(x, A.state, seg_map<real, LR>(A, 0));
+  C.load_state(x, A.state, rlay(A, 0));
   const int nseg = A.nseg;
   const QS_K int32_t* seg_begin = kc(A.seg_begin);
   for (int s = 0; s < nseg; ++s) {
     if (s > 0 && map_changed(A, s))
-      C.remap(x, seg_map<real, LR>(A, s - 1), seg_map<real, LR>(A, s));
+      C.remap(x, wlay(A, s - 1), rlay(A, s));
     const int e = seg_begin[s + 1];
     for (int o = seg_begin[s]; o < e; ++o) {
       const SvOp cur = kload(A.ops, o);
@@ -1145,11 +1160,11 @@ __device__ __forceinline__ void forward_body(const Args<real>& A, unsigned char*
     }
     const int ck = kc(A.seg_ckpt)[s];
     if (ck >= 0 && A.ckpt != nullptr)
-      C.store_state(x, A.ckpt + (size_t)ck * A.B * (2ull << A.n),
-                    seg_map<real, LR>(A, s));
+      C.store_state(x, A.ckpt + (size_t)ck * A.B * (2ull << A.n), wlay(A, s));
   }
+  // The last segment ends in a plain placement (no folded CNOTs).
   const QS_K uint8_t* last = seg_map<real, LR>(A, nseg - 1);
-  C.store_state(x, A.state, last);
+  C.store_state(x, A.state, wlay(A, nseg - 1));
 
   if (A.expz != nullptr) {
     // <Z_q> partials in FP64, reduced over the sample's threads.
@@ -1211,9 +1226,9 @@ __device__ __forceinline__ void adjoint_body(const Args<real>& A, unsigned char*
   const QS_K uint8_t* last = seg_map<real, LR>(A, nseg - 1);
 
   St<real, R> psi, lam;
-  C.load_state(psi, A.state, last);
+  C.load_state(psi, A.state, wlay(A, nseg - 1));
   if (A.dstate != nullptr) {
-    C.load_state(lam, A.dstate, last);
+    C.load_state(lam, A.dstate, wlay(A, nseg - 1));
   } else {
     // lam = sum_q g_q Z_q psi: coefficient of amplitude with logical index L
     // is sum_q g_q - 2 sum_{q : bit q of L = 1} g_q.
@@ -1249,8 +1264,7 @@ __device__ __forceinline__ void adjoint_body(const Args<real>& A, unsigned char*
   for (int s = nseg - 1; s >= 0; --s) {
     const int ck = kc(A.seg_ckpt)[s];
     if (ck >= 0 && A.ckpt != nullptr)  // re-anchor psi to the stored state
-      C.load_state(psi, A.ckpt + (size_t)ck * A.B * (2ull << A.n),
-                   seg_map<real, LR>(A, s));
+      C.load_state(psi, A.ckpt + (size_t)ck * A.B * (2ull << A.n), wlay(A, s));
     const int beg = seg_begin[s];
     for (int o = seg_begin[s + 1] - 1; o >= beg; --o) {
       const SvOp cur = kload(A.ops, o);
@@ -1275,12 +1289,12 @@ __device__ __forceinline__ void adjoint_body(const Args<real>& A, unsigned char*
       C.apply(lam, kind, a, bq, c, sn);
     }
     if (s > 0 && map_changed(A, s)) {
-      C.remap(psi, seg_map<real, LR>(A, s), seg_map<real, LR>(A, s - 1));
-      C.remap(lam, seg_map<real, LR>(A, s), seg_map<real, LR>(A, s - 1));
+      C.remap(psi, rlay(A, s), wlay(A, s - 1));
+      C.remap(lam, rlay(A, s), wlay(A, s - 1));
     }
   }
-  if (A.out_psi != nullptr) C.store_state(psi, A.out_psi, seg_map<real, LR>(A, 0));
-  if (A.out_lam != nullptr) C.store_state(lam, A.out_lam, seg_map<real, LR>(A, 0));
+  if (A.out_psi != nullptr) C.store_state(psi, A.out_psi, rlay(A, 0));
+  if (A.out_lam != nullptr) C.store_state(lam, A.out_lam, rlay(A, 0));
   __syncthreads();
   const int waves = blockDim.x >> 6;
   if (!A.per_sample_params)
@@ -1338,6 +1352,7 @@ sv_program(const ProgClass* classes, const ProgItem* items, int n_items,
     const ProgClass cd = kload(classes, w.cls);
     Args<real> A;
     A.seg_map = cd.seg_map;
+    A.seg_lay = cd.seg_lay;
     A.seg_begin = cd.seg_begin;
     A.seg_ckpt = cd.seg_ckpt;
     A.ops = cd.ops;
@@ -1393,6 +1408,7 @@ Args<real> make_args(const SvLaunch& L) {
   const SvDevPlan& p = *L.p;
   Args<real> A;
   A.seg_map = p.seg_map;
+  A.seg_lay = p.seg_lay;
   A.seg_begin = p.seg_begin;
   A.seg_ckpt = p.seg_ckpt;
   A.ops = p.ops;

@@ -106,19 +106,31 @@ def _check_plan(c, dtype, flags=0, B=8):
     for s in range(info["n_segments"]):
         m = sm[s, :n]
         assert sorted(m.tolist()) == list(range(n)), "placement is a permutation"
-        if s and not np.array_equal(sm[s - 1], sm[s]):
-            remaps += 1
+        # a remap follows unless the previous segment's end layout (its
+        # placement mapped through the CNOTs folded at its end) is this
+        # segment's placement
+        if s:
+            lay = [1 << int(q) for q in sm[s - 1, :n]]
+            for o in range(sb[s - 1], sb[s]):
+                if ops[o, 1] < 0:
+                    gc, gt = c.gates[ops[o, 3]]["q0"], c.gates[ops[o, 3]]["q1"]
+                    lay = [v ^ (((v >> gc) & 1) << gt) for v in lay]
+            if lay != [1 << int(q) for q in m]:
+                remaps += 1
         for o in range(sb[s], sb[s + 1]):
             kind, a, b, g = ops[o]
             gate = c.gates[g]
             assert kind == gate["op"]
+            if a < 0:
+                # a CNOT folded into the remap that closes this segment
+                assert kind == C.OP["CNOT"] and b < 0
+                continue
             assert m[a] == gate["q0"]
             if gate["q1"] >= 0:
                 assert m[b] == gate["q1"]
             if kind in MIXING:
                 assert a < r, "pair-mixing target on a register bit"
-            if kind == C.OP["CNOT"]:
-                assert b < r, "CNOT target on a register bit"
+            assert kind != C.OP["CNOT"], "CNOTs are folded into remaps"
     assert remaps == info["n_remaps"]
     return info
 
