@@ -363,12 +363,30 @@ int tile_qubits(int dtype, int n, int m_pref = 0) {
   return m;
 }
 
+// Tile size and the register split of the epochs' forward and adjoint
+// launches (0: the defaults).
+struct TileCfg {
+  int m_pref = 0, fwd_r = 0, adj_r = 0;
+};
+TileCfg tile_cfg(bool tuned, const TuneVal& tv) {
+  TileCfg t;
+  t.m_pref = tuned ? tv.m : 0;
+  t.fwd_r = env_int("QS_TILE_FWD_LOG2_REGS", 0);
+  if (t.fwd_r == 0) t.fwd_r = g_force_fwd_r;
+  if (t.fwd_r == 0 && tuned) t.fwd_r = tv.fwd_r;
+  t.adj_r = env_int("QS_TILE_ADJ_LOG2_REGS", 0);
+  if (t.adj_r == 0) t.adj_r = g_force_adj_r;
+  if (t.adj_r == 0 && tuned) t.adj_r = tv.adj_r;
+  return t;
+}
+
 TiledEntry* get_tiled(const qs_circuit& c, int dtype, bool ps, const int32_t* ck,
-                      int n_ck, int m_pref, int* rc) {
+                      int n_ck, const TileCfg& tc, int* rc) {
   int device = 0;
   (void)hipGetDevice(&device);
-  const int m = tile_qubits(dtype, c.n_qubits, m_pref);
-  Key key = make_key(c, -100 - m - 32 * dtype, ps, ck, n_ck, device);
+  const int m = tile_qubits(dtype, c.n_qubits, tc.m_pref);
+  Key key = make_key(c, -100 - m - 32 * dtype - 1024 * tc.fwd_r - 8192 * tc.adj_r, ps, ck,
+                     n_ck, device);
   {
     std::lock_guard<std::mutex> lock(g_mu);
     auto it = g_tiled.find(key);
@@ -391,8 +409,8 @@ TiledEntry* get_tiled(const qs_circuit& c, int dtype, bool ps, const int32_t* ck
         if (is_rotation(x.op) && (ps ? (x.p_w >= 0 || x.p_b >= 0 || x.feat >= 0) : x.feat >= 0)) ++k;
       return k;
     }();
-    if (!choose_shape(dtype, sub, slots, 0, false, &d.fshape, ps) ||
-        !choose_shape(dtype, sub, slots, 0, true, &d.ashape, ps)) {
+    if (!choose_shape(dtype, sub, slots, tc.fwd_r, false, &d.fshape, ps) ||
+        !choose_shape(dtype, sub, slots, tc.adj_r, true, &d.ashape, ps)) {
       *rc = QS_ERR_UNSUPPORTED;
       return nullptr;
     }
@@ -421,9 +439,9 @@ struct TiledHostInfo {
   bool ok = true;
 };
 TiledHostInfo tiled_host_info(const qs_circuit& c, int dtype, int64_t B, bool ps,
-                              int m_pref) {
+                              const TileCfg& tc) {
   TiledHostInfo h;
-  h.m = tile_qubits(dtype, c.n_qubits, m_pref);
+  h.m = tile_qubits(dtype, c.n_qubits, tc.m_pref);
   const int low_keep = h.m >= 6 ? 4 : (h.m >= 4 ? h.m - 2 : 0);
   std::vector<TiledEpoch> eps = plan_tiled(c, h.m, low_keep, nullptr, 0);
   h.n_epochs = (int)eps.size();
@@ -436,16 +454,16 @@ TiledHostInfo tiled_host_info(const qs_circuit& c, int dtype, int64_t B, bool ps
       if (is_rotation(x.op) && (ps ? (x.p_w >= 0 || x.p_b >= 0 || x.feat >= 0) : x.feat >= 0))
         ++slots;
     SvShape a;
-    if (!choose_shape(dtype, sub, slots, 0, true, &a, ps)) { h.ok = false; continue; }
+    if (!choose_shape(dtype, sub, slots, tc.adj_r, true, &a, ps)) { h.ok = false; continue; }
     const int64_t g = (samples + a.samples_per_block - 1) / a.samples_per_block;
     if (g > h.max_grid) h.max_grid = g;
   }
   return h;
 }
 
-size_t tiled_ws_bytes(const qs_circuit& c, int dtype, int64_t B, bool ps, int m_pref,
-                      int* rc) {
-  TiledHostInfo h = tiled_host_info(c, dtype, B, ps, m_pref);
+size_t tiled_ws_bytes(const qs_circuit& c, int dtype, int64_t B, bool ps,
+                      const TileCfg& tc, int* rc) {
+  TiledHostInfo h = tiled_host_info(c, dtype, B, ps, tc);
   if (!h.ok) {
     *rc = QS_ERR_UNSUPPORTED;
     return 0;
@@ -647,20 +665,48 @@ int qs_autotune(const qs_circuit* c, int dtype, int64_t B, int flags, void* stre
       if (ms < ba) { ba = ms; best.adj_r = r; }
     }
   } else {
+    // Tile size m, and for each m the register split of the epochs'
+    // forward and adjoint launches, timed separately.
     const int hi = std::min(c->n_qubits, dtype == QS_C64 ? kMaxQubitsFused : 13);
+    const int rmax = dtype == QS_C64 ? 5 : 4;
     float bt = 1e30f;
     for (int m = std::max(6, hi - 3); m <= hi; ++m) {
       g_force_m = m;
-      const size_t wsb = tiled_ws_bytes(*c, dtype, B, ps, m, &rc);
-      void* ws = rc == QS_OK ? sc.get(wsb) : nullptr;
-      if (!ws) { g_force_m = 0; rc = QS_OK; continue; }
-      const float mf = time_ms(st, fwd, 1, &rc);
-      const float ma = rc == QS_OK ? time_ms(st, [&]() { return adj(ws, wsb); }, 1, &rc) : 0.f;
+      float mf = 1e30f, ma = 1e30f;
+      int rf_best = 0, ra_best = 0;
+      for (int r = 3; r <= rmax; ++r) {
+        g_force_fwd_r = r;
+        const float t = time_ms(st, fwd, 1, &rc);
+        g_force_fwd_r = 0;
+        if (rc != QS_OK) { rc = QS_OK; continue; }  // shape infeasible for this m
+        info.n_candidates++;
+        if (t < mf) { mf = t; rf_best = r; }
+      }
+      for (int r = 3; r <= rmax; ++r) {
+        g_force_adj_r = r;
+        TileCfg tc;
+        tc.m_pref = m;
+        tc.adj_r = r;
+        const size_t wsb = tiled_ws_bytes(*c, dtype, B, ps, tc, &rc);
+        void* ws = rc == QS_OK ? sc.get(wsb) : nullptr;
+        const float t = ws ? time_ms(st, [&]() { return adj(ws, wsb); }, 1, &rc) : 0.f;
+        g_force_adj_r = 0;
+        if (!ws || rc != QS_OK) { rc = QS_OK; continue; }
+        info.n_candidates++;
+        if (t < ma) { ma = t; ra_best = r; }
+      }
       g_force_m = 0;
-      info.n_candidates++;
-      if (rc != QS_OK) return rc;
-      if (mf + ma < bt) { bt = mf + ma; bf = mf; ba = ma; best.m = m; }
+      if (rf_best == 0 || ra_best == 0) continue;
+      if (mf + ma < bt) {
+        bt = mf + ma;
+        bf = mf;
+        ba = ma;
+        best.m = m;
+        best.fwd_r = rf_best;
+        best.adj_r = ra_best;
+      }
     }
+    if (best.m == 0) return QS_ERR_UNSUPPORTED;
   }
   info.fwd_log2_regs = best.fwd_r;
   info.adj_log2_regs = best.adj_r;
@@ -754,7 +800,7 @@ int qs_forward(const qs_circuit* c, int dtype, int64_t B, const void* params,
     return run_plain_forward(L);
   }
   if (path == QS_PATH_HBM) {
-    TiledEntry* te = get_tiled(*c, dtype, ps, ckpt_gates, n_ckpt, tuned ? tv.m : 0, &rc);
+    TiledEntry* te = get_tiled(*c, dtype, ps, ckpt_gates, n_ckpt, tile_cfg(tuned, tv), &rc);
     if (!te) return rc;
     const int64_t per = B << c->n_qubits;  // complex elements per state batch
     const size_t cs = dtype == QS_C64 ? 8 : 16;
@@ -810,7 +856,7 @@ size_t qs_workspace_size(const qs_circuit* c, int dtype, int64_t B, int flags) {
   if (path == QS_PATH_FUSED) return fused_ws_bytes(*c, dtype, shape, B, ps);
   if (path == QS_PATH_HBM) {
     int rc = QS_OK;
-    return tiled_ws_bytes(*c, dtype, B, ps, tuned ? tv.m : 0, &rc);
+    return tiled_ws_bytes(*c, dtype, B, ps, tile_cfg(tuned, tv), &rc);
   }
   return 0;
 }
@@ -843,14 +889,14 @@ int qs_adjoint_backward(const qs_circuit* c, int dtype, int64_t B,
   const int path = pick_path(*c, dtype, flags, &shape, count_slots(*c, ps), true,
                              tuned ? tv.adj_r : 0);
   if (path < 0) return path;
-  const int m_pref = tuned ? tv.m : 0;
+  const TileCfg tcfg = tile_cfg(tuned, tv);
   const size_t need = path == QS_PATH_PLAIN ? plain_workspace_bytes(*c, dtype, B)
-                     : path == QS_PATH_HBM ? tiled_ws_bytes(*c, dtype, B, ps, m_pref, &rc)
+                     : path == QS_PATH_HBM ? tiled_ws_bytes(*c, dtype, B, ps, tcfg, &rc)
                                            : fused_ws_bytes(*c, dtype, shape, B, ps);
   if (rc != QS_OK) return rc;
   if (need > 0 && (!ws || ws_bytes < need)) return QS_ERR_WORKSPACE;
   if (path == QS_PATH_HBM) {
-    TiledEntry* te = get_tiled(*c, dtype, ps, ckpt_gates, n_ckpt, m_pref, &rc);
+    TiledEntry* te = get_tiled(*c, dtype, ps, ckpt_gates, n_ckpt, tcfg, &rc);
     if (!te) return rc;
     const int64_t per = B << c->n_qubits;
     const size_t cs = dtype == QS_C64 ? 8 : 16;
@@ -987,7 +1033,7 @@ int qs_plan_info_get(const qs_circuit* c, int dtype, int64_t B, int flags,
   std::memset(out, 0, sizeof(*out));
   out->path = path;
   if (path == QS_PATH_HBM) {
-    TiledHostInfo h = tiled_host_info(*c, dtype, B, ps, tuned ? tv.m : 0);
+    TiledHostInfo h = tiled_host_info(*c, dtype, B, ps, tile_cfg(tuned, tv));
     if (!h.ok) return QS_ERR_UNSUPPORTED;
     out->n_segments = h.n_epochs;  // epochs
     out->log2_threads = h.m;       // tile qubits
