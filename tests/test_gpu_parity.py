@@ -11,6 +11,7 @@ import pytest
 import oracle as O
 from workloads import circuits as C
 from workloads import data as Dt
+from _patterns import cnot_pattern
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -321,6 +322,48 @@ def test_checkpoints_store_states_and_reanchor(path):
     np.testing.assert_allclose(gp.cpu().numpy(), rp, atol=1e-4)
 
 
+# ------------------------------------------------- CNOTs folded into remaps
+@pytest.mark.parametrize("kind", ["start_end", "zz", "cancel", "only"])
+@pytest.mark.parametrize("n", [3, 7, 11])
+def test_cnot_folding_patterns(n, kind):
+    rng = np.random.default_rng(700 + n)
+    c = cnot_pattern(n, kind)
+    _run_expz_case(c, "c64", "fused", 9, seed=n)
+    if c.n_params:
+        _run_expz_case(c, "c64", "fused", 5, seed=n + 1, per_sample=True)
+    if n <= 7:
+        _run_expz_case(c, "c128", "fused", 4, seed=n + 2)
+
+
+def test_cnot_folding_with_checkpoints_after_cnot_runs():
+    """Checkpoints placed right after CNOT runs: the stored states are the
+    states after those gates, and the backward re-anchors to them."""
+    rng = np.random.default_rng(9)
+    n = 9
+    c = cnot_pattern(n, "start_end")
+    ops = c.gates["op"]
+    ck = [g + 1 for g in range(c.n_gates - 1)
+          if ops[g] == C.OP["CNOT"] and ops[g + 1] != C.OP["CNOT"]]
+    B = 6
+    params = rng.uniform(-np.pi, np.pi, c.n_params).astype(np.float32)
+    x = rng.standard_normal((B, 1 << n)).astype(np.float32)
+    s = sim.Simulator(c, "c64", PATHS["fused"])
+    st = s.encode_amplitude(_dev(x, torch.float32))
+    buf = torch.empty((len(ck),) + tuple(st.shape), dtype=st.dtype, device="cuda")
+    p = _dev(params, torch.float32)
+    s.forward(p, None, st, ckpt_gates=ck, ckpt=buf)
+    dz = torch.as_tensor(rng.uniform(-1, 1, (B, n)), device="cuda")
+    gp, _ = s.adjoint(p, None, st, dexpz=dz, ckpt_gates=ck, ckpt=buf)
+    torch.cuda.synchronize()
+    psi0 = O.encode_amplitude(x, n)
+    for i, g in enumerate(ck):
+        ref = O.run_circuit(C.Circuit(n, c.gates[:g], c.n_params), params, None, psi0)
+        np.testing.assert_allclose(buf[i].cpu().numpy(), ref, atol=1e-5)
+    gth, _ = O.adjoint_vjp(c, params, None, psi0, dexpz=dz.cpu().numpy())
+    np.testing.assert_allclose(gp.cpu().numpy(),
+                               O.theta_to_param_grads(c, params, None, gth)[0], atol=1e-4)
+
+
 def test_autograd_function_matches_oracle():
     rng = np.random.default_rng(5)
     c = C.random_circuit(5, 40, rng, n_params=6, n_features=2)
@@ -360,6 +403,13 @@ def test_tiled_path_random_circuits(n, m, tile_qubits):
     _run_expz_case(c, "c64", "hbm", 5, seed=n)
     _run_expz_case(c, "c64", "hbm", 3, seed=n + 1, per_sample=True)
     _run_expz_case(c, "c64", "hbm", 3, seed=n + 2, dstate_mode=True, amplitude=False)
+
+
+@pytest.mark.parametrize("kind", ["start_end", "zz"])
+def test_tiled_path_cnot_patterns(kind, tile_qubits):
+    tile_qubits(6)
+    c = cnot_pattern(10, kind)
+    _run_expz_case(c, "c64", "hbm", 3, seed=4)
 
 
 def test_tiled_path_c128(tile_qubits):

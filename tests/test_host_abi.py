@@ -12,6 +12,7 @@ import pytest
 from paper_2509_25075_amd import _native as N
 from workloads import circuits as C
 from workloads import data as Dt
+from _patterns import cnot_pattern
 
 HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "qs.h")
 
@@ -160,6 +161,17 @@ def test_plans_of_random_circuits(n):
             continue
         _check_plan(c, dt)
         _check_plan(c, dt, flags=N.QS_FLAG_PER_SAMPLE_PARAMS)
+
+
+@pytest.mark.parametrize("kind", ["start_end", "zz", "cancel", "only"])
+@pytest.mark.parametrize("n", [3, 7, 11])
+def test_plans_fold_cnots_into_remaps(n, kind):
+    c = cnot_pattern(n, kind)
+    info = _check_plan(c, N.QS_C64)
+    _check_plan(c, N.QS_C64, flags=N.QS_FLAG_PER_SAMPLE_PARAMS)
+    if kind == "only":
+        # chain, ring and chain again: one remap carries all of them
+        assert info["n_engine_ops"] == 0 and info["n_remaps"] == 1
 
 
 def test_large_circuits_take_the_tiled_path():
