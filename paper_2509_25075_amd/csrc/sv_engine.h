@@ -63,6 +63,23 @@ __device__ __forceinline__ float dpp(float v) { return dpp_f32<CTRL>(v); }
 template <int CTRL>
 __device__ __forceinline__ double dpp(double v) { return dpp_f64<CTRL>(v); }
 
+// v + (v of lane ^ 16), v + (v of lane ^ 32): gfx950's row-swapping
+// permlanes exchange a value between paired rows without LDS; called with
+// the same register twice, one result keeps the lane's own value and the
+// other receives the partner's, so their sum is the pair sum on every lane.
+__device__ __forceinline__ float xor16_sum(float v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v),
+                                                  false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float xor32_sum(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v),
+                                                  false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ double xor16_sum(double v) { return v + __shfl_xor(v, 16); }
+__device__ __forceinline__ double xor32_sum(double v) { return v + __shfl_xor(v, 32); }
+
 // Sum over aligned groups of G lanes (G a power of two, 1..64, uniform);
 // every lane of a group receives the group's sum. Requires a full wave.
 template <typename real>
@@ -71,8 +88,8 @@ __device__ __forceinline__ real group_sum(real v, int G) {
   if (G >= 4) v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]  (lane ^ 2)
   if (G >= 8) v += dpp<0x141>(v);  // row_half_mirror: the other quad of 8
   if (G >= 16) v += dpp<0x140>(v); // row_mirror: the other 8 of a row
-  if (G >= 32) v += __shfl_xor(v, 16);
-  if (G >= 64) v += __shfl_xor(v, 32);
+  if (G >= 32) v = xor16_sum(v);
+  if (G >= 64) v = xor32_sum(v);
   return v;
 }
 
