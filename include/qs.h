@@ -272,6 +272,30 @@ int qs_plan_export(const qs_circuit* circuit, int dtype, int64_t B, int flags,
                    qs_plan_info* info, int32_t* ops, int32_t* seg_begin,
                    uint8_t* seg_map);
 
+/* Host only: the engine program itself, for inspection and for checking the
+ * planner on the CPU (a test can execute it and compare with a reference).
+ * `adjoint` selects the register split of the adjoint's plan instead of the
+ * forward's. Call once with NULL arrays to get the sizes in `info`, then with
+ * arrays of those sizes:
+ *   ops        [n_ops][5] int32  kind, a, b, aux, gate (SvOp fields; kinds
+ *                                16 = fused single-qubit blocks on every
+ *                                register bit, 17 = CZ sign pattern)
+ *   seg_begin  [n_segments + 1] int32 op ranges
+ *   seg_lay    [n_segments][32] uint16 logical index mask of each physical
+ *              bit: 16 for reading the segment in, 16 for writing it out
+ *   l1q        [n_l1q][8] int32 block id per register bit (-1: none)
+ *   diag       [n_diag][24] uint32 sign-pattern records
+ *   blk_begin  [n_blocks + 1] int32, blk_gates [n_block_gates] int32: the
+ *              gates of each block in application order
+ * Returns QS_ERR_UNSUPPORTED when the circuit does not take the fused path. */
+typedef struct qs_engine_dump {
+  int32_t n_qubits, log2_regs, n_ops, n_segments;
+  int32_t n_l1q, n_diag, n_blocks, n_block_gates;
+} qs_engine_dump;
+int qs_plan_dump(const qs_circuit* circuit, int dtype, int64_t B, int flags, int adjoint,
+                 qs_engine_dump* info, int32_t* ops, int32_t* seg_begin, uint16_t* seg_lay,
+                 int32_t* l1q, uint32_t* diag, int32_t* blk_begin, int32_t* blk_gates);
+
 /* ------------------------------------------------------------- autotuner */
 typedef struct qs_tune_info {
   int32_t path;           /* QS_PATH_FUSED or QS_PATH_HBM                    */

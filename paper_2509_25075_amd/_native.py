@@ -60,6 +60,12 @@ class QsProgram(ctypes.Structure):
                 ("counts", ctypes.POINTER(ctypes.c_int64))]
 
 
+class QsEngineDump(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int32) for k in (
+        "n_qubits", "log2_regs", "n_ops", "n_segments", "n_l1q", "n_diag",
+        "n_blocks", "n_block_gates")]
+
+
 class QsTuneInfo(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("fwd_log2_regs", ctypes.c_int32),
                 ("adj_log2_regs", ctypes.c_int32), ("tile_qubits", ctypes.c_int32),
@@ -118,6 +124,9 @@ def lib() -> ctypes.CDLL:
                                               vp, vp, vp, vp]),
         "qs_autotune": (ctypes.c_int, [cp, ctypes.c_int, i64, ctypes.c_int, vp,
                                        ctypes.POINTER(QsTuneInfo)]),
+        "qs_plan_dump": (ctypes.c_int, [cp, ctypes.c_int, i64, ctypes.c_int, ctypes.c_int,
+                                        ctypes.POINTER(QsEngineDump), vp, vp, vp, vp, vp,
+                                        vp, vp]),
         "qs_shutdown": (None, []),
     }
     for name, (res, args) in sig.items():
@@ -310,6 +319,31 @@ def qs_autotune(h: CircuitHandle, dtype: int, B: int, flags: int = 0, stream=Non
     _check(lib().qs_autotune(h.ptr, dtype, B, flags, _stream(stream), ctypes.byref(info)),
            "qs_autotune")
     return {k: getattr(info, k) for k, _ in QsTuneInfo._fields_}
+
+
+def qs_plan_dump(h: CircuitHandle, dtype: int, B: int, flags: int = 0,
+                 adjoint: bool = False) -> dict:
+    """Host-only dump of the engine program (see include/qs.h)."""
+    info = QsEngineDump()
+    args = (h.ptr, dtype, B, flags, int(adjoint), ctypes.byref(info))
+    _check(lib().qs_plan_dump(*args, None, None, None, None, None, None, None),
+           "qs_plan_dump")
+    d = {k: getattr(info, k) for k, _ in QsEngineDump._fields_}
+    arr = {
+        "ops": np.zeros((max(d["n_ops"], 1), 5), np.int32),
+        "seg_begin": np.zeros(d["n_segments"] + 1, np.int32),
+        "seg_lay": np.zeros((max(d["n_segments"], 1), 32), np.uint16),
+        "l1q": np.zeros((max(d["n_l1q"], 1), 8), np.int32),
+        "diag": np.zeros((max(d["n_diag"], 1), 24), np.uint32),
+        "blk_begin": np.zeros(d["n_blocks"] + 1, np.int32),
+        "blk_gates": np.zeros(max(d["n_block_gates"], 1), np.int32),
+    }
+    _check(lib().qs_plan_dump(*args, *(a.ctypes.data_as(ctypes.c_void_p) for a in (
+        arr["ops"], arr["seg_begin"], arr["seg_lay"], arr["l1q"], arr["diag"],
+        arr["blk_begin"], arr["blk_gates"]))), "qs_plan_dump")
+    arr["ops"] = arr["ops"][:d["n_ops"]]
+    d.update(arr)
+    return d
 
 
 def qs_shutdown():

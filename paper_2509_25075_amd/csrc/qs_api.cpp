@@ -1082,6 +1082,46 @@ int qs_plan_export(const qs_circuit* c, int dtype, int64_t B, int flags,
   return QS_OK;
 }
 
+int qs_plan_dump(const qs_circuit* c, int dtype, int64_t B, int flags, int adjoint,
+                 qs_engine_dump* info, int32_t* ops, int32_t* seg_begin, uint16_t* seg_lay,
+                 int32_t* l1q, uint32_t* diag, int32_t* blk_begin, int32_t* blk_gates) {
+  if (!info) return QS_ERR_INVALID;
+  qs_plan_info pi;
+  int rc = qs_plan_info_get(c, dtype, B, flags, &pi);
+  if (rc != QS_OK) return rc;
+  if (pi.path != QS_PATH_FUSED) return QS_ERR_UNSUPPORTED;
+  const bool ps = (flags & QS_FLAG_PER_SAMPLE_PARAMS) != 0;
+  const int r = adjoint ? pi.adj_log2_regs : pi.log2_regs;
+  if (r <= 0) return QS_ERR_UNSUPPORTED;
+  SvPlan P = plan_sv(*c, r, ps, nullptr, 0);
+  info->n_qubits = P.n;
+  info->log2_regs = P.r;
+  info->n_ops = (int32_t)P.ops.size();
+  info->n_segments = P.nseg();
+  info->n_l1q = (int32_t)(P.l1q.size() / kL1QWords);
+  info->n_diag = (int32_t)(P.diag.size() / kDiagWords);
+  info->n_blocks = P.n_blocks();
+  info->n_block_gates = (int32_t)P.blk_gates.size();
+  if (ops)
+    for (size_t o = 0; o < P.ops.size(); ++o) {
+      ops[5 * o] = P.ops[o].kind;
+      ops[5 * o + 1] = P.ops[o].a;
+      ops[5 * o + 2] = P.ops[o].b;
+      ops[5 * o + 3] = P.ops[o].aux;
+      ops[5 * o + 4] = P.ops[o].gate;
+    }
+  if (seg_begin)
+    std::memcpy(seg_begin, P.seg_begin.data(), sizeof(int32_t) * P.seg_begin.size());
+  if (seg_lay) std::memcpy(seg_lay, P.seg_lay.data(), sizeof(uint16_t) * P.seg_lay.size());
+  if (l1q) std::memcpy(l1q, P.l1q.data(), sizeof(int32_t) * P.l1q.size());
+  if (diag) std::memcpy(diag, P.diag.data(), sizeof(uint32_t) * P.diag.size());
+  if (blk_begin)
+    std::memcpy(blk_begin, P.blk_begin.data(), sizeof(int32_t) * P.blk_begin.size());
+  if (blk_gates)
+    std::memcpy(blk_gates, P.blk_gates.data(), sizeof(int32_t) * P.blk_gates.size());
+  return QS_OK;
+}
+
 void qs_shutdown(void) {
   std::lock_guard<std::mutex> lock(g_mu);
   for (auto& kv : g_cache) {

@@ -222,3 +222,116 @@ def test_workspace_sizes():
     assert fused == blocks * w.circuit.n_params * 4
     plain = N.qs_workspace_size(h, N.QS_C64, 4096, N.QS_PATH_PLAIN)
     assert plain == 2 * 4096 * 1024 * 8 + 4096 * w.circuit.n_gates * 8
+
+
+# ------------------------------------------------ the engine program, on CPU
+def _popc(x):
+    return bin(int(x)).count("1")
+
+
+def _run_engine_program(c, d, params, feats, psi0):
+    """Executes a dumped engine program with NumPy, in the engine's own
+    physical index space: read the state in under the first segment's
+    layout, apply each op to physical bits, remap between segments through
+    the write/read layouts, write the final state out. Independent of the
+    HIP kernels; gate matrices and angles come from the oracle."""
+    import oracle as O
+
+    n, r = d["n_qubits"], d["log2_regs"]
+    N, R = 1 << n, 1 << r
+    B = psi0.shape[0]
+    phys = np.arange(N)
+
+    def logical(lay):
+        L = np.zeros(N, dtype=np.int64)
+        for bit in range(n):
+            L ^= ((phys >> bit) & 1) * int(lay[bit])
+        return L
+
+    def gate_u(g):
+        gt = c.gates[g]
+        op = int(gt["op"])
+        if op <= C.OP["RZ"]:
+            return O.gate_matrix(op, O.gate_angles(gt, params, feats, B))
+        return np.broadcast_to(O.gate_matrix(op), (B, 2, 2))
+
+    lay = d["seg_lay"]
+    sb = d["seg_begin"]
+    cur = psi0[:, logical(lay[0][:16])]
+    pat = [0xAAAAAAAA, 0xCCCCCCCC, 0xF0F0F0F0, 0xFF00FF00, 0xFFFF0000]
+    for s in range(d["n_segments"]):
+        if s > 0:
+            lg = np.empty_like(cur)
+            lg[:, logical(lay[s - 1][16:])] = cur
+            cur = lg[:, logical(lay[s][:16])]
+        for o in range(sb[s], sb[s + 1]):
+            kind, a, b, aux, rec = (int(v) for v in d["ops"][o])
+            if kind == 16:
+                for j in range(r):
+                    bid = int(d["l1q"][rec][j])
+                    if bid < 0:
+                        continue
+                    U = np.broadcast_to(np.eye(2, dtype=np.complex128), (B, 2, 2))
+                    for g in d["blk_gates"][d["blk_begin"][bid]:d["blk_begin"][bid + 1]]:
+                        U = gate_u(int(g)) @ U
+                    cur = O.apply_1q(cur, j, U)
+            elif kind == 17:
+                rd = d["diag"][rec]
+                sign = np.ones(N)
+                for p in range(N):
+                    k, tau = p & (R - 1), p >> r
+                    par = _popc(tau & int(rd[1]))
+                    for i in range(n - r):
+                        if (tau >> i) & 1:
+                            par += _popc(tau & int(rd[7 + i]))
+                    m = int(rd[0]) ^ (0xFFFFFFFF if par & 1 else 0)
+                    for j in range(r):
+                        if _popc(tau & int(rd[2 + j])) & 1:
+                            m ^= pat[j]
+                    if (m >> k) & 1:
+                        sign[p] = -1
+                cur = cur * sign[None, :]
+            else:
+                assert kind <= C.OP["H"], "only single-qubit gates stay single ops"
+                cur = O.apply_1q(cur, a, gate_u(rec))
+    out = np.empty_like(cur)
+    out[:, logical(lay[d["n_segments"] - 1][16:])] = cur
+    return out
+
+
+def _engine_program_case(c, seed, flags=0, B=3):
+    import oracle as O
+
+    rng = np.random.default_rng(seed)
+    ps = bool(flags & N.QS_FLAG_PER_SAMPLE_PARAMS)
+    params = rng.uniform(-np.pi, np.pi, (B, c.n_params) if ps else c.n_params)
+    feats = rng.uniform(-1, 1, (B, c.n_features)) if c.n_features else None
+    x = rng.standard_normal((B, 1 << c.n_qubits))
+    psi0 = O.encode_amplitude(x, c.n_qubits)
+    ref = O.run_circuit(c, params, feats, psi0)
+    h = N.CircuitHandle(c)
+    for adjoint in (False, True):
+        d = N.qs_plan_dump(h, N.QS_C64, 64, flags, adjoint=adjoint)
+        got = _run_engine_program(c, d, params, feats, psi0)
+        np.testing.assert_allclose(got, ref, atol=1e-12, rtol=0)
+
+
+@pytest.mark.parametrize("n", [2, 4, 5, 6, 8, 9])
+def test_engine_program_executes_the_circuit(n):
+    """The planner's engine program (fused blocks, sign patterns, CNOTs folded
+    into remap layouts), executed on the CPU, gives the oracle's state."""
+    rng = np.random.default_rng(900 + n)
+    c = C.random_circuit(n, 70, rng, n_params=5, n_features=2)
+    _engine_program_case(c, seed=n)
+    _engine_program_case(c, seed=n, flags=N.QS_FLAG_PER_SAMPLE_PARAMS)
+
+
+@pytest.mark.parametrize("kind", ["start_end", "zz", "cancel", "only"])
+def test_engine_program_cnot_patterns(kind):
+    _engine_program_case(cnot_pattern(7, kind), seed=3)
+
+
+@pytest.mark.parametrize("key", ["c1", "c2", "c3"])
+def test_engine_program_of_workloads(key):
+    w = Dt.make_workload(key, 2)
+    _engine_program_case(w.circuit, seed=1, B=2)
