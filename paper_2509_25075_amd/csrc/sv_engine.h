@@ -80,6 +80,20 @@ __device__ __forceinline__ float xor32_sum(float v) {
 __device__ __forceinline__ double xor16_sum(double v) { return v + __shfl_xor(v, 16); }
 __device__ __forceinline__ double xor32_sum(double v) { return v + __shfl_xor(v, 32); }
 
+// Sum over the lanes l, l ^ G, l ^ 2G, ... (G a power of two, uniform): with
+// every lane of each aligned group of G lanes holding that group's value,
+// each lane receives the sum over all groups of the wave.
+template <typename real>
+__device__ __forceinline__ real cross_sum(real v, int G) {
+  if (G <= 1) v += dpp<0xB1>(v);
+  if (G <= 2) v += dpp<0x4E>(v);
+  if (G <= 4) v += dpp<0x141>(v);
+  if (G <= 8) v += dpp<0x140>(v);
+  if (G <= 16) v = xor16_sum(v);
+  if (G <= 32) v = xor32_sum(v);
+  return v;
+}
+
 // Sum over aligned groups of G lanes (G a power of two, 1..64, uniform);
 // every lane of a group receives the group's sum. Requires a full wave.
 template <typename real>
@@ -905,12 +919,13 @@ struct Ctx {
         if (gt.p_b >= 0) atomicAdd(&gp[gt.p_b], (double)(gth * scale));
       }
     } else {
+      // every lane of a sample holds its gth: sum over the wave's samples
       if (gt.p_w >= 0) {
-        const real v = group_sum(leader ? gth * scale * f : (real)0, 64);
+        const real v = cross_sum(active ? gth * scale * f : (real)0, Tw);
         if (lane == 0) atomicAdd(&gacc[(size_t)wave * A.n_params + gt.p_w], v);
       }
       if (gt.p_b >= 0) {
-        const real v = group_sum(leader ? gth * scale : (real)0, 64);
+        const real v = cross_sum(active ? gth * scale : (real)0, Tw);
         if (lane == 0) atomicAdd(&gacc[(size_t)wave * A.n_params + gt.p_b], v);
       }
     }
