@@ -414,6 +414,35 @@ __device__ __forceinline__ U2<real> gate_u(int kind, real c, real s) {
   }
 }
 
+// G U for a gate G of `kind` (rotations with (c, s) of theta/2), using the
+// gate's structure instead of a full 2x2 complex product.
+template <typename real>
+__device__ __forceinline__ U2<real> gate_lmul(int kind, real c, real s, const U2<real>& u) {
+  U2<real> o;
+  switch (kind) {
+    case QS_OP_RX:  // [[c, -i s], [-i s, c]]: row0' = c row0 - i s row1, row1' = c row1 - i s row0
+      o.r00 = c * u.r00 + s * u.i10; o.i00 = c * u.i00 - s * u.r10;
+      o.r01 = c * u.r01 + s * u.i11; o.i01 = c * u.i01 - s * u.r11;
+      o.r10 = c * u.r10 + s * u.i00; o.i10 = c * u.i10 - s * u.r00;
+      o.r11 = c * u.r11 + s * u.i01; o.i11 = c * u.i11 - s * u.r01;
+      return o;
+    case QS_OP_RY:  // [[c, -s], [s, c]]
+      o.r00 = c * u.r00 - s * u.r10; o.i00 = c * u.i00 - s * u.i10;
+      o.r01 = c * u.r01 - s * u.r11; o.i01 = c * u.i01 - s * u.i11;
+      o.r10 = s * u.r00 + c * u.r10; o.i10 = s * u.i00 + c * u.i10;
+      o.r11 = s * u.r01 + c * u.r11; o.i11 = s * u.i01 + c * u.i11;
+      return o;
+    case QS_OP_RZ:  // row0 * (c - i s), row1 * (c + i s)
+      o.r00 = c * u.r00 + s * u.i00; o.i00 = c * u.i00 - s * u.r00;
+      o.r01 = c * u.r01 + s * u.i01; o.i01 = c * u.i01 - s * u.r01;
+      o.r10 = c * u.r10 - s * u.i10; o.i10 = c * u.i10 + s * u.r10;
+      o.r11 = c * u.r11 - s * u.i11; o.i11 = c * u.i11 + s * u.r11;
+      return o;
+    default:
+      return u_mul(gate_u<real>(kind, c, s), u);
+  }
+}
+
 // x <- U x on register bit J.
 template <int J, typename real, int R>
 __device__ __forceinline__ void g_u(St<real, R>& x, const U2<real>& u) {
@@ -839,8 +868,7 @@ struct Ctx {
       const int kind = kload(A.gates, g).op;
       real c = 1, s = 0;
       if (kind <= QS_OP_RZ) gate_cs(g, c, s);
-      const U2<real> m = gate_u<real>(kind, c, s);
-      u = i == b0 ? m : u_mul(m, u);
+      u = i == b0 ? gate_u<real>(kind, c, s) : gate_lmul(kind, c, s, u);
     }
     return u;
   }
@@ -1126,7 +1154,7 @@ __device__ __forceinline__ void setup(Ctx<real, LR, FLY>& C, const Args<real>& A
     U2<real> u{1, 0, 0, 0, 0, 0, 1, 0};
     for (int i = A.blk_begin[bid]; i < A.blk_begin[bid + 1]; ++i) {
       const int g = A.blk_gates[i];
-      u = u_mul(gate_u<real>(A.gates[g].op, C.ang_sh[2 * g], C.ang_sh[2 * g + 1]), u);
+      u = gate_lmul(A.gates[g].op, C.ang_sh[2 * g], C.ang_sh[2 * g + 1], u);
     }
     real* f = C.fu_sh + 8 * (size_t)fu;
     f[0] = u.r00; f[1] = u.i00; f[2] = u.r01; f[3] = u.i01;
