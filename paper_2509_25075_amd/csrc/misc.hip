@@ -185,19 +185,29 @@ fidelity_kernel(int n, int nt, const real* psi, const real* chi, double* fid,
   }
 }
 
-// out[c] = sum_r partials[r][c] in FP64: one block per column, threads
-// stride over rows, then a block reduction.
+// out[col_param[c]] (+)= sum_r partials[r][c] in FP64: one block per column,
+// threads stride over rows with four independent sums each, then a block
+// reduction. The order of the additions is fixed, so the result is
+// reproducible bit for bit.
 template <typename acc_t>
 __global__ void __launch_bounds__(kBlock)
-reduce_partials(const acc_t* partials, int64_t rows, int cols, double* out,
-                int accumulate) {
+reduce_partials(const acc_t* partials, int64_t rows, int cols, const int32_t* col_param,
+                double* out, int accumulate) {
   __shared__ double sh[kBlock / 64];
   const int c = blockIdx.x;
-  double s = 0;
-  for (int64_t r = threadIdx.x; r < rows; r += blockDim.x)
-    s += (double)partials[r * cols + c];
-  s = block_sum(s, sh);
-  if (threadIdx.x == 0) out[c] = accumulate ? out[c] + s : s;
+  const int64_t step = blockDim.x;
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  int64_t r = threadIdx.x;
+  for (; r + 3 * step < rows; r += 4 * step) {
+    s0 += (double)partials[r * cols + c];
+    s1 += (double)partials[(r + step) * cols + c];
+    s2 += (double)partials[(r + 2 * step) * cols + c];
+    s3 += (double)partials[(r + 3 * step) * cols + c];
+  }
+  for (; r < rows; r += step) s0 += (double)partials[r * cols + c];
+  double s = block_sum((s0 + s1) + (s2 + s3), sh);
+  const int o = col_param != nullptr ? col_param[c] : c;
+  if (threadIdx.x == 0) out[o] = accumulate ? out[o] + s : s;
 }
 
 __global__ void __launch_bounds__(kBlock) fill_f64(double* p, int64_t n) {
@@ -328,15 +338,16 @@ int launch_fidelity(int dtype, int n, int n_trash, int64_t B, const void* psi,
 }
 
 int launch_reduce_partials(int dtype, const void* partials, int64_t rows,
-                           int cols, double* out, int accumulate, void* stream) {
+                           int cols, const int32_t* col_param, double* out,
+                           int accumulate, void* stream) {
   if (cols <= 0) return QS_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (dtype == QS_C64)
     hipLaunchKernelGGL(reduce_partials<float>, dim3((unsigned)cols), kBlock, 0, st,
-                       (const float*)partials, rows, cols, out, accumulate);
+                       (const float*)partials, rows, cols, col_param, out, accumulate);
   else
     hipLaunchKernelGGL(reduce_partials<double>, dim3((unsigned)cols), kBlock, 0, st,
-                       (const double*)partials, rows, cols, out, accumulate);
+                       (const double*)partials, rows, cols, col_param, out, accumulate);
   return ok();
 }
 

@@ -373,7 +373,35 @@ SvPlan plan_sv(const qs_circuit& c, int r, bool per_sample_angles_all,
                     &P.seg_lay[(size_t)s * kLayWords], kMapStride * 2) != 0)
       ++changes;
   P.n_remaps = changes;
+  // Gradient columns of the shared parameters, and each rotation's columns.
+  P.grad_cols = grad_columns(c, per_sample_angles_all);
+  if (!per_sample_angles_all) {
+    std::vector<int32_t> col(c.n_params > 0 ? c.n_params : 1, -1);
+    for (size_t j = 0; j < P.grad_cols.size(); ++j) col[P.grad_cols[j]] = (int32_t)j;
+    P.gate_cols.assign(2 * (size_t)G, -1);
+    for (int g = 0; g < G; ++g) {
+      const qs_gate& x = c.gates[g];
+      if (!is_rotation(x.op)) continue;
+      if (x.p_w >= 0) P.gate_cols[2 * (size_t)g] = col[x.p_w];
+      if (x.p_b >= 0) P.gate_cols[2 * (size_t)g + 1] = col[x.p_b];
+    }
+  }
   return P;
+}
+
+std::vector<int32_t> grad_columns(const qs_circuit& c, bool per_sample_params) {
+  std::vector<int32_t> cols;
+  if (per_sample_params || c.n_params <= 0) return cols;
+  std::vector<char> used(c.n_params, 0);
+  for (int g = 0; g < c.n_gates; ++g) {
+    const qs_gate& x = c.gates[g];
+    if (!is_rotation(x.op)) continue;
+    if (x.p_w >= 0) used[x.p_w] = 1;
+    if (x.p_b >= 0) used[x.p_b] = 1;
+  }
+  for (int p = 0; p < c.n_params; ++p)
+    if (used[p]) cols.push_back(p);
+  return cols;
 }
 
 std::vector<TiledEpoch> plan_tiled(const qs_circuit& c, int m, int low_keep,

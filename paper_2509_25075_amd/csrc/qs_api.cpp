@@ -153,7 +153,8 @@ int64_t lds_bytes(int dtype, const qs_circuit& c, int S, int n_slots, int block,
   b += 8 * rs * n1q;                                // fused block matrices
   b += 2 * rs * (int64_t)n_slots * S;               // per-sample angle table
   if (adjoint)                                      // gradient sums
-    b += rs * ((ps ? 0 : waves * c.n_params) + (int64_t)S * wps * c.n_features);
+    b += rs * (waves * (int64_t)grad_columns(c, ps).size() +
+               (int64_t)S * wps * c.n_features);
   return (b + 15) & ~15ll;
 }
 
@@ -266,6 +267,8 @@ void free_dev(SvDevPlan& d) {
   (void)hipFree(d.blk_begin);
   (void)hipFree(d.blk_gates);
   (void)hipFree(d.blk_fu);
+  (void)hipFree(d.gate_cols);
+  (void)hipFree(d.grad_cols);
 }
 
 // Plans on the host and uploads once per (circuit, r, flags, device). The
@@ -296,6 +299,7 @@ Entry* get_plan(const qs_circuit& c, int r, bool ps, const int32_t* ck, int n_ck
   d.n_ops = (int)P.ops.size();
   d.n_blocks = P.n_blocks();
   d.n_fu = P.n_fu;
+  d.n_acc = (int)P.grad_cols.size();
   bool okk = upload(&d.seg_map, P.seg_map.data(), P.seg_map.size()) &&
              upload(&d.seg_lay, P.seg_lay.data(), P.seg_lay.size()) &&
              upload(&d.seg_begin, P.seg_begin.data(), P.seg_begin.size()) &&
@@ -308,7 +312,9 @@ Entry* get_plan(const qs_circuit& c, int r, bool ps, const int32_t* ck, int n_ck
              upload(&d.diag, P.diag.data(), P.diag.size()) &&
              upload(&d.blk_begin, P.blk_begin.data(), P.blk_begin.size()) &&
              upload(&d.blk_gates, P.blk_gates.data(), P.blk_gates.size()) &&
-             upload(&d.blk_fu, P.blk_fu.data(), P.blk_fu.size());
+             upload(&d.blk_fu, P.blk_fu.data(), P.blk_fu.size()) &&
+             upload(&d.gate_cols, P.gate_cols.data(), P.gate_cols.size()) &&
+             upload(&d.grad_cols, P.grad_cols.data(), P.grad_cols.size());
   if (!okk) {
     free_dev(d);
     delete e;
@@ -432,10 +438,11 @@ TiledEntry* get_tiled(const qs_circuit& c, int dtype, bool ps, const int32_t* ck
   return te;
 }
 
-// Host-only view of the tiled plan: tile size, epochs, largest adjoint grid.
+// Host-only view of the tiled plan: tile size, epochs, largest adjoint grid
+// and largest per-block gradient-sum array (blocks x gradient columns).
 struct TiledHostInfo {
   int m = 0, n_epochs = 0;
-  int64_t max_grid = 1;
+  int64_t max_grid = 1, max_part = 1;
   bool ok = true;
 };
 TiledHostInfo tiled_host_info(const qs_circuit& c, int dtype, int64_t B, bool ps,
@@ -457,6 +464,8 @@ TiledHostInfo tiled_host_info(const qs_circuit& c, int dtype, int64_t B, bool ps
     if (!choose_shape(dtype, sub, slots, tc.adj_r, true, &a, ps)) { h.ok = false; continue; }
     const int64_t g = (samples + a.samples_per_block - 1) / a.samples_per_block;
     if (g > h.max_grid) h.max_grid = g;
+    const int64_t cols = (int64_t)grad_columns(sub, ps).size();
+    if (g * cols > h.max_part) h.max_part = g * cols;
   }
   return h;
 }
@@ -471,7 +480,7 @@ size_t tiled_ws_bytes(const qs_circuit& c, int dtype, int64_t B, bool ps,
   const size_t cs = dtype == QS_C64 ? 8 : 16;
   const size_t acc = dtype == QS_C64 ? 4 : 8;
   const size_t st = ((size_t)B << c.n_qubits) * cs;
-  size_t part = ps ? 0 : (size_t)h.max_grid * (size_t)(c.n_params ? c.n_params : 1) * acc;
+  size_t part = ps ? 0 : (size_t)h.max_part * acc;
   return 2 * st + ((part + 255) & ~(size_t)255);
 }
 
@@ -513,7 +522,8 @@ size_t fused_ws_bytes(const qs_circuit& c, int dtype, const SvShape& s, int64_t 
                       bool ps) {
   if (ps) return 0;
   const size_t acc = dtype == QS_C64 ? sizeof(float) : sizeof(double);
-  return (size_t)grid_of(s, B) * (size_t)(c.n_params ? c.n_params : 1) * acc;
+  const size_t cols = std::max<size_t>(grad_columns(c, false).size(), 1);
+  return (size_t)grid_of(s, B) * cols * acc;
 }
 
 bool tuned_for_call(const qs_circuit& c, int dtype, int64_t B, int flags, void* stream,
@@ -941,9 +951,10 @@ int qs_adjoint_backward(const qs_circuit* c, int dtype, int64_t B,
       L.outer_q = d.outer_q;
       L.stream = stream;
       if ((rc = launch_sv_adjoint(dtype, L)) != QS_OK) return rc;
-      if (!ps && c->n_params) {
+      if (!ps && d.adj->dev.n_acc) {
         const int64_t grid = (samples + d.ashape.samples_per_block - 1) / d.ashape.samples_per_block;
-        rc = launch_reduce_partials(dtype, part, grid, c->n_params, grad_params, 1, stream);
+        rc = launch_reduce_partials(dtype, part, grid, d.adj->dev.n_acc, d.adj->dev.grad_cols,
+                                    grad_params, 1, stream);
         if (rc != QS_OK) return rc;
       }
     }
@@ -993,9 +1004,14 @@ int qs_adjoint_backward(const qs_circuit* c, int dtype, int64_t B,
   L.grad_feats = c->n_features ? grad_feats : nullptr;
   L.stream = stream;
   if ((rc = launch_sv_adjoint(dtype, L)) != QS_OK) return rc;
-  if (!ps && c->n_params)
-    rc = launch_reduce_partials(dtype, ws, grid_of(shape, B), c->n_params,
-                                grad_params, 0, stream);
+  if (!ps && c->n_params) {
+    // Parameters no rotation reads get a zero gradient.
+    const int n_acc = e->dev.n_acc;
+    if (n_acc < c->n_params && (rc = launch_fill_f64(grad_params, c->n_params, stream)) != QS_OK)
+      return rc;
+    rc = launch_reduce_partials(dtype, ws, grid_of(shape, B), n_acc, e->dev.grad_cols,
+                                grad_params, n_acc < c->n_params, stream);
+  }
   return rc;
 }
 

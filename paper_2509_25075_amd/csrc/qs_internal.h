@@ -72,6 +72,8 @@ struct SvPlan {
                                       // (angles shared), -1: built per sample
   std::vector<int32_t> exec;          // [G][3] gate, physical a, physical b
   std::vector<int32_t> exec_seg;      // [nseg + 1] ranges of exec rows
+  std::vector<int32_t> grad_cols;     // shared parameter of each gradient column
+  std::vector<int32_t> gate_cols;     // [G][2] columns of p_w and p_b, or -1
   int n_remaps = 0;
   int nseg() const { return (int)seg_begin.size() - 1; }
   int n_fu = 0;                       // blocks with a fused-matrix slot
@@ -83,6 +85,12 @@ struct SvPlan {
 // rotations with a feature are. Checkpoint boundaries force segment ends.
 SvPlan plan_sv(const qs_circuit& c, int r, bool per_sample_angles_all,
                const int32_t* ckpt_gates, int n_ckpt);
+
+// The shared parameters that the circuit's rotations read, ascending. The
+// adjoint keeps per-block gradient sums only for these (its "gradient
+// columns"); a sub-circuit of a large state touches few of the parameters.
+// Empty for per-sample parameter sets, whose gradients go straight to HBM.
+std::vector<int32_t> grad_columns(const qs_circuit& c, bool per_sample_params);
 
 // Large states: the gate list is cut into epochs; each epoch acts only on a
 // tile set L of m qubits (sorted; always containing the `low_keep` lowest
@@ -115,7 +123,9 @@ struct SvDevPlan {
   int32_t* blk_begin;
   int32_t* blk_gates;
   int32_t* blk_fu;
-  int n_blocks, n_fu;
+  int32_t* gate_cols;  // [G][2] gradient columns of p_w, p_b (shared params)
+  int32_t* grad_cols;  // [n_acc] parameter of each gradient column
+  int n_blocks, n_fu, n_acc;
 };
 
 // Launch geometry of the engine for a plan.
@@ -162,8 +172,10 @@ int launch_expz(int dtype, int n, int64_t B, const void* state, double* expz,
 int launch_fidelity(int dtype, int n, int n_trash, int64_t B, const void* psi,
                     const void* chi, double* fid, const double* dfid,
                     void* lam_psi, void* lam_chi, void* stream);
+// out[col_param[j]] (+)= sum over rows of partials[row][j], j < cols.
 int launch_reduce_partials(int dtype, const void* partials, int64_t rows,
-                           int cols, double* out, int accumulate, void* stream);
+                           int cols, const int32_t* col_param, double* out,
+                           int accumulate, void* stream);
 int launch_obs_cot(int dtype, int n, int64_t B, const double* dexpz,
                    const void* psi, void* lam, void* stream);
 int launch_fill_f64(double* p, int64_t n, void* stream);

@@ -128,6 +128,11 @@ __device__ __forceinline__ T kload(const T* base, int i) {
   return out;
 }
 
+// Gradient columns of a rotation's two shared parameters (-1: none).
+struct ColPair {
+  int32_t w, b;
+};
+
 __device__ __forceinline__ int uni(int v) {
   return __builtin_amdgcn_readfirstlane(v);
 }
@@ -617,8 +622,10 @@ struct Args {
   const int32_t* blk_begin;  // fused single-qubit blocks
   const int32_t* blk_gates;
   const int32_t* blk_fu;
+  const int32_t* gate_cols;  // [G][2] gradient columns of p_w, p_b (shared params)
   int n_blocks, n_fu;
   int n, t, nseg, n_gates, n_slots, n_params, n_feats, S;
+  int n_acc;                 // gradient columns: shared parameters the plan reads
   int per_sample_params;
   int64_t B;               // samples processed (tiled: batch rows << ob)
   int n_tot, ob;           // tiled: qubits of the whole state, outer bits
@@ -692,7 +699,7 @@ struct Ctx {
   real* ang_sh;      // [G][2] shared (cos, sin) of theta/2, by gate
   real* ang_ps;      // [n_slots][S][2] per-sample
   real* fu_sh;       // [n_fu][8] fused matrices of blocks with shared angles
-  real* gacc;        // [waves][n_params] shared-parameter gradient sums
+  real* gacc;        // [waves][n_acc] shared-parameter gradient sums
   real* facc;        // [S * wps][n_feats] feature gradient sums
   int wps;           // waves per sample (1 when a wave holds whole samples)
 
@@ -921,16 +928,17 @@ struct Ctx {
   // LDS slot has a single writer (one lane of one wave), so its LDS atomic
   // adds (which need no wait) happen in program order: the sums stay
   // bitwise reproducible.
-  __device__ __forceinline__ void accum(const qs_gate& gt, real part, int lane, int wave,
-                                        int Tw) {
+  __device__ __forceinline__ void accum(int g, const qs_gate& gt, real part, int lane,
+                                        int wave, int Tw) {
     const real scale = (real)gt.scale;
     if (!A.per_sample_params && gt.feat < 0) {
       // shared parameters, no feature: dL/dP += scale sum_b dL/dtheta_b
       const real v = group_sum(part, 64);
       if (lane == 0) {
-        real* g = gacc + (size_t)wave * A.n_params;
-        if (gt.p_w >= 0) atomicAdd(&g[gt.p_w], scale * v);
-        if (gt.p_b >= 0) atomicAdd(&g[gt.p_b], scale * v);
+        const ColPair cp = kload(reinterpret_cast<const ColPair*>(A.gate_cols), g);
+        real* ga = gacc + (size_t)wave * A.n_acc;
+        if (cp.w >= 0) atomicAdd(&ga[cp.w], scale * v);
+        if (cp.b >= 0) atomicAdd(&ga[cp.b], scale * v);
       }
       return;
     }
@@ -948,13 +956,14 @@ struct Ctx {
       }
     } else {
       // every lane of a sample holds its gth: sum over the wave's samples
+      const ColPair cp = kload(reinterpret_cast<const ColPair*>(A.gate_cols), g);
       if (gt.p_w >= 0) {
         const real v = cross_sum(active ? gth * scale * f : (real)0, Tw);
-        if (lane == 0) atomicAdd(&gacc[(size_t)wave * A.n_params + gt.p_w], v);
+        if (lane == 0) atomicAdd(&gacc[(size_t)wave * A.n_acc + cp.w], v);
       }
       if (gt.p_b >= 0) {
         const real v = cross_sum(active ? gth * scale : (real)0, Tw);
-        if (lane == 0) atomicAdd(&gacc[(size_t)wave * A.n_params + gt.p_b], v);
+        if (lane == 0) atomicAdd(&gacc[(size_t)wave * A.n_acc + cp.b], v);
       }
     }
     if (gt.feat >= 0 && leader)
@@ -980,7 +989,7 @@ struct Ctx {
           real c = 1, sn = 0;
           if (gt.op <= QS_OP_RZ) {
             gate_cs(g, c, sn);
-            accum(gt, im_tr(gt.op, q), lane, wave, Tw);
+            accum(g, gt, im_tr(gt.op, q), lane, wave, Tw);
           }
           if (i > b0) q = q_back(gt.op, c, sn, q);
         }
@@ -1116,7 +1125,7 @@ __device__ __forceinline__ void setup(Ctx<real, LR, FLY>& C, const Args<real>& A
   C.gacc = C.fu_sh + 8 * (size_t)A.n_fu;
   C.wps = A.t > 6 ? (1 << (A.t - 6)) : 1;
   const int waves = blockDim.x >> 6;
-  C.facc = C.gacc + (A.per_sample_params ? 0 : (size_t)waves * A.n_params);
+  C.facc = C.gacc + (A.per_sample_params ? 0 : (size_t)waves * A.n_acc);
 
   // Shared angles, by gate.
   for (int g = tid; g < A.n_gates; g += blockDim.x) {
@@ -1143,7 +1152,7 @@ __device__ __forceinline__ void setup(Ctx<real, LR, FLY>& C, const Args<real>& A
   }
   if (adjoint) {
     if (!A.per_sample_params)
-      for (int i = tid; i < waves * A.n_params; i += blockDim.x) C.gacc[i] = 0;
+      for (int i = tid; i < waves * A.n_acc; i += blockDim.x) C.gacc[i] = 0;
     for (int i = tid; i < A.S * C.wps * A.n_feats; i += blockDim.x) C.facc[i] = 0;
   }
   __syncthreads();
@@ -1342,7 +1351,7 @@ __device__ __forceinline__ void adjoint_body(const Args<real>& A, unsigned char*
       if (kind <= QS_OP_RZ) {
         C.gate_cs(cur.gate, c, sn);
         const qs_gate gt = kload(A.gates, cur.gate);
-        C.accum(gt, C.grad_partial(kind, a, psi, lam), lane, wave, Tw);
+        C.accum(cur.gate, gt, C.grad_partial(kind, a, psi, lam), lane, wave, Tw);
         sn = -sn;  // inverse rotation
       }
       C.apply(psi, kind, a, bq, c, sn);
@@ -1358,10 +1367,10 @@ __device__ __forceinline__ void adjoint_body(const Args<real>& A, unsigned char*
   __syncthreads();
   const int waves = blockDim.x >> 6;
   if (!A.per_sample_params)
-    for (int i = threadIdx.x; i < A.n_params; i += blockDim.x) {
+    for (int i = threadIdx.x; i < A.n_acc; i += blockDim.x) {
       real t = 0;
-      for (int w = 0; w < waves; ++w) t += C.gacc[(size_t)w * A.n_params + i];
-      A.ws_partials[(size_t)blockIdx.x * A.n_params + i] = t;
+      for (int w = 0; w < waves; ++w) t += C.gacc[(size_t)w * A.n_acc + i];
+      A.ws_partials[(size_t)blockIdx.x * A.n_acc + i] = t;
     }
   if (A.grad_feats != nullptr)
     for (int i = threadIdx.x; i < A.S * A.n_feats; i += blockDim.x) {
@@ -1432,6 +1441,8 @@ sv_program(const ProgClass* classes, const ProgItem* items, int n_items,
     A.n_gates = cd.n_gates;
     A.n_slots = cd.n_slots;
     A.n_params = cd.n_params;
+    A.gate_cols = nullptr;  // per-sample parameter sets: no gradient columns
+    A.n_acc = 0;
     A.n_feats = 0;
     A.S = cd.S;
     A.per_sample_params = 1;
@@ -1488,6 +1499,8 @@ Args<real> make_args(const SvLaunch& L) {
   A.n_gates = p.n_gates;
   A.n_slots = p.n_slots;
   A.n_params = p.n_params;
+  A.gate_cols = p.gate_cols;
+  A.n_acc = p.n_acc;
   A.n_feats = p.n_features;
   A.S = L.shape.samples_per_block;
   A.per_sample_params = L.per_sample_params;

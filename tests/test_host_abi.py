@@ -219,7 +219,12 @@ def test_workspace_sizes():
     fused = N.qs_workspace_size(h, N.QS_C64, 4096)
     info = N.qs_plan_info_get(h, N.QS_C64, 4096)
     blocks = -(-4096 // info["adj_samples_per_block"])
-    assert fused == blocks * w.circuit.n_params * 4
+    # one FP32 partial sum per block and shared parameter that a rotation reads
+    gs = w.circuit.gates
+    rot = gs["op"] <= 2
+    read = set(gs["p_w"][rot].tolist()) | set(gs["p_b"][rot].tolist())
+    read.discard(-1)
+    assert fused == blocks * max(len(read), 1) * 4
     plain = N.qs_workspace_size(h, N.QS_C64, 4096, N.QS_PATH_PLAIN)
     assert plain == 2 * 4096 * 1024 * 8 + 4096 * w.circuit.n_gates * 8
 
