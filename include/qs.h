@@ -277,14 +277,17 @@ int qs_plan_export(const qs_circuit* circuit, int dtype, int64_t B, int flags,
  * `adjoint` selects the register split of the adjoint's plan instead of the
  * forward's. Call once with NULL arrays to get the sizes in `info`, then with
  * arrays of those sizes:
- *   ops        [n_ops][5] int32  kind, a, b, aux, gate (SvOp fields; kinds
- *                                16 = fused single-qubit blocks on every
- *                                register bit, 17 = CZ sign pattern)
+ *   ops        [n_ops][5] int32  kind, a, b, aux, gate: kind 16 (a layer
+ *                                op), a = mask of register bits with a
+ *                                block, aux bit 0 = per-sample angles,
+ *                                gate = its l1q record
  *   seg_begin  [n_segments + 1] int32 op ranges
  *   seg_lay    [n_segments][32] uint16 logical index mask of each physical
  *              bit: 16 for reading the segment in, 16 for writing it out
- *   l1q        [n_l1q][8] int32 block id per register bit (-1: none)
- *   diag       [n_diag][24] uint32 sign-pattern records
+ *   l1q        [n_l1q][8] int32 words 0..4: block id per register bit (-1:
+ *              none); word 5: sign pattern applied before the blocks, word
+ *              7: after them (diag record, -1: none)
+ *   diag       [n_diag][24] uint32 sign-pattern records (CZ sets)
  *   blk_begin  [n_blocks + 1] int32, blk_gates [n_block_gates] int32: the
  *              gates of each block in application order
  * Returns QS_ERR_UNSUPPORTED when the circuit does not take the fused path. */

@@ -1,19 +1,23 @@
 // Host planner for the register-resident engine.
 //
 // A sample's 2^n amplitudes are spread over 2^t threads holding 2^r
-// amplitudes each (n = r + t). A gate that mixes amplitude pairs (RX, RY, X,
-// Y, H, and the target of CNOT) can be applied without communication only
-// when its target qubit sits on a register bit; diagonal gates (RZ, Z, CZ)
-// and CNOT controls can sit anywhere. The planner cuts the gate list into
-// segments with one qubit placement each; between segments the engine
-// re-places the state through LDS (a "remap").
+// amplitudes each (n = r + t). Single-qubit gates are applied in registers:
+// the runs of them on each register-resident qubit are multiplied into one
+// 2x2 block per qubit, and one layer op (L1Q) applies the blocks of all r
+// register bits in one pass. CZs act on any bits (a sign pattern). The
+// planner cuts the gate list into segments with one qubit placement each;
+// between segments the engine re-places the state through LDS (a "remap").
 //
 // Gates on disjoint qubits commute, so the planner list-schedules the gate
-// dependency DAG (only the order of gates sharing a qubit is kept): it runs
-// every ready gate the current placement can execute, and re-places only
-// when every ready gate mixes a thread-resident qubit. At a re-placement the
-// register bits receive the r qubits whose next pending pair-mixing gate is
-// soonest (ties: lower qubit). Checkpoint positions are scheduling barriers.
+// dependency DAG (only the order of gates sharing a qubit is kept), in
+// rounds: every ready CZ, then the ready single-qubit runs of the register
+// qubits as one L1Q round. It re-places when no round can start. At a
+// re-placement the register bits receive the r qubits whose next pending
+// single-qubit gate is soonest (ties: lower qubit). A round that finds fewer
+// than r runs ready costs as much as a full one; the planner also plans with
+// such partial rounds deferred (to a later segment holding their qubits) once
+// a segment has made progress, and keeps the cheaper plan. Checkpoint
+// positions are scheduling barriers.
 //
 // CNOTs are never applied as engine ops. A CNOT maps the amplitude index
 // x -> x ^ (x_c << t), a linear map over GF(2); so is the LDS slot of a remap.
@@ -30,13 +34,11 @@ namespace qs {
 
 namespace {
 
-int mixing_target(const qs_gate& g) {
-  switch (g.op) {
-    case QS_OP_RX: case QS_OP_RY: case QS_OP_X: case QS_OP_Y: case QS_OP_H:
-      return g.q0;
-    default:
-      return -1;  // RZ, Z, CZ are diagonal; CNOTs are folded into remaps
-  }
+// The qubit a gate needs on a register bit: every single-qubit gate runs in
+// registers as part of a block; CZs act on any bits; CNOTs are folded into
+// remaps.
+int register_target(const qs_gate& g) {
+  return g.op <= QS_OP_H ? g.q0 : -1;
 }
 
 // x -> x ^ (bit c of x) << t on a logical index mask.
@@ -96,10 +98,13 @@ bool is_one_qubit(int op) { return op <= QS_OP_H; }
 // segment the placement is fixed, and only the order of gates sharing a
 // qubit matters. Alternately (a) every register bit takes the run of
 // single-qubit gates at the head of its qubit's pending list as one block,
-// and all blocks go into one L1Q op; (b) every other op whose qubits all have
-// it at the head of their pending lists is emitted, in the original order,
-// with consecutive CZs merged into one DIAG op. The earliest pending gate is
-// always at the head of its lists, so every round makes progress.
+// and all blocks go into one L1Q op; (b) every CZ whose two qubits have it at
+// the head of their pending lists joins one sign pattern (a DIAG record)
+// that the same L1Q op applies after its blocks. CZs ready before the
+// segment's first round form a pattern applied before its blocks. The
+// earliest pending gate is always at the head of its lists, so every round
+// makes progress. Any other op (which the scheduler never emits) marks the
+// plan as not layered.
 void build_layers(SvPlan& P, const qs_circuit& c, bool per_sample_angles_all) {
   const int r = P.r, R = 1 << r;
   std::vector<SvOp> in = std::move(P.ops);
@@ -127,7 +132,53 @@ void build_layers(SvPlan& P, const qs_circuit& c, bool per_sample_angles_all) {
     auto is_u = [&](int o) { return is_one_qubit(in[o].kind) && in[o].a < r; };
     std::vector<char> done(end - beg, 0);
     int left = end - beg;
-    while (left > 0) {
+    // (b) the ready CZs as one sign pattern: its DIAG record, or -1.
+    auto take_czs = [&]() {
+      int rec = -1;
+      bool progress = true;
+      while (progress) {
+        progress = false;
+        for (int o = beg; o < end; ++o) {
+          if (done[o - beg] || is_u(o)) continue;
+          const SvOp& x = in[o];
+          const bool two = x.kind == QS_OP_CNOT || x.kind == QS_OP_CZ;
+          if (!at_head(x.a, o) || (two && !at_head(x.b, o))) continue;
+          head[x.a]++;
+          if (two) head[x.b]++;
+          done[o - beg] = 1;
+          --left;
+          progress = true;
+          P.exec.insert(P.exec.end(), {x.gate, x.a, two ? x.b : 0});
+          if (x.kind != QS_OP_CZ) {
+            P.layered = false;
+            continue;
+          }
+          if (rec < 0) {
+            rec = (int)(P.diag.size() / kDiagWords);
+            P.diag.resize(P.diag.size() + kDiagWords, 0u);
+          }
+          uint32_t* d = &P.diag[(size_t)rec * kDiagWords];
+          const int lo = x.a < x.b ? x.a : x.b, hi = x.a < x.b ? x.b : x.a;
+          if (hi < r) {
+            for (int k = 0; k < R; ++k)
+              if (((k >> lo) & 1) && ((k >> hi) & 1)) d[0] ^= 1u << k;
+          } else if (lo < r) {
+            d[2 + lo] ^= 1u << (hi - r);
+          } else {
+            d[7 + (lo - r)] ^= 1u << (hi - r);
+          }
+        }
+      }
+      return rec;
+    };
+    auto new_op = [&](uint8_t mask, uint8_t ps, const int32_t* rec) {
+      const int id = (int)(P.l1q.size() / kL1QWords);
+      P.ops.push_back(SvOp{kOpL1Q, mask, 0, ps, id});
+      P.l1q.insert(P.l1q.end(), rec, rec + kL1QWords);
+      return id;
+    };
+    int pre = take_czs();
+    while (left > 0 || pre >= 0) {
       // (a) one block per register bit
       int32_t rec[kL1QWords];
       for (int j = 0; j < kL1QWords; ++j) rec[j] = -1;
@@ -153,50 +204,20 @@ void build_layers(SvPlan& P, const qs_circuit& c, bool per_sample_angles_all) {
         mask |= (uint8_t)(1u << j);
         ps |= bps;
       }
-      if (mask) {
-        SvOp op{kOpL1Q, mask, 0, ps, (int32_t)(P.l1q.size() / kL1QWords)};
-        P.ops.push_back(op);
-        P.l1q.insert(P.l1q.end(), rec, rec + kL1QWords);
+      int id = -1;  // this round's L1Q record
+      if (mask || pre >= 0) {
+        rec[kL1QPreDiag] = pre;
+        pre = -1;
+        id = new_op(mask, ps, rec);
       }
-      // (b) every other op that is ready, in order
-      bool progress = true;
-      int open_diag = -1;  // record index of the DIAG op being extended
-      while (progress) {
-        progress = false;
-        for (int o = beg; o < end; ++o) {
-          if (done[o - beg] || is_u(o)) continue;
-          const SvOp& x = in[o];
-          const bool two = x.kind == QS_OP_CNOT || x.kind == QS_OP_CZ;
-          if (!at_head(x.a, o) || (two && !at_head(x.b, o))) continue;
-          head[x.a]++;
-          if (two) head[x.b]++;
-          done[o - beg] = 1;
-          --left;
-          progress = true;
-          P.exec.insert(P.exec.end(), {x.gate, x.a, two ? x.b : 0});
-          if (x.kind != QS_OP_CZ) {
-            open_diag = -1;
-            SvOp y = x;
-            y.aux = per_sample(c.gates[x.gate]) ? 1 : 0;
-            P.ops.push_back(y);
-            continue;
-          }
-          if (open_diag < 0) {
-            open_diag = (int)(P.diag.size() / kDiagWords);
-            P.diag.resize(P.diag.size() + kDiagWords, 0u);
-            P.ops.push_back(SvOp{kOpDiag, 0, 0, 0, open_diag});
-          }
-          uint32_t* d = &P.diag[(size_t)open_diag * kDiagWords];
-          const int lo = x.a < x.b ? x.a : x.b, hi = x.a < x.b ? x.b : x.a;
-          if (hi < r) {
-            for (int k = 0; k < R; ++k)
-              if (((k >> lo) & 1) && ((k >> hi) & 1)) d[0] ^= 1u << k;
-          } else if (lo < r) {
-            d[2 + lo] ^= 1u << (hi - r);
-          } else {
-            d[7 + (lo - r)] ^= 1u << (hi - r);
-          }
+      // (b) the CZs this round made ready, applied after its blocks
+      const int post = take_czs();
+      if (post >= 0) {
+        if (id < 0) {
+          for (int j = 0; j < kL1QWords; ++j) rec[j] = -1;
+          id = new_op(0, 0, rec);
         }
+        P.l1q[(size_t)id * kL1QWords + kL1QPostDiag] = post;
       }
     }
     for (int g : P.seg_folded[s]) P.exec.insert(P.exec.end(), {g, -1, -1});
@@ -207,8 +228,12 @@ void build_layers(SvPlan& P, const qs_circuit& c, bool per_sample_angles_all) {
 
 }  // namespace
 
-SvPlan plan_sv(const qs_circuit& c, int r, bool per_sample_angles_all,
-               const int32_t* ckpt_gates, int n_ckpt) {
+namespace {
+
+// One scheduling pass (see the file comment); `defer` holds back partial
+// L1Q rounds once the segment has made progress.
+SvPlan plan_once(const qs_circuit& c, int r, bool per_sample_angles_all,
+                 const int32_t* ckpt_gates, int n_ckpt, bool defer) {
   SvPlan P;
   const int n = c.n_qubits, G = c.n_gates;
   P.n = n;
@@ -237,19 +262,18 @@ SvPlan plan_sv(const qs_circuit& c, int r, bool per_sample_angles_all,
     if (x.q1 >= 0 && seq[x.q1][head[x.q1]] != g) return false;
     return true;
   };
-  // Soonest pending pair-mixing use of each qubit, counted in gate order.
+  // Soonest pending single-qubit gate of each qubit, counted in gate order.
   auto next_use_from_heads = [&]() {
     std::vector<int> nu(n, INT_MAX);
     for (int q = 0; q < n; ++q)
       for (size_t i = head[q]; i < seq[q].size(); ++i) {
         int g = seq[q][i];
-        if (mixing_target(c.gates[g]) == q) { nu[q] = g; break; }
+        if (register_target(c.gates[g]) == q) { nu[q] = g; break; }
       }
     return nu;
   };
 
   std::vector<SvOp> ops;
-  std::vector<int> op_gate;
   Placement cur = choose(n, r, next_use_from_heads());
   auto open_segment = [&](const Placement& pl) {
     P.seg_begin.push_back((int32_t)ops.size());
@@ -260,6 +284,20 @@ SvPlan plan_sv(const qs_circuit& c, int r, bool per_sample_angles_all,
   auto seg_empty = [&]() {
     return P.seg_begin.back() == (int32_t)ops.size() && P.seg_ckpt.back() < 0 &&
            P.seg_folded.back().empty();
+  };
+  auto emit = [&](int g, int& remaining) {
+    const qs_gate& x = c.gates[g];
+    SvOp op;
+    op.kind = (uint8_t)x.op;
+    op.aux = 0;
+    op.gate = g;
+    op.a = cur.log2phys[x.q0];
+    op.b = x.q1 >= 0 ? cur.log2phys[x.q1] : 0;
+    ops.push_back(op);
+    done[g] = 1;
+    head[x.q0]++;
+    if (x.q1 >= 0) head[x.q1]++;
+    --remaining;
   };
   // Folds every ready CNOT of [lo, hi) (repeatedly: a chain folds whole) into
   // the current segment's closing remap.
@@ -285,36 +323,42 @@ SvPlan plan_sv(const qs_circuit& c, int r, bool per_sample_angles_all,
     const int hi = bounds[ep];  // gates [lo, hi) form this epoch
     int remaining = hi - lo;
     while (remaining > 0) {
-      // Schedule every ready, executable gate of the epoch (lowest index
-      // first) until none is left.
-      bool progress = true;
-      while (progress) {
-        progress = false;
-        for (int g = lo; g < hi; ++g) {
-          if (done[g] || !ready(g)) continue;
-          const qs_gate& x = c.gates[g];
-          if (x.op == QS_OP_CNOT) continue;  // folded at the next remap
-          const int m = mixing_target(x);
-          if (m >= 0 && cur.log2phys[m] >= r) continue;
-          SvOp op;
-          op.kind = (uint8_t)x.op;
-          op.aux = 0;
-          op.gate = g;
-          op.a = cur.log2phys[x.q0];
-          op.b = x.q1 >= 0 ? cur.log2phys[x.q1] : 0;
-          ops.push_back(op);
-          done[g] = 1;
-          head[x.q0]++;
-          if (x.q1 >= 0) head[x.q1]++;
-          --remaining;
-          progress = true;
+      // Rounds: every ready CZ of the epoch, then the ready single-qubit
+      // runs of the register qubits, until no round can start.
+      for (;;) {
+        bool more = true;
+        while (more) {
+          more = false;
+          for (int g = lo; g < hi; ++g)
+            if (!done[g] && c.gates[g].op == QS_OP_CZ && ready(g)) {
+              emit(g, remaining);
+              more = true;
+            }
+        }
+        int runs = 0;
+        for (int j = 0; j < r; ++j) {
+          const int q = cur.phys2log[j];
+          if (head[q] < seq[q].size()) {
+            const int g = seq[q][head[q]];
+            if (g >= lo && g < hi && register_target(c.gates[g]) == q) ++runs;
+          }
+        }
+        if (runs == 0) break;
+        if (defer && runs < r && P.seg_begin.back() < (int32_t)ops.size()) break;
+        for (int j = 0; j < r; ++j) {
+          const int q = cur.phys2log[j];
+          while (head[q] < seq[q].size()) {
+            const int g = seq[q][head[q]];
+            if (g < lo || g >= hi || register_target(c.gates[g]) != q) break;
+            emit(g, remaining);
+          }
         }
       }
-      // Stuck: every ready gate mixes a thread-resident qubit or is a
-      // CNOT. Fold the ready CNOTs into this segment's closing remap and
-      // re-place (an epoch ending in CNOTs gets a remap to the same
-      // placement, so every checkpoint and the last segment end in a plain
-      // placement).
+      // Stuck: every ready gate needs a thread-resident qubit in a register
+      // or is a CNOT (or a partial round was held back). Fold the ready
+      // CNOTs into this segment's closing remap and re-place (an epoch
+      // ending in CNOTs gets a remap to the same placement, so every
+      // checkpoint and the last segment end in a plain placement).
       const bool folded = remaining > 0 && fold_cnots(lo, hi, remaining);
       if (remaining == 0) {
         if (folded) open_segment(cur);
@@ -373,7 +417,21 @@ SvPlan plan_sv(const qs_circuit& c, int r, bool per_sample_angles_all,
                     &P.seg_lay[(size_t)s * kLayWords], kMapStride * 2) != 0)
       ++changes;
   P.n_remaps = changes;
+  return P;
+}
+
+}  // namespace
+
+SvPlan plan_sv(const qs_circuit& c, int r, bool per_sample_angles_all,
+               const int32_t* ckpt_gates, int n_ckpt) {
+  // Cost of a plan: an L1Q op does about 30 times the work of a remap.
+  auto cost = [](const SvPlan& p) { return 32 * (int64_t)p.ops.size() + p.n_remaps; };
+  SvPlan P = plan_once(c, r, per_sample_angles_all, ckpt_gates, n_ckpt, false);
+  SvPlan D = plan_once(c, r, per_sample_angles_all, ckpt_gates, n_ckpt, true);
+  if (D.layered && (!P.layered || cost(D) < cost(P))) P = std::move(D);
+
   // Gradient columns of the shared parameters, and each rotation's columns.
+  const int G = c.n_gates;
   P.grad_cols = grad_columns(c, per_sample_angles_all);
   if (!per_sample_angles_all) {
     std::vector<int32_t> col(c.n_params > 0 ? c.n_params : 1, -1);

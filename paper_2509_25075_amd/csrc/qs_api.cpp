@@ -286,6 +286,11 @@ Entry* get_plan(const qs_circuit& c, int r, bool ps, const int32_t* ck, int n_ck
   e->device = device;
   e->host = plan_sv(c, r, ps, ck, n_ck);
   const SvPlan& P = e->host;
+  if (!P.layered) {  // the engine runs layer ops only
+    delete e;
+    *rc = QS_ERR_UNSUPPORTED;
+    return nullptr;
+  }
   SvDevPlan& d = e->dev;
   d.n = P.n;
   d.r = P.r;
@@ -359,8 +364,9 @@ struct TiledEntry {
 std::unordered_map<Key, TiledEntry*, KeyHash> g_tiled;
 
 int tile_qubits(int dtype, int n, int m_pref = 0) {
-  int m = env_int("QS_TILE_QUBITS", 0);
-  if (m == 0) m = g_force_m;
+  // The tuner's trial choice first, then the environment override.
+  int m = g_force_m;
+  if (m == 0) m = env_int("QS_TILE_QUBITS", 0);
   if (m == 0) m = m_pref;
   if (m == 0) m = dtype == QS_C64 ? 13 : 12;
   if (m > n) m = n;
@@ -377,11 +383,11 @@ struct TileCfg {
 TileCfg tile_cfg(bool tuned, const TuneVal& tv) {
   TileCfg t;
   t.m_pref = tuned ? tv.m : 0;
-  t.fwd_r = env_int("QS_TILE_FWD_LOG2_REGS", 0);
-  if (t.fwd_r == 0) t.fwd_r = g_force_fwd_r;
+  t.fwd_r = g_force_fwd_r;
+  if (t.fwd_r == 0) t.fwd_r = env_int("QS_TILE_FWD_LOG2_REGS", 0);
   if (t.fwd_r == 0 && tuned) t.fwd_r = tv.fwd_r;
-  t.adj_r = env_int("QS_TILE_ADJ_LOG2_REGS", 0);
-  if (t.adj_r == 0) t.adj_r = g_force_adj_r;
+  t.adj_r = g_force_adj_r;
+  if (t.adj_r == 0) t.adj_r = env_int("QS_TILE_ADJ_LOG2_REGS", 0);
   if (t.adj_r == 0 && tuned) t.adj_r = tv.adj_r;
   return t;
 }
@@ -487,8 +493,8 @@ size_t tiled_ws_bytes(const qs_circuit& c, int dtype, int64_t B, bool ps,
 int pick_path(const qs_circuit& c, int dtype, int flags, SvShape* shape,
               int n_slots, bool adjoint, int tuned_r = 0) {
   int path = flags & QS_PATH_MASK;
-  int rf = env_int(adjoint ? "QS_ADJ_LOG2_REGS" : "QS_FWD_LOG2_REGS", 0);
-  if (rf == 0) rf = adjoint ? g_force_adj_r : g_force_fwd_r;
+  int rf = adjoint ? g_force_adj_r : g_force_fwd_r;  // the tuner's trial first
+  if (rf == 0) rf = env_int(adjoint ? "QS_ADJ_LOG2_REGS" : "QS_FWD_LOG2_REGS", 0);
   if (rf == 0) rf = tuned_r;
   const bool ps = (flags & QS_FLAG_PER_SAMPLE_PARAMS) != 0;
   if (path == QS_PATH_AUTO) {

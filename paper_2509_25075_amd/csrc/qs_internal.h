@@ -9,33 +9,38 @@
 
 namespace qs {
 
-// One operation of the register-resident engine. Positions are PHYSICAL bit
-// positions inside a sample's state: 0 .. r-1 are register bits (amplitude
-// index within a thread), r .. n-1 are thread bits (thread index within the
-// sample's thread group).
-//   kind  gate kind (QS_OP_*) or one of the layer kinds below
-//   a     target (1-qubit), control (CNOT); L1Q: mask of register bits used
-//   b     target (CNOT), unused otherwise
+// One operation of the register-resident engine: a layer op (L1Q). Positions
+// are PHYSICAL bit positions inside a sample's state: 0 .. r-1 are register
+// bits (amplitude index within a thread), r .. n-1 are thread bits (thread
+// index within the sample's thread group). The scheduler's intermediate
+// single-gate ops use the same record.
+//   kind  kOpL1Q (single-gate ops: the gate kind QS_OP_*)
+//   a     L1Q: mask of register bits with a block (single gate: position of
+//         q0)
+//   b     single gate: position of q1, unused otherwise
 //   aux   bit 0: some angle of the op differs per sample
-//   gate  descriptor gate of a single-gate op; record index of a layer op
+//   gate  L1Q: record index (single gate: descriptor gate)
 struct SvOp {
   uint8_t kind, a, b, aux;
   int32_t gate;
 };
 static_assert(sizeof(SvOp) == 8, "SvOp layout");
 
-// Layer ops. L1Q applies, on every register bit j at once, the product of a
-// run of consecutive single-qubit gates ("block") acting on the qubit held
-// there; its record is kL1QWords int32: the block id per register bit (-1:
-// none). DIAG applies a set of CZ gates as one sign pattern over the
-// amplitude index; its record is kDiagWords uint32:
+// An L1Q op applies, in order, an optional sign pattern (DIAG record), on
+// every register bit j at once the product of a run of consecutive
+// single-qubit gates ("block") acting on the qubit held there, and an
+// optional second sign pattern. Its record is kL1QWords int32: the block id
+// per register bit (-1: none; identity), then at kL1QPreDiag and
+// kL1QPostDiag the DIAG records (-1: none). A DIAG record (a set of CZs as
+// one sign pattern over the amplitude index) is kDiagWords uint32:
 //   [0]      sign parity of register index k (bit k) from register-register CZs
-//   [1]      thread-bit mask of single thread-bit sign terms (Z on thread bits)
+//   [1]      thread-bit mask of single thread-bit sign terms
 //   [2 + j]  thread bits paired with register bit j (register-thread CZs)
 //   [7 + i]  higher thread bits paired with thread bit i (thread-thread CZs)
 constexpr uint8_t kOpL1Q = 16;
-constexpr uint8_t kOpDiag = 17;
 constexpr int kL1QWords = 8;
+constexpr int kL1QPreDiag = 5;
+constexpr int kL1QPostDiag = 7;
 constexpr int kDiagWords = 24;
 
 constexpr int kMaxQubitsFused = 14;  // 2^14 complex64 = 128 KiB LDS staging
@@ -44,10 +49,9 @@ constexpr int kLayWords = 32;        // uint16 per segment layout record
 
 // A planned gate program: a sequence of segments, each with a fixed
 // placement of the logical qubits onto physical bit positions, such that
-// every non-diagonal gate of the segment acts on a register-resident qubit.
-// Within a segment the gates are grouped into layer ops (L1Q, DIAG) where
-// possible; the rest (diagonal gates on thread bits) stay one op per gate.
-// CNOTs are folded into the remap that closes their segment. `exec` lists
+// every single-qubit gate of the segment acts on a register-resident qubit.
+// Within a segment the gates are grouped into L1Q layer ops. CNOTs are
+// folded into the remap that closes their segment. `exec` lists
 // every gate once in execution order with its physical positions (-1, -1 for
 // a folded CNOT, listed after its segment's ops), for inspection.
 struct SvPlan {
@@ -75,6 +79,7 @@ struct SvPlan {
   std::vector<int32_t> grad_cols;     // shared parameter of each gradient column
   std::vector<int32_t> gate_cols;     // [G][2] columns of p_w and p_b, or -1
   int n_remaps = 0;
+  bool layered = true;                // every op is an L1Q op
   int nseg() const { return (int)seg_begin.size() - 1; }
   int n_fu = 0;                       // blocks with a fused-matrix slot
   int n_blocks() const { return (int)blk_fu.size(); }

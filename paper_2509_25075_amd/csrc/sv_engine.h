@@ -8,16 +8,19 @@
 // amplitude k of thread tau is k + R * tau, so physical bits 0..r-1 are
 // register bits and r..n-1 are thread bits. A segment of the planned gate
 // program fixes which logical qubit sits on which physical bit; every
-// pair-mixing gate of a segment targets a register bit, so it is applied
-// with no communication. Diagonal gates (RZ, Z, CZ) and CNOT controls on
-// thread bits use the lane's own bit. Between segments the state is written
-// to LDS in logical order and read back under the next placement (a remap).
+// single-qubit gate of a segment acts on a register bit, so it is applied
+// with no communication, and CZs on thread bits use the lane's own bits.
+// Between segments the state is written to LDS in logical order and read
+// back under the next placement (a remap); CNOTs are folded into the remap
+// addresses.
 //
 // Layer ops. Runs of single-qubit gates on the qubit of each register bit
 // are multiplied into one 2x2 matrix per bit ("block"), and one L1Q op
-// applies the blocks of all register bits in straight-line code; a set of
-// CZ gates becomes one DIAG op, a per-thread sign mask over the register
-// index. The adjoint takes every rotation gradient of a block from the 2x2
+// applies the blocks of all register bits in straight-line code, with a set
+// of CZ gates before and after as per-thread sign masks over the register
+// index. Every op of a plan is an L1Q op, so the op loop has one path and
+// the state stays in the same registers from op to op. The adjoint takes
+// every rotation gradient of a block from the 2x2
 // correlation Q = sum psi lam^dagger on that bit at the block output, moved
 // back through the block gate by gate (Q <- G^dagger Q G).
 //
@@ -151,232 +154,13 @@ __device__ __forceinline__ uint32_t swz(uint32_t L) {
 }
 
 // --------------------------------------------------------------- state ops
-// Amplitudes of one thread: R-wide vector values (not arrays), so branches
-// that touch different elements can never be merged into a pointer select
-// that would push the state out of registers.
+// Amplitudes of one thread. The engine runs layer ops only, so every index
+// into these arrays is a compile-time constant and they live in registers.
 template <typename real, int R>
 struct St {
-  typedef real V __attribute__((ext_vector_type(R)));
-  V re;
-  V im;
+  real re[R];
+  real im[R];
 };
-
-// Dispatch a uniform runtime position j in [0, LR) to a compile-time one.
-template <int LR, typename F>
-__device__ __forceinline__ void for_pos(int j, F&& f) {
-  if constexpr (LR > 0) { if (j == 0) { f(IC<0>{}); return; } }
-  if constexpr (LR > 1) { if (j == 1) { f(IC<1>{}); return; } }
-  if constexpr (LR > 2) { if (j == 2) { f(IC<2>{}); return; } }
-  if constexpr (LR > 3) { if (j == 3) { f(IC<3>{}); return; } }
-  if constexpr (LR > 4) { if (j == 4) { f(IC<4>{}); return; } }
-}
-
-// RX(theta) = [[c, -i s], [-i s, c]] on register bit J (s may carry the sign
-// of an inverse).
-template <int J, typename real, int R>
-__device__ __forceinline__ void g_rx(St<real, R>& x, real c, real s) {
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    if (k & (1 << J)) continue;
-    const int k1 = k | (1 << J);
-    real a0r = x.re[k], a0i = x.im[k], a1r = x.re[k1], a1i = x.im[k1];
-    x.re[k] = c * a0r + s * a1i;
-    x.im[k] = c * a0i - s * a1r;
-    x.re[k1] = c * a1r + s * a0i;
-    x.im[k1] = c * a1i - s * a0r;
-  }
-}
-// RY(theta) = [[c, -s], [s, c]].
-template <int J, typename real, int R>
-__device__ __forceinline__ void g_ry(St<real, R>& x, real c, real s) {
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    if (k & (1 << J)) continue;
-    const int k1 = k | (1 << J);
-    real a0r = x.re[k], a0i = x.im[k], a1r = x.re[k1], a1i = x.im[k1];
-    x.re[k] = c * a0r - s * a1r;
-    x.im[k] = c * a0i - s * a1i;
-    x.re[k1] = s * a0r + c * a1r;
-    x.im[k1] = s * a0i + c * a1i;
-  }
-}
-// RZ(theta) = diag(c - i s, c + i s) on register bit J.
-template <int J, typename real, int R>
-__device__ __forceinline__ void g_rz(St<real, R>& x, real c, real s) {
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    const real sk = (k & (1 << J)) ? s : -s;  // phase c + i sk
-    real ar = x.re[k], ai = x.im[k];
-    x.re[k] = c * ar - sk * ai;
-    x.im[k] = c * ai + sk * ar;
-  }
-}
-// A lane-uniform phase c + i s on every amplitude (RZ on a thread bit).
-template <typename real, int R>
-__device__ __forceinline__ void g_phase_all(St<real, R>& x, real c, real s) {
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    real ar = x.re[k], ai = x.im[k];
-    x.re[k] = c * ar - s * ai;
-    x.im[k] = c * ai + s * ar;
-  }
-}
-template <int J, typename real, int R>
-__device__ __forceinline__ void g_x(St<real, R>& x) {
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    if (k & (1 << J)) continue;
-    const int k1 = k | (1 << J);
-    real tr = x.re[k], ti = x.im[k];
-    x.re[k] = x.re[k1];
-    x.im[k] = x.im[k1];
-    x.re[k1] = tr;
-    x.im[k1] = ti;
-  }
-}
-// Y = [[0, -i], [i, 0]]: (a0, a1) -> (-i a1, i a0).
-template <int J, typename real, int R>
-__device__ __forceinline__ void g_y(St<real, R>& x) {
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    if (k & (1 << J)) continue;
-    const int k1 = k | (1 << J);
-    real a0r = x.re[k], a0i = x.im[k], a1r = x.re[k1], a1i = x.im[k1];
-    x.re[k] = a1i;
-    x.im[k] = -a1r;
-    x.re[k1] = -a0i;
-    x.im[k1] = a0r;
-  }
-}
-template <int J, typename real, int R>
-__device__ __forceinline__ void g_z(St<real, R>& x) {
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    if (!(k & (1 << J))) continue;
-    x.re[k] = -x.re[k];
-    x.im[k] = -x.im[k];
-  }
-}
-template <int J, typename real, int R>
-__device__ __forceinline__ void g_h(St<real, R>& x) {
-  const real h = (real)0.70710678118654752440;
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    if (k & (1 << J)) continue;
-    const int k1 = k | (1 << J);
-    real a0r = x.re[k], a0i = x.im[k], a1r = x.re[k1], a1i = x.im[k1];
-    x.re[k] = h * (a0r + a1r);
-    x.im[k] = h * (a0i + a1i);
-    x.re[k1] = h * (a0r - a1r);
-    x.im[k1] = h * (a0i - a1i);
-  }
-}
-// Negate every amplitude of lanes where `cond` holds.
-template <typename real, int R>
-__device__ __forceinline__ void g_neg_if(St<real, R>& x, bool cond) {
-  const real sg = cond ? (real)-1 : (real)1;
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    x.re[k] *= sg;
-    x.im[k] *= sg;
-  }
-}
-// CZ between register bits A < B.
-template <int A, int B, typename real, int R>
-__device__ __forceinline__ void g_cz_rr(St<real, R>& x) {
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    if ((k & (1 << A)) && (k & (1 << B))) {
-      x.re[k] = -x.re[k];
-      x.im[k] = -x.im[k];
-    }
-  }
-}
-// CZ between register bit A and a thread bit whose value is `tb`.
-template <int A, typename real, int R>
-__device__ __forceinline__ void g_cz_rt(St<real, R>& x, bool tb) {
-  const real sg = tb ? (real)-1 : (real)1;
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    if (k & (1 << A)) {
-      x.re[k] *= sg;
-      x.im[k] *= sg;
-    }
-  }
-}
-// CNOT, control register bit C, target register bit J.
-template <int C, int J, typename real, int R>
-__device__ __forceinline__ void g_cnot_rr(St<real, R>& x) {
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    if ((k & (1 << J)) || !(k & (1 << C))) continue;
-    const int k1 = k | (1 << J);
-    real tr = x.re[k], ti = x.im[k];
-    x.re[k] = x.re[k1];
-    x.im[k] = x.im[k1];
-    x.re[k1] = tr;
-    x.im[k1] = ti;
-  }
-}
-// CNOT, control on a thread bit (value tb), target register bit J.
-template <int J, typename real, int R>
-__device__ __forceinline__ void g_cnot_tr(St<real, R>& x, bool tb) {
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    if (k & (1 << J)) continue;
-    const int k1 = k | (1 << J);
-    real a0r = x.re[k], a0i = x.im[k], a1r = x.re[k1], a1i = x.im[k1];
-    x.re[k] = tb ? a1r : a0r;
-    x.im[k] = tb ? a1i : a0i;
-    x.re[k1] = tb ? a0r : a1r;
-    x.im[k1] = tb ? a0i : a1i;
-  }
-}
-
-// Per-thread partial sums of Im <lam|P|psi> for the rotation generators.
-template <int J, typename real, int R>
-__device__ __forceinline__ real gr_x(const St<real, R>& p, const St<real, R>& l) {
-  real acc = 0;
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    if (k & (1 << J)) continue;
-    const int k1 = k | (1 << J);
-    // Im(conj(l0) p1 + conj(l1) p0)
-    acc += l.re[k] * p.im[k1] - l.im[k] * p.re[k1];
-    acc += l.re[k1] * p.im[k] - l.im[k1] * p.re[k];
-  }
-  return acc;
-}
-template <int J, typename real, int R>
-__device__ __forceinline__ real gr_y(const St<real, R>& p, const St<real, R>& l) {
-  real acc = 0;
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    if (k & (1 << J)) continue;
-    const int k1 = k | (1 << J);
-    // Im(conj(l0)(-i p1) + conj(l1)(i p0)) = -Re(conj(l0) p1) + Re(conj(l1) p0)
-    acc += l.re[k1] * p.re[k] + l.im[k1] * p.im[k];
-    acc -= l.re[k] * p.re[k1] + l.im[k] * p.im[k1];
-  }
-  return acc;
-}
-template <int J, typename real, int R>
-__device__ __forceinline__ real gr_z(const St<real, R>& p, const St<real, R>& l) {
-  real acc = 0;
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    real v = l.re[k] * p.im[k] - l.im[k] * p.re[k];  // Im(conj(l) p)
-    acc += (k & (1 << J)) ? -v : v;
-  }
-  return acc;
-}
-template <typename real, int R>
-__device__ __forceinline__ real gr_all(const St<real, R>& p, const St<real, R>& l) {
-  real acc = 0;
-#pragma unroll
-  for (int k = 0; k < R; ++k) acc += l.re[k] * p.im[k] - l.im[k] * p.re[k];
-  return acc;
-}
 
 // ------------------------------------------------------ 2x2 complex blocks
 // A single-qubit operator [[u00, u01], [u10, u11]] (real, imaginary parts).
@@ -463,41 +247,11 @@ __device__ __forceinline__ void g_u(St<real, R>& x, const U2<real>& u) {
   }
 }
 
-// Per-thread partial of Q = sum psi lam^dagger restricted to register bit J:
-// Q_ab = sum over the other index bits of psi_a conj(lam_b). For any
-// single-qubit generator P on that bit, Im <lam|P|psi> = Im Tr(P Q).
-template <int J, typename real, int R>
-__device__ __forceinline__ U2<real> q_part(const St<real, R>& p, const St<real, R>& l) {
-  U2<real> q{0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    if (k & (1 << J)) continue;
-    const int k1 = k | (1 << J);
-    const real p0r = p.re[k], p0i = p.im[k], p1r = p.re[k1], p1i = p.im[k1];
-    const real l0r = l.re[k], l0i = l.im[k], l1r = l.re[k1], l1i = l.im[k1];
-    // one fused multiply-add per product into the running sums
-    q.r00 = p0r * l0r + q.r00;
-    q.r00 = p0i * l0i + q.r00;
-    q.i00 = p0i * l0r + q.i00;
-    q.i00 = -p0r * l0i + q.i00;
-    q.r01 = p0r * l1r + q.r01;
-    q.r01 = p0i * l1i + q.r01;
-    q.i01 = p0i * l1r + q.i01;
-    q.i01 = -p0r * l1i + q.i01;
-    q.r10 = p1r * l0r + q.r10;
-    q.r10 = p1i * l0i + q.r10;
-    q.i10 = p1i * l0r + q.i10;
-    q.i10 = -p1r * l0i + q.i10;
-    q.r11 = p1r * l1r + q.r11;
-    q.r11 = p1i * l1i + q.r11;
-    q.i11 = p1i * l1r + q.i11;
-    q.i11 = -p1r * l1i + q.i11;
-  }
-  return q;
-}
-
-// One pass over the pairs of register bit J: the correlation Q of the
-// incoming psi and lam (as q_part), and psi <- V psi, lam <- V lam. Each
+// One pass over the pairs of register bit J: the per-thread part of the
+// correlation Q = sum psi lam^dagger restricted to that bit (Q_ab = sum over
+// the other index bits of psi_a conj(lam_b); for a single-qubit generator P
+// on the bit, Im <lam|P|psi> = Im Tr(P Q)) of the incoming psi and lam, and
+// psi <- V psi, lam <- V lam. Each
 // pair's old values die as soon as its new values exist, so the pass needs
 // no second copy of either state.
 template <int J, typename real, int R>
@@ -888,13 +642,15 @@ struct Ctx {
     return block_u(bid);
   }
 
-  // L1Q: each register bit's block (its inverse when `inv`).
-  __device__ __forceinline__ void apply_l1q(St<real, R>& x, int rec, bool inv) const {
+  // L1Q: its first sign pattern, each register bit's block, its second
+  // sign pattern.
+  __device__ __forceinline__ void apply_l1q(St<real, R>& x, int rec) const {
     const QS_K int32_t* r = kc(A.l1q) + (size_t)rec * kL1QWords;
+    apply_signs(x, r[kL1QPreDiag]);
     static_for<LR>([&](auto J) QS_AI {
-      const U2<real> u = block_or_id(r[decltype(J)::value]);
-      g_u<decltype(J)::value>(x, inv ? u_dag(u) : u);
+      g_u<decltype(J)::value>(x, block_or_id(r[decltype(J)::value]));
     });
+    apply_signs(x, r[kL1QPostDiag]);
   }
 
   // DIAG: the sign (-1)^(sum over the CZ pairs of bit_a bit_b) of every
@@ -904,7 +660,7 @@ struct Ctx {
     const uint32_t tb = (uint32_t)tau;
     uint32_t par = __builtin_popcount(tb & d[1]);
     for (int i = 0; i < A.t; ++i)
-      if ((tb >> i) & 1) par += __builtin_popcount(tb & d[7 + i]);
+      par += __builtin_popcount(tb & d[7 + i] & (0u - ((tb >> i) & 1u)));
     uint32_t m = d[0] ^ ((par & 1) ? 0xffffffffu : 0u);
     constexpr uint32_t pat[5] = {0xAAAAAAAAu, 0xCCCCCCCCu, 0xF0F0F0F0u, 0xFF00FF00u,
                                  0xFFFF0000u};
@@ -913,13 +669,29 @@ struct Ctx {
       if (__builtin_popcount(tb & d[2 + j]) & 1) m ^= pat[j];
     return m;
   }
-  __device__ __forceinline__ void apply_diag(St<real, R>& x, int rec) const {
+  // The sign pattern of DIAG record `rec` (none for rec < 0) on x; the
+  // update is in place, so the branch costs no state copies.
+  __device__ __forceinline__ void apply_signs(St<real, R>& x, int rec) const {
+    if (rec < 0) return;
     const uint32_t m = diag_mask(rec);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const uint32_t bit = (m >> k) & 1u;
       x.re[k] = flip_sign(x.re[k], bit);
       x.im[k] = flip_sign(x.im[k], bit);
+    }
+  }
+  __device__ __forceinline__ void apply_signs(St<real, R>& x, St<real, R>& y,
+                                              int rec) const {
+    if (rec < 0) return;
+    const uint32_t m = diag_mask(rec);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const uint32_t bit = (m >> k) & 1u;
+      x.re[k] = flip_sign(x.re[k], bit);
+      x.im[k] = flip_sign(x.im[k], bit);
+      y.re[k] = flip_sign(y.re[k], bit);
+      y.im[k] = flip_sign(y.im[k], bit);
     }
   }
   // Adds this thread's partial dL/dtheta of rotation gate `gt` (gate index g)
@@ -971,12 +743,15 @@ struct Ctx {
                 gth * scale * w);
   }
 
-  // Backward through an L1Q op: for each register bit's block, the
+  // Backward through an L1Q op: its second sign pattern un-applied (a sign
+  // pattern is its own inverse); for each register bit's block, the
   // gradients of its rotations from the correlation Q at the block output
-  // (moved back gate by gate), then psi and lam un-applied.
+  // (moved back gate by gate), then psi and lam un-applied; its first sign
+  // pattern un-applied.
   __device__ __forceinline__ void adjoint_l1q(St<real, R>& psi, St<real, R>& lam, int rec,
                                               int lane, int wave, int Tw) {
     const QS_K int32_t* r = kc(A.l1q) + (size_t)rec * kL1QWords;
+    apply_signs(psi, lam, r[kL1QPostDiag]);
     static_for<LR>([&](auto J) QS_AI {
       constexpr int j = decltype(J)::value;
       const int bid = r[j];
@@ -995,95 +770,9 @@ struct Ctx {
         }
       }
     });
+    apply_signs(psi, lam, r[kL1QPreDiag]);
   }
 
-  // Apply op (its inverse when `inv`) to x. For rotations (c, s) are
-  // cos, sin of theta/2 already signed for the direction.
-  __device__ __forceinline__ void apply(St<real, R>& x, int kind, int a, int bq,
-                                        real c, real s) const {
-    switch (kind) {
-      case QS_OP_RX:
-        for_pos<LR>(a, [&](auto J) QS_AI { g_rx<decltype(J)::value>(x, c, s); });
-        break;
-      case QS_OP_RY:
-        for_pos<LR>(a, [&](auto J) QS_AI { g_ry<decltype(J)::value>(x, c, s); });
-        break;
-      case QS_OP_RZ:
-        if (a < LR)
-          for_pos<LR>(a, [&](auto J) QS_AI { g_rz<decltype(J)::value>(x, c, s); });
-        else
-          g_phase_all(x, c, tbit(a) ? s : -s);
-        break;
-      case QS_OP_X:
-        for_pos<LR>(a, [&](auto J) QS_AI { g_x<decltype(J)::value>(x); });
-        break;
-      case QS_OP_Y:
-        for_pos<LR>(a, [&](auto J) QS_AI { g_y<decltype(J)::value>(x); });
-        break;
-      case QS_OP_Z:
-        if (a < LR)
-          for_pos<LR>(a, [&](auto J) QS_AI { g_z<decltype(J)::value>(x); });
-        else
-          g_neg_if(x, tbit(a));
-        break;
-      case QS_OP_H:
-        for_pos<LR>(a, [&](auto J) QS_AI { g_h<decltype(J)::value>(x); });
-        break;
-      case QS_OP_CNOT:  // a = control, bq = target (register)
-        if (a < LR) {
-          for_pos<LR>(a, [&](auto C) QS_AI {
-            for_pos<LR>(bq, [&](auto J) QS_AI {
-              if constexpr (decltype(C)::value != decltype(J)::value)
-                g_cnot_rr<decltype(C)::value, decltype(J)::value>(x);
-            });
-          });
-        } else {
-          const bool tb = tbit(a);
-          for_pos<LR>(bq, [&](auto J) QS_AI { g_cnot_tr<decltype(J)::value>(x, tb); });
-        }
-        break;
-      case QS_OP_CZ: {
-        int lo = a < bq ? a : bq, hi = a < bq ? bq : a;
-        if (hi < LR) {
-          for_pos<LR>(lo, [&](auto A0) QS_AI {
-            for_pos<LR>(hi, [&](auto B0) QS_AI {
-              if constexpr (decltype(A0)::value < decltype(B0)::value)
-                g_cz_rr<decltype(A0)::value, decltype(B0)::value>(x);
-            });
-          });
-        } else if (lo < LR) {
-          const bool tb = tbit(hi);
-          for_pos<LR>(lo, [&](auto A0) QS_AI { g_cz_rt<decltype(A0)::value>(x, tb); });
-        } else {
-          g_neg_if(x, tbit(lo) && tbit(hi));
-        }
-        break;
-      }
-      default:
-        break;
-    }
-  }
-
-  __device__ __forceinline__ real grad_partial(int kind, int a,
-                                               const St<real, R>& p,
-                                               const St<real, R>& l) const {
-    real v = 0;
-    switch (kind) {
-      case QS_OP_RX:
-        for_pos<LR>(a, [&](auto J) QS_AI { v = gr_x<decltype(J)::value>(p, l); });
-        break;
-      case QS_OP_RY:
-        for_pos<LR>(a, [&](auto J) QS_AI { v = gr_y<decltype(J)::value>(p, l); });
-        break;
-      default:  // RZ
-        if (a < LR)
-          for_pos<LR>(a, [&](auto J) QS_AI { v = gr_z<decltype(J)::value>(p, l); });
-        else
-          v = tbit(a) ? -gr_all(p, l) : gr_all(p, l);
-        break;
-    }
-    return v;
-  }
 };
 
 // Common prologue: LDS carve-up and angle tables.
@@ -1214,19 +903,7 @@ __device__ __forceinline__ void forward_body(const Args<real>& A, unsigned char*
     if (s > 0 && map_changed(A, s))
       C.remap(x, wlay(A, s - 1), rlay(A, s));
     const int e = seg_begin[s + 1];
-    for (int o = seg_begin[s]; o < e; ++o) {
-      const SvOp cur = kload(A.ops, o);
-      const int kind = uni(cur.kind);
-      if (kind == kOpL1Q) {
-        C.apply_l1q(x, cur.gate, false);
-      } else if (kind == kOpDiag) {
-        C.apply_diag(x, cur.gate);
-      } else {
-        real c = 1, sn = 0;
-        if (kind <= QS_OP_RZ) C.gate_cs(cur.gate, c, sn);
-        C.apply(x, kind, uni(cur.a), uni(cur.b), c, sn);
-      }
-    }
+    for (int o = seg_begin[s]; o < e; ++o) C.apply_l1q(x, kload(A.ops, o).gate);
     const int ck = kc(A.seg_ckpt)[s];
     if (ck >= 0 && A.ckpt != nullptr)
       C.store_state(x, A.ckpt + (size_t)ck * A.B * (2ull << A.n), wlay(A, s));
@@ -1335,28 +1012,8 @@ __device__ __forceinline__ void adjoint_body(const Args<real>& A, unsigned char*
     if (ck >= 0 && A.ckpt != nullptr)  // re-anchor psi to the stored state
       C.load_state(psi, A.ckpt + (size_t)ck * A.B * (2ull << A.n), wlay(A, s));
     const int beg = seg_begin[s];
-    for (int o = seg_begin[s + 1] - 1; o >= beg; --o) {
-      const SvOp cur = kload(A.ops, o);
-      const int kind = uni(cur.kind), a = uni(cur.a), bq = uni(cur.b);
-      if (kind == kOpL1Q) {
-        C.adjoint_l1q(psi, lam, cur.gate, lane, wave, Tw);
-        continue;
-      }
-      if (kind == kOpDiag) {  // its own inverse
-        C.apply_diag(psi, cur.gate);
-        C.apply_diag(lam, cur.gate);
-        continue;
-      }
-      real c = 1, sn = 0;
-      if (kind <= QS_OP_RZ) {
-        C.gate_cs(cur.gate, c, sn);
-        const qs_gate gt = kload(A.gates, cur.gate);
-        C.accum(cur.gate, gt, C.grad_partial(kind, a, psi, lam), lane, wave, Tw);
-        sn = -sn;  // inverse rotation
-      }
-      C.apply(psi, kind, a, bq, c, sn);
-      C.apply(lam, kind, a, bq, c, sn);
-    }
+    for (int o = seg_begin[s + 1] - 1; o >= beg; --o)
+      C.adjoint_l1q(psi, lam, kload(A.ops, o).gate, lane, wave, Tw);
     if (s > 0 && map_changed(A, s)) {
       C.remap(psi, rlay(A, s), wlay(A, s - 1));
       C.remap(lam, rlay(A, s), wlay(A, s - 1));

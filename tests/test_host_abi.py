@@ -264,6 +264,24 @@ def _run_engine_program(c, d, params, feats, psi0):
     sb = d["seg_begin"]
     cur = psi0[:, logical(lay[0][:16])]
     pat = [0xAAAAAAAA, 0xCCCCCCCC, 0xF0F0F0F0, 0xFF00FF00, 0xFFFF0000]
+
+    def signs(rec):
+        rd = d["diag"][rec]
+        sign = np.ones(N)
+        for p in range(N):
+            k, tau = p & (R - 1), p >> r
+            par = _popc(tau & int(rd[1]))
+            for i in range(n - r):
+                if (tau >> i) & 1:
+                    par += _popc(tau & int(rd[7 + i]))
+            m = int(rd[0]) ^ (0xFFFFFFFF if par & 1 else 0)
+            for j in range(r):
+                if _popc(tau & int(rd[2 + j])) & 1:
+                    m ^= pat[j]
+            if (m >> k) & 1:
+                sign[p] = -1
+        return sign[None, :]
+
     for s in range(d["n_segments"]):
         if s > 0:
             lg = np.empty_like(cur)
@@ -271,34 +289,21 @@ def _run_engine_program(c, d, params, feats, psi0):
             cur = lg[:, logical(lay[s][:16])]
         for o in range(sb[s], sb[s + 1]):
             kind, a, b, aux, rec = (int(v) for v in d["ops"][o])
-            if kind == 16:
-                for j in range(r):
-                    bid = int(d["l1q"][rec][j])
-                    if bid < 0:
-                        continue
-                    U = np.broadcast_to(np.eye(2, dtype=np.complex128), (B, 2, 2))
-                    for g in d["blk_gates"][d["blk_begin"][bid]:d["blk_begin"][bid + 1]]:
-                        U = gate_u(int(g)) @ U
-                    cur = O.apply_1q(cur, j, U)
-            elif kind == 17:
-                rd = d["diag"][rec]
-                sign = np.ones(N)
-                for p in range(N):
-                    k, tau = p & (R - 1), p >> r
-                    par = _popc(tau & int(rd[1]))
-                    for i in range(n - r):
-                        if (tau >> i) & 1:
-                            par += _popc(tau & int(rd[7 + i]))
-                    m = int(rd[0]) ^ (0xFFFFFFFF if par & 1 else 0)
-                    for j in range(r):
-                        if _popc(tau & int(rd[2 + j])) & 1:
-                            m ^= pat[j]
-                    if (m >> k) & 1:
-                        sign[p] = -1
-                cur = cur * sign[None, :]
-            else:
-                assert kind <= C.OP["H"], "only single-qubit gates stay single ops"
-                cur = O.apply_1q(cur, a, gate_u(rec))
+            assert kind == 16, "every engine op is a layer op"
+            words = d["l1q"][rec]
+            assert a == sum(1 << j for j in range(r) if words[j] >= 0)
+            if words[5] >= 0:
+                cur = cur * signs(int(words[5]))
+            for j in range(r):
+                bid = int(words[j])
+                if bid < 0:
+                    continue
+                U = np.broadcast_to(np.eye(2, dtype=np.complex128), (B, 2, 2))
+                for g in d["blk_gates"][d["blk_begin"][bid]:d["blk_begin"][bid + 1]]:
+                    U = gate_u(int(g)) @ U
+                cur = O.apply_1q(cur, j, U)
+            if words[7] >= 0:
+                cur = cur * signs(int(words[7]))
     out = np.empty_like(cur)
     out[:, logical(lay[d["n_segments"] - 1][16:])] = cur
     return out
