@@ -135,8 +135,10 @@ ProgPlan* get_prog(const qs_program* p, int dtype, int* rc) {
     d.blk_begin = ep.dev->blk_begin;
     d.blk_gates = ep.dev->blk_gates;
     d.blk_fu = ep.dev->blk_fu;
+    d.blk_gen = ep.dev->blk_gen;
     d.n_blocks = ep.dev->n_blocks;
     d.n_fu = ep.dev->n_fu;
+    d.n_gen = ep.dev->n_gen;
     d.n = c.n_qubits;
     d.t = c.n_qubits - r;
     d.nseg = ep.dev->nseg;

@@ -132,8 +132,15 @@ bool tuned_lookup(const qs_circuit& c, int dtype, int64_t B, int flags, TuneVal*
 // `block` threads hold S samples of T = block / S threads each; gradient sums
 // take one slot per wave (shared parameters) and per wave of a sample
 // (features); per-sample parameter sets take none.
+// Sizes of a plan's LDS tables: fused-matrix slots and generator-frame
+// slots. Without them lds_bytes bounds both by the single-qubit gates with
+// shared angles, which holds for every plan of the circuit.
+struct TableCounts {
+  int n_fu = 0, n_gen = 0;
+};
+
 int64_t lds_bytes(int dtype, const qs_circuit& c, int S, int n_slots, int block,
-                  bool ps, bool adjoint) {
+                  bool ps, bool adjoint, const TableCounts* tc = nullptr) {
   const int64_t rs = dtype == QS_C64 ? 4 : 8;
   const int64_t waves = (block + 63) / 64;
   const int64_t T = block / (S > 0 ? S : 1);
@@ -150,7 +157,9 @@ int64_t lds_bytes(int dtype, const qs_circuit& c, int S, int n_slots, int block,
   }
   int64_t b = (int64_t)S * (2 * rs << c.n_qubits);  // states
   b += 2 * rs * c.n_gates;                          // shared angle table
-  b += 8 * rs * n1q;                                // fused block matrices
+  const int64_t n_fu = tc ? tc->n_fu : n1q, n_gen = tc ? tc->n_gen : n1q;
+  b += 8 * rs * n_fu;                               // fused block matrices
+  if (adjoint) b += 3 * rs * n_gen;                 // generator frames
   b += 2 * rs * (int64_t)n_slots * S;               // per-sample angle table
   if (adjoint)                                      // gradient sums
     b += rs * (waves * (int64_t)grad_columns(c, ps).size() +
@@ -163,8 +172,11 @@ int64_t lds_bytes(int dtype, const qs_circuit& c, int S, int n_slots, int block,
 // orders come from the register budgets of the instantiations: the forward
 // holds one state per thread group, the adjoint two (psi and lam), so the
 // adjoint prefers a narrower register tile.
+TableCounts plan_counts(const qs_circuit& c, int r, bool ps, const int32_t* ck, int n_ck);
+
 bool choose_shape(int dtype, const qs_circuit& c, int n_slots, int r_force,
-                  bool adjoint, SvShape* out, bool ps = false) {
+                  bool adjoint, SvShape* out, bool ps = false,
+                  const int32_t* ck = nullptr, int n_ck = 0, bool exact = true) {
   const int n = c.n_qubits;
   if (n > kMaxQubitsFused) return false;
   static const int pref_c64_fwd[] = {5, 4, 3, 2, 1};
@@ -189,8 +201,13 @@ bool choose_shape(int dtype, const qs_circuit& c, int n_slots, int r_force,
     int block = T > 256 ? T : 256;
     if (block > maxT) block = maxT;
     int S = block / T;
+    // LDS tables sized for the plan of this split (exact), or bounded for
+    // any plan of the circuit.
+    TableCounts counts;
+    if (exact) counts = plan_counts(c, r, ps, ck, n_ck);
+    const TableCounts* tc = exact ? &counts : nullptr;
     // Shrink the block until the LDS fits.
-    while (S > 1 && lds_bytes(dtype, c, S, n_slots, S * T, ps, adjoint) > kMaxLds) {
+    while (S > 1 && lds_bytes(dtype, c, S, n_slots, S * T, ps, adjoint, tc) > kMaxLds) {
       S >>= 1;
     }
     block = S * T;
@@ -198,7 +215,7 @@ bool choose_shape(int dtype, const qs_circuit& c, int n_slots, int r_force,
       S = 64 / T;
       block = 64;
     }
-    const int64_t lds = lds_bytes(dtype, c, S, n_slots, block, ps, adjoint);
+    const int64_t lds = lds_bytes(dtype, c, S, n_slots, block, ps, adjoint, tc);
     if (lds > kMaxLds) continue;
     out->r = r;
     out->t = t;
@@ -243,6 +260,26 @@ Key make_key(const qs_circuit& c, int r, bool ps, const int32_t* ck, int n_ck,
   return k;
 }
 
+// Table sizes of the host plan for (circuit, r, flags, checkpoints), planned
+// once and cached (host only, so plan queries work without a device).
+TableCounts plan_counts(const qs_circuit& c, int r, bool ps, const int32_t* ck, int n_ck) {
+  static std::mutex mu;
+  static std::unordered_map<Key, TableCounts, KeyHash> cache;
+  Key key = make_key(c, r, ps, ck, n_ck, -1);
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
+  const SvPlan P = plan_sv(c, r, ps, ck, n_ck);
+  TableCounts t;
+  t.n_fu = P.n_fu;
+  t.n_gen = P.n_gen;
+  std::lock_guard<std::mutex> lock(mu);
+  cache.emplace(std::move(key), t);
+  return t;
+}
+
 template <typename T>
 bool upload(T** dst, const T* src, size_t n) {
   *dst = nullptr;
@@ -267,6 +304,7 @@ void free_dev(SvDevPlan& d) {
   (void)hipFree(d.blk_begin);
   (void)hipFree(d.blk_gates);
   (void)hipFree(d.blk_fu);
+  (void)hipFree(d.blk_gen);
   (void)hipFree(d.gate_cols);
   (void)hipFree(d.grad_cols);
 }
@@ -304,6 +342,7 @@ Entry* get_plan(const qs_circuit& c, int r, bool ps, const int32_t* ck, int n_ck
   d.n_ops = (int)P.ops.size();
   d.n_blocks = P.n_blocks();
   d.n_fu = P.n_fu;
+  d.n_gen = P.n_gen;
   d.n_acc = (int)P.grad_cols.size();
   bool okk = upload(&d.seg_map, P.seg_map.data(), P.seg_map.size()) &&
              upload(&d.seg_lay, P.seg_lay.data(), P.seg_lay.size()) &&
@@ -318,6 +357,7 @@ Entry* get_plan(const qs_circuit& c, int r, bool ps, const int32_t* ck, int n_ck
              upload(&d.blk_begin, P.blk_begin.data(), P.blk_begin.size()) &&
              upload(&d.blk_gates, P.blk_gates.data(), P.blk_gates.size()) &&
              upload(&d.blk_fu, P.blk_fu.data(), P.blk_fu.size()) &&
+             upload(&d.blk_gen, P.blk_gen.data(), P.blk_gen.size()) &&
              upload(&d.gate_cols, P.gate_cols.data(), P.gate_cols.size()) &&
              upload(&d.grad_cols, P.grad_cols.data(), P.grad_cols.size());
   if (!okk) {
@@ -328,6 +368,17 @@ Entry* get_plan(const qs_circuit& c, int r, bool ps, const int32_t* ck, int n_ck
   }
   g_cache.emplace(std::move(key), e);
   return e;
+}
+
+// The plan's LDS tables fit the launch's dynamic LDS (the shape was sized
+// from the same plan; this guards the kernel's LDS carve-up).
+bool tables_fit(const Entry& e, int dtype, const qs_circuit& c, const SvShape& shape,
+                bool ps, bool adjoint) {
+  TableCounts tc;
+  tc.n_fu = e.host.n_fu;
+  tc.n_gen = e.host.n_gen;
+  return lds_bytes(dtype, c, shape.samples_per_block, (int)e.host.slot_gate.size(),
+                   shape.block_threads, ps, adjoint, &tc) <= shape.lds_bytes;
 }
 
 qs_gate* get_dev_gates(const qs_circuit& c, int* rc) {
@@ -491,19 +542,21 @@ size_t tiled_ws_bytes(const qs_circuit& c, int dtype, int64_t B, bool ps,
 }
 
 int pick_path(const qs_circuit& c, int dtype, int flags, SvShape* shape,
-              int n_slots, bool adjoint, int tuned_r = 0) {
+              int n_slots, bool adjoint, int tuned_r = 0, const int32_t* ck = nullptr,
+              int n_ck = 0) {
   int path = flags & QS_PATH_MASK;
   int rf = adjoint ? g_force_adj_r : g_force_fwd_r;  // the tuner's trial first
   if (rf == 0) rf = env_int(adjoint ? "QS_ADJ_LOG2_REGS" : "QS_FWD_LOG2_REGS", 0);
   if (rf == 0) rf = tuned_r;
   const bool ps = (flags & QS_FLAG_PER_SAMPLE_PARAMS) != 0;
   if (path == QS_PATH_AUTO) {
-    if (choose_shape(dtype, c, n_slots, rf, adjoint, shape, ps))
+    if (choose_shape(dtype, c, n_slots, rf, adjoint, shape, ps, ck, n_ck))
       path = QS_PATH_FUSED;
     else
       path = c.n_qubits > kMaxQubitsFused ? QS_PATH_HBM : QS_PATH_PLAIN;
   } else if (path == QS_PATH_FUSED) {
-    if (!choose_shape(dtype, c, n_slots, rf, adjoint, shape, ps)) return QS_ERR_UNSUPPORTED;
+    if (!choose_shape(dtype, c, n_slots, rf, adjoint, shape, ps, ck, n_ck))
+      return QS_ERR_UNSUPPORTED;
   } else if (path != QS_PATH_PLAIN && path != QS_PATH_HBM) {
     return QS_ERR_INVALID;
   }
@@ -524,12 +577,21 @@ int64_t grid_of(const SvShape& s, int64_t B) {
   return (B + s.samples_per_block - 1) / s.samples_per_block;
 }
 
+// Partial-sum workspace of the fused adjoint with register split s.r. The
+// grid is counted with the LDS tables bounded (fewer samples per block than
+// any plan of the circuit gets, with or without checkpoints), so the size
+// covers every launch of that split.
 size_t fused_ws_bytes(const qs_circuit& c, int dtype, const SvShape& s, int64_t B,
                       bool ps) {
   if (ps) return 0;
   const size_t acc = dtype == QS_C64 ? sizeof(float) : sizeof(double);
   const size_t cols = std::max<size_t>(grad_columns(c, false).size(), 1);
-  return (size_t)grid_of(s, B) * cols * acc;
+  SvShape wide = s;
+  if (!choose_shape(dtype, c, count_slots(c, ps), s.r, true, &wide, ps, nullptr, 0, false) ||
+      wide.r != s.r)
+    wide = s;
+  const int64_t S = std::min(wide.samples_per_block, s.samples_per_block);
+  return (size_t)((B + S - 1) / S) * cols * acc;
 }
 
 bool tuned_for_call(const qs_circuit& c, int dtype, int64_t B, int flags, void* stream,
@@ -797,7 +859,7 @@ int qs_forward(const qs_circuit* c, int dtype, int64_t B, const void* params,
   const bool tuned = tuned_for_call(*c, dtype, B, flags, stream, &tv);
   SvShape shape;
   const int path = pick_path(*c, dtype, flags, &shape, count_slots(*c, ps), false,
-                             tuned ? tv.fwd_r : 0);
+                             tuned ? tv.fwd_r : 0, ckpt_gates, n_ckpt);
   if (path < 0) return path;
   if (path == QS_PATH_PLAIN) {
     PlainLaunch L{};
@@ -846,6 +908,7 @@ int qs_forward(const qs_circuit* c, int dtype, int64_t B, const void* params,
   }
   Entry* e = get_plan(*c, shape.r, ps, ckpt_gates, n_ckpt, &rc);
   if (!e) return rc;
+  if (!tables_fit(*e, dtype, *c, shape, ps, false)) return QS_ERR_UNSUPPORTED;
   SvLaunch L{};
   L.p = &e->dev;
   L.shape = shape;
@@ -903,7 +966,7 @@ int qs_adjoint_backward(const qs_circuit* c, int dtype, int64_t B,
   const bool tuned = tuned_for_call(*c, dtype, B, flags, stream, &tv);
   SvShape shape;
   const int path = pick_path(*c, dtype, flags, &shape, count_slots(*c, ps), true,
-                             tuned ? tv.adj_r : 0);
+                             tuned ? tv.adj_r : 0, ckpt_gates, n_ckpt);
   if (path < 0) return path;
   const TileCfg tcfg = tile_cfg(tuned, tv);
   const size_t need = path == QS_PATH_PLAIN ? plain_workspace_bytes(*c, dtype, B)
@@ -991,6 +1054,7 @@ int qs_adjoint_backward(const qs_circuit* c, int dtype, int64_t B,
   }
   Entry* e = get_plan(*c, shape.r, ps, ckpt_gates, n_ckpt, &rc);
   if (!e) return rc;
+  if (!tables_fit(*e, dtype, *c, shape, ps, true)) return QS_ERR_UNSUPPORTED;
   if (ps && c->n_params) {
     if ((rc = launch_fill_f64(grad_params, B * c->n_params, stream)) != QS_OK) return rc;
   }

@@ -74,6 +74,9 @@ struct SvPlan {
   std::vector<int32_t> blk_gates;     // gates of each block, forward order
   std::vector<int32_t> blk_fu;        // [n_blocks] slot of the block's fused matrix
                                       // (angles shared), -1: built per sample
+  std::vector<int32_t> blk_gen;       // [n_blocks] first generator-frame slot of a
+                                      // block with shared angles (one slot per
+                                      // gate), -1: built per sample
   std::vector<int32_t> exec;          // [G][3] gate, physical a, physical b
   std::vector<int32_t> exec_seg;      // [nseg + 1] ranges of exec rows
   std::vector<int32_t> grad_cols;     // shared parameter of each gradient column
@@ -82,6 +85,7 @@ struct SvPlan {
   bool layered = true;                // every op is an L1Q op
   int nseg() const { return (int)seg_begin.size() - 1; }
   int n_fu = 0;                       // blocks with a fused-matrix slot
+  int n_gen = 0;                      // generator-frame slots
   int n_blocks() const { return (int)blk_fu.size(); }
 };
 
@@ -128,9 +132,10 @@ struct SvDevPlan {
   int32_t* blk_begin;
   int32_t* blk_gates;
   int32_t* blk_fu;
+  int32_t* blk_gen;
   int32_t* gate_cols;  // [G][2] gradient columns of p_w, p_b (shared params)
   int32_t* grad_cols;  // [n_acc] parameter of each gradient column
-  int n_blocks, n_fu, n_acc;
+  int n_blocks, n_fu, n_acc, n_gen;
 };
 
 // Launch geometry of the engine for a plan.
@@ -203,7 +208,8 @@ struct ProgClass {
   const int32_t* blk_begin;
   const int32_t* blk_gates;
   const int32_t* blk_fu;
-  int32_t n, t, nseg, n_gates, n_slots, n_params, S, n_blocks, n_fu, pad;
+  const int32_t* blk_gen;
+  int32_t n, t, nseg, n_gates, n_slots, n_params, S, n_blocks, n_fu, n_gen;
   int64_t count;       // circuits in the class
   int64_t state_off;   // complex-element offset of the class's first state
   int64_t param_off;   // element offset of the class's parameters [count][P]

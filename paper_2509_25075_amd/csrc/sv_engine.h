@@ -20,9 +20,10 @@
 // of CZ gates before and after as per-thread sign masks over the register
 // index. Every op of a plan is an L1Q op, so the op loop has one path and
 // the state stays in the same registers from op to op. The adjoint takes
-// every rotation gradient of a block from the 2x2
-// correlation Q = sum psi lam^dagger on that bit at the block output, moved
-// back through the block gate by gate (Q <- G^dagger Q G).
+// every rotation gradient of a block from three Pauli partials
+// Im <lam|sigma|psi> (sigma = X, Y, Z on the block's bit) at the block
+// output, dotted with the rotation's generator as conjugated by the block's
+// later gates.
 //
 // LDS slots are swizzled, slot(L) = L ^ fold5(L >> 5) ^ (per-sample salt),
 // which is linear over GF(2), so the address of amplitude k of a lane is
@@ -247,39 +248,47 @@ __device__ __forceinline__ void g_u(St<real, R>& x, const U2<real>& u) {
   }
 }
 
-// One pass over the pairs of register bit J: the per-thread part of the
-// correlation Q = sum psi lam^dagger restricted to that bit (Q_ab = sum over
-// the other index bits of psi_a conj(lam_b); for a single-qubit generator P
-// on the bit, Im <lam|P|psi> = Im Tr(P Q)) of the incoming psi and lam, and
-// psi <- V psi, lam <- V lam. Each
-// pair's old values die as soon as its new values exist, so the pass needs
-// no second copy of either state.
+// The adjoint's rotation gradients come from three Pauli partials of the
+// block output. For a rotation R_P(theta) = exp(-i theta P / 2) of a block
+// whose later gates multiply to V, dL/dtheta is a multiple of
+// Im <lam|V P V^dagger|psi> at the block output, and V P V^dagger = sum over
+// sigma in {X, Y, Z} of e_sigma sigma with real e (the gate's "generator
+// frame"), so it is e . (g_X, g_Y, g_Z) with g_sigma = Im <lam|sigma|psi> on
+// the block's bit.
+template <typename real>
+struct G3 {
+  real x, y, z;
+};
+
+// One pass over the pairs of register bit J: the per-thread parts of the
+// Pauli partials g_sigma of the incoming psi and lam (sums over the thread's
+// pairs), and psi <- V psi, lam <- V lam. Each pair's old values die as soon
+// as its new values exist, so the pass needs no second copy of either state.
 template <int J, typename real, int R>
-__device__ __forceinline__ U2<real> q_and_apply(St<real, R>& p, St<real, R>& l,
-                                                const U2<real>& v) {
-  U2<real> q{0, 0, 0, 0, 0, 0, 0, 0};
+__device__ __forceinline__ G3<real> pauli_and_apply(St<real, R>& p, St<real, R>& l,
+                                                    const U2<real>& v) {
+  G3<real> g{0, 0, 0};
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     if (k & (1 << J)) continue;
     const int k1 = k | (1 << J);
     const real p0r = p.re[k], p0i = p.im[k], p1r = p.re[k1], p1i = p.im[k1];
     const real l0r = l.re[k], l0i = l.im[k], l1r = l.re[k1], l1i = l.im[k1];
-    q.r00 = p0r * l0r + q.r00;
-    q.r00 = p0i * l0i + q.r00;
-    q.i00 = p0i * l0r + q.i00;
-    q.i00 = -p0r * l0i + q.i00;
-    q.r01 = p0r * l1r + q.r01;
-    q.r01 = p0i * l1i + q.r01;
-    q.i01 = p0i * l1r + q.i01;
-    q.i01 = -p0r * l1i + q.i01;
-    q.r10 = p1r * l0r + q.r10;
-    q.r10 = p1i * l0i + q.r10;
-    q.i10 = p1i * l0r + q.i10;
-    q.i10 = -p1r * l0i + q.i10;
-    q.r11 = p1r * l1r + q.r11;
-    q.r11 = p1i * l1i + q.r11;
-    q.i11 = p1i * l1r + q.i11;
-    q.i11 = -p1r * l1i + q.i11;
+    // X: Im(p1 conj(l0) + p0 conj(l1))
+    g.x = p1i * l0r + g.x;
+    g.x = -p1r * l0i + g.x;
+    g.x = p0i * l1r + g.x;
+    g.x = -p0r * l1i + g.x;
+    // Y: Re(p0 conj(l1)) - Re(p1 conj(l0))
+    g.y = p0r * l1r + g.y;
+    g.y = p0i * l1i + g.y;
+    g.y = -p1r * l0r + g.y;
+    g.y = -p1i * l0i + g.y;
+    // Z: Im(p0 conj(l0)) - Im(p1 conj(l1))
+    g.z = p0i * l0r + g.z;
+    g.z = -p0r * l0i + g.z;
+    g.z = -p1i * l1r + g.z;
+    g.z = p1r * l1i + g.z;
     p.re[k] = v.r00 * p0r - v.i00 * p0i + v.r01 * p1r - v.i01 * p1i;
     p.im[k] = v.r00 * p0i + v.i00 * p0r + v.r01 * p1i + v.i01 * p1r;
     p.re[k1] = v.r10 * p0r - v.i10 * p0i + v.r11 * p1r - v.i11 * p1i;
@@ -289,60 +298,60 @@ __device__ __forceinline__ U2<real> q_and_apply(St<real, R>& p, St<real, R>& l,
     l.re[k1] = v.r10 * l0r - v.i10 * l0i + v.r11 * l1r - v.i11 * l1i;
     l.im[k1] = v.r10 * l0i + v.i10 * l0r + v.r11 * l1i + v.i11 * l1r;
   }
-  return q;
+  return g;
 }
 
-// Im Tr(P Q) for the rotation generator P of `kind`.
+// Generator frames: column a holds the X, Y, Z coefficients of V sigma_a
+// V^dagger for the product V of the gates already passed (walking a block
+// from its last gate to its first). Passing gate G (V <- V G) maps each
+// sigma_a through G sigma_a G^dagger first: a rotation by theta about P
+// turns the other two Paulis, R_Z: X -> cos X + sin Y, Y -> -sin X + cos Y
+// (and cyclically: R_X turns Y toward Z, R_Y turns Z toward X); a Pauli
+// gate negates the other two; H swaps X and Z and negates Y.
 template <typename real>
-__device__ __forceinline__ real im_tr(int kind, const U2<real>& q) {
-  if (kind == QS_OP_RX) return q.i10 + q.i01;
-  if (kind == QS_OP_RY) return q.r01 - q.r10;
-  return q.i00 - q.i11;
-}
+struct P3 {
+  real c[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};  // c[column][row]
 
-// Q <- G^dagger Q G: the correlation moved from a gate's output to its
-// input. For a rotation G = c I - i s P this is
-// c^2 Q + s^2 P Q P + i c s (P Q - Q P), written out per generator.
-template <typename real>
-__device__ __forceinline__ U2<real> q_back(int kind, real c, real s, const U2<real>& q) {
-  const real cc = c * c, ss = s * s, cs = c * s;
-  U2<real> o;
-  if (kind == QS_OP_RX) {
-    // i cs (Q10 - Q01), i cs (Q11 - Q00), i cs (Q00 - Q11), i cs (Q01 - Q10)
-    o.r00 = cc * q.r00 + ss * q.r11 - cs * (q.i10 - q.i01);
-    o.i00 = cc * q.i00 + ss * q.i11 + cs * (q.r10 - q.r01);
-    o.r01 = cc * q.r01 + ss * q.r10 - cs * (q.i11 - q.i00);
-    o.i01 = cc * q.i01 + ss * q.i10 + cs * (q.r11 - q.r00);
-    o.r10 = cc * q.r10 + ss * q.r01 - cs * (q.i00 - q.i11);
-    o.i10 = cc * q.i10 + ss * q.i01 + cs * (q.r00 - q.r11);
-    o.r11 = cc * q.r11 + ss * q.r00 - cs * (q.i01 - q.i10);
-    o.i11 = cc * q.i11 + ss * q.i00 + cs * (q.r01 - q.r10);
-  } else if (kind == QS_OP_RY) {
-    o.r00 = cc * q.r00 + ss * q.r11 + cs * (q.r10 + q.r01);
-    o.i00 = cc * q.i00 + ss * q.i11 + cs * (q.i10 + q.i01);
-    o.r01 = cc * q.r01 - ss * q.r10 - cs * (q.r00 - q.r11);
-    o.i01 = cc * q.i01 - ss * q.i10 - cs * (q.i00 - q.i11);
-    o.r10 = cc * q.r10 - ss * q.r01 - cs * (q.r00 - q.r11);
-    o.i10 = cc * q.i10 - ss * q.i01 - cs * (q.i00 - q.i11);
-    o.r11 = cc * q.r11 + ss * q.r00 - cs * (q.r01 + q.r10);
-    o.i11 = cc * q.i11 + ss * q.i00 - cs * (q.i01 + q.i10);
-  } else if (kind == QS_OP_RZ) {
-    // diagonal entries scale by c^2 + s^2; Q01 by (c + i s)^2, Q10 by (c - i s)^2
-    const real n2 = cc + ss, a = cc - ss, b = 2 * cs;
-    o.r00 = n2 * q.r00;
-    o.i00 = n2 * q.i00;
-    o.r11 = n2 * q.r11;
-    o.i11 = n2 * q.i11;
-    o.r01 = a * q.r01 - b * q.i01;
-    o.i01 = a * q.i01 + b * q.r01;
-    o.r10 = a * q.r10 + b * q.i10;
-    o.i10 = a * q.i10 - b * q.r10;
-  } else {
-    const U2<real> g = gate_u<real>(kind, c, s);
-    o = u_mul(u_dag(g), u_mul(q, g));
+  __device__ __forceinline__ void turn(int a, int b, real co, real si) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const real x = c[a][r], y = c[b][r];
+      c[a][r] = co * x + si * y;
+      c[b][r] = co * y - si * x;
+    }
   }
-  return o;
-}
+  __device__ __forceinline__ void negate(int a, int b) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      c[a][r] = -c[a][r];
+      c[b][r] = -c[b][r];
+    }
+  }
+  // (c, s) = cos, sin of theta/2 for a rotation; ignored otherwise.
+  __device__ __forceinline__ void conj_by(int kind, real cs, real sn) {
+    const real co = cs * cs - sn * sn, si = 2 * cs * sn;  // cos, sin of theta
+    switch (kind) {
+      case QS_OP_RX: turn(1, 2, co, si); break;
+      case QS_OP_RY: turn(2, 0, co, si); break;
+      case QS_OP_RZ: turn(0, 1, co, si); break;
+      case QS_OP_X: negate(1, 2); break;
+      case QS_OP_Y: negate(0, 2); break;
+      case QS_OP_Z: negate(0, 1); break;
+      default:  // H
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          const real t = c[0][r];
+          c[0][r] = c[2][r];
+          c[2][r] = t;
+          c[1][r] = -c[1][r];
+        }
+        break;
+    }
+  }
+  __device__ __forceinline__ real dot(int a, const G3<real>& g) const {
+    return c[a][0] * g.x + c[a][1] * g.y + c[a][2] * g.z;
+  }
+};
 
 __device__ __forceinline__ float flip_sign(float v, uint32_t bit) {
   return __uint_as_float(__float_as_uint(v) ^ (bit << 31));
@@ -376,8 +385,9 @@ struct Args {
   const int32_t* blk_begin;  // fused single-qubit blocks
   const int32_t* blk_gates;
   const int32_t* blk_fu;
+  const int32_t* blk_gen;    // first generator-frame slot of a shared block
   const int32_t* gate_cols;  // [G][2] gradient columns of p_w, p_b (shared params)
-  int n_blocks, n_fu;
+  int n_blocks, n_fu, n_gen;
   int n, t, nseg, n_gates, n_slots, n_params, n_feats, S;
   int n_acc;                 // gradient columns: shared parameters the plan reads
   int per_sample_params;
@@ -453,6 +463,7 @@ struct Ctx {
   real* ang_sh;      // [G][2] shared (cos, sin) of theta/2, by gate
   real* ang_ps;      // [n_slots][S][2] per-sample
   real* fu_sh;       // [n_fu][8] fused matrices of blocks with shared angles
+  real* gen_sh;      // [n_gen][3] generator frames of their gates (adjoint)
   real* gacc;        // [waves][n_acc] shared-parameter gradient sums
   real* facc;        // [S * wps][n_feats] feature gradient sums
   int wps;           // waves per sample (1 when a wave holds whole samples)
@@ -744,10 +755,12 @@ struct Ctx {
   }
 
   // Backward through an L1Q op: its second sign pattern un-applied (a sign
-  // pattern is its own inverse); for each register bit's block, the
-  // gradients of its rotations from the correlation Q at the block output
-  // (moved back gate by gate), then psi and lam un-applied; its first sign
-  // pattern un-applied.
+  // pattern is its own inverse); for each register bit, one pass forms the
+  // Pauli partials at the block output and un-applies the block from psi
+  // and lam, and each rotation of the block takes its gradient as its
+  // generator frame dotted with the partials (frames of blocks with shared
+  // angles come from LDS; per-sample blocks walk theirs here); then its
+  // first sign pattern un-applied.
   __device__ __forceinline__ void adjoint_l1q(St<real, R>& psi, St<real, R>& lam, int rec,
                                               int lane, int wave, int Tw) {
     const QS_K int32_t* r = kc(A.l1q) + (size_t)rec * kL1QWords;
@@ -755,24 +768,37 @@ struct Ctx {
     static_for<LR>([&](auto J) QS_AI {
       constexpr int j = decltype(J)::value;
       const int bid = r[j];
-      U2<real> q = q_and_apply<j>(psi, lam, u_dag(block_or_id(bid)));
-      if (bid >= 0) {  // Q only: no state copies at the join
+      const G3<real> pg = pauli_and_apply<j>(psi, lam, u_dag(block_or_id(bid)));
+      if (bid >= 0) {  // reads pg only: no state copies at the join
         const int b0 = kc(A.blk_begin)[bid], b1 = kc(A.blk_begin)[bid + 1];
-        for (int i = b1 - 1; i >= b0; --i) {
-          const int g = kc(A.blk_gates)[i];
-          const qs_gate gt = kload(A.gates, g);
-          real c = 1, sn = 0;
-          if (gt.op <= QS_OP_RZ) {
-            gate_cs(g, c, sn);
-            accum(g, gt, im_tr(gt.op, q), lane, wave, Tw);
+        const int gen = kc(A.blk_gen)[bid];
+        if (gen >= 0) {
+          for (int i = b0; i < b1; ++i) {
+            const int g = kc(A.blk_gates)[i];
+            const qs_gate gt = kload(A.gates, g);
+            if (gt.op > QS_OP_RZ) continue;
+            const real* e = gen_sh + 3 * (size_t)(gen + i - b0);
+            accum(g, gt, e[0] * pg.x + e[1] * pg.y + e[2] * pg.z, lane, wave, Tw);
           }
-          if (i > b0) q = q_back(gt.op, c, sn, q);
+        } else {
+          P3<real> m;
+          for (int i = b1 - 1; i >= b0; --i) {
+            const int g = kc(A.blk_gates)[i];
+            const qs_gate gt = kload(A.gates, g);
+            real c = 1, sn = 0;
+            if (gt.op <= QS_OP_RZ) {
+              gate_cs(g, c, sn);
+              const real part = gt.op == QS_OP_RX ? m.dot(0, pg)
+                                : gt.op == QS_OP_RY ? m.dot(1, pg) : m.dot(2, pg);
+              accum(g, gt, part, lane, wave, Tw);
+            }
+            if (i > b0) m.conj_by(gt.op, c, sn);
+          }
         }
       }
     });
     apply_signs(psi, lam, r[kL1QPreDiag]);
   }
-
 };
 
 // Common prologue: LDS carve-up and angle tables.
@@ -811,7 +837,8 @@ __device__ __forceinline__ void setup(Ctx<real, LR, FLY>& C, const Args<real>& A
   C.ang_sh = tail;
   C.ang_ps = C.ang_sh + 2 * (size_t)A.n_gates;
   C.fu_sh = C.ang_ps + (FLY ? 0 : 2 * (size_t)A.n_slots * A.S);
-  C.gacc = C.fu_sh + 8 * (size_t)A.n_fu;
+  C.gen_sh = C.fu_sh + 8 * (size_t)A.n_fu;
+  C.gacc = C.gen_sh + (adjoint ? 3 * (size_t)A.n_gen : 0);
   C.wps = A.t > 6 ? (1 << (A.t - 6)) : 1;
   const int waves = blockDim.x >> 6;
   C.facc = C.gacc + (A.per_sample_params ? 0 : (size_t)waves * A.n_acc);
@@ -857,6 +884,20 @@ __device__ __forceinline__ void setup(Ctx<real, LR, FLY>& C, const Args<real>& A
     real* f = C.fu_sh + 8 * (size_t)fu;
     f[0] = u.r00; f[1] = u.i00; f[2] = u.r01; f[3] = u.i01;
     f[4] = u.r10; f[5] = u.i10; f[6] = u.r11; f[7] = u.i11;
+    if (!adjoint) continue;
+    // Generator frames, last gate first (see Ctx::adjoint_l1q).
+    const int b0 = A.blk_begin[bid], gen = A.blk_gen[bid];
+    P3<real> m;
+    for (int i = A.blk_begin[bid + 1] - 1; i >= b0; --i) {
+      const int g = A.blk_gates[i];
+      const int kind = A.gates[g].op;
+      const real c = C.ang_sh[2 * g], sn = C.ang_sh[2 * g + 1];
+      real* e = C.gen_sh + 3 * (size_t)(gen + i - b0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k)  // constant indices keep m in registers
+        e[k] = kind == QS_OP_RX ? m.c[0][k] : kind == QS_OP_RY ? m.c[1][k] : m.c[2][k];
+      m.conj_by(kind, c, sn);
+    }
   }
   __syncthreads();
 }
@@ -1090,6 +1131,8 @@ sv_program(const ProgClass* classes, const ProgItem* items, int n_items,
     A.blk_begin = cd.blk_begin;
     A.blk_gates = cd.blk_gates;
     A.blk_fu = cd.blk_fu;
+    A.blk_gen = cd.blk_gen;
+    A.n_gen = cd.n_gen;
     A.n_blocks = cd.n_blocks;
     A.n_fu = cd.n_fu;
     A.n = cd.n;
@@ -1148,6 +1191,8 @@ Args<real> make_args(const SvLaunch& L) {
   A.blk_begin = p.blk_begin;
   A.blk_gates = p.blk_gates;
   A.blk_fu = p.blk_fu;
+  A.blk_gen = p.blk_gen;
+  A.n_gen = p.n_gen;
   A.n_blocks = p.n_blocks;
   A.n_fu = p.n_fu;
   A.n = p.n;
