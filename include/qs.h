@@ -308,12 +308,15 @@ typedef struct qs_tune_info {
   float fwd_ms;           /* best forward time measured                      */
   float adj_ms;           /* best adjoint time measured                      */
   int32_t n_candidates;   /* configurations timed                            */
+  int32_t fwd_samples_cap; /* chosen cap on samples per workgroup, forward
+                              (0: as many as the LDS holds)                  */
+  int32_t adj_samples_cap; /* the same for the adjoint                       */
   int32_t reserved;
 } qs_tune_info;
 
 /* Time every feasible launch configuration of this circuit at batch size B
- * (register tile per direction on the fused path, tile size on the
- * large-state path) on library-allocated scratch buffers, synchronously on
+ * (register tile and samples per workgroup per direction on the fused path,
+ * tile size and register tiles on the large-state path) on library-allocated scratch buffers, synchronously on
  * `stream`, and use the fastest for later calls with the same circuit, dtype,
  * flags and a batch of the same power-of-two size class. When the environment
  * variable QS_AUTOTUNE_CACHE names a file, the choice is appended to it and

@@ -70,12 +70,14 @@ int env_int(const char* name, int dflt) {
 // class, flags). Overrides set while tuning take precedence.
 struct TuneVal {
   int fwd_r = 0, adj_r = 0, m = 0;
+  int fwd_s = 0, adj_s = 0;  // samples-per-block caps (0: the LDS-limited default)
 };
 std::mutex g_tmu;
 std::mutex g_tune_run_mu;  // one tuning run at a time (overrides are global)
 std::unordered_map<std::string, TuneVal> g_tune;
 bool g_tune_loaded = false;
 int g_force_fwd_r = 0, g_force_adj_r = 0, g_force_m = 0;
+int g_force_fwd_s = 0, g_force_adj_s = 0;
 thread_local bool g_in_tune = false;  // calls made by the tuner itself
 
 int batch_class(int64_t B) {
@@ -106,13 +108,14 @@ void load_tune_file_locked() {
   if (!path || !*path) return;
   FILE* f = std::fopen(path, "r");
   if (!f) return;
-  char key[64];
-  int fr, ar, m;
-  while (std::fscanf(f, "%63s %d %d %d", key, &fr, &ar, &m) == 4) {
+  // One line per tuned key: key fwd_r adj_r m [fwd_s adj_s].
+  char line[256], key[64];
+  while (std::fgets(line, sizeof(line), f)) {
     TuneVal v;
-    v.fwd_r = fr;
-    v.adj_r = ar;
-    v.m = m;
+    const int k = std::sscanf(line, "%63s %d %d %d %d %d", key, &v.fwd_r, &v.adj_r, &v.m,
+                              &v.fwd_s, &v.adj_s);
+    if (k != 4 && k != 6) continue;
+    if (k == 4) v.fwd_s = v.adj_s = 0;
     g_tune[key] = v;
   }
   std::fclose(f);
@@ -176,7 +179,8 @@ TableCounts plan_counts(const qs_circuit& c, int r, bool ps, const int32_t* ck, 
 
 bool choose_shape(int dtype, const qs_circuit& c, int n_slots, int r_force,
                   bool adjoint, SvShape* out, bool ps = false,
-                  const int32_t* ck = nullptr, int n_ck = 0, bool exact = true) {
+                  const int32_t* ck = nullptr, int n_ck = 0, bool exact = true,
+                  int s_cap = 0) {
   const int n = c.n_qubits;
   if (n > kMaxQubitsFused) return false;
   static const int pref_c64_fwd[] = {5, 4, 3, 2, 1};
@@ -210,6 +214,8 @@ bool choose_shape(int dtype, const qs_circuit& c, int n_slots, int r_force,
     while (S > 1 && lds_bytes(dtype, c, S, n_slots, S * T, ps, adjoint, tc) > kMaxLds) {
       S >>= 1;
     }
+    // A smaller block can fit more workgroups per CU (an autotuner choice).
+    while (s_cap > 0 && S > s_cap) S >>= 1;
     block = S * T;
     if (block < 64) {  // keep whole waves
       S = 64 / T;
@@ -541,21 +547,27 @@ size_t tiled_ws_bytes(const qs_circuit& c, int dtype, int64_t B, bool ps,
   return 2 * st + ((part + 255) & ~(size_t)255);
 }
 
+// Path and launch shape of one direction: the tuner's trial first, then the
+// environment overrides, then the tuned choice for this circuit (tv).
 int pick_path(const qs_circuit& c, int dtype, int flags, SvShape* shape,
-              int n_slots, bool adjoint, int tuned_r = 0, const int32_t* ck = nullptr,
-              int n_ck = 0) {
+              int n_slots, bool adjoint, const TuneVal* tv = nullptr,
+              const int32_t* ck = nullptr, int n_ck = 0) {
   int path = flags & QS_PATH_MASK;
-  int rf = adjoint ? g_force_adj_r : g_force_fwd_r;  // the tuner's trial first
+  int rf = adjoint ? g_force_adj_r : g_force_fwd_r;
   if (rf == 0) rf = env_int(adjoint ? "QS_ADJ_LOG2_REGS" : "QS_FWD_LOG2_REGS", 0);
-  if (rf == 0) rf = tuned_r;
+  if (rf == 0 && tv) rf = adjoint ? tv->adj_r : tv->fwd_r;
+  int sc = adjoint ? g_force_adj_s : g_force_fwd_s;
+  if (sc == 0)
+    sc = env_int(adjoint ? "QS_ADJ_SAMPLES_PER_BLOCK" : "QS_FWD_SAMPLES_PER_BLOCK", 0);
+  if (sc == 0 && tv) sc = adjoint ? tv->adj_s : tv->fwd_s;
   const bool ps = (flags & QS_FLAG_PER_SAMPLE_PARAMS) != 0;
   if (path == QS_PATH_AUTO) {
-    if (choose_shape(dtype, c, n_slots, rf, adjoint, shape, ps, ck, n_ck))
+    if (choose_shape(dtype, c, n_slots, rf, adjoint, shape, ps, ck, n_ck, true, sc))
       path = QS_PATH_FUSED;
     else
       path = c.n_qubits > kMaxQubitsFused ? QS_PATH_HBM : QS_PATH_PLAIN;
   } else if (path == QS_PATH_FUSED) {
-    if (!choose_shape(dtype, c, n_slots, rf, adjoint, shape, ps, ck, n_ck))
+    if (!choose_shape(dtype, c, n_slots, rf, adjoint, shape, ps, ck, n_ck, true, sc))
       return QS_ERR_UNSUPPORTED;
   } else if (path != QS_PATH_PLAIN && path != QS_PATH_HBM) {
     return QS_ERR_INVALID;
@@ -719,28 +731,47 @@ int qs_autotune(const qs_circuit* c, int dtype, int64_t B, int flags, void* stre
     ~InTune() { g_in_tune = false; }
   } in_tune;
   if (path == QS_PATH_FUSED) {
-    for (int r = 1; r <= 5; ++r) {
-      SvShape sh;
-      if (!choose_shape(dtype, *c, count_slots(*c, ps), r, false, &sh, ps) || sh.r != r) continue;
-      g_force_fwd_r = r;
-      const float ms = time_ms(st, fwd, 3, &rc);
-      g_force_fwd_r = 0;
-      info.n_candidates++;
-      if (rc != QS_OK) return rc;
-      if (ms < bf) { bf = ms; best.fwd_r = r; }
-    }
-    for (int r = 1; r <= 5; ++r) {
-      SvShape sh;
-      if (!choose_shape(dtype, *c, count_slots(*c, ps), r, true, &sh, ps) || sh.r != r) continue;
-      g_force_adj_r = r;
-      const size_t wsb = fused_ws_bytes(*c, dtype, sh, B, ps);
-      void* ws = sc.get(wsb);
-      if (!ws) { g_force_adj_r = 0; return QS_ERR_NOMEM; }
-      const float ms = time_ms(st, [&]() { return adj(ws, wsb); }, 3, &rc);
-      g_force_adj_r = 0;
-      info.n_candidates++;
-      if (rc != QS_OK) return rc;
-      if (ms < ba) { ba = ms; best.adj_r = r; }
+    // Register split r, and for each the samples per block: the LDS-limited
+    // default and two smaller blocks (more workgroups per CU).
+    const int slots = count_slots(*c, ps);
+    for (int dir = 0; dir < 2; ++dir) {
+      const bool adjoint = dir == 1;
+      int& force_r = adjoint ? g_force_adj_r : g_force_fwd_r;
+      int& force_s = adjoint ? g_force_adj_s : g_force_fwd_s;
+      float& bt = adjoint ? ba : bf;
+      for (int r = 1; r <= 5; ++r) {
+        SvShape base;
+        if (!choose_shape(dtype, *c, slots, r, adjoint, &base, ps) || base.r != r) continue;
+        int last_block = 0;
+        for (int div = 1; div <= 4; div *= 2) {
+          const int cap = div == 1 ? 0 : base.samples_per_block / div;
+          if (div > 1 && cap < 1) break;
+          SvShape sh;
+          if (!choose_shape(dtype, *c, slots, r, adjoint, &sh, ps, nullptr, 0, true, cap) ||
+              sh.r != r || sh.block_threads == last_block)
+            continue;
+          last_block = sh.block_threads;
+          force_r = r;
+          force_s = cap;
+          float ms;
+          if (adjoint) {
+            const size_t wsb = fused_ws_bytes(*c, dtype, sh, B, ps);
+            void* ws = sc.get(wsb);
+            if (!ws) { force_r = force_s = 0; return QS_ERR_NOMEM; }
+            ms = time_ms(st, [&]() { return adj(ws, wsb); }, 3, &rc);
+          } else {
+            ms = time_ms(st, fwd, 3, &rc);
+          }
+          force_r = force_s = 0;
+          info.n_candidates++;
+          if (rc != QS_OK) return rc;
+          if (ms < bt) {
+            bt = ms;
+            (adjoint ? best.adj_r : best.fwd_r) = r;
+            (adjoint ? best.adj_s : best.fwd_s) = cap;
+          }
+        }
+      }
     }
   } else {
     // Tile size m, and for each m the register split of the epochs'
@@ -788,6 +819,8 @@ int qs_autotune(const qs_circuit* c, int dtype, int64_t B, int flags, void* stre
   }
   info.fwd_log2_regs = best.fwd_r;
   info.adj_log2_regs = best.adj_r;
+  info.fwd_samples_cap = best.fwd_s;
+  info.adj_samples_cap = best.adj_s;
   info.tile_qubits = best.m;
   info.fwd_ms = bf;
   info.adj_ms = ba;
@@ -799,7 +832,8 @@ int qs_autotune(const qs_circuit* c, int dtype, int64_t B, int flags, void* stre
     const char* path_env = std::getenv("QS_AUTOTUNE_CACHE");
     if (path_env && *path_env) {
       if (FILE* f = std::fopen(path_env, "a")) {
-        std::fprintf(f, "%s %d %d %d\n", key.c_str(), best.fwd_r, best.adj_r, best.m);
+        std::fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), best.fwd_r, best.adj_r, best.m,
+                     best.fwd_s, best.adj_s);
         std::fclose(f);
       }
     }
@@ -859,7 +893,7 @@ int qs_forward(const qs_circuit* c, int dtype, int64_t B, const void* params,
   const bool tuned = tuned_for_call(*c, dtype, B, flags, stream, &tv);
   SvShape shape;
   const int path = pick_path(*c, dtype, flags, &shape, count_slots(*c, ps), false,
-                             tuned ? tv.fwd_r : 0, ckpt_gates, n_ckpt);
+                             tuned ? &tv : nullptr, ckpt_gates, n_ckpt);
   if (path < 0) return path;
   if (path == QS_PATH_PLAIN) {
     PlainLaunch L{};
@@ -930,7 +964,7 @@ size_t qs_workspace_size(const qs_circuit* c, int dtype, int64_t B, int flags) {
   const bool tuned = tuned_lookup(*c, dtype, B, flags, &tv);
   SvShape shape;
   const int path = pick_path(*c, dtype, flags, &shape, count_slots(*c, ps), true,
-                             tuned ? tv.adj_r : 0);
+                             tuned ? &tv : nullptr);
   if (path == QS_PATH_PLAIN) return plain_workspace_bytes(*c, dtype, B);
   if (path == QS_PATH_FUSED) return fused_ws_bytes(*c, dtype, shape, B, ps);
   if (path == QS_PATH_HBM) {
@@ -966,7 +1000,7 @@ int qs_adjoint_backward(const qs_circuit* c, int dtype, int64_t B,
   const bool tuned = tuned_for_call(*c, dtype, B, flags, stream, &tv);
   SvShape shape;
   const int path = pick_path(*c, dtype, flags, &shape, count_slots(*c, ps), true,
-                             tuned ? tv.adj_r : 0, ckpt_gates, n_ckpt);
+                             tuned ? &tv : nullptr, ckpt_gates, n_ckpt);
   if (path < 0) return path;
   const TileCfg tcfg = tile_cfg(tuned, tv);
   const size_t need = path == QS_PATH_PLAIN ? plain_workspace_bytes(*c, dtype, B)
@@ -1114,7 +1148,7 @@ int qs_plan_info_get(const qs_circuit* c, int dtype, int64_t B, int flags,
   const bool tuned = tuned_lookup(*c, dtype, B, flags, &tv);
   SvShape shape, ashape;
   const int path = pick_path(*c, dtype, flags, &shape, count_slots(*c, ps), false,
-                             tuned ? tv.fwd_r : 0);
+                             tuned ? &tv : nullptr);
   if (path < 0) return path;
   std::memset(out, 0, sizeof(*out));
   out->path = path;
@@ -1127,7 +1161,7 @@ int qs_plan_info_get(const qs_circuit* c, int dtype, int64_t B, int flags,
   }
   if (path != QS_PATH_FUSED) return QS_OK;
   if (pick_path(*c, dtype, flags, &ashape, count_slots(*c, ps), true,
-                tuned ? tv.adj_r : 0) == QS_PATH_FUSED) {
+                tuned ? &tv : nullptr) == QS_PATH_FUSED) {
     out->adj_log2_regs = ashape.r;
     out->adj_samples_per_block = ashape.samples_per_block;
     out->adj_block_threads = ashape.block_threads;

@@ -623,7 +623,13 @@ def test_autotune_picks_a_config_and_results_stay_exact(tmp_path, monkeypatch):
     assert info["n_candidates"] >= 2 and info["fwd_ms"] > 0 and info["adj_ms"] > 0
     line = cache.read_text().split()
     assert int(line[1]) == info["fwd_log2_regs"] and int(line[2]) == info["adj_log2_regs"]
+    assert int(line[4]) == info["fwd_samples_cap"] and int(line[5]) == info["adj_samples_cap"]
     pi = s.plan_info(96)
     assert pi["log2_regs"] == info["fwd_log2_regs"]
     assert pi["adj_log2_regs"] == info["adj_log2_regs"]
+    for cap, S, r in ((info["fwd_samples_cap"], pi["samples_per_block"], pi["log2_regs"]),
+                      (info["adj_samples_cap"], pi["adj_samples_per_block"],
+                       pi["adj_log2_regs"])):
+        whole_wave = max(1, 64 >> (10 - r))  # a block keeps whole waves
+        assert cap == 0 or S <= max(cap, whole_wave)
     test_workload_step_vs_oracle("c2", 96)  # the tuned configuration is exact too
