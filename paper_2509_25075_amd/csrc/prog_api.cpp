@@ -133,7 +133,7 @@ ProgPlan* get_prog(const qs_program* p, int dtype, int* rc) {
     d.l1q = ep.dev->l1q;
     d.diag = ep.dev->diag;
     d.blk_begin = ep.dev->blk_begin;
-    d.blk_gates = ep.dev->blk_gates;
+    d.blk_rec = ep.dev->blk_rec;
     d.blk_fu = ep.dev->blk_fu;
     d.blk_gen = ep.dev->blk_gen;
     d.n_blocks = ep.dev->n_blocks;

@@ -308,10 +308,9 @@ void free_dev(SvDevPlan& d) {
   (void)hipFree(d.l1q);
   (void)hipFree(d.diag);
   (void)hipFree(d.blk_begin);
-  (void)hipFree(d.blk_gates);
+  (void)hipFree(d.blk_rec);
   (void)hipFree(d.blk_fu);
   (void)hipFree(d.blk_gen);
-  (void)hipFree(d.gate_cols);
   (void)hipFree(d.grad_cols);
 }
 
@@ -350,6 +349,20 @@ Entry* get_plan(const qs_circuit& c, int r, bool ps, const int32_t* ck, int n_ck
   d.n_fu = P.n_fu;
   d.n_gen = P.n_gen;
   d.n_acc = (int)P.grad_cols.size();
+  std::vector<BGate> rec(P.blk_gates.size());
+  for (size_t i = 0; i < rec.size(); ++i) {
+    const int g = P.blk_gates[i];
+    const qs_gate& x = c.gates[g];
+    BGate& b = rec[i];
+    b.g = g;
+    b.kind_slot = x.op | ((P.gate_slot[g] + 1) << 4);
+    b.feat = x.feat;
+    b.p_w = x.p_w;
+    b.p_b = x.p_b;
+    b.col_w = P.gate_cols.empty() ? -1 : P.gate_cols[2 * (size_t)g];
+    b.col_b = P.gate_cols.empty() ? -1 : P.gate_cols[2 * (size_t)g + 1];
+    b.scale = x.scale;
+  }
   bool okk = upload(&d.seg_map, P.seg_map.data(), P.seg_map.size()) &&
              upload(&d.seg_lay, P.seg_lay.data(), P.seg_lay.size()) &&
              upload(&d.seg_begin, P.seg_begin.data(), P.seg_begin.size()) &&
@@ -361,10 +374,9 @@ Entry* get_plan(const qs_circuit& c, int r, bool ps, const int32_t* ck, int n_ck
              upload(&d.l1q, P.l1q.data(), P.l1q.size()) &&
              upload(&d.diag, P.diag.data(), P.diag.size()) &&
              upload(&d.blk_begin, P.blk_begin.data(), P.blk_begin.size()) &&
-             upload(&d.blk_gates, P.blk_gates.data(), P.blk_gates.size()) &&
+             upload(&d.blk_rec, rec.data(), rec.size()) &&
              upload(&d.blk_fu, P.blk_fu.data(), P.blk_fu.size()) &&
              upload(&d.blk_gen, P.blk_gen.data(), P.blk_gen.size()) &&
-             upload(&d.gate_cols, P.gate_cols.data(), P.gate_cols.size()) &&
              upload(&d.grad_cols, P.grad_cols.data(), P.grad_cols.size());
   if (!okk) {
     free_dev(d);
@@ -765,7 +777,9 @@ int qs_autotune(const qs_circuit* c, int dtype, int64_t B, int flags, void* stre
           force_r = force_s = 0;
           info.n_candidates++;
           if (rc != QS_OK) return rc;
-          if (ms < bt) {
+          // A smaller block must win clearly: within timing noise the
+          // LDS-limited default is kept.
+          if (ms < (cap ? 0.98f : 1.0f) * bt) {
             bt = ms;
             (adjoint ? best.adj_r : best.fwd_r) = r;
             (adjoint ? best.adj_s : best.fwd_s) = cap;

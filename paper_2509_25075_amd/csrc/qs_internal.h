@@ -101,6 +101,17 @@ SvPlan plan_sv(const qs_circuit& c, int r, bool per_sample_angles_all,
 // Empty for per-sample parameter sets, whose gradients go straight to HBM.
 std::vector<int32_t> grad_columns(const qs_circuit& c, bool per_sample_params);
 
+// A block's gate as the engine reads it: one 32-byte record per position of
+// blk_gates, so a gate costs one scalar load in the kernels' inner loops.
+struct BGate {
+  int32_t g;          // descriptor gate
+  int32_t kind_slot;  // gate kind (bits 0..3) | (per-sample angle slot + 1) << 4
+  int32_t feat, p_w, p_b;
+  int32_t col_w, col_b;  // gradient columns of p_w, p_b (-1: none)
+  float scale;
+};
+static_assert(sizeof(BGate) == 32, "BGate layout");
+
 // Large states: the gate list is cut into epochs; each epoch acts only on a
 // tile set L of m qubits (sorted; always containing the `low_keep` lowest
 // qubits so that a tile reads contiguous runs of 2^low_keep amplitudes), and
@@ -130,10 +141,9 @@ struct SvDevPlan {
   int32_t* l1q;
   uint32_t* diag;
   int32_t* blk_begin;
-  int32_t* blk_gates;
+  BGate* blk_rec;      // [n_block_gates] the gate records of the blocks
   int32_t* blk_fu;
   int32_t* blk_gen;
-  int32_t* gate_cols;  // [G][2] gradient columns of p_w, p_b (shared params)
   int32_t* grad_cols;  // [n_acc] parameter of each gradient column
   int n_blocks, n_fu, n_acc, n_gen;
 };
@@ -206,7 +216,7 @@ struct ProgClass {
   const int32_t* l1q;
   const uint32_t* diag;
   const int32_t* blk_begin;
-  const int32_t* blk_gates;
+  const BGate* blk_rec;
   const int32_t* blk_fu;
   const int32_t* blk_gen;
   int32_t n, t, nseg, n_gates, n_slots, n_params, S, n_blocks, n_fu, n_gen;

@@ -132,11 +132,6 @@ __device__ __forceinline__ T kload(const T* base, int i) {
   return out;
 }
 
-// Gradient columns of a rotation's two shared parameters (-1: none).
-struct ColPair {
-  int32_t w, b;
-};
-
 __device__ __forceinline__ int uni(int v) {
   return __builtin_amdgcn_readfirstlane(v);
 }
@@ -383,10 +378,9 @@ struct Args {
   const int32_t* l1q;        // layer-op records
   const uint32_t* diag;
   const int32_t* blk_begin;  // fused single-qubit blocks
-  const int32_t* blk_gates;
+  const BGate* blk_rec;      // gate records of the blocks, in block order
   const int32_t* blk_fu;
   const int32_t* blk_gen;    // first generator-frame slot of a shared block
-  const int32_t* gate_cols;  // [G][2] gradient columns of p_w, p_b (shared params)
   int n_blocks, n_fu, n_gen;
   int n, t, nseg, n_gates, n_slots, n_params, n_feats, S;
   int n_acc;                 // gradient columns: shared parameters the plan reads
@@ -427,6 +421,18 @@ __device__ __forceinline__ const real* param_row(const Args<real>& A, int64_t b)
 template <typename real>
 __device__ __forceinline__ real theta_of(const Args<real>& A, const qs_gate& g,
                                          int64_t b) {
+  const real* P = param_row(A, b);
+  real w = g.p_w >= 0 ? P[g.p_w] : (real)1;
+  real f = g.feat >= 0 ? A.feats[(size_t)b * A.n_feats + g.feat] : (real)1;
+  real bias = g.p_b >= 0 ? P[g.p_b] : (real)0;
+  return (real)g.scale * (w * f + bias);
+}
+
+__device__ __forceinline__ int bg_kind(const BGate& b) { return b.kind_slot & 15; }
+__device__ __forceinline__ int bg_slot(const BGate& b) { return (b.kind_slot >> 4) - 1; }
+
+template <typename real>
+__device__ __forceinline__ real theta_of(const Args<real>& A, const BGate& g, int64_t b) {
   const real* P = param_row(A, b);
   real w = g.p_w >= 0 ? P[g.p_w] : (real)1;
   real f = g.feat >= 0 ? A.feats[(size_t)b * A.n_feats + g.feat] : (real)1;
@@ -606,14 +612,13 @@ struct Ctx {
     }
   }
 
-  // cos, sin of theta/2 of rotation gate g (uniform g).
-  __device__ __forceinline__ void gate_cs(int g, real& c, real& s) const {
-    const int slot = kc(A.gate_slot)[g];
+  // cos, sin of theta/2 of a block's rotation (uniform record).
+  __device__ __forceinline__ void gate_cs(const BGate& b, real& c, real& s) const {
+    const int slot = bg_slot(b);
     if (slot >= 0) {
       if constexpr (FLY) {
         // per-sample angle computed in place (no per-sample table in LDS)
-        const qs_gate gt = kload(A.gates, g);
-        const real th = active ? theta_of(A, gt, row) : (real)0;
+        const real th = active ? theta_of(A, b, row) : (real)0;
         fsincos(th * (real)0.5, &s, &c);
       } else {
         const real* p = ang_ps + 2 * ((size_t)slot * A.S + sl);
@@ -621,8 +626,8 @@ struct Ctx {
         s = p[1];
       }
     } else {
-      c = ang_sh[2 * g];
-      s = ang_sh[2 * g + 1];
+      c = ang_sh[2 * b.g];
+      s = ang_sh[2 * b.g + 1];
     }
   }
 
@@ -636,10 +641,10 @@ struct Ctx {
     const int b0 = kc(A.blk_begin)[bid], b1 = kc(A.blk_begin)[bid + 1];
     U2<real> u{1, 0, 0, 0, 0, 0, 1, 0};
     for (int i = b0; i < b1; ++i) {
-      const int g = kc(A.blk_gates)[i];
-      const int kind = kload(A.gates, g).op;
+      const BGate bg = kload(A.blk_rec, i);
+      const int kind = bg_kind(bg);
       real c = 1, s = 0;
-      if (kind <= QS_OP_RZ) gate_cs(g, c, s);
+      if (kind <= QS_OP_RZ) gate_cs(bg, c, s);
       u = i == b0 ? gate_u<real>(kind, c, s) : gate_lmul(kind, c, s, u);
     }
     return u;
@@ -705,23 +710,22 @@ struct Ctx {
       y.im[k] = flip_sign(y.im[k], bit);
     }
   }
-  // Adds this thread's partial dL/dtheta of rotation gate `gt` (gate index g)
+  // Adds this thread's partial dL/dtheta of the rotation with record `gt`
   // to the gradient sums: shared parameters through per-wave LDS slots,
   // per-sample parameter sets with FP64 atomics, features per sample. Each
   // LDS slot has a single writer (one lane of one wave), so its LDS atomic
   // adds (which need no wait) happen in program order: the sums stay
   // bitwise reproducible.
-  __device__ __forceinline__ void accum(int g, const qs_gate& gt, real part, int lane,
-                                        int wave, int Tw) {
+  __device__ __forceinline__ void accum(const BGate& gt, real part, int lane, int wave,
+                                        int Tw) {
     const real scale = (real)gt.scale;
     if (!A.per_sample_params && gt.feat < 0) {
       // shared parameters, no feature: dL/dP += scale sum_b dL/dtheta_b
       const real v = group_sum(part, 64);
       if (lane == 0) {
-        const ColPair cp = kload(reinterpret_cast<const ColPair*>(A.gate_cols), g);
         real* ga = gacc + (size_t)wave * A.n_acc;
-        if (cp.w >= 0) atomicAdd(&ga[cp.w], scale * v);
-        if (cp.b >= 0) atomicAdd(&ga[cp.b], scale * v);
+        if (gt.col_w >= 0) atomicAdd(&ga[gt.col_w], scale * v);
+        if (gt.col_b >= 0) atomicAdd(&ga[gt.col_b], scale * v);
       }
       return;
     }
@@ -739,14 +743,13 @@ struct Ctx {
       }
     } else {
       // every lane of a sample holds its gth: sum over the wave's samples
-      const ColPair cp = kload(reinterpret_cast<const ColPair*>(A.gate_cols), g);
       if (gt.p_w >= 0) {
         const real v = cross_sum(active ? gth * scale * f : (real)0, Tw);
-        if (lane == 0) atomicAdd(&gacc[(size_t)wave * A.n_acc + cp.w], v);
+        if (lane == 0) atomicAdd(&gacc[(size_t)wave * A.n_acc + gt.col_w], v);
       }
       if (gt.p_b >= 0) {
         const real v = cross_sum(active ? gth * scale : (real)0, Tw);
-        if (lane == 0) atomicAdd(&gacc[(size_t)wave * A.n_acc + cp.b], v);
+        if (lane == 0) atomicAdd(&gacc[(size_t)wave * A.n_acc + gt.col_b], v);
       }
     }
     if (gt.feat >= 0 && leader)
@@ -774,25 +777,24 @@ struct Ctx {
         const int gen = kc(A.blk_gen)[bid];
         if (gen >= 0) {
           for (int i = b0; i < b1; ++i) {
-            const int g = kc(A.blk_gates)[i];
-            const qs_gate gt = kload(A.gates, g);
-            if (gt.op > QS_OP_RZ) continue;
+            const BGate gt = kload(A.blk_rec, i);
+            if (bg_kind(gt) > QS_OP_RZ) continue;
             const real* e = gen_sh + 3 * (size_t)(gen + i - b0);
-            accum(g, gt, e[0] * pg.x + e[1] * pg.y + e[2] * pg.z, lane, wave, Tw);
+            accum(gt, e[0] * pg.x + e[1] * pg.y + e[2] * pg.z, lane, wave, Tw);
           }
         } else {
           P3<real> m;
           for (int i = b1 - 1; i >= b0; --i) {
-            const int g = kc(A.blk_gates)[i];
-            const qs_gate gt = kload(A.gates, g);
+            const BGate gt = kload(A.blk_rec, i);
+            const int kind = bg_kind(gt);
             real c = 1, sn = 0;
-            if (gt.op <= QS_OP_RZ) {
-              gate_cs(g, c, sn);
-              const real part = gt.op == QS_OP_RX ? m.dot(0, pg)
-                                : gt.op == QS_OP_RY ? m.dot(1, pg) : m.dot(2, pg);
-              accum(g, gt, part, lane, wave, Tw);
+            if (kind <= QS_OP_RZ) {
+              gate_cs(gt, c, sn);
+              const real part = kind == QS_OP_RX ? m.dot(0, pg)
+                                : kind == QS_OP_RY ? m.dot(1, pg) : m.dot(2, pg);
+              accum(gt, part, lane, wave, Tw);
             }
-            if (i > b0) m.conj_by(gt.op, c, sn);
+            if (i > b0) m.conj_by(kind, c, sn);
           }
         }
       }
@@ -878,8 +880,8 @@ __device__ __forceinline__ void setup(Ctx<real, LR, FLY>& C, const Args<real>& A
     if (fu < 0) continue;
     U2<real> u{1, 0, 0, 0, 0, 0, 1, 0};
     for (int i = A.blk_begin[bid]; i < A.blk_begin[bid + 1]; ++i) {
-      const int g = A.blk_gates[i];
-      u = gate_lmul(A.gates[g].op, C.ang_sh[2 * g], C.ang_sh[2 * g + 1], u);
+      const int g = A.blk_rec[i].g;
+      u = gate_lmul(bg_kind(A.blk_rec[i]), C.ang_sh[2 * g], C.ang_sh[2 * g + 1], u);
     }
     real* f = C.fu_sh + 8 * (size_t)fu;
     f[0] = u.r00; f[1] = u.i00; f[2] = u.r01; f[3] = u.i01;
@@ -889,8 +891,8 @@ __device__ __forceinline__ void setup(Ctx<real, LR, FLY>& C, const Args<real>& A
     const int b0 = A.blk_begin[bid], gen = A.blk_gen[bid];
     P3<real> m;
     for (int i = A.blk_begin[bid + 1] - 1; i >= b0; --i) {
-      const int g = A.blk_gates[i];
-      const int kind = A.gates[g].op;
+      const int g = A.blk_rec[i].g;
+      const int kind = bg_kind(A.blk_rec[i]);
       const real c = C.ang_sh[2 * g], sn = C.ang_sh[2 * g + 1];
       real* e = C.gen_sh + 3 * (size_t)(gen + i - b0);
 #pragma unroll
@@ -1129,7 +1131,7 @@ sv_program(const ProgClass* classes, const ProgItem* items, int n_items,
     A.l1q = cd.l1q;
     A.diag = cd.diag;
     A.blk_begin = cd.blk_begin;
-    A.blk_gates = cd.blk_gates;
+    A.blk_rec = cd.blk_rec;
     A.blk_fu = cd.blk_fu;
     A.blk_gen = cd.blk_gen;
     A.n_gen = cd.n_gen;
@@ -1141,7 +1143,6 @@ sv_program(const ProgClass* classes, const ProgItem* items, int n_items,
     A.n_gates = cd.n_gates;
     A.n_slots = cd.n_slots;
     A.n_params = cd.n_params;
-    A.gate_cols = nullptr;  // per-sample parameter sets: no gradient columns
     A.n_acc = 0;
     A.n_feats = 0;
     A.S = cd.S;
@@ -1189,7 +1190,7 @@ Args<real> make_args(const SvLaunch& L) {
   A.l1q = p.l1q;
   A.diag = p.diag;
   A.blk_begin = p.blk_begin;
-  A.blk_gates = p.blk_gates;
+  A.blk_rec = p.blk_rec;
   A.blk_fu = p.blk_fu;
   A.blk_gen = p.blk_gen;
   A.n_gen = p.n_gen;
@@ -1201,7 +1202,6 @@ Args<real> make_args(const SvLaunch& L) {
   A.n_gates = p.n_gates;
   A.n_slots = p.n_slots;
   A.n_params = p.n_params;
-  A.gate_cols = p.gate_cols;
   A.n_acc = p.n_acc;
   A.n_feats = p.n_features;
   A.S = L.shape.samples_per_block;
