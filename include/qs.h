@@ -284,9 +284,10 @@ int qs_plan_export(const qs_circuit* circuit, int dtype, int64_t B, int flags,
  *   seg_begin  [n_segments + 1] int32 op ranges
  *   seg_lay    [n_segments][32] uint16 logical index mask of each physical
  *              bit: 16 for reading the segment in, 16 for writing it out
- *   l1q        [n_l1q][8] int32 words 0..4: block id per register bit (-1:
+ *   l1q        [n_l1q][16] int32 words 0..4: block id per register bit (-1:
  *              none); word 5: sign pattern applied before the blocks, word
- *              7: after them (diag record, -1: none)
+ *              7: after them (diag record, -1: none); words 8..12: the
+ *              block's fused-matrix slot (-1: none or built per sample)
  *   diag       [n_diag][24] uint32 sign-pattern records (CZ sets)
  *   blk_begin  [n_blocks + 1] int32, blk_gates [n_block_gates] int32: the
  *              gates of each block in application order

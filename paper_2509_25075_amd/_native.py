@@ -334,7 +334,7 @@ def qs_plan_dump(h: CircuitHandle, dtype: int, B: int, flags: int = 0,
         "ops": np.zeros((max(d["n_ops"], 1), 5), np.int32),
         "seg_begin": np.zeros(d["n_segments"] + 1, np.int32),
         "seg_lay": np.zeros((max(d["n_segments"], 1), 32), np.uint16),
-        "l1q": np.zeros((max(d["n_l1q"], 1), 8), np.int32),
+        "l1q": np.zeros((max(d["n_l1q"], 1), 16), np.int32),
         "diag": np.zeros((max(d["n_diag"], 1), 24), np.uint32),
         "blk_begin": np.zeros(d["n_blocks"] + 1, np.int32),
         "blk_gates": np.zeros(max(d["n_block_gates"], 1), np.int32),

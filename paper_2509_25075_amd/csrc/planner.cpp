@@ -200,6 +200,7 @@ void build_layers(SvPlan& P, const qs_circuit& c, bool per_sample_angles_all) {
         rec[j] = (int32_t)P.blk_fu.size();
         P.blk_gates.insert(P.blk_gates.end(), gl.begin(), gl.end());
         P.blk_begin.push_back((int32_t)P.blk_gates.size());
+        rec[kL1QFused + j] = bps ? -1 : P.n_fu;
         P.blk_fu.push_back(bps ? -1 : P.n_fu++);
         P.blk_gen.push_back(bps ? -1 : P.n_gen);
         if (!bps) P.n_gen += (int)gl.size();

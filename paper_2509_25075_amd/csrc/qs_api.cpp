@@ -329,7 +329,9 @@ Entry* get_plan(const qs_circuit& c, int r, bool ps, const int32_t* ck, int n_ck
   e->device = device;
   e->host = plan_sv(c, r, ps, ck, n_ck);
   const SvPlan& P = e->host;
-  if (!P.layered) {  // the engine runs layer ops only
+  bool in_order = true;  // the kernels read op o's record as record o
+  for (size_t o = 0; o < P.ops.size(); ++o) in_order &= P.ops[o].gate == (int32_t)o;
+  if (!P.layered || !in_order) {  // the engine runs layer ops only
     delete e;
     *rc = QS_ERR_UNSUPPORTED;
     return nullptr;

@@ -31,16 +31,19 @@ static_assert(sizeof(SvOp) == 8, "SvOp layout");
 // single-qubit gates ("block") acting on the qubit held there, and an
 // optional second sign pattern. Its record is kL1QWords int32: the block id
 // per register bit (-1: none; identity), then at kL1QPreDiag and
-// kL1QPostDiag the DIAG records (-1: none). A DIAG record (a set of CZs as
+// kL1QPostDiag the DIAG records (-1: none), and from kL1QFused the block's
+// fused-matrix slot per register bit (-1: none, or built per sample). The
+// record of op o is record o. A DIAG record (a set of CZs as
 // one sign pattern over the amplitude index) is kDiagWords uint32:
 //   [0]      sign parity of register index k (bit k) from register-register CZs
 //   [1]      thread-bit mask of single thread-bit sign terms
 //   [2 + j]  thread bits paired with register bit j (register-thread CZs)
 //   [7 + i]  higher thread bits paired with thread bit i (thread-thread CZs)
 constexpr uint8_t kOpL1Q = 16;
-constexpr int kL1QWords = 8;
+constexpr int kL1QWords = 16;  // one 64-byte scalar load
 constexpr int kL1QPreDiag = 5;
 constexpr int kL1QPostDiag = 7;
+constexpr int kL1QFused = 8;
 constexpr int kDiagWords = 24;
 
 constexpr int kMaxQubitsFused = 14;  // 2^14 complex64 = 128 KiB LDS staging

@@ -132,6 +132,11 @@ __device__ __forceinline__ T kload(const T* base, int i) {
   return out;
 }
 
+// A layer op's record, read in one scalar load.
+struct L1QRec {
+  int32_t w[kL1QWords];
+};
+
 __device__ __forceinline__ int uni(int v) {
   return __builtin_amdgcn_readfirstlane(v);
 }
@@ -631,9 +636,9 @@ struct Ctx {
     }
   }
 
-  // The product of block `bid`'s gates (first gate rightmost).
-  __device__ __forceinline__ U2<real> block_u(int bid) const {
-    const int fu = kc(A.blk_fu)[bid];
+  // The product of block `bid`'s gates (first gate rightmost); `fu` is its
+  // fused-matrix slot, or -1 when its angles differ per sample.
+  __device__ __forceinline__ U2<real> block_u(int bid, int fu) const {
     if (fu >= 0) {
       const real* p = fu_sh + 8 * (size_t)fu;
       return U2<real>{p[0], p[1], p[2], p[3], p[4], p[5], p[6], p[7]};
@@ -653,20 +658,21 @@ struct Ctx {
   // The block's matrix, the identity for bid < 0. Register bits without a
   // block still get the (identity) update: a branch around the update would
   // make the compiler copy the whole state at the join.
-  __device__ __forceinline__ U2<real> block_or_id(int bid) const {
+  __device__ __forceinline__ U2<real> block_or_id(int bid, int fu) const {
     if (bid < 0) return U2<real>{1, 0, 0, 0, 0, 0, 1, 0};
-    return block_u(bid);
+    return block_u(bid, fu);
   }
 
   // L1Q: its first sign pattern, each register bit's block, its second
-  // sign pattern.
+  // sign pattern. The whole record comes in one scalar load.
   __device__ __forceinline__ void apply_l1q(St<real, R>& x, int rec) const {
-    const QS_K int32_t* r = kc(A.l1q) + (size_t)rec * kL1QWords;
-    apply_signs(x, r[kL1QPreDiag]);
+    const L1QRec r = kload(reinterpret_cast<const L1QRec*>(A.l1q), rec);
+    apply_signs(x, r.w[kL1QPreDiag]);
     static_for<LR>([&](auto J) QS_AI {
-      g_u<decltype(J)::value>(x, block_or_id(r[decltype(J)::value]));
+      constexpr int j = decltype(J)::value;
+      g_u<j>(x, block_or_id(r.w[j], r.w[kL1QFused + j]));
     });
-    apply_signs(x, r[kL1QPostDiag]);
+    apply_signs(x, r.w[kL1QPostDiag]);
   }
 
   // DIAG: the sign (-1)^(sum over the CZ pairs of bit_a bit_b) of every
@@ -766,12 +772,13 @@ struct Ctx {
   // first sign pattern un-applied.
   __device__ __forceinline__ void adjoint_l1q(St<real, R>& psi, St<real, R>& lam, int rec,
                                               int lane, int wave, int Tw) {
-    const QS_K int32_t* r = kc(A.l1q) + (size_t)rec * kL1QWords;
-    apply_signs(psi, lam, r[kL1QPostDiag]);
+    const L1QRec r = kload(reinterpret_cast<const L1QRec*>(A.l1q), rec);
+    apply_signs(psi, lam, r.w[kL1QPostDiag]);
     static_for<LR>([&](auto J) QS_AI {
       constexpr int j = decltype(J)::value;
-      const int bid = r[j];
-      const G3<real> pg = pauli_and_apply<j>(psi, lam, u_dag(block_or_id(bid)));
+      const int bid = r.w[j];
+      const G3<real> pg =
+          pauli_and_apply<j>(psi, lam, u_dag(block_or_id(bid, r.w[kL1QFused + j])));
       if (bid >= 0) {  // reads pg only: no state copies at the join
         const int b0 = kc(A.blk_begin)[bid], b1 = kc(A.blk_begin)[bid + 1];
         const int gen = kc(A.blk_gen)[bid];
@@ -799,7 +806,7 @@ struct Ctx {
         }
       }
     });
-    apply_signs(psi, lam, r[kL1QPreDiag]);
+    apply_signs(psi, lam, r.w[kL1QPreDiag]);
   }
 };
 
@@ -946,7 +953,7 @@ __device__ __forceinline__ void forward_body(const Args<real>& A, unsigned char*
     if (s > 0 && map_changed(A, s))
       C.remap(x, wlay(A, s - 1), rlay(A, s));
     const int e = seg_begin[s + 1];
-    for (int o = seg_begin[s]; o < e; ++o) C.apply_l1q(x, kload(A.ops, o).gate);
+    for (int o = seg_begin[s]; o < e; ++o) C.apply_l1q(x, o);
     const int ck = kc(A.seg_ckpt)[s];
     if (ck >= 0 && A.ckpt != nullptr)
       C.store_state(x, A.ckpt + (size_t)ck * A.B * (2ull << A.n), wlay(A, s));
@@ -1056,7 +1063,7 @@ __device__ __forceinline__ void adjoint_body(const Args<real>& A, unsigned char*
       C.load_state(psi, A.ckpt + (size_t)ck * A.B * (2ull << A.n), wlay(A, s));
     const int beg = seg_begin[s];
     for (int o = seg_begin[s + 1] - 1; o >= beg; --o)
-      C.adjoint_l1q(psi, lam, kload(A.ops, o).gate, lane, wave, Tw);
+      C.adjoint_l1q(psi, lam, o, lane, wave, Tw);
     if (s > 0 && map_changed(A, s)) {
       C.remap(psi, rlay(A, s), wlay(A, s - 1));
       C.remap(lam, rlay(A, s), wlay(A, s - 1));

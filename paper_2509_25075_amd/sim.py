@@ -143,6 +143,7 @@ class DeviceWorkload:
     flags: int
     ckpt_gates: list | None = None   # gate counts after which psi is stored
     ckpt: torch.Tensor | None = None  # [n_ckpt, B, 2^n] stored states
+    dz: torch.Tensor | None = None    # [B, n] float64 upstream gradient buffer
 
 
 def to_device(w, flags: int = 0, device="cuda", ckpt_every_layers: int = 0) -> DeviceWorkload:
@@ -162,6 +163,13 @@ def to_device(w, flags: int = 0, device="cuda", ckpt_every_layers: int = 0) -> D
                                dtype=sim.cdtype, device=device)
         else:
             ckpt_gates = None
+    # Upstream gradient dL/d<Z>: MSE on qubit 0 writes column 0 each step
+    # (the others stay zero); a weighted sum has a constant one.
+    dz = None
+    if w.loss == "mse_z0":
+        dz = torch.zeros((B, w.n_qubits), dtype=torch.float64, device=device)
+    elif w.loss == "weighted_z":
+        dz = t(w.weights, torch.float64)[None, :].expand(B, w.n_qubits).contiguous()
     return DeviceWorkload(
         w=w, sim=sim, sim_dec=sim_dec, x=t(w.x), feats=t(w.feats),
         params=t(w.params), params_dec=t(w.params_dec),
@@ -169,7 +177,7 @@ def to_device(w, flags: int = 0, device="cuda", ckpt_every_layers: int = 0) -> D
         state=state, state_dec=sim.empty_state(B, device) if sim_dec else None,
         ws=sim.workspace(B, device, flags),
         ws_dec=sim_dec.workspace(B, device, flags) if sim_dec else None,
-        flags=flags, ckpt_gates=ckpt_gates, ckpt=ckpt)
+        flags=flags, ckpt_gates=ckpt_gates, ckpt=ckpt, dz=dz)
 
 
 def step(d: DeviceWorkload, backward: bool = True) -> dict:
@@ -207,14 +215,13 @@ def step(d: DeviceWorkload, backward: bool = True) -> dict:
     out["expz"] = z
     if w.loss == "none" or not backward:
         return out
+    dz = d.dz
     if w.loss == "mse_z0":
         r = z[:, 0] - d.labels
         out["loss"] = (r * r).mean()
-        dz = torch.zeros_like(z)
-        dz[:, 0] = 2.0 * r / B
+        torch.mul(r, 2.0 / B, out=dz[:, 0])
     elif w.loss == "weighted_z":
         out["loss"] = (z * d.weights[None, :]).sum()
-        dz = d.weights[None, :].expand_as(z).contiguous()
     else:
         raise ValueError(w.loss)
     gp, gf = sim.adjoint(d.params, d.feats, d.state, dexpz=dz, ws=d.ws,

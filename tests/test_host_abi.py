@@ -292,8 +292,10 @@ def _run_engine_program(c, d, params, feats, psi0):
         for o in range(sb[s], sb[s + 1]):
             kind, a, b, aux, rec = (int(v) for v in d["ops"][o])
             assert kind == 16, "every engine op is a layer op"
+            assert rec == o, "the kernels read op o's record as record o"
             words = d["l1q"][rec]
             assert a == sum(1 << j for j in range(r) if words[j] >= 0)
+            assert all(words[8 + j] == -1 for j in range(r) if words[j] < 0)
             if words[5] >= 0:
                 cur = cur * signs(int(words[5]))
             for j in range(r):
