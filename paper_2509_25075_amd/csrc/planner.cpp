@@ -227,6 +227,11 @@ void build_layers(SvPlan& P, const qs_circuit& c, bool per_sample_angles_all) {
     P.exec_seg.push_back((int32_t)(P.exec.size() / 3));
   }
   P.seg_begin.back() = (int32_t)P.ops.size();
+  // Register bits without a block read the identity from the slot after the
+  // fused matrices.
+  for (size_t o = 0; o < P.l1q.size() / kL1QWords; ++o)
+    for (int j = 0; j < r; ++j)
+      if (P.l1q[o * kL1QWords + j] < 0) P.l1q[o * kL1QWords + kL1QFused + j] = P.n_fu;
 }
 
 }  // namespace

@@ -161,7 +161,7 @@ int64_t lds_bytes(int dtype, const qs_circuit& c, int S, int n_slots, int block,
   int64_t b = (int64_t)S * (2 * rs << c.n_qubits);  // states
   b += 2 * rs * c.n_gates;                          // shared angle table
   const int64_t n_fu = tc ? tc->n_fu : n1q, n_gen = tc ? tc->n_gen : n1q;
-  b += 8 * rs * n_fu;                               // fused block matrices
+  b += 8 * rs * (n_fu + 1);                         // fused block matrices, identity
   if (adjoint) b += 3 * rs * n_gen;                 // generator frames
   b += 2 * rs * (int64_t)n_slots * S;               // per-sample angle table
   if (adjoint)                                      // gradient sums

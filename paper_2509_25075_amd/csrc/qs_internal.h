@@ -32,8 +32,8 @@ static_assert(sizeof(SvOp) == 8, "SvOp layout");
 // optional second sign pattern. Its record is kL1QWords int32: the block id
 // per register bit (-1: none; identity), then at kL1QPreDiag and
 // kL1QPostDiag the DIAG records (-1: none), and from kL1QFused the block's
-// fused-matrix slot per register bit (-1: none, or built per sample). The
-// record of op o is record o. A DIAG record (a set of CZs as
+// fused-matrix slot per register bit (-1: built per sample; n_fu: the
+// identity, for a bit without a block). The record of op o is record o. A DIAG record (a set of CZs as
 // one sign pattern over the amplitude index) is kDiagWords uint32:
 //   [0]      sign parity of register index k (bit k) from register-register CZs
 //   [1]      thread-bit mask of single thread-bit sign terms

@@ -457,8 +457,10 @@ __device__ __forceinline__ void sample_sync(int t) {
   }
 }
 
-// The engine's per-thread context.
-template <typename real, int LR, bool FLY = false>
+// The engine's per-thread context. SHARED: every block of the plan has
+// shared angles (its fused matrix and generator frames are in LDS), so the
+// per-sample block code is left out.
+template <typename real, int LR, bool FLY = false, bool SHARED = false>
 struct Ctx {
   static constexpr int R = 1 << LR;
   using v2 = typename V2<real>::T;
@@ -658,9 +660,14 @@ struct Ctx {
   // The block's matrix, the identity for bid < 0. Register bits without a
   // block still get the (identity) update: a branch around the update would
   // make the compiler copy the whole state at the join.
+  // (`fu` is the identity's slot for a register bit without a block.)
   __device__ __forceinline__ U2<real> block_or_id(int bid, int fu) const {
-    if (bid < 0) return U2<real>{1, 0, 0, 0, 0, 0, 1, 0};
-    return block_u(bid, fu);
+    if constexpr (SHARED) {
+      const real* p = fu_sh + 8 * (size_t)fu;
+      return U2<real>{p[0], p[1], p[2], p[3], p[4], p[5], p[6], p[7]};
+    } else {
+      return block_u(bid, fu);
+    }
   }
 
   // L1Q: its first sign pattern, each register bit's block, its second
@@ -782,14 +789,14 @@ struct Ctx {
       if (bid >= 0) {  // reads pg only: no state copies at the join
         const int b0 = kc(A.blk_begin)[bid], b1 = kc(A.blk_begin)[bid + 1];
         const int gen = kc(A.blk_gen)[bid];
-        if (gen >= 0) {
+        if (SHARED || gen >= 0) {
           for (int i = b0; i < b1; ++i) {
             const BGate gt = kload(A.blk_rec, i);
             if (bg_kind(gt) > QS_OP_RZ) continue;
             const real* e = gen_sh + 3 * (size_t)(gen + i - b0);
             accum(gt, e[0] * pg.x + e[1] * pg.y + e[2] * pg.z, lane, wave, Tw);
           }
-        } else {
+        } else if constexpr (!SHARED) {
           P3<real> m;
           for (int i = b1 - 1; i >= b0; --i) {
             const BGate gt = kload(A.blk_rec, i);
@@ -814,8 +821,8 @@ struct Ctx {
 // `blk` is the global index of the block's first sample. Gradient sums are
 // kept in per-wave LDS slots (each written by one lane of one wave) and added
 // in a fixed order at the end, so the adjoint is bitwise reproducible.
-template <typename real, int LR, bool FLY>
-__device__ __forceinline__ void setup(Ctx<real, LR, FLY>& C, const Args<real>& A,
+template <typename real, int LR, bool FLY, bool SHARED>
+__device__ __forceinline__ void setup(Ctx<real, LR, FLY, SHARED>& C, const Args<real>& A,
                                       unsigned char* smem, bool adjoint, int64_t blk) {
   const int tid = threadIdx.x;
   const int N = 1 << A.n;
@@ -846,7 +853,7 @@ __device__ __forceinline__ void setup(Ctx<real, LR, FLY>& C, const Args<real>& A
   C.ang_sh = tail;
   C.ang_ps = C.ang_sh + 2 * (size_t)A.n_gates;
   C.fu_sh = C.ang_ps + (FLY ? 0 : 2 * (size_t)A.n_slots * A.S);
-  C.gen_sh = C.fu_sh + 8 * (size_t)A.n_fu;
+  C.gen_sh = C.fu_sh + 8 * ((size_t)A.n_fu + 1);
   C.gacc = C.gen_sh + (adjoint ? 3 * (size_t)A.n_gen : 0);
   C.wps = A.t > 6 ? (1 << (A.t - 6)) : 1;
   const int waves = blockDim.x >> 6;
@@ -881,7 +888,12 @@ __device__ __forceinline__ void setup(Ctx<real, LR, FLY>& C, const Args<real>& A
     for (int i = tid; i < A.S * C.wps * A.n_feats; i += blockDim.x) C.facc[i] = 0;
   }
   __syncthreads();
-  // Fused matrices of the blocks whose angles are shared.
+  // Fused matrices of the blocks whose angles are shared; slot n_fu holds the
+  // identity (register bits without a block).
+  if (tid == 0) {
+    real* f = C.fu_sh + 8 * (size_t)A.n_fu;
+    f[0] = 1; f[1] = 0; f[2] = 0; f[3] = 0; f[4] = 0; f[5] = 0; f[6] = 1; f[7] = 0;
+  }
   for (int bid = tid; bid < A.n_blocks; bid += blockDim.x) {
     const int fu = A.blk_fu[bid];
     if (fu < 0) continue;
@@ -938,12 +950,12 @@ __device__ __forceinline__ bool map_changed(const Args<real>& A, int s) {
 }
 
 // ------------------------------------------------------------------ forward
-template <typename real, int LR, bool FLY = false>
+template <typename real, int LR, bool FLY = false, bool SHARED = false>
 __device__ __forceinline__ void forward_body(const Args<real>& A, unsigned char* smem,
                                              int64_t blk) {
   constexpr int R = 1 << LR;
-  Ctx<real, LR, FLY> C(A);
-  setup<real, LR, FLY>(C, A, smem, false, blk);
+  Ctx<real, LR, FLY, SHARED> C(A);
+  setup(C, A, smem, false, blk);
 
   St<real, R> x;
   C.load_state(x, A.state, rlay(A, 0));
@@ -1012,12 +1024,12 @@ __device__ __forceinline__ void forward_body(const Args<real>& A, unsigned char*
 }
 
 // ------------------------------------------------------------------ adjoint
-template <typename real, int LR, bool FLY = false>
+template <typename real, int LR, bool FLY = false, bool SHARED = false>
 __device__ __forceinline__ void adjoint_body(const Args<real>& A, unsigned char* smem,
                                              int64_t blk) {
   constexpr int R = 1 << LR;
-  Ctx<real, LR, FLY> C(A);
-  setup<real, LR, FLY>(C, A, smem, true, blk);
+  Ctx<real, LR, FLY, SHARED> C(A);
+  setup(C, A, smem, true, blk);
   const int nseg = A.nseg;
   const QS_K uint8_t* last = seg_map<real, LR>(A, nseg - 1);
 
@@ -1094,16 +1106,16 @@ __device__ __forceinline__ void adjoint_body(const Args<real>& A, unsigned char*
     }
 }
 
-template <typename real, int LR, int MAXT>
+template <typename real, int LR, int MAXT, bool SHARED>
 __global__ void __launch_bounds__(MAXT) sv_forward(Args<real> A) {
   extern __shared__ __align__(16) unsigned char smem[];
-  forward_body<real, LR>(A, smem, (int64_t)blockIdx.x * A.S);
+  forward_body<real, LR, false, SHARED>(A, smem, (int64_t)blockIdx.x * A.S);
 }
 
-template <typename real, int LR, int MAXT>
+template <typename real, int LR, int MAXT, bool SHARED>
 __global__ void __launch_bounds__(MAXT) sv_adjoint(Args<real> A) {
   extern __shared__ __align__(16) unsigned char smem[];
-  adjoint_body<real, LR>(A, smem, (int64_t)blockIdx.x * A.S);
+  adjoint_body<real, LR, false, SHARED>(A, smem, (int64_t)blockIdx.x * A.S);
 }
 
 // Uneven batches in one persistent launch: workgroups pull work items (a
@@ -1233,7 +1245,7 @@ Args<real> make_args(const SvLaunch& L) {
   return A;
 }
 
-template <typename real, int LR, int MAXT, bool ADJ>
+template <typename real, int LR, int MAXT, bool ADJ, bool SHARED = false>
 int launch_one(const SvLaunch& L) {
   Args<real> A = make_args<real>(L);
   const int64_t grid = (A.B + A.S - 1) / A.S;
@@ -1243,9 +1255,9 @@ int launch_one(const SvLaunch& L) {
   // Only the kernel of this direction is instantiated.
   auto kern = [] {
     if constexpr (ADJ)
-      return sv_adjoint<real, LR, MAXT>;
+      return sv_adjoint<real, LR, MAXT, SHARED>;
     else
-      return sv_forward<real, LR, MAXT>;
+      return sv_forward<real, LR, MAXT, SHARED>;
   }();
   if (L.shape.lds_bytes > 65536) {
     if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
