@@ -296,7 +296,8 @@ def main():
                 t = N.qs_autotune(s0.h, s0.qs_dtype, w.batch, 0)
                 tuned[name] = {k: t[k] for k in ("fwd_log2_regs", "adj_log2_regs",
                                                  "tile_qubits", "fwd_samples_cap",
-                                                 "adj_samples_cap")}
+                                                 "adj_samples_cap", "fwd_half_staging",
+                                                 "adj_half_staging")}
             torch.cuda.synchronize()
         ck = 4 if key == "c5b" else 0
         # automatic path: register/LDS engine when it fits, else tiled HBM

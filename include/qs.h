@@ -312,6 +312,9 @@ typedef struct qs_tune_info {
   int32_t fwd_samples_cap; /* chosen cap on samples per workgroup, forward
                               (0: as many as the LDS holds)                  */
   int32_t adj_samples_cap; /* the same for the adjoint                       */
+  int32_t fwd_half_staging; /* 1: the forward stages one state component at a
+                               time in LDS (half the LDS per sample)        */
+  int32_t adj_half_staging; /* the same for the adjoint                      */
   int32_t reserved;
 } qs_tune_info;
 

@@ -71,7 +71,8 @@ class QsTuneInfo(ctypes.Structure):
                 ("adj_log2_regs", ctypes.c_int32), ("tile_qubits", ctypes.c_int32),
                 ("fwd_ms", ctypes.c_float), ("adj_ms", ctypes.c_float),
                 ("n_candidates", ctypes.c_int32), ("fwd_samples_cap", ctypes.c_int32),
-                ("adj_samples_cap", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("adj_samples_cap", ctypes.c_int32), ("fwd_half_staging", ctypes.c_int32),
+                ("adj_half_staging", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class QsError(RuntimeError):

@@ -71,6 +71,7 @@ int env_int(const char* name, int dflt) {
 struct TuneVal {
   int fwd_r = 0, adj_r = 0, m = 0;
   int fwd_s = 0, adj_s = 0;  // samples-per-block caps (0: the LDS-limited default)
+  int fwd_h = 0, adj_h = 0;  // 1: stage one state component at a time in LDS
 };
 std::mutex g_tmu;
 std::mutex g_tune_run_mu;  // one tuning run at a time (overrides are global)
@@ -78,6 +79,7 @@ std::unordered_map<std::string, TuneVal> g_tune;
 bool g_tune_loaded = false;
 int g_force_fwd_r = 0, g_force_adj_r = 0, g_force_m = 0;
 int g_force_fwd_s = 0, g_force_adj_s = 0;
+int g_force_fwd_h = -1, g_force_adj_h = -1;  // -1: not forced
 thread_local bool g_in_tune = false;  // calls made by the tuner itself
 
 int batch_class(int64_t B) {
@@ -108,14 +110,15 @@ void load_tune_file_locked() {
   if (!path || !*path) return;
   FILE* f = std::fopen(path, "r");
   if (!f) return;
-  // One line per tuned key: key fwd_r adj_r m [fwd_s adj_s].
+  // One line per tuned key: key fwd_r adj_r m [fwd_s adj_s [fwd_h adj_h]].
   char line[256], key[64];
   while (std::fgets(line, sizeof(line), f)) {
     TuneVal v;
-    const int k = std::sscanf(line, "%63s %d %d %d %d %d", key, &v.fwd_r, &v.adj_r, &v.m,
-                              &v.fwd_s, &v.adj_s);
-    if (k != 4 && k != 6) continue;
-    if (k == 4) v.fwd_s = v.adj_s = 0;
+    const int k = std::sscanf(line, "%63s %d %d %d %d %d %d %d", key, &v.fwd_r, &v.adj_r,
+                              &v.m, &v.fwd_s, &v.adj_s, &v.fwd_h, &v.adj_h);
+    if (k != 4 && k != 6 && k != 8) continue;
+    if (k < 6) v.fwd_s = v.adj_s = 0;
+    if (k < 8) v.fwd_h = v.adj_h = 0;
     g_tune[key] = v;
   }
   std::fclose(f);
@@ -143,7 +146,7 @@ struct TableCounts {
 };
 
 int64_t lds_bytes(int dtype, const qs_circuit& c, int S, int n_slots, int block,
-                  bool ps, bool adjoint, const TableCounts* tc = nullptr) {
+                  bool ps, bool adjoint, const TableCounts* tc = nullptr, bool half = false) {
   const int64_t rs = dtype == QS_C64 ? 4 : 8;
   const int64_t waves = (block + 63) / 64;
   const int64_t T = block / (S > 0 ? S : 1);
@@ -158,7 +161,7 @@ int64_t lds_bytes(int dtype, const qs_circuit& c, int S, int n_slots, int block,
                             (ps ? (x.p_w >= 0 || x.p_b >= 0 || x.feat >= 0) : x.feat >= 0);
     n1q += per_sample ? 0 : 1;
   }
-  int64_t b = (int64_t)S * (2 * rs << c.n_qubits);  // states
+  int64_t b = (int64_t)S * ((half ? 1 : 2) * rs << c.n_qubits);  // state staging
   b += 2 * rs * c.n_gates;                          // shared angle table
   const int64_t n_fu = tc ? tc->n_fu : n1q, n_gen = tc ? tc->n_gen : n1q;
   b += 8 * rs * (n_fu + 1);                         // fused block matrices, identity
@@ -180,7 +183,8 @@ TableCounts plan_counts(const qs_circuit& c, int r, bool ps, const int32_t* ck, 
 bool choose_shape(int dtype, const qs_circuit& c, int n_slots, int r_force,
                   bool adjoint, SvShape* out, bool ps = false,
                   const int32_t* ck = nullptr, int n_ck = 0, bool exact = true,
-                  int s_cap = 0) {
+                  int s_cap = 0, bool half = false) {
+  if (dtype != QS_C64) half = false;  // half staging exists for complex64 only
   const int n = c.n_qubits;
   if (n > kMaxQubitsFused) return false;
   static const int pref_c64_fwd[] = {5, 4, 3, 2, 1};
@@ -211,7 +215,7 @@ bool choose_shape(int dtype, const qs_circuit& c, int n_slots, int r_force,
     if (exact) counts = plan_counts(c, r, ps, ck, n_ck);
     const TableCounts* tc = exact ? &counts : nullptr;
     // Shrink the block until the LDS fits.
-    while (S > 1 && lds_bytes(dtype, c, S, n_slots, S * T, ps, adjoint, tc) > kMaxLds) {
+    while (S > 1 && lds_bytes(dtype, c, S, n_slots, S * T, ps, adjoint, tc, half) > kMaxLds) {
       S >>= 1;
     }
     // A smaller block can fit more workgroups per CU (an autotuner choice).
@@ -221,13 +225,14 @@ bool choose_shape(int dtype, const qs_circuit& c, int n_slots, int r_force,
       S = 64 / T;
       block = 64;
     }
-    const int64_t lds = lds_bytes(dtype, c, S, n_slots, block, ps, adjoint, tc);
+    const int64_t lds = lds_bytes(dtype, c, S, n_slots, block, ps, adjoint, tc, half);
     if (lds > kMaxLds) continue;
     out->r = r;
     out->t = t;
     out->block_threads = block;
     out->samples_per_block = S;
     out->lds_bytes = lds;
+    out->half = half ? 1 : 0;
     return true;
   }
   return false;
@@ -398,7 +403,7 @@ bool tables_fit(const Entry& e, int dtype, const qs_circuit& c, const SvShape& s
   tc.n_fu = e.host.n_fu;
   tc.n_gen = e.host.n_gen;
   return lds_bytes(dtype, c, shape.samples_per_block, (int)e.host.slot_gate.size(),
-                   shape.block_threads, ps, adjoint, &tc) <= shape.lds_bytes;
+                   shape.block_threads, ps, adjoint, &tc, shape.half != 0) <= shape.lds_bytes;
 }
 
 qs_gate* get_dev_gates(const qs_circuit& c, int* rc) {
@@ -574,14 +579,17 @@ int pick_path(const qs_circuit& c, int dtype, int flags, SvShape* shape,
   if (sc == 0)
     sc = env_int(adjoint ? "QS_ADJ_SAMPLES_PER_BLOCK" : "QS_FWD_SAMPLES_PER_BLOCK", 0);
   if (sc == 0 && tv) sc = adjoint ? tv->adj_s : tv->fwd_s;
+  int hf = adjoint ? g_force_adj_h : g_force_fwd_h;
+  if (hf < 0) hf = env_int(adjoint ? "QS_ADJ_HALF_STAGING" : "QS_FWD_HALF_STAGING", -1);
+  if (hf < 0) hf = tv ? (adjoint ? tv->adj_h : tv->fwd_h) : 0;
   const bool ps = (flags & QS_FLAG_PER_SAMPLE_PARAMS) != 0;
   if (path == QS_PATH_AUTO) {
-    if (choose_shape(dtype, c, n_slots, rf, adjoint, shape, ps, ck, n_ck, true, sc))
+    if (choose_shape(dtype, c, n_slots, rf, adjoint, shape, ps, ck, n_ck, true, sc, hf > 0))
       path = QS_PATH_FUSED;
     else
       path = c.n_qubits > kMaxQubitsFused ? QS_PATH_HBM : QS_PATH_PLAIN;
   } else if (path == QS_PATH_FUSED) {
-    if (!choose_shape(dtype, c, n_slots, rf, adjoint, shape, ps, ck, n_ck, true, sc))
+    if (!choose_shape(dtype, c, n_slots, rf, adjoint, shape, ps, ck, n_ck, true, sc, hf > 0))
       return QS_ERR_UNSUPPORTED;
   } else if (path != QS_PATH_PLAIN && path != QS_PATH_HBM) {
     return QS_ERR_INVALID;
@@ -745,46 +753,58 @@ int qs_autotune(const qs_circuit* c, int dtype, int64_t B, int flags, void* stre
     ~InTune() { g_in_tune = false; }
   } in_tune;
   if (path == QS_PATH_FUSED) {
-    // Register split r, and for each the samples per block: the LDS-limited
-    // default and two smaller blocks (more workgroups per CU).
+    // Register split r; for each, the LDS staging mode (whole amplitudes,
+    // or one component at a time: half the LDS per sample) and the samples
+    // per block: the LDS-limited default and two smaller blocks (more
+    // workgroups per CU).
     const int slots = count_slots(*c, ps);
     for (int dir = 0; dir < 2; ++dir) {
       const bool adjoint = dir == 1;
       int& force_r = adjoint ? g_force_adj_r : g_force_fwd_r;
       int& force_s = adjoint ? g_force_adj_s : g_force_fwd_s;
+      int& force_h = adjoint ? g_force_adj_h : g_force_fwd_h;
       float& bt = adjoint ? ba : bf;
       for (int r = 1; r <= 5; ++r) {
-        SvShape base;
-        if (!choose_shape(dtype, *c, slots, r, adjoint, &base, ps) || base.r != r) continue;
-        int last_block = 0;
-        for (int div = 1; div <= 4; div *= 2) {
-          const int cap = div == 1 ? 0 : base.samples_per_block / div;
-          if (div > 1 && cap < 1) break;
-          SvShape sh;
-          if (!choose_shape(dtype, *c, slots, r, adjoint, &sh, ps, nullptr, 0, true, cap) ||
-              sh.r != r || sh.block_threads == last_block)
+        for (int half = 0; half <= (dtype == QS_C64 ? 1 : 0); ++half) {
+          SvShape base;
+          if (!choose_shape(dtype, *c, slots, r, adjoint, &base, ps, nullptr, 0, true, 0,
+                            half != 0) ||
+              base.r != r)
             continue;
-          last_block = sh.block_threads;
-          force_r = r;
-          force_s = cap;
-          float ms;
-          if (adjoint) {
-            const size_t wsb = fused_ws_bytes(*c, dtype, sh, B, ps);
-            void* ws = sc.get(wsb);
-            if (!ws) { force_r = force_s = 0; return QS_ERR_NOMEM; }
-            ms = time_ms(st, [&]() { return adj(ws, wsb); }, 3, &rc);
-          } else {
-            ms = time_ms(st, fwd, 3, &rc);
-          }
-          force_r = force_s = 0;
-          info.n_candidates++;
-          if (rc != QS_OK) return rc;
-          // A smaller block must win clearly: within timing noise the
-          // LDS-limited default is kept.
-          if (ms < (cap ? 0.98f : 1.0f) * bt) {
-            bt = ms;
-            (adjoint ? best.adj_r : best.fwd_r) = r;
-            (adjoint ? best.adj_s : best.fwd_s) = cap;
+          int last_block = 0;
+          for (int div = 1; div <= 4; div *= 2) {
+            const int cap = div == 1 ? 0 : base.samples_per_block / div;
+            if (div > 1 && cap < 1) break;
+            SvShape sh;
+            if (!choose_shape(dtype, *c, slots, r, adjoint, &sh, ps, nullptr, 0, true, cap,
+                              half != 0) ||
+                sh.r != r || sh.block_threads == last_block)
+              continue;
+            last_block = sh.block_threads;
+            force_r = r;
+            force_s = cap;
+            force_h = half;
+            float ms;
+            if (adjoint) {
+              const size_t wsb = fused_ws_bytes(*c, dtype, sh, B, ps);
+              void* ws = sc.get(wsb);
+              if (!ws) { force_r = force_s = 0; force_h = -1; return QS_ERR_NOMEM; }
+              ms = time_ms(st, [&]() { return adj(ws, wsb); }, 3, &rc);
+            } else {
+              ms = time_ms(st, fwd, 3, &rc);
+            }
+            force_r = force_s = 0;
+            force_h = -1;
+            info.n_candidates++;
+            if (rc != QS_OK) return rc;
+            // A smaller block or half staging must win clearly: within timing
+            // noise the LDS-limited default is kept.
+            if (ms < ((cap || half) ? 0.98f : 1.0f) * bt) {
+              bt = ms;
+              (adjoint ? best.adj_r : best.fwd_r) = r;
+              (adjoint ? best.adj_s : best.fwd_s) = cap;
+              (adjoint ? best.adj_h : best.fwd_h) = half;
+            }
           }
         }
       }
@@ -837,6 +857,8 @@ int qs_autotune(const qs_circuit* c, int dtype, int64_t B, int flags, void* stre
   info.adj_log2_regs = best.adj_r;
   info.fwd_samples_cap = best.fwd_s;
   info.adj_samples_cap = best.adj_s;
+  info.fwd_half_staging = best.fwd_h;
+  info.adj_half_staging = best.adj_h;
   info.tile_qubits = best.m;
   info.fwd_ms = bf;
   info.adj_ms = ba;
@@ -848,8 +870,8 @@ int qs_autotune(const qs_circuit* c, int dtype, int64_t B, int flags, void* stre
     const char* path_env = std::getenv("QS_AUTOTUNE_CACHE");
     if (path_env && *path_env) {
       if (FILE* f = std::fopen(path_env, "a")) {
-        std::fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), best.fwd_r, best.adj_r, best.m,
-                     best.fwd_s, best.adj_s);
+        std::fprintf(f, "%s %d %d %d %d %d %d %d\n", key.c_str(), best.fwd_r, best.adj_r,
+                     best.m, best.fwd_s, best.adj_s, best.fwd_h, best.adj_h);
         std::fclose(f);
       }
     }

@@ -157,6 +157,7 @@ struct SvShape {
   int block_threads;        // threads per workgroup
   int samples_per_block;
   int64_t lds_bytes;
+  int half = 0;             // LDS staging one state component at a time
 };
 
 // Kernel launchers (defined in the .hip files).

@@ -459,8 +459,12 @@ __device__ __forceinline__ void sample_sync(int t) {
 
 // The engine's per-thread context. SHARED: every block of the plan has
 // shared angles (its fused matrix and generator frames are in LDS), so the
-// per-sample block code is left out.
-template <typename real, int LR, bool FLY = false, bool SHARED = false>
+// per-sample block code is left out. HALF: the LDS staging region of a
+// sample holds one component (real or imaginary parts) of its state at a
+// time, so remaps and HBM transfers run as two passes; it halves the LDS a
+// sample needs, which lets more workgroups share a CU when LDS is what
+// limits them (an autotuner choice).
+template <typename real, int LR, bool FLY = false, bool SHARED = false, bool HALF = false>
 struct Ctx {
   static constexpr int R = 1 << LR;
   using v2 = typename V2<real>::T;
@@ -471,7 +475,8 @@ struct Ctx {
   int64_t base;      // offset (complex elements) of the sample's amplitude 0
   uint32_t dep_tau;  // tiled: global offset of this thread's low local bits
   bool active;
-  v2* lds;           // this sample's state region
+  real* ldr;         // this sample's LDS staging region
+  v2* lds;           // the same, as complex elements (full staging)
   uint32_t salt;     // per-sample slot salt
   real* ang_sh;      // [G][2] shared (cos, sin) of theta/2, by gate
   real* ang_ps;      // [n_slots][S][2] per-sample
@@ -498,6 +503,9 @@ struct Ctx {
     return swz(L) ^ salt;
   }
 
+  // Staging writes and reads under a layout: component P of the state
+  // (HALF), or whole complex amplitudes (P ignored).
+  template <int P>
   __device__ __forceinline__ void write_mapped(const St<real, R>& x,
                                                const QS_K uint16_t* lay) {
     const uint32_t base = lane_part(lay);
@@ -510,14 +518,18 @@ struct Ctx {
 #pragma unroll
       for (int j = 0; j < LR; ++j)
         if (k & (1 << j)) off ^= m[j];
-      v2 v;
-      v.x = x.re[k];
-      v.y = x.im[k];
-      lds[base ^ off] = v;
+      if constexpr (HALF) {
+        ldr[base ^ off] = P ? x.im[k] : x.re[k];
+      } else {
+        v2 v;
+        v.x = x.re[k];
+        v.y = x.im[k];
+        lds[base ^ off] = v;
+      }
     }
   }
-  __device__ __forceinline__ void read_mapped(St<real, R>& x,
-                                              const QS_K uint16_t* lay) {
+  template <int P>
+  __device__ __forceinline__ void read_mapped(St<real, R>& x, const QS_K uint16_t* lay) {
     const uint32_t base = lane_part(lay);
     uint32_t m[LR > 0 ? LR : 1];
 #pragma unroll
@@ -528,17 +540,27 @@ struct Ctx {
 #pragma unroll
       for (int j = 0; j < LR; ++j)
         if (k & (1 << j)) off ^= m[j];
-      v2 v = lds[base ^ off];
-      x.re[k] = v.x;
-      x.im[k] = v.y;
+      if constexpr (HALF) {
+        (P ? x.im[k] : x.re[k]) = ldr[base ^ off];
+      } else {
+        const v2 v = lds[base ^ off];
+        x.re[k] = v.x;
+        x.im[k] = v.y;
+      }
     }
   }
+  // Staging passes: two with HALF (real parts, then imaginary), else one.
+  static constexpr int kPasses = HALF ? 2 : 1;
+
   __device__ __forceinline__ void remap(St<real, R>& x, const QS_K uint16_t* from,
                                         const QS_K uint16_t* to) {
-    sample_sync(A.t);
-    write_mapped(x, from);
-    sample_sync(A.t);
-    read_mapped(x, to);
+    static_for<kPasses>([&](auto PC) QS_AI {
+      constexpr int P = decltype(PC)::value;
+      sample_sync(A.t);
+      write_mapped<P>(x, from);
+      sample_sync(A.t);
+      read_mapped<P>(x, to);
+    });
   }
 
   // HBM offsets of the R amplitudes this thread moves between HBM and LDS:
@@ -576,47 +598,66 @@ struct Ctx {
       x.re[u] = v.x;  // staging only: read_mapped below sets the placement
       x.im[u] = v.y;
     }
-    sample_sync(A.t);
     const uint32_t tb = opaque((uint32_t)tau);
+    static_for<kPasses>([&](auto PC) QS_AI {
+      constexpr int P = decltype(PC)::value;
+      sample_sync(A.t);
 #pragma unroll
-    for (int u = 0; u < R; ++u) {
-      v2 v;
-      v.x = x.re[u];
-      v.y = x.im[u];
-      lds[swz(tb + ((uint32_t)u << A.t)) ^ salt] = v;
-    }
-    sample_sync(A.t);
-    read_mapped(x, map);
+      for (int u = 0; u < R; ++u) {
+        const uint32_t a = swz(tb + ((uint32_t)u << A.t)) ^ salt;
+        if constexpr (HALF) {
+          ldr[a] = P ? x.im[u] : x.re[u];
+        } else {
+          v2 v;
+          v.x = x.re[u];
+          v.y = x.im[u];
+          lds[a] = v;
+        }
+      }
+      sample_sync(A.t);
+      read_mapped<P>(x, map);  // with HALF, the other component is still staged
+    });
   }
   // Registers under `map` -> LDS -> HBM (logical order), in runs of 8.
+  // In runs of 8. With HALF each pass stores every other real of a run of
+  // amplitudes and the second pass fills the gaps (the lines merge in L2).
   __device__ __forceinline__ void store_state(const St<real, R>& x, real* dst,
                                               const QS_K uint16_t* map) {
-    sample_sync(A.t);
-    write_mapped(x, map);
-    sample_sync(A.t);
-    if (!active) return;
-    v2* d2 = reinterpret_cast<v2*>(dst);
     int64_t off[LR > 0 ? LR : 1];
     hbm_offsets(off);
     const int64_t a0 = hbm_a0();
     constexpr int W = R < 8 ? R : 8;
     const uint32_t tb = opaque((uint32_t)tau);
+    static_for<kPasses>([&](auto PC) QS_AI {
+      constexpr int P = decltype(PC)::value;
+      sample_sync(A.t);
+      write_mapped<P>(x, map);
+      sample_sync(A.t);
+      if (active) {
 #pragma unroll
-    for (int u0 = 0; u0 < R; u0 += W) {
-      v2 v[W];
+        for (int u0 = 0; u0 < R; u0 += W) {
+          using E = typename std::conditional<HALF, real, v2>::type;
+          E v[W];
 #pragma unroll
-      for (int w = 0; w < W; ++w)
-        v[w] = lds[swz(tb + ((uint32_t)(u0 + w) << A.t)) ^ salt];
+          for (int w = 0; w < W; ++w) {
+            const uint32_t a = swz(tb + ((uint32_t)(u0 + w) << A.t)) ^ salt;
+            if constexpr (HALF) v[w] = ldr[a]; else v[w] = lds[a];
+          }
 #pragma unroll
-      for (int w = 0; w < W; ++w) {
-        const int u = u0 + w;
-        int64_t o = 0;
+          for (int w = 0; w < W; ++w) {
+            const int u = u0 + w;
+            int64_t o = 0;
 #pragma unroll
-        for (int j = 0; j < LR; ++j)
-          if (u & (1 << j)) o += off[j];
-        d2[a0 + o] = v[w];
+            for (int j = 0; j < LR; ++j)
+              if (u & (1 << j)) o += off[j];
+            if constexpr (HALF)
+              dst[2 * (a0 + o) + P] = v[w];
+            else
+              reinterpret_cast<v2*>(dst)[a0 + o] = v[w];
+          }
+        }
       }
-    }
+    });
   }
 
   // cos, sin of theta/2 of a block's rotation (uniform record).
@@ -821,9 +862,10 @@ struct Ctx {
 // `blk` is the global index of the block's first sample. Gradient sums are
 // kept in per-wave LDS slots (each written by one lane of one wave) and added
 // in a fixed order at the end, so the adjoint is bitwise reproducible.
-template <typename real, int LR, bool FLY, bool SHARED>
-__device__ __forceinline__ void setup(Ctx<real, LR, FLY, SHARED>& C, const Args<real>& A,
-                                      unsigned char* smem, bool adjoint, int64_t blk) {
+template <typename real, int LR, bool FLY, bool SHARED, bool HALF>
+__device__ __forceinline__ void setup(Ctx<real, LR, FLY, SHARED, HALF>& C,
+                                      const Args<real>& A, unsigned char* smem, bool adjoint,
+                                      int64_t blk) {
   const int tid = threadIdx.x;
   const int N = 1 << A.n;
   C.tau = tid & ((1 << A.t) - 1);
@@ -845,11 +887,12 @@ __device__ __forceinline__ void setup(Ctx<real, LR, FLY, SHARED>& C, const Args<
       if ((C.tau >> j) & 1) d |= 1u << kc(A.tile_q)[j];
     C.dep_tau = d;
   }
-  using v2 = typename V2<real>::T;
-  v2* st = reinterpret_cast<v2*>(smem);
-  C.lds = st + (size_t)C.sl * N;
+  constexpr int comps = HALF ? 1 : 2;  // reals per staged amplitude
+  real* st = reinterpret_cast<real*>(smem);
+  C.ldr = st + (size_t)C.sl * N * comps;
+  C.lds = reinterpret_cast<typename V2<real>::T*>(C.ldr);
   C.salt = ((uint32_t)C.sl << A.t) & 31u & (uint32_t)(N - 1);
-  real* tail = reinterpret_cast<real*>(st + (size_t)A.S * N);
+  real* tail = st + (size_t)A.S * N * comps;
   C.ang_sh = tail;
   C.ang_ps = C.ang_sh + 2 * (size_t)A.n_gates;
   C.fu_sh = C.ang_ps + (FLY ? 0 : 2 * (size_t)A.n_slots * A.S);
@@ -950,11 +993,11 @@ __device__ __forceinline__ bool map_changed(const Args<real>& A, int s) {
 }
 
 // ------------------------------------------------------------------ forward
-template <typename real, int LR, bool FLY = false, bool SHARED = false>
+template <typename real, int LR, bool FLY = false, bool SHARED = false, bool HALF = false>
 __device__ __forceinline__ void forward_body(const Args<real>& A, unsigned char* smem,
                                              int64_t blk) {
   constexpr int R = 1 << LR;
-  Ctx<real, LR, FLY, SHARED> C(A);
+  Ctx<real, LR, FLY, SHARED, HALF> C(A);
   setup(C, A, smem, false, blk);
 
   St<real, R> x;
@@ -978,7 +1021,7 @@ __device__ __forceinline__ void forward_body(const Args<real>& A, unsigned char*
     // <Z_q> partials in FP64, reduced over the sample's threads.
     const int Tw = (1 << A.t) < 64 ? (1 << A.t) : 64;
     const int nw = (1 << A.t) / Tw;  // waves per sample
-    double* red = reinterpret_cast<double*>(C.lds);
+    double* red = reinterpret_cast<double*>(C.ldr);
     sample_sync(A.t);
     // tot = sum_k |x_k|^2 and hi[j] = the part with register bit j set, so a
     // register-bit qubit reads tot - 2 hi[j] and a thread-bit one +-tot.
@@ -1024,11 +1067,11 @@ __device__ __forceinline__ void forward_body(const Args<real>& A, unsigned char*
 }
 
 // ------------------------------------------------------------------ adjoint
-template <typename real, int LR, bool FLY = false, bool SHARED = false>
+template <typename real, int LR, bool FLY = false, bool SHARED = false, bool HALF = false>
 __device__ __forceinline__ void adjoint_body(const Args<real>& A, unsigned char* smem,
                                              int64_t blk) {
   constexpr int R = 1 << LR;
-  Ctx<real, LR, FLY, SHARED> C(A);
+  Ctx<real, LR, FLY, SHARED, HALF> C(A);
   setup(C, A, smem, true, blk);
   const int nseg = A.nseg;
   const QS_K uint8_t* last = seg_map<real, LR>(A, nseg - 1);
@@ -1106,16 +1149,16 @@ __device__ __forceinline__ void adjoint_body(const Args<real>& A, unsigned char*
     }
 }
 
-template <typename real, int LR, int MAXT, bool SHARED>
+template <typename real, int LR, int MAXT, bool SHARED, bool HALF>
 __global__ void __launch_bounds__(MAXT) sv_forward(Args<real> A) {
   extern __shared__ __align__(16) unsigned char smem[];
-  forward_body<real, LR, false, SHARED>(A, smem, (int64_t)blockIdx.x * A.S);
+  forward_body<real, LR, false, SHARED, HALF>(A, smem, (int64_t)blockIdx.x * A.S);
 }
 
-template <typename real, int LR, int MAXT, bool SHARED>
+template <typename real, int LR, int MAXT, bool SHARED, bool HALF>
 __global__ void __launch_bounds__(MAXT) sv_adjoint(Args<real> A) {
   extern __shared__ __align__(16) unsigned char smem[];
-  adjoint_body<real, LR, false, SHARED>(A, smem, (int64_t)blockIdx.x * A.S);
+  adjoint_body<real, LR, false, SHARED, HALF>(A, smem, (int64_t)blockIdx.x * A.S);
 }
 
 // Uneven batches in one persistent launch: workgroups pull work items (a
@@ -1245,7 +1288,7 @@ Args<real> make_args(const SvLaunch& L) {
   return A;
 }
 
-template <typename real, int LR, int MAXT, bool ADJ, bool SHARED = false>
+template <typename real, int LR, int MAXT, bool ADJ, bool SHARED = false, bool HALF = false>
 int launch_one(const SvLaunch& L) {
   Args<real> A = make_args<real>(L);
   const int64_t grid = (A.B + A.S - 1) / A.S;
@@ -1255,9 +1298,9 @@ int launch_one(const SvLaunch& L) {
   // Only the kernel of this direction is instantiated.
   auto kern = [] {
     if constexpr (ADJ)
-      return sv_adjoint<real, LR, MAXT, SHARED>;
+      return sv_adjoint<real, LR, MAXT, SHARED, HALF>;
     else
-      return sv_forward<real, LR, MAXT, SHARED>;
+      return sv_forward<real, LR, MAXT, SHARED, HALF>;
   }();
   if (L.shape.lds_bytes > 65536) {
     if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern),

@@ -251,6 +251,41 @@ def test_full_size_autoencoder_sampled_rows():
     np.testing.assert_allclose(g2.cpu().numpy(), gph, atol=1e-4)
 
 
+# ------------------------------------------- LDS staging, one component a time
+@pytest.fixture
+def half_staging(monkeypatch):
+    monkeypatch.setenv("QS_FWD_HALF_STAGING", "1")
+    monkeypatch.setenv("QS_ADJ_HALF_STAGING", "1")
+
+
+@pytest.mark.parametrize("n", [1, 3, 6, 10, 13, 14])
+def test_half_staging_random_circuits(n, half_staging, monkeypatch):
+    rng = np.random.default_rng(900 + n)
+    c = C.random_circuit(n, 80, rng, n_params=7, n_features=3)
+    half = sim.Simulator(c, "c64").plan_info(5)
+    monkeypatch.delenv("QS_FWD_HALF_STAGING")
+    full = sim.Simulator(c, "c64").plan_info(5)
+    monkeypatch.setenv("QS_FWD_HALF_STAGING", "1")
+    # the same samples per block need less LDS with one component staged
+    per_sample = (full["lds_bytes"] / full["samples_per_block"],
+                  half["lds_bytes"] / half["samples_per_block"])
+    assert per_sample[1] < per_sample[0]
+    _run_expz_case(c, "c64", "fused", 33 if n <= 10 else 3, seed=n)
+
+
+@pytest.mark.parametrize("kind", ["start_end", "zz", "cancel"])
+def test_half_staging_cnot_patterns_and_per_sample(kind, half_staging):
+    _run_expz_case(cnot_pattern(9, kind), "c64", "fused", 21, seed=6)
+    rng = np.random.default_rng(33)
+    c = C.random_circuit(8, 60, rng, n_params=6, n_features=2)
+    _run_expz_case(c, "c64", "fused", 19, seed=7, per_sample=True)
+    _run_expz_case(c, "c64", "fused", 13, seed=8, dstate_mode=True, amplitude=False)
+
+
+def test_half_staging_full_size_c3_sampled_rows(half_staging):
+    test_full_size_sampled_rows("c3")
+
+
 # ----------------------------------------------------------------- edge cases
 def test_zero_norm_rows_are_counted_and_nan():
     c = C.hea_ry_rz_ring(3, 1)
@@ -624,6 +659,7 @@ def test_autotune_picks_a_config_and_results_stay_exact(tmp_path, monkeypatch):
     line = cache.read_text().split()
     assert int(line[1]) == info["fwd_log2_regs"] and int(line[2]) == info["adj_log2_regs"]
     assert int(line[4]) == info["fwd_samples_cap"] and int(line[5]) == info["adj_samples_cap"]
+    assert int(line[6]) == info["fwd_half_staging"] and int(line[7]) == info["adj_half_staging"]
     pi = s.plan_info(96)
     assert pi["log2_regs"] == info["fwd_log2_regs"]
     assert pi["adj_log2_regs"] == info["adj_log2_regs"]
