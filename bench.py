@@ -19,6 +19,7 @@ of the batch (the ``cpu_baseline`` leg, c2 only).
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import subprocess
@@ -43,13 +44,21 @@ WORKLOAD_TEXT = {
            "hardware-efficient layers (RY,RZ + ring CNOT), one amplitude-encoded "
            "N(0,1) input each, loss sum_q g_q <Z_q>; one persistent launch per "
            "direction; complex64 forward + adjoint",
-    "c5b": "26 qubits, one complex64 state (512 MiB in HBM), 20 hardware-efficient "
+    "c5b": "26 qubits, one complex64 state (512 MiB in HBM; 1 GiB in complex128), 20 hardware-efficient "
            "layers (RY,RZ + ring CNOT; 1560 gates), loss sum_q g_q <Z_q>, state "
            "checkpoints every 4 layers; forward + adjoint on the tiled large-state "
            "path",
 }
+
+
+def workload_text(key, dtype):
+    t = WORKLOAD_TEXT[key]
+    return t.replace("complex64 forward", "complex128 forward") if dtype == "c128" else t
+
+
 # MI355X published peaks: fp32 vector 157.3 TFLOP/s, HBM 8 TB/s.
 PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBPS = 8000.0
 # LDS: 128 B per clock per CU (the CDNA figure; not re-measured here) x 256
 # CUs x 2.4 GHz. Used only for the pass-equivalent context figure.
@@ -217,6 +226,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--dtype", choices=["c64", "c128"], default=None,
+                    help="run the workload in this complex type (default: its own)")
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--cpu-rows", type=int, default=256,
                     help="oracle rows per host process for cpu_baseline")
@@ -264,7 +275,7 @@ def main():
 
     if key == "c5a":
         ub = uneven_batch()
-        dev = sim.UnevenDevice(ub)
+        dev = sim.UnevenDevice(ub, dtype=args.dtype or "c64")
         updates = ub.updates_per_step()
         N.qs_program_adjoint = timer.wrap(N.qs_program_adjoint)
         ms, wall = timed_loop(torch, stream, dev.step, args.steps, args.warmup, timer)
@@ -272,16 +283,21 @@ def main():
         flops_adj = FLOPS_ROT_ADJ * rot_amp
         adj_ms = timer.mean_ms()
         roof = {"bound": "alu", "achieved": flops_adj / (adj_ms * 1e-3) / 1e12,
-                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "traffic": None,
-                "kernel": "sv_program (adjoint)", "kernel_ms": adj_ms,
+                "peak": PEAK_FP64_TFLOPS if args.dtype == "c128" else PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "traffic": None,
+                "kernel": "sv_program (adjoint)" if dev.dtype == "c64" else
+                "qs_program_adjoint (sv_program; 14-qubit classes on the tiled path)",
+                "kernel_ms": adj_ms,
                 "launches_per_step": 1, "algorithmic_flops_per_launch": flops_adj}
         roof["frac"] = roof["achieved"] / roof["peak"]
-        cfg = {"workload": f"c5a: {WORKLOAD_TEXT[key]}", "circuits": ub.n_circuits,
+        cfg = {"workload": f"c5a: {workload_text(key, args.dtype)}", "circuits": ub.n_circuits,
                "classes": len(ub.classes), "updates_per_step": updates,
-               "path": "persistent"}
-        dtype = "fp32"
+               "path": "persistent", "complex": args.dtype or "c64"}
+        dtype = "fp64" if args.dtype == "c128" else "fp32"
     else:
         w = make_workload(key)
+        if args.dtype:
+            w = dataclasses.replace(w, dtype=args.dtype)
         tuned = None
         if not args.no_tune:
             # The library's autotuner times the register-split candidates of
@@ -325,8 +341,10 @@ def main():
         else:
             flops_adj = FLOPS_ROT_ADJ * rot * amps
             roof = {"bound": "alu", "achieved": flops_adj / (adj_ms * 1e-3) / 1e12,
-                    "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                    "traffic": measured_traffic(key), "kernel": "sv_adjoint",
+                    "peak": PEAK_FP32_TFLOPS if w.dtype == "c64" else PEAK_FP64_TFLOPS,
+                    "unit": "TFLOP/s",
+                    "traffic": measured_traffic(key) if w.dtype == "c64" else None,
+                    "kernel": "sv_adjoint",
                     "kernel_ms": adj_ms, "launches_per_step": n_adj,
                     "algorithmic_flops_per_launch": flops_adj}
         if roof is not None:
@@ -345,7 +363,8 @@ def main():
             pms = p0.elapsed_time(p1) / args.plain_steps
             plain = {"value": updates / (pms * 1e-3), "ms_per_step": pms}
             del dp
-        cfg = {"workload": f"{key}: {WORKLOAD_TEXT[key]}", "batch": w.batch,
+        cfg = {"workload": f"{key}: {workload_text(key, w.dtype)}", "complex": w.dtype,
+               "batch": w.batch,
                "qubits": w.n_qubits,
                "gates": w.circuit.n_gates + (w.decoder.n_gates if w.decoder else 0),
                "updates_per_step": updates, "path": path, "tuned": tuned}

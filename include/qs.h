@@ -205,9 +205,12 @@ int qs_fidelity_reset(int dtype, int n_qubits, int n_trash, int64_t B,
  *   grad_params   [sum_k counts[k] * P_k]     double (overwritten)
  * Workgroups pull work items (a run of circuits of one class) from an atomic
  * queue ordered longest first, so the uneven costs balance across the chip.
- * Restrictions: no features; 5 <= n_k <= 14 for QS_C64, 4 <= n_k <= 13 for
+ * A class whose 2^n_k amplitudes need more than one workgroup (QS_C128 at 14
+ * qubits) runs after the persistent launch through qs_forward /
+ * qs_adjoint_backward on its slices of the same buffers.
+ * Restrictions: no features; 5 <= n_k <= 14 for QS_C64, 4 <= n_k <= 14 for
  * QS_C128. Calls on the same program must not overlap in time (they share
- * the library-owned queue counter). */
+ * the library-owned queue counter and adjoint workspace). */
 typedef struct qs_program {
   int32_t n_classes;
   const qs_circuit* circuits; /* [n_classes] (host) */

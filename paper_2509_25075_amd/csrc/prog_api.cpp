@@ -2,7 +2,10 @@
 // circuits are planned once (cached), cut into work items of S circuits
 // (S = 512 threads / threads per circuit), ordered longest first (cost
 // = circuits x 2^n x gates), and run by one persistent launch that pulls
-// items from an atomic queue.
+// items from an atomic queue. A class whose circuit needs more than one
+// workgroup (2^n amplitudes over more than 512 threads: complex128 at 14
+// qubits) runs after it through the batched calls on its own slices of the
+// packed buffers, with per-circuit parameters.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,7 +24,7 @@ struct ProgEnginePlan {
 };
 ProgEnginePlan program_engine_plan(const qs_circuit& c, int r, int* rc);
 int64_t engine_lds_bytes(int dtype, const qs_circuit& c, int S, int n_slots, int block,
-                         bool ps, bool adjoint);
+                         bool ps, bool adjoint, bool half);
 }  // namespace qs
 
 using namespace qs;
@@ -36,12 +39,15 @@ struct ProgPlan {
   ProgItem* d_items = nullptr;
   int n_items = 0;
   int* d_counter = nullptr;
-  int grid = 0, r = 0;
+  int grid = 0, r = 0, half = 0;
   int64_t lds = 0;
   int64_t* d_cum = nullptr;
   int32_t* d_nq = nullptr;
   int64_t* d_state_off = nullptr;
   int64_t n_circuits = 0;
+  std::vector<int> overflow;  // classes run through the batched calls
+  void* d_ws = nullptr;       // their adjoint workspace
+  size_t ws_bytes = 0;
 };
 
 std::mutex g_pmu;
@@ -50,7 +56,7 @@ std::unordered_map<std::string, ProgPlan*> g_prog;
 int check_program(const qs_program* p, int dtype) {
   if (!p || p->n_classes < 1 || !p->circuits || !p->counts) return QS_ERR_INVALID;
   if (dtype != QS_C64 && dtype != QS_C128) return QS_ERR_INVALID;
-  const int nlo = dtype == QS_C64 ? 5 : 4, nhi = dtype == QS_C64 ? 14 : 13;
+  const int nlo = dtype == QS_C64 ? 5 : 4, nhi = kMaxQubitsFused;
   for (int k = 0; k < p->n_classes; ++k) {
     if (p->counts[k] < 0) return QS_ERR_INVALID;
     if (qs_validate(&p->circuits[k]) != QS_OK) return QS_ERR_INVALID;
@@ -115,9 +121,20 @@ ProgPlan* get_prog(const qs_program* p, int dtype, int* rc) {
   std::vector<int32_t> nq(p->n_classes);
   struct Cand { ProgItem it; double cost; };
   std::vector<Cand> items;
-  int64_t lds = 0;
+  int64_t lds = 0, lds_half = 0;
+  std::vector<int> overflow;
+  size_t ws_bytes = 0;
   for (int k = 0; k < p->n_classes; ++k) {
     const qs_circuit& c = p->circuits[k];
+    cum[k + 1] = cum[k] + p->counts[k];
+    nq[k] = c.n_qubits;
+    if ((kBlock >> (c.n_qubits - r)) < 1) {
+      overflow.push_back(k);
+      std::memset(&cls[k], 0, sizeof(ProgClass));
+      ws_bytes = std::max(ws_bytes, qs_workspace_size(&c, dtype, p->counts[k],
+                                                      QS_FLAG_PER_SAMPLE_PARAMS));
+      continue;
+    }
     ProgEnginePlan ep = program_engine_plan(c, r, rc);
     if (!ep.dev) return nullptr;
     ProgClass& d = cls[k];
@@ -150,14 +167,20 @@ ProgPlan* get_prog(const qs_program* p, int dtype, int* rc) {
     d.state_off = so[k];
     d.param_off = po[k];
     d.expz_off = eo[k];
-    lds = std::max(lds, engine_lds_bytes(dtype, c, d.S, 0, kBlock, true, true));
-    cum[k + 1] = cum[k] + p->counts[k];
-    nq[k] = c.n_qubits;
+    lds = std::max(lds, engine_lds_bytes(dtype, c, d.S, 0, kBlock, true, true, false));
+    lds_half = std::max(lds_half, engine_lds_bytes(dtype, c, d.S, 0, kBlock, true, true, true));
     for (int64_t f = 0; f < d.count; f += d.S) {
       const int64_t m = std::min<int64_t>(d.S, d.count - f);
       items.push_back({{k, (int32_t)f}, (double)m * (double)(1ll << d.n) *
                                             (double)(c.n_gates > 0 ? c.n_gates : 1)});
     }
+  }
+  // Whole-amplitude staging when the largest class fits it, else one state
+  // component at a time (half the staging LDS).
+  int half = 0;
+  if (lds > kMaxLds) {
+    half = 1;
+    lds = lds_half;
   }
   if (lds > kMaxLds) {
     *rc = QS_ERR_UNSUPPORTED;
@@ -170,8 +193,11 @@ ProgPlan* get_prog(const qs_program* p, int dtype, int* rc) {
   ProgPlan* pp = new ProgPlan();
   pp->n_items = (int)its.size();
   pp->r = r;
+  pp->half = half;
   pp->lds = lds;
   pp->n_circuits = cum.back();
+  pp->overflow = overflow;
+  pp->ws_bytes = ws_bytes;
   hipDeviceProp_t prop;
   int cus = 256;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) cus = prop.multiProcessorCount;
@@ -179,7 +205,8 @@ ProgPlan* get_prog(const qs_program* p, int dtype, int* rc) {
   pp->grid = std::max(1, std::min(pp->n_items, cus * per_cu));
   std::vector<int32_t> zero(1, 0);
   if (!up(&pp->d_classes, cls) || !up(&pp->d_items, its) || !up(&pp->d_counter, zero) ||
-      !up(&pp->d_cum, cum) || !up(&pp->d_nq, nq) || !up(&pp->d_state_off, so)) {
+      !up(&pp->d_cum, cum) || !up(&pp->d_nq, nq) || !up(&pp->d_state_off, so) ||
+      (ws_bytes && hipMalloc(&pp->d_ws, ws_bytes) != hipSuccess)) {
     *rc = QS_ERR_NOMEM;
     return nullptr;
   }
@@ -188,18 +215,45 @@ ProgPlan* get_prog(const qs_program* p, int dtype, int* rc) {
   return pp;
 }
 
+int run_persistent(ProgPlan* pp, int dtype, const void* params, void* states, double* expz,
+                   const double* dexpz, double* grad, bool adjoint, void* stream);
+
 int run(const qs_program* p, int dtype, const void* params, void* states,
         double* expz, const double* dexpz, double* grad, bool adjoint, void* stream) {
   int rc = QS_OK;
   ProgPlan* pp = get_prog(p, dtype, &rc);
   if (!pp) return rc;
-  if (pp->n_items == 0) return QS_OK;
-  if (adjoint) {
-    int64_t tot[3];
-    std::vector<int64_t> so, po, eo;
-    layout(p, so, po, eo, tot);
-    if (tot[1] && (rc = launch_fill_f64(grad, tot[1], stream)) != QS_OK) return rc;
+  int64_t tot[3];
+  std::vector<int64_t> so, po, eo;
+  layout(p, so, po, eo, tot);
+  if (adjoint && tot[1] && (rc = launch_fill_f64(grad, tot[1], stream)) != QS_OK) return rc;
+  if ((rc = run_persistent(pp, dtype, params, states, expz, dexpz, grad, adjoint, stream)) !=
+      QS_OK)
+    return rc;
+  // Classes beyond one workgroup, each through the batched path on its slices.
+  const size_t rs = dtype == QS_C64 ? sizeof(float) : sizeof(double);
+  for (int k : pp->overflow) {
+    const qs_circuit& c = p->circuits[k];
+    const int64_t B = p->counts[k];
+    if (B == 0) continue;
+    const void* pk = static_cast<const char*>(params) + rs * po[k];
+    void* sk = static_cast<char*>(states) + 2 * rs * so[k];
+    if (adjoint)
+      rc = qs_adjoint_backward(&c, dtype, B, pk, nullptr, sk, dexpz + eo[k], nullptr,
+                               grad + po[k], nullptr, nullptr, 0, nullptr, pp->d_ws,
+                               pp->ws_bytes, QS_FLAG_PER_SAMPLE_PARAMS, stream);
+    else
+      rc = qs_forward(&c, dtype, B, pk, nullptr, sk, expz ? expz + eo[k] : nullptr, nullptr,
+                      0, nullptr, QS_FLAG_PER_SAMPLE_PARAMS, stream);
+    if (rc != QS_OK) return rc;
   }
+  return QS_OK;
+}
+
+int run_persistent(ProgPlan* pp, int dtype, const void* params, void* states, double* expz,
+                   const double* dexpz, double* grad, bool adjoint, void* stream) {
+  int rc = QS_OK;
+  if (pp->n_items == 0) return QS_OK;
   if ((rc = launch_zero_i32(pp->d_counter, stream)) != QS_OK) return rc;
   ProgLaunch L{};
   L.classes = pp->d_classes;
@@ -209,6 +263,7 @@ int run(const qs_program* p, int dtype, const void* params, void* states,
   L.grid = pp->grid;
   L.block = kBlock;
   L.r = pp->r;
+  L.half = pp->half;
   L.lds_bytes = pp->lds;
   L.params = params;
   L.states = states;

@@ -586,8 +586,10 @@ int pick_path(const qs_circuit& c, int dtype, int flags, SvShape* shape,
   if (path == QS_PATH_AUTO) {
     if (choose_shape(dtype, c, n_slots, rf, adjoint, shape, ps, ck, n_ck, true, sc, hf > 0))
       path = QS_PATH_FUSED;
-    else
-      path = c.n_qubits > kMaxQubitsFused ? QS_PATH_HBM : QS_PATH_PLAIN;
+    else  // states too large for one workgroup: LDS tiles, else gate by gate
+      path = c.n_qubits > kMaxQubitsFused || tile_qubits(dtype, c.n_qubits) < c.n_qubits
+                 ? QS_PATH_HBM
+                 : QS_PATH_PLAIN;
   } else if (path == QS_PATH_FUSED) {
     if (!choose_shape(dtype, c, n_slots, rf, adjoint, shape, ps, ck, n_ck, true, sc, hf > 0))
       return QS_ERR_UNSUPPORTED;
@@ -643,8 +645,8 @@ ProgEnginePlan program_engine_plan(const qs_circuit& c, int r, int* rc) {
   return {e ? &e->dev : nullptr};
 }
 int64_t engine_lds_bytes(int dtype, const qs_circuit& c, int S, int n_slots, int block,
-                         bool ps, bool adjoint) {
-  return lds_bytes(dtype, c, S, n_slots, block, ps, adjoint);
+                         bool ps, bool adjoint, bool half) {
+  return lds_bytes(dtype, c, S, n_slots, block, ps, adjoint, nullptr, half);
 }
 }  // namespace qs
 

@@ -239,6 +239,7 @@ struct ProgLaunch {
   int n_items;
   int* counter;              // device work-queue counter
   int grid, block, r;
+  int half;                  // LDS staging one state component at a time
   int64_t lds_bytes;
   const void* params;
   void* states;

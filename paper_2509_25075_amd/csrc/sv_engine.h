@@ -1166,7 +1166,7 @@ __global__ void __launch_bounds__(MAXT) sv_adjoint(Args<real> A) {
 // from an atomic counter until the queue is empty; items are ordered longest
 // first. Every workgroup runs the same engine as the batched kernels, with
 // per-circuit angles computed in place (no per-sample LDS table).
-template <typename real, int LR, int MAXT, bool ADJ>
+template <typename real, int LR, int MAXT, bool ADJ, bool HALF>
 __global__ void __launch_bounds__(MAXT)
 sv_program(const ProgClass* classes, const ProgItem* items, int n_items,
            int* counter, const real* params, real* states, double* expz,
@@ -1229,9 +1229,9 @@ sv_program(const ProgClass* classes, const ProgItem* items, int n_items,
     A.grad_params = grad_params ? grad_params + cd.param_off + first * cd.n_params : nullptr;
     A.grad_feats = nullptr;
     if (ADJ)
-      adjoint_body<real, LR, true>(A, smem, 0);
+      adjoint_body<real, LR, true, false, HALF>(A, smem, 0);
     else
-      forward_body<real, LR, true>(A, smem, 0);
+      forward_body<real, LR, true, false, HALF>(A, smem, 0);
     __syncthreads();  // the next item reuses the LDS
   }
 }
@@ -1312,10 +1312,11 @@ int launch_one(const SvLaunch& L) {
   return hipGetLastError() == hipSuccess ? QS_OK : QS_ERR_LAUNCH;
 }
 
-template <typename real, int LR, int MAXT>
+template <typename real, int LR, int MAXT, bool HALF>
 int launch_prog(const ProgLaunch& L, bool adjoint) {
   hipStream_t st = static_cast<hipStream_t>(L.stream);
-  auto kern = adjoint ? sv_program<real, LR, MAXT, true> : sv_program<real, LR, MAXT, false>;
+  auto kern = adjoint ? sv_program<real, LR, MAXT, true, HALF>
+                      : sv_program<real, LR, MAXT, false, HALF>;
   if (L.lds_bytes > 65536 &&
       hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                           hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -242,6 +242,7 @@ class UnevenDevice:
     def __init__(self, ub, dtype: str = "c64", device="cuda"):
         require_gpu()
         self.ub = ub
+        self.dtype = dtype
         self.qs_dtype, self.cdtype, self.rdtype = _DT[dtype]
         self.ph = N.ProgramHandle([c for (_, _, c, _) in ub.classes],
                                   [len(idx) for (_, _, _, idx) in ub.classes])

@@ -5,6 +5,8 @@ match within 1e-5 absolute on expectations and states and 1e-4 absolute on
 gradients; complex128 runs within 1e-10. Inputs are the seeded workloads of
 ``workloads`` and seeded random circuits over every gate kind.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -152,6 +154,38 @@ def test_workload_step_vs_oracle(key, B):
     np.testing.assert_allclose(out["grad_params"].cpu().numpy(), gp, atol=tol["grad"])
     if feats is not None:
         np.testing.assert_allclose(out["grad_feats"].cpu().numpy(), gf, atol=tol["grad"])
+
+
+@pytest.mark.parametrize("key,B", [("c2", 9), ("c3", 11)])
+def test_workload_step_c128_vs_oracle(key, B):
+    """The complex64 workloads run in complex128 end to end (the same seeded
+    inputs), matching the oracle to the FP64 tolerance."""
+    w = dataclasses.replace(Dt.make_workload(key, B), dtype="c128")
+    _announce(f"workload {key} B={B} c128")
+    d = sim.to_device(w)
+    out = sim.step(d)
+    torch.cuda.synchronize()
+    idx, feats, psi0 = _oracle_workload(w)
+    z = O.expz(O.run_circuit(w.circuit, w.params, feats, psi0))
+    np.testing.assert_allclose(out["expz"].cpu().numpy(), z, atol=1e-10)
+    L, dz = O.loss_and_dexpz(w.loss, z, w.labels, w.weights)
+    gth, _ = O.adjoint_vjp(w.circuit, w.params, feats, psi0, dexpz=dz)
+    gp, gf = O.theta_to_param_grads(w.circuit, w.params, feats, gth)
+    np.testing.assert_allclose(out["grad_params"].cpu().numpy(), gp, atol=1e-10)
+    if feats is not None:
+        np.testing.assert_allclose(out["grad_feats"].cpu().numpy(), gf, atol=1e-10)
+
+
+def test_autoencoder_step_c128_vs_oracle():
+    w = dataclasses.replace(Dt.make_workload("c4", 3), dtype="c128")
+    _announce("workload c4 B=3 c128")
+    d = sim.to_device(w)
+    out = sim.step(d)
+    torch.cuda.synchronize()
+    F, gth, gph = _fidelity_oracle(w, None, w.batch)
+    np.testing.assert_allclose(out["fid"].cpu().numpy(), F, atol=1e-10)
+    np.testing.assert_allclose(out["grad_params"].cpu().numpy(), gth, atol=1e-10)
+    np.testing.assert_allclose(out["grad_params_dec"].cpu().numpy(), gph, atol=1e-10)
 
 
 def _fidelity_oracle(w, rows, B_total):
@@ -592,6 +626,40 @@ def test_uneven_batch_small_all_circuits():
             _, ps, es = ub.circuit_slices(k, j)
             np.testing.assert_allclose(z[es], zo, atol=1e-5)
             np.testing.assert_allclose(gp[ps], go, atol=1e-4)
+
+
+def test_uneven_batch_c128():
+    ub = Dt.uneven_batch(40, seed=5, n_lo=4, n_hi=9, d_lo=1, d_hi=3)
+    _announce(f"uneven batch c128: {ub.n_circuits} circuits, {len(ub.classes)} classes")
+    dev = sim.UnevenDevice(ub, dtype="c128")
+    out = dev.step()
+    torch.cuda.synchronize()
+    z = out["expz"].cpu().numpy()
+    gp = out["grad_params"].cpu().numpy()
+    for k, (n, d, c, idx) in enumerate(ub.classes):
+        for j in range(len(idx)):
+            zo, go = _oracle_program_circuit(ub, k, j)
+            _, ps, es = ub.circuit_slices(k, j)
+            np.testing.assert_allclose(z[es], zo, atol=1e-10)
+            np.testing.assert_allclose(gp[ps], go, atol=1e-10)
+
+
+def test_uneven_batch_c128_wide():
+    """Classes up to 14 qubits in complex128: the program stages one state
+    component at a time in LDS when whole amplitudes do not fit."""
+    ub = Dt.uneven_batch(24, seed=7, n_lo=12, n_hi=14, d_lo=2, d_hi=6)
+    _announce(f"uneven batch c128 wide: {ub.n_circuits} circuits, {len(ub.classes)} classes")
+    dev = sim.UnevenDevice(ub, dtype="c128")
+    out = dev.step()
+    torch.cuda.synchronize()
+    z = out["expz"].cpu().numpy()
+    gp = out["grad_params"].cpu().numpy()
+    for k, (n, d, c, idx) in enumerate(ub.classes):
+        for j in range(len(idx)):
+            zo, go = _oracle_program_circuit(ub, k, j)
+            _, ps, es = ub.circuit_slices(k, j)
+            np.testing.assert_allclose(z[es], zo, atol=1e-10)
+            np.testing.assert_allclose(gp[ps], go, atol=1e-10)
 
 
 def test_uneven_batch_full_size_sampled():
