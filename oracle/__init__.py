@@ -18,7 +18,9 @@ from the textbook definitions of the operations:
   *Quantum* 4, 226, 2020);
 * Pauli-Z expectation readout, and the fidelity of a quantum autoencoder whose
   trash qubits are reset to |0> (Romero, Olson & Aspuru-Guzik,
-  *Quantum Sci. Technol.* 2, 045001, 2017);
+  *Quantum Sci. Technol.* 2, 045001, 2017), or measured with only the
+  all-zero outcome kept (post-selection, renormalised; Nielsen & Chuang
+  §2.2.3, the projective-measurement postulate);
 * gradients three ways: the adjoint (reverse state propagation) method
   (Jones & Gacon, arXiv:2009.02823, §3), the parameter-shift rule
   (Mitarai et al., *Phys. Rev. A* 98, 032309, 2018; Schuld et al.,
@@ -32,6 +34,7 @@ from .statevector import (  # noqa: F401
     gate_matrix, apply_1q, apply_cnot, apply_cz, apply_gate, gate_angles,
     encode_amplitude, encode_zero, run_circuit, expz, fidelity_reset,
     fidelity_reset_direct, reset_channel_fidelity_cotangents,
+    fidelity_postselect, postselect_fidelity_cotangents, fidelity_postselect_direct,
 )
 from .gradients import (  # noqa: F401
     adjoint_vjp, param_shift_theta_jacobian, theta_to_param_grads,

@@ -189,6 +189,49 @@ def reset_channel_fidelity_cotangents(psi, chi, c, dF, n_trash: int):
     return lam * dF, mu.reshape(B, N) * dF
 
 
+def fidelity_postselect(psi: np.ndarray, chi: np.ndarray, n_trash: int):
+    """Autoencoder fidelity when the trash qubits are measured and only the
+    all-zero outcome is kept (post-selection), renormalised in FP64.
+
+    The projector Pi_0 = |0><0| on the trash qubits keeps psi_0, the slice of
+    psi whose trash bits are 0, with probability p = ||psi_0||^2; the kept
+    state is Pi_0 psi / sqrt(p). Its fidelity with |x> after the decoder is
+    F' = |<chi_0 | psi_0>|^2 / p  (chi = V|x>, chi_0 its trash-0 slice).
+    Rows with p = 0 (nothing survives the post-selection) give NaN.
+    Returns (F' [B], c [B] = <chi_0|psi_0>, p [B]).
+    """
+    B, N = psi.shape
+    k = (N.bit_length() - 1) - n_trash
+    psi0 = psi.reshape(B, 1 << n_trash, 1 << k)[:, 0, :]
+    chi0 = chi.reshape(B, 1 << n_trash, 1 << k)[:, 0, :]
+    c = np.sum(np.conj(chi0) * psi0, axis=1)
+    p = np.sum(np.abs(psi0) ** 2, axis=1)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        F = np.abs(c) ** 2 / p
+    return F, c, p
+
+
+def postselect_fidelity_cotangents(psi, chi, c, p, dF, n_trash: int):
+    """State cotangents of F' = |c|^2 / p (convention dL = 2 Re<lam|d psi>),
+    scaled by dF[b] = dL/dF'_b. With dc = <chi_0|d psi_0> and
+    dp = 2 Re<psi_0|d psi_0>, dF' = 2 Re(conj(c) dc) / p - |c|^2 dp / p^2, so
+        lam = (c / p) chi_0 - (F' / p) psi_0     on the trash-0 slice, 0 elsewhere;
+    and with dc = conj(<psi_0|d chi_0>),
+        mu = (conj(c) / p) psi_0                  on the trash-0 slice, 0 elsewhere.
+    """
+    B, N = psi.shape
+    k = (N.bit_length() - 1) - n_trash
+    psi0 = psi.reshape(B, 1 << n_trash, 1 << k)[:, 0, :]
+    chi0 = chi.reshape(B, 1 << n_trash, 1 << k)[:, 0, :]
+    F = np.abs(c) ** 2 / p
+    lam = np.zeros((B, 1 << n_trash, 1 << k), dtype=np.complex128)
+    mu = np.zeros_like(lam)
+    lam[:, 0, :] = (c / p)[:, None] * chi0 - (F / p)[:, None] * psi0
+    mu[:, 0, :] = (np.conj(c) / p)[:, None] * psi0
+    dF = np.asarray(dF, dtype=np.float64)[:, None]
+    return lam.reshape(B, N) * dF, mu.reshape(B, N) * dF
+
+
 def circuit_unitary(circuit, params, feats_row=None) -> np.ndarray:
     """Full 2^n x 2^n matrix of a circuit for one sample, column j = the
     circuit applied to basis state |j>."""
@@ -226,5 +269,31 @@ def fidelity_reset_direct(x_state, enc, params_enc, dec, params_dec,
                 K[j, (m << k) | j] = 1.0    # |0>_t|j> <m|_t<j|
             rho_r += K @ rho @ K.conj().T
         rho2 = D @ rho_r @ D.conj().T
+        out[b] = np.real(np.conj(x) @ rho2 @ x)
+    return out
+
+
+def fidelity_postselect_direct(x_state, enc, params_enc, dec, params_dec,
+                               n_trash: int) -> np.ndarray:
+    """The post-selected autoencoder fidelity from its definition, with
+    density matrices: rho = U|x><x|U^dagger, the trash qubits measured with
+    outcome 0: rho' = Pi_0 rho Pi_0 / tr(Pi_0 rho) with Pi_0 = |0><0|_t (x) I,
+    rho'' = D rho' D^dagger, F' = <x|rho''|x>. For small n only."""
+    B, N = x_state.shape
+    n = N.bit_length() - 1
+    k = n - n_trash
+    U = circuit_unitary(enc, params_enc)
+    D = circuit_unitary(dec, params_dec)
+    Pi = np.zeros((N, N), dtype=np.complex128)
+    for j in range(1 << k):
+        Pi[j, j] = 1.0          # trash bits (the top n_trash) all zero
+    out = np.empty(B)
+    for b in range(B):
+        x = x_state[b]
+        psi = U @ x
+        rho = np.outer(psi, np.conj(psi))
+        kept = Pi @ rho @ Pi
+        rho_p = kept / np.real(np.trace(kept))
+        rho2 = D @ rho_p @ D.conj().T
         out[b] = np.real(np.conj(x) @ rho2 @ x)
     return out

@@ -7,7 +7,11 @@
 * invariants: unitarity, norm preservation, U then U^dagger = identity, the
   CNOT ring as a permutation of basis states, fidelity in [0, 1] and = 1 for
   a mirrored autoencoder without trash qubits;
-* the autoencoder's two-pass fidelity against its density-matrix definition;
+* the autoencoder's two-pass fidelity against its density-matrix definition,
+  for the reset channel and for post-selection on the all-zero trash outcome
+  (plus a hand value, its reduction to the reset fidelity when only that
+  outcome is populated, scale invariance, Cauchy-Schwarz bounds, and its
+  state cotangents against finite differences entry by entry);
 * gradients: adjoint = parameter shift (exact) = central finite differences.
 """
 import json
@@ -273,6 +277,113 @@ def test_fidelity_mirrored_without_trash_is_one(rng):
     psi = O.run_circuit(enc, th, None, x)
     F, _ = O.fidelity_reset(psi, psi.copy(), 0)
     np.testing.assert_allclose(F, 1.0, atol=1e-13)
+
+
+# ------------------------------------------------ post-selected fidelity
+@pytest.mark.parametrize("n,t", [(3, 1), (4, 2), (5, 2), (4, 3)])
+def test_postselect_two_pass_equals_density_matrix_definition(n, t, rng):
+    enc = C.ry_rz_chain(n, 2)
+    B = 3
+    th = rng.uniform(-np.pi, np.pi, enc.n_params)
+    ph = rng.uniform(-np.pi, np.pi, enc.n_params)
+    x = O.encode_amplitude(rng.standard_normal((B, 1 << n)), n)
+    psi = O.run_circuit(enc, th, None, x)
+    chi = O.run_circuit(enc, ph, None, x)
+    F, c, p = O.fidelity_postselect(psi, chi, t)
+    Fd = O.fidelity_postselect_direct(x, enc, th, C.inverse_structure(enc), ph, t)
+    np.testing.assert_allclose(F, Fd, atol=1e-12)
+    # Cauchy-Schwarz: 0 <= F' <= ||chi_0||^2 <= 1
+    k = n - t
+    chi0 = chi.reshape(B, 1 << t, 1 << k)[:, 0, :]
+    assert np.all(F >= -1e-12)
+    assert np.all(F <= np.sum(np.abs(chi0) ** 2, axis=1) + 1e-12)
+    assert np.all((p > 0) & (p <= 1 + 1e-12))
+
+
+def test_postselect_hand_value():
+    """n = 2, one trash qubit (bit 1): psi = (1, i, 1, 0)/sqrt 3 keeps
+    (1, i)/sqrt 3 with probability 2/3; against chi = |00> the overlap is
+    1/sqrt 3, so F' = (1/3) / (2/3) = 1/2 (and the reset fidelity is
+    |<00|psi>|^2 + |<00|10-slice>|^2 = 1/3 + 1/3)."""
+    psi = np.array([[1, 1j, 1, 0]]) / np.sqrt(3)
+    chi = np.array([[1, 0, 0, 0]], dtype=np.complex128)
+    F, c, p = O.fidelity_postselect(psi, chi, 1)
+    np.testing.assert_allclose(F, [0.5], atol=1e-15)
+    np.testing.assert_allclose(p, [2 / 3], atol=1e-15)
+    np.testing.assert_allclose(c, [1 / np.sqrt(3)], atol=1e-15)
+    np.testing.assert_allclose(O.fidelity_reset(psi, chi, 1)[0], [2 / 3], atol=1e-15)
+
+
+def test_postselect_equals_reset_when_only_trash_zero_is_populated(rng):
+    n, t, B = 5, 2, 4
+    k = n - t
+    psi = np.zeros((B, 1 << n), dtype=np.complex128)
+    v = rng.standard_normal((B, 1 << k)) + 1j * rng.standard_normal((B, 1 << k))
+    psi[:, :1 << k] = v / np.linalg.norm(v, axis=1, keepdims=True)
+    chi = O.encode_amplitude(rng.standard_normal((B, 1 << n)), n)
+    F, _, p = O.fidelity_postselect(psi, chi, t)
+    np.testing.assert_allclose(p, 1.0, atol=1e-14)
+    np.testing.assert_allclose(F, O.fidelity_reset(psi, chi, t)[0], atol=1e-14)
+
+
+def test_postselect_renormalisation_scale_invariance_and_empty_outcome(rng):
+    n, t, B = 4, 2, 3
+    psi = O.encode_amplitude(rng.standard_normal((B, 1 << n)), n)
+    chi = O.encode_amplitude(rng.standard_normal((B, 1 << n)), n)
+    F, _, _ = O.fidelity_postselect(psi, chi, t)
+    F2, _, _ = O.fidelity_postselect(psi * (0.3 - 1.7j), chi, t)
+    np.testing.assert_allclose(F2, F, rtol=1e-13)
+    # nothing in the trash-0 slice: probability 0, fidelity undefined (NaN)
+    psi[0, :1 << (n - t)] = 0
+    F3, _, p3 = O.fidelity_postselect(psi, chi, t)
+    assert p3[0] == 0 and np.isnan(F3[0]) and np.all(np.isfinite(F3[1:]))
+
+
+def test_postselect_cotangents_match_finite_differences_of_the_states(rng):
+    """dF'/d Re psi_i = 2 Re lam_i and dF'/d Im psi_i = 2 Im lam_i (and the
+    same for chi with mu), by central differences on every entry."""
+    n, t, B = 3, 1, 2
+    psi = O.encode_amplitude(rng.standard_normal((B, 8)), n) * (0.8 + 0.3j)
+    chi = O.encode_amplitude(rng.standard_normal((B, 8)), n) * np.exp(0.4j)
+    F, c, p = O.fidelity_postselect(psi, chi, t)
+    lam, mu = O.postselect_fidelity_cotangents(psi, chi, c, p, np.ones(B), t)
+    h = 1e-6
+    for which, st, cot in (("psi", psi, lam), ("chi", chi, mu)):
+        for i in range(8):
+            for unit in (1.0, 1j):
+                e = np.zeros_like(st)
+                e[:, i] = unit * h
+                a = (st + e, chi) if which == "psi" else (psi, st + e)
+                b_ = (st - e, chi) if which == "psi" else (psi, st - e)
+                fd = (O.fidelity_postselect(*a, t)[0] - O.fidelity_postselect(*b_, t)[0]) / (2 * h)
+                want = 2 * (cot[:, i].real if unit == 1.0 else cot[:, i].imag)
+                np.testing.assert_allclose(fd, want, atol=1e-8)
+
+
+def test_postselect_parameter_gradients_adjoint_vs_fd(rng):
+    n, t, B = 4, 2, 2
+    enc = C.ry_rz_chain(n, 2)
+    th = rng.uniform(-np.pi, np.pi, enc.n_params)
+    ph = rng.uniform(-np.pi, np.pi, enc.n_params)
+    x = O.encode_amplitude(rng.standard_normal((B, 16)), n)
+
+    def L(th_, ph_):
+        psi = O.run_circuit(enc, th_, None, x)
+        chi = O.run_circuit(enc, ph_, None, x)
+        return 1.0 - float(np.mean(O.fidelity_postselect(psi, chi, t)[0]))
+
+    psi = O.run_circuit(enc, th, None, x)
+    chi = O.run_circuit(enc, ph, None, x)
+    F, c, p = O.fidelity_postselect(psi, chi, t)
+    lam, mu = O.postselect_fidelity_cotangents(psi, chi, c, p, -np.ones(B) / B, t)
+    g1, _ = O.adjoint_vjp(enc, th, None, x, lam_final=lam)
+    g2, _ = O.adjoint_vjp(enc, ph, None, x, lam_final=mu)
+    d_th, _ = O.theta_to_param_grads(enc, th, None, g1)
+    d_ph, _ = O.theta_to_param_grads(enc, ph, None, g2)
+    np.testing.assert_allclose(d_th, O.finite_difference(lambda v: L(v, ph), th.copy()),
+                               atol=1e-8)
+    np.testing.assert_allclose(d_ph, O.finite_difference(lambda v: L(th, v), ph.copy()),
+                               atol=1e-8)
 
 
 # ---------------------------------------------------------------- gradients
