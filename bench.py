@@ -51,8 +51,12 @@ WORKLOAD_TEXT = {
 }
 
 
-def workload_text(key, dtype):
+def workload_text(key, dtype, loss=None):
     t = WORKLOAD_TEXT[key]
+    if loss == "fidelity_postselect":
+        t = t.replace("4 trash qubits reset, loss 1 - fidelity",
+                      "4 trash qubits measured with only the all-zero outcome kept "
+                      "(renormalised in FP64), loss 1 - post-selected fidelity")
     return t.replace("complex64 forward", "complex128 forward") if dtype == "c128" else t
 
 
@@ -228,6 +232,9 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--dtype", choices=["c64", "c128"], default=None,
                     help="run the workload in this complex type (default: its own)")
+    ap.add_argument("--fidelity", choices=["reset", "postselect"], default="reset",
+                    help="c4: trash qubits reset (default), or measured with only "
+                         "the all-zero outcome kept and renormalised")
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--cpu-rows", type=int, default=256,
                     help="oracle rows per host process for cpu_baseline")
@@ -298,6 +305,8 @@ def main():
         w = make_workload(key)
         if args.dtype:
             w = dataclasses.replace(w, dtype=args.dtype)
+        if key == "c4" and args.fidelity == "postselect":
+            w = dataclasses.replace(w, loss="fidelity_postselect")
         tuned = None
         if not args.no_tune:
             # The library's autotuner times the register-split candidates of
@@ -331,9 +340,10 @@ def main():
             roof = None
         elif path == "tiled_hbm":
             # Each epoch's adjoint launch reads psi and lam and writes them
-            # back (4 x 8 B per amplitude); the timed call runs all epochs.
+            # back (4 complex amplitudes of 8 or 16 B); the timed call runs
+            # all epochs.
             n_ep = d.sim.plan_info(w.batch)["n_segments"]
-            bytes_call = n_ep * 4 * 8 * amps
+            bytes_call = n_ep * 4 * (8 if w.dtype == "c64" else 16) * amps
             roof = {"bound": "hbm", "achieved": bytes_call / (adj_ms * 1e-3) / 1e9,
                     "peak": PEAK_HBM_GBPS, "unit": "GB/s", "traffic": None,
                     "kernel": "sv_adjoint (tiled epochs)", "kernel_ms": adj_ms,
@@ -363,7 +373,7 @@ def main():
             pms = p0.elapsed_time(p1) / args.plain_steps
             plain = {"value": updates / (pms * 1e-3), "ms_per_step": pms}
             del dp
-        cfg = {"workload": f"{key}: {workload_text(key, w.dtype)}", "complex": w.dtype,
+        cfg = {"workload": f"{key}: {workload_text(key, w.dtype, w.loss)}", "complex": w.dtype,
                "batch": w.batch,
                "qubits": w.n_qubits,
                "gates": w.circuit.n_gates + (w.decoder.n_gates if w.decoder else 0),

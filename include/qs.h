@@ -193,6 +193,27 @@ int qs_fidelity_reset(int dtype, int n_qubits, int n_trash, int64_t B,
                       const double* dfid, void* lam_psi, void* lam_chi,
                       void* stream);
 
+/* Post-selected autoencoder fidelity: the top n_trash qubits are measured
+ * and only the all-zero outcome is kept, renormalised (the projective
+ * measurement postulate, Nielsen & Chuang sec. 2.2.3). With psi_0 and chi_0
+ * the trash-0 slices (the first 2^(n - n_trash) amplitudes), in FP64:
+ *   c = <chi_0|psi_0>,  p = ||psi_0||^2,  F'_b = |c|^2 / p;
+ * a row with p = 0 (the outcome cannot occur) gives NaN.
+ *   psi, chi (device) [B][2^n] complex, read only; 0 <= n_trash < n
+ *   fid      (device) [B] double output
+ *   dfid     (device, optional) [B] double dL/dF'_b; when given, the state
+ *            cotangents (dL = 2 Re<lam|d psi>)
+ *              lam_psi = dfid_b ((c/p) chi_0 - (F'/p) psi_0),
+ *              lam_chi = dfid_b (conj(c)/p) psi_0
+ *            on the trash-0 slice and zero elsewhere are written (both
+ *            [B][2^n] complex, device, caller-owned).
+ * B = 0 does nothing. Returns QS_ERR_INVALID for a bad dtype or size, or a
+ * missing pointer when B > 0. */
+int qs_fidelity_postselect(int dtype, int n_qubits, int n_trash, int64_t B,
+                           const void* psi, const void* chi, double* fid,
+                           const double* dfid, void* lam_psi, void* lam_chi,
+                           void* stream);
+
 /* ------------------------------------------------------- uneven batches */
 /* Many circuits of uneven qubit count and depth in one persistent launch.
  * Circuits are grouped into classes of identical structure (same gate list);

@@ -4,7 +4,9 @@
 // norm summed in FP64 (Schuld & Petruccione 2018, sec. 5.2); Pauli-Z readout
 // <Z_q> = sum_i |psi_i|^2 (1 - 2 bit_q(i)) summed in FP64; autoencoder
 // fidelity with reset trash qubits F = sum_m |<chi_0|psi_m>|^2 (Romero, Olson
-// & Aspuru-Guzik 2017) and its state cotangents.
+// & Aspuru-Guzik 2017), the post-selected variant F' = |<chi_0|psi_0>|^2 /
+// ||psi_0||^2 (trash qubits measured, only the all-zero outcome kept and
+// renormalised), and their state cotangents.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -185,6 +187,55 @@ fidelity_kernel(int n, int nt, const real* psi, const real* chi, double* fid,
   }
 }
 
+// Post-selected fidelity, one block per sample. In FP64: c = <chi_0|psi_0>
+// and p = ||psi_0||^2 over the trash-0 slice (the first K = 2^(n-nt)
+// amplitudes), F' = |c|^2 / p (NaN when p = 0). Cotangents (dL = 2 Re<lam|d psi>)
+// scaled by d = dL/dF': lam_psi = d ((c/p) chi_0 - (F'/p) psi_0) and
+// lam_chi = d (conj(c)/p) psi_0 on that slice, zero on the others.
+template <typename real>
+__global__ void __launch_bounds__(kBlock)
+fidelity_postselect_kernel(int n, int nt, const real* psi, const real* chi, double* fid,
+                           const double* dfid, real* lam_psi, real* lam_chi) {
+  __shared__ double sh[kBlock / 64];
+  const int64_t b = blockIdx.x;
+  const int64_t K = 1ll << (n - nt), N = 1ll << n;
+  const real* p = psi + 2 * b * N;
+  const real* c = chi + 2 * b * N;
+  double ar = 0, ai = 0, pp = 0;
+  for (int64_t j = threadIdx.x; j < K; j += blockDim.x) {
+    const double xr = c[2 * j], xi = c[2 * j + 1];
+    const double yr = p[2 * j], yi = p[2 * j + 1];
+    ar += xr * yr + xi * yi;  // conj(x) y
+    ai += xr * yi - xi * yr;
+    pp += yr * yr + yi * yi;
+  }
+  ar = block_sum(ar, sh);
+  ai = block_sum(ai, sh);
+  pp = block_sum(pp, sh);
+  const double F = (ar * ar + ai * ai) / pp;
+  if (threadIdx.x == 0) fid[b] = F;
+  if (dfid == nullptr) return;
+  const double d = dfid[b];
+  const double gr = d * ar / pp, gi = d * ai / pp, gf = d * F / pp;
+  real* lp = lam_psi + 2 * b * N;
+  real* lc = lam_chi + 2 * b * N;
+  for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
+    if (i < K) {
+      const double xr = c[2 * i], xi = c[2 * i + 1];
+      const double yr = p[2 * i], yi = p[2 * i + 1];
+      lp[2 * i] = (real)(gr * xr - gi * xi - gf * yr);
+      lp[2 * i + 1] = (real)(gr * xi + gi * xr - gf * yi);
+      lc[2 * i] = (real)(gr * yr + gi * yi);
+      lc[2 * i + 1] = (real)(gr * yi - gi * yr);
+    } else {
+      lp[2 * i] = 0;
+      lp[2 * i + 1] = 0;
+      lc[2 * i] = 0;
+      lc[2 * i + 1] = 0;
+    }
+  }
+}
+
 // out[col_param[c]] (+)= sum_r partials[r][c] in FP64: one block per column,
 // threads stride over rows with four independent sums each, then a block
 // reduction. The order of the additions is fixed, so the result is
@@ -334,6 +385,22 @@ int launch_fidelity(int dtype, int n, int n_trash, int64_t B, const void* psi,
     hipLaunchKernelGGL(fidelity_kernel<double>, dim3((unsigned)B), kBlock, 0,
                        st, n, n_trash, (const double*)psi, (const double*)chi,
                        fid, dfid, (double*)lam_psi, (double*)lam_chi);
+  return ok();
+}
+
+int launch_fidelity_postselect(int dtype, int n, int n_trash, int64_t B, const void* psi,
+                               const void* chi, double* fid, const double* dfid,
+                               void* lam_psi, void* lam_chi, void* stream) {
+  if (B == 0) return QS_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dtype == QS_C64)
+    hipLaunchKernelGGL(fidelity_postselect_kernel<float>, dim3((unsigned)B), kBlock, 0, st,
+                       n, n_trash, (const float*)psi, (const float*)chi, fid, dfid,
+                       (float*)lam_psi, (float*)lam_chi);
+  else
+    hipLaunchKernelGGL(fidelity_postselect_kernel<double>, dim3((unsigned)B), kBlock, 0, st,
+                       n, n_trash, (const double*)psi, (const double*)chi, fid, dfid,
+                       (double*)lam_psi, (double*)lam_chi);
   return ok();
 }
 

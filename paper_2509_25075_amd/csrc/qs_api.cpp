@@ -1178,6 +1178,18 @@ int qs_fidelity_reset(int dtype, int n, int n_trash, int64_t B, const void* psi,
                          lam_chi, stream);
 }
 
+int qs_fidelity_postselect(int dtype, int n, int n_trash, int64_t B, const void* psi,
+                           const void* chi, double* fid, const double* dfid,
+                           void* lam_psi, void* lam_chi, void* stream) {
+  if ((dtype != QS_C64 && dtype != QS_C128) || n < 1 || n > 30 || B < 0 ||
+      B > 0x7fffffff || n_trash < 0 || n_trash >= n)
+    return QS_ERR_INVALID;
+  if (B == 0) return QS_OK;
+  if (!psi || !chi || !fid || (dfid && (!lam_psi || !lam_chi))) return QS_ERR_INVALID;
+  return launch_fidelity_postselect(dtype, n, n_trash, B, psi, chi, fid, dfid, lam_psi,
+                                    lam_chi, stream);
+}
+
 int qs_plan_info_get(const qs_circuit* c, int dtype, int64_t B, int flags,
                      qs_plan_info* out) {
   int rc = validate(c);

@@ -190,7 +190,7 @@ def step(d: DeviceWorkload, backward: bool = True) -> dict:
     else:
         sim.zero_state(B, d.state.device, out=d.state)
     out = {}
-    if w.loss == "fidelity_reset":
+    if w.loss in ("fidelity_reset", "fidelity_postselect"):
         sim.encode_amplitude(d.x, out=d.state_dec)
         sim.forward(d.params, d.feats, d.state, want_expz=False)
         d.sim_dec.forward(d.params_dec, d.feats, d.state_dec, want_expz=False)
@@ -198,10 +198,11 @@ def step(d: DeviceWorkload, backward: bool = True) -> dict:
         dfid = torch.full((B,), -1.0 / B, dtype=torch.float64, device=d.state.device)
         lam_psi = torch.empty_like(d.state)
         lam_chi = torch.empty_like(d.state)
-        N.qs_fidelity_reset(sim.qs_dtype, sim.n, w.n_trash, d.state, d.state_dec,
-                            fid, dfid if backward else None,
-                            lam_psi if backward else None,
-                            lam_chi if backward else None)
+        fn = N.qs_fidelity_reset if w.loss == "fidelity_reset" else N.qs_fidelity_postselect
+        fn(sim.qs_dtype, sim.n, w.n_trash, d.state, d.state_dec,
+           fid, dfid if backward else None,
+           lam_psi if backward else None,
+           lam_chi if backward else None)
         out["fid"] = fid
         out["loss"] = 1.0 - fid.mean()
         if backward:

@@ -192,9 +192,13 @@ def _fidelity_oracle(w, rows, B_total):
     idx, _, x = _oracle_workload(w, rows)
     psi = O.run_circuit(w.circuit, w.params, None, x)
     chi = O.run_circuit(w.decoder, w.params_dec, None, x)
-    F, cm = O.fidelity_reset(psi, chi, w.n_trash)
     dF = -np.ones(len(idx)) / B_total
-    lam, mu = O.reset_channel_fidelity_cotangents(psi, chi, cm, dF, w.n_trash)
+    if w.loss == "fidelity_postselect":
+        F, c, p = O.fidelity_postselect(psi, chi, w.n_trash)
+        lam, mu = O.postselect_fidelity_cotangents(psi, chi, c, p, dF, w.n_trash)
+    else:
+        F, cm = O.fidelity_reset(psi, chi, w.n_trash)
+        lam, mu = O.reset_channel_fidelity_cotangents(psi, chi, cm, dF, w.n_trash)
     g1, _ = O.adjoint_vjp(w.circuit, w.params, None, x, lam_final=lam)
     g2, _ = O.adjoint_vjp(w.decoder, w.params_dec, None, x, lam_final=mu)
     return F, O.theta_to_param_grads(w.circuit, w.params, None, g1)[0], \
@@ -211,6 +215,91 @@ def test_autoencoder_step_vs_oracle():
     np.testing.assert_allclose(out["fid"].cpu().numpy(), F, atol=1e-5)
     np.testing.assert_allclose(out["grad_params"].cpu().numpy(), gth, atol=1e-4)
     np.testing.assert_allclose(out["grad_params_dec"].cpu().numpy(), gph, atol=1e-4)
+
+
+@pytest.mark.parametrize("dtype,B", [("c64", 5), ("c128", 3)])
+def test_autoencoder_postselect_step_vs_oracle(dtype, B):
+    w = dataclasses.replace(Dt.make_workload("c4", B), dtype=dtype,
+                            loss="fidelity_postselect")
+    _announce(f"workload c4 post-selected B={B} {dtype}")
+    d = sim.to_device(w)
+    out = sim.step(d)
+    torch.cuda.synchronize()
+    F, gth, gph = _fidelity_oracle(w, None, w.batch)
+    tol = TOL[dtype]
+    np.testing.assert_allclose(out["fid"].cpu().numpy(), F, atol=tol["z"])
+    np.testing.assert_allclose(float(out["loss"]), 1.0 - F.mean(), atol=tol["z"])
+    np.testing.assert_allclose(out["grad_params"].cpu().numpy(), gth, atol=tol["grad"])
+    np.testing.assert_allclose(out["grad_params_dec"].cpu().numpy(), gph, atol=tol["grad"])
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("n,t,B", [(1, 0, 3), (5, 0, 4), (6, 5, 7), (9, 3, 33), (12, 4, 10),
+                                   (15, 2, 2), (3, 1, 0)])
+def test_postselect_fidelity_kernel_vs_oracle(dtype, n, t, B):
+    """The kernel alone on seeded random (unnormalised) states: F', both
+    cotangents element by element, a row where the kept outcome has zero
+    probability (NaN there, the other rows untouched), and B = 0."""
+    _announce(f"post-selected fidelity kernel n={n} t={t} B={B} {dtype}")
+    rng = np.random.default_rng(1000 + 37 * n + t)
+    N_ = 1 << n
+    cd = torch.complex64 if dtype == "c64" else torch.complex128
+    qd = N.QS_C64 if dtype == "c64" else N.QS_C128
+    psi = (rng.standard_normal((B, N_)) + 1j * rng.standard_normal((B, N_))) * 0.7
+    chi = rng.standard_normal((B, N_)) + 1j * rng.standard_normal((B, N_))
+    if B > 1:
+        psi[1, :N_ >> t] = 0                       # post-selection impossible
+    P = torch.as_tensor(psi).to("cuda", cd).contiguous()
+    X = torch.as_tensor(chi).to("cuda", cd).contiguous()
+    psi_r, chi_r = P.cpu().numpy().astype(np.complex128), X.cpu().numpy().astype(np.complex128)
+    dF = rng.uniform(-1, 1, B)
+    fid = torch.full((B,), 7.0, dtype=torch.float64, device="cuda")
+    lp = torch.full_like(P, 3.0)
+    lc = torch.full_like(P, 3.0)
+    N.qs_fidelity_postselect(qd, n, t, P, X, fid, _dev(dF, torch.float64), lp, lc)
+    torch.cuda.synchronize()
+    if B == 0:
+        return
+    F, c, p = O.fidelity_postselect(psi_r, chi_r, t)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        lam, mu = O.postselect_fidelity_cotangents(psi_r, chi_r, c, p, dF, t)
+    ok = p > 0
+    f = fid.cpu().numpy()
+    assert np.all(np.isnan(f[~ok]))
+    # inputs are not normalised: compare relative to the size of each quantity
+    rt = 1e-5 if dtype == "c64" else 1e-12
+    np.testing.assert_allclose(f[ok], F[ok], rtol=rt, atol=rt)
+    scale = np.abs(lam[ok]).max() + np.abs(mu[ok]).max()
+    np.testing.assert_allclose(lp.cpu().numpy()[ok], lam[ok], atol=rt * scale, rtol=0)
+    np.testing.assert_allclose(lc.cpu().numpy()[ok], mu[ok], atol=rt * scale, rtol=0)
+
+
+def test_full_size_autoencoder_postselect_sampled_rows():
+    w = dataclasses.replace(Dt.make_workload("c4"), loss="fidelity_postselect")
+    _announce(f"full-size c4 post-selected B={w.batch}")
+    rows = np.array([0, 5, 700, 1023])
+    d = sim.to_device(w)
+    s, sd = d.sim, d.sim_dec
+    s.encode_amplitude(d.x, out=d.state)
+    sd.encode_amplitude(d.x, out=d.state_dec)
+    s.forward(d.params, None, d.state, want_expz=False)
+    sd.forward(d.params_dec, None, d.state_dec, want_expz=False)
+    B = w.batch
+    fid = torch.empty(B, dtype=torch.float64, device="cuda")
+    dfid = torch.zeros(B, dtype=torch.float64, device="cuda")
+    dfid[rows] = -1.0 / B
+    lp, lc = torch.empty_like(d.state), torch.empty_like(d.state)
+    N.qs_fidelity_postselect(s.qs_dtype, s.n, w.n_trash, d.state, d.state_dec, fid,
+                             dfid, lp, lc)
+    g1, _ = s.adjoint(d.params, None, d.state, dstate=lp, ws=d.ws)
+    g2, _ = sd.adjoint(d.params_dec, None, d.state_dec, dstate=lc, ws=d.ws_dec)
+    torch.cuda.synchronize()
+    F, gth, gph = _fidelity_oracle(w, rows, B)
+    np.testing.assert_allclose(fid.cpu().numpy()[rows], F, atol=1e-5)
+    f_all = fid.cpu().numpy()
+    assert np.all((f_all >= -1e-6) & (f_all <= 1 + 1e-6))
+    np.testing.assert_allclose(g1.cpu().numpy(), gth, atol=1e-4)
+    np.testing.assert_allclose(g2.cpu().numpy(), gph, atol=1e-4)
 
 
 # ------------------------------------------------- full sizes, sampled rows

@@ -65,7 +65,9 @@ class Workload:
     or "zero" (start from |0...0>; ``feats`` may carry angle-encoded data).
     ``loss`` names how the upstream gradient is formed: "none" (forward only),
     "mse_z0" (mean (<Z_0> - y)^2), "fidelity_reset" (1 - mean fidelity after
-    resetting the trash qubits), "weighted_z" (sum_b sum_q g_q <Z_q>_b).
+    resetting the trash qubits), "fidelity_postselect" (1 - mean fidelity when
+    the trash qubits are measured and only the all-zero outcome is kept,
+    renormalised), "weighted_z" (sum_b sum_q g_q <Z_q>_b).
     """
 
     name: str
