@@ -227,8 +227,11 @@ int qs_fidelity_postselect(int dtype, int n_qubits, int n_trash, int64_t B,
  * Workgroups pull work items (a run of circuits of one class) from an atomic
  * queue ordered longest first, so the uneven costs balance across the chip.
  * A class whose 2^n_k amplitudes need more than one workgroup (QS_C128 at 14
- * qubits) runs after the persistent launch through qs_forward /
- * qs_adjoint_backward on its slices of the same buffers.
+ * qubits) runs through qs_forward / qs_adjoint_backward on its slices of the
+ * same buffers, on up to three library-owned side streams that are forked
+ * from `stream` before the persistent launch and joined back into it (with
+ * events) before the call returns: all work of the call is ordered on
+ * `stream` as usual.
  * Restrictions: no features; 5 <= n_k <= 14 for QS_C64, 4 <= n_k <= 14 for
  * QS_C128. Calls on the same program must not overlap in time (they share
  * the library-owned queue counter and adjoint workspace). */

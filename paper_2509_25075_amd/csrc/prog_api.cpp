@@ -4,8 +4,11 @@
 // = circuits x 2^n x gates), and run by one persistent launch that pulls
 // items from an atomic queue. A class whose circuit needs more than one
 // workgroup (2^n amplitudes over more than 512 threads: complex128 at 14
-// qubits) runs after it through the batched calls on its own slices of the
-// packed buffers, with per-circuit parameters.
+// qubits) runs through the batched calls on its own slices of the packed
+// buffers, with per-circuit parameters; such classes go to a few
+// library-owned side streams, forked from and joined back into the caller's
+// stream with events, so that they overlap each other and the persistent
+// launch (one class alone fills only part of the chip).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -46,9 +49,15 @@ struct ProgPlan {
   int64_t* d_state_off = nullptr;
   int64_t n_circuits = 0;
   std::vector<int> overflow;  // classes run through the batched calls
-  void* d_ws = nullptr;       // their adjoint workspace
-  size_t ws_bytes = 0;
+  std::vector<int> lane;      // side stream of each overflow class
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> side_done;
+  hipEvent_t fork = nullptr;
+  void* d_ws = nullptr;       // adjoint workspace, one slice per side stream
+  size_t ws_bytes = 0;        // bytes per slice
 };
+
+constexpr int kSideStreams = 3;
 
 std::mutex g_pmu;
 std::unordered_map<std::string, ProgPlan*> g_prog;
@@ -197,7 +206,36 @@ ProgPlan* get_prog(const qs_program* p, int dtype, int* rc) {
   pp->lds = lds;
   pp->n_circuits = cum.back();
   pp->overflow = overflow;
-  pp->ws_bytes = ws_bytes;
+  pp->ws_bytes = (ws_bytes + 255) & ~(size_t)255;
+  // Overflow classes, longest first, each to the least-loaded side stream.
+  const int n_side = std::min<int>(kSideStreams, (int)overflow.size());
+  if (n_side > 0) {
+    std::vector<double> load(n_side, 0.0);
+    std::vector<int> order(overflow.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    auto cost = [&](int i) {
+      const qs_circuit& c = p->circuits[overflow[i]];
+      return (double)p->counts[overflow[i]] * (double)(1ll << c.n_qubits) * (c.n_gates + 1);
+    };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return cost(a) > cost(b); });
+    pp->lane.assign(overflow.size(), 0);
+    for (int i : order) {
+      const int s = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      pp->lane[i] = s;
+      load[s] += cost(i);
+    }
+    pp->side.assign(n_side, nullptr);
+    pp->side_done.assign(n_side, nullptr);
+    bool okk = hipEventCreateWithFlags(&pp->fork, hipEventDisableTiming) == hipSuccess;
+    for (int s = 0; s < n_side && okk; ++s)
+      okk = hipStreamCreateWithFlags(&pp->side[s], hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&pp->side_done[s], hipEventDisableTiming) == hipSuccess;
+    if (!okk) {
+      *rc = QS_ERR_LAUNCH;
+      return nullptr;
+    }
+  }
   hipDeviceProp_t prop;
   int cus = 256;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) cus = prop.multiProcessorCount;
@@ -206,7 +244,7 @@ ProgPlan* get_prog(const qs_program* p, int dtype, int* rc) {
   std::vector<int32_t> zero(1, 0);
   if (!up(&pp->d_classes, cls) || !up(&pp->d_items, its) || !up(&pp->d_counter, zero) ||
       !up(&pp->d_cum, cum) || !up(&pp->d_nq, nq) || !up(&pp->d_state_off, so) ||
-      (ws_bytes && hipMalloc(&pp->d_ws, ws_bytes) != hipSuccess)) {
+      (pp->ws_bytes && hipMalloc(&pp->d_ws, pp->ws_bytes * pp->side.size()) != hipSuccess)) {
     *rc = QS_ERR_NOMEM;
     return nullptr;
   }
@@ -227,27 +265,42 @@ int run(const qs_program* p, int dtype, const void* params, void* states,
   std::vector<int64_t> so, po, eo;
   layout(p, so, po, eo, tot);
   if (adjoint && tot[1] && (rc = launch_fill_f64(grad, tot[1], stream)) != QS_OK) return rc;
-  if ((rc = run_persistent(pp, dtype, params, states, expz, dexpz, grad, adjoint, stream)) !=
-      QS_OK)
-    return rc;
-  // Classes beyond one workgroup, each through the batched path on its slices.
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool forked = !pp->side.empty();
+  if (forked) {
+    if (hipEventRecord(pp->fork, st) != hipSuccess) return QS_ERR_LAUNCH;
+    for (hipStream_t s : pp->side)
+      if (hipStreamWaitEvent(s, pp->fork, 0) != hipSuccess) return QS_ERR_LAUNCH;
+  }
+  rc = run_persistent(pp, dtype, params, states, expz, dexpz, grad, adjoint, stream);
+  // Classes beyond one workgroup, each through the batched path on its slices,
+  // on the side streams.
   const size_t rs = dtype == QS_C64 ? sizeof(float) : sizeof(double);
-  for (int k : pp->overflow) {
+  for (size_t i = 0; i < pp->overflow.size() && rc == QS_OK; ++i) {
+    const int k = pp->overflow[i];
     const qs_circuit& c = p->circuits[k];
     const int64_t B = p->counts[k];
     if (B == 0) continue;
+    hipStream_t s = pp->side[pp->lane[i]];
+    void* ws = static_cast<char*>(pp->d_ws) + pp->ws_bytes * pp->lane[i];
     const void* pk = static_cast<const char*>(params) + rs * po[k];
     void* sk = static_cast<char*>(states) + 2 * rs * so[k];
     if (adjoint)
       rc = qs_adjoint_backward(&c, dtype, B, pk, nullptr, sk, dexpz + eo[k], nullptr,
-                               grad + po[k], nullptr, nullptr, 0, nullptr, pp->d_ws,
-                               pp->ws_bytes, QS_FLAG_PER_SAMPLE_PARAMS, stream);
+                               grad + po[k], nullptr, nullptr, 0, nullptr, ws,
+                               pp->ws_bytes, QS_FLAG_PER_SAMPLE_PARAMS, s);
     else
       rc = qs_forward(&c, dtype, B, pk, nullptr, sk, expz ? expz + eo[k] : nullptr, nullptr,
-                      0, nullptr, QS_FLAG_PER_SAMPLE_PARAMS, stream);
-    if (rc != QS_OK) return rc;
+                      0, nullptr, QS_FLAG_PER_SAMPLE_PARAMS, s);
   }
-  return QS_OK;
+  // Join every side stream back into the caller's, also after an error.
+  if (forked) {
+    for (size_t s = 0; s < pp->side.size(); ++s)
+      if (hipEventRecord(pp->side_done[s], pp->side[s]) != hipSuccess ||
+          hipStreamWaitEvent(st, pp->side_done[s], 0) != hipSuccess)
+        return QS_ERR_LAUNCH;
+  }
+  return rc;
 }
 
 int run_persistent(ProgPlan* pp, int dtype, const void* params, void* states, double* expz,

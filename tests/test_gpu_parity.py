@@ -802,6 +802,27 @@ def test_graph_replay_matches_eager():
         torch.cuda.synchronize()
 
 
+def test_graph_replay_uneven_with_side_streams():
+    """Complex128 classes of 14 qubits run on the program's side streams; a
+    captured step (fork and join inside the graph) replays to the eager
+    result, with eager work between the replays."""
+    ub = Dt.uneven_batch(16, seed=9, n_lo=13, n_hi=14, d_lo=1, d_hi=3)
+    assert any(n == 14 for n, _, _, _ in ub.classes)
+    _announce(f"graph replay, uneven c128 with side streams: {len(ub.classes)} classes")
+    dev = sim.UnevenDevice(ub, dtype="c128")
+    e = dev.step()
+    torch.cuda.synchronize()
+    rz, rg = e["expz"].clone(), e["grad_params"].clone()
+    gu = sim.GraphStep(lambda: dev.step())
+    for rep in range(3):
+        out = gu.replay()
+        torch.cuda.synchronize()
+        assert torch.allclose(out["expz"], rz, rtol=0, atol=1e-12), rep
+        assert torch.allclose(out["grad_params"], rg, rtol=0, atol=1e-12), rep
+        dev.step()
+        torch.cuda.synchronize()
+
+
 # ------------------------------------------------------------- autotuner
 def test_autotune_picks_a_config_and_results_stay_exact(tmp_path, monkeypatch):
     cache = tmp_path / "tune.txt"
