@@ -62,6 +62,22 @@ constexpr int kSideStreams = 3;
 std::mutex g_pmu;
 std::unordered_map<std::string, ProgPlan*> g_prog;
 
+void destroy_plan(ProgPlan* pp) {
+  for (hipStream_t s : pp->side)
+    if (s) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : pp->side_done)
+    if (e) (void)hipEventDestroy(e);
+  if (pp->fork) (void)hipEventDestroy(pp->fork);
+  (void)hipFree(pp->d_classes);
+  (void)hipFree(pp->d_items);
+  (void)hipFree(pp->d_counter);
+  (void)hipFree(pp->d_cum);
+  (void)hipFree(pp->d_nq);
+  (void)hipFree(pp->d_state_off);
+  (void)hipFree(pp->d_ws);
+  delete pp;
+}
+
 int check_program(const qs_program* p, int dtype) {
   if (!p || p->n_classes < 1 || !p->circuits || !p->counts) return QS_ERR_INVALID;
   if (dtype != QS_C64 && dtype != QS_C128) return QS_ERR_INVALID;
@@ -232,6 +248,7 @@ ProgPlan* get_prog(const qs_program* p, int dtype, int* rc) {
       okk = hipStreamCreateWithFlags(&pp->side[s], hipStreamNonBlocking) == hipSuccess &&
             hipEventCreateWithFlags(&pp->side_done[s], hipEventDisableTiming) == hipSuccess;
     if (!okk) {
+      destroy_plan(pp);
       *rc = QS_ERR_LAUNCH;
       return nullptr;
     }
@@ -245,11 +262,16 @@ ProgPlan* get_prog(const qs_program* p, int dtype, int* rc) {
   if (!up(&pp->d_classes, cls) || !up(&pp->d_items, its) || !up(&pp->d_counter, zero) ||
       !up(&pp->d_cum, cum) || !up(&pp->d_nq, nq) || !up(&pp->d_state_off, so) ||
       (pp->ws_bytes && hipMalloc(&pp->d_ws, pp->ws_bytes * pp->side.size()) != hipSuccess)) {
+    destroy_plan(pp);
     *rc = QS_ERR_NOMEM;
     return nullptr;
   }
   std::lock_guard<std::mutex> lock(g_pmu);
-  g_prog.emplace(key, pp);
+  auto ins = g_prog.emplace(key, pp);
+  if (!ins.second) {  // planned meanwhile by another thread: keep that one
+    destroy_plan(pp);
+    return ins.first->second;
+  }
   return pp;
 }
 
@@ -328,6 +350,17 @@ int run_persistent(ProgPlan* pp, int dtype, const void* params, void* states, do
 }
 
 }  // namespace
+
+namespace qs {
+// Releases every program plan (device tables, queue counter, side streams,
+// events, workspace). Program plans point into the engine plan cache, so
+// they go first when the library releases its caches.
+void free_programs() {
+  std::lock_guard<std::mutex> lock(g_pmu);
+  for (auto& kv : g_prog) destroy_plan(kv.second);
+  g_prog.clear();
+}
+}  // namespace qs
 
 extern "C" {
 

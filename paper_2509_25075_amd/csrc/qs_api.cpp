@@ -483,6 +483,14 @@ TiledEntry* get_tiled(const qs_circuit& c, int dtype, bool ps, const int32_t* ck
   const int low_keep = m >= 6 ? 4 : (m >= 4 ? m - 2 : 0);
   std::vector<TiledEpoch> eps = plan_tiled(c, m, low_keep, ck, n_ck);
   TiledEntry* te = new TiledEntry();
+  auto drop = [&te]() -> TiledEntry* {  // a failed plan: release what was uploaded
+    for (auto& d : te->epochs) {
+      (void)hipFree(d.tile_q);
+      (void)hipFree(d.outer_q);
+    }
+    delete te;
+    return nullptr;
+  };
   te->m = m;
   te->epochs.resize(eps.size());
   for (size_t i = 0; i < eps.size(); ++i) {
@@ -500,11 +508,11 @@ TiledEntry* get_tiled(const qs_circuit& c, int dtype, bool ps, const int32_t* ck
     if (!choose_shape(dtype, sub, slots, tc.fwd_r, false, &d.fshape, ps) ||
         !choose_shape(dtype, sub, slots, tc.adj_r, true, &d.ashape, ps)) {
       *rc = QS_ERR_UNSUPPORTED;
-      return nullptr;
+      return drop();
     }
     d.fwd = get_plan(sub, d.fshape.r, ps, nullptr, 0, rc);
     d.adj = get_plan(sub, d.ashape.r, ps, nullptr, 0, rc);
-    if (!d.fwd || !d.adj) return nullptr;
+    if (!d.fwd || !d.adj) return drop();
     std::vector<uint8_t> tq(eps[i].L.begin(), eps[i].L.end()), oq;
     std::vector<char> in(c.n_qubits, 0);
     for (int q : eps[i].L) in[q] = 1;
@@ -512,11 +520,19 @@ TiledEntry* get_tiled(const qs_circuit& c, int dtype, bool ps, const int32_t* ck
       if (!in[q]) oq.push_back((uint8_t)q);
     if (!upload(&d.tile_q, tq.data(), tq.size()) || !upload(&d.outer_q, oq.data(), oq.size())) {
       *rc = QS_ERR_NOMEM;
-      return nullptr;
+      return drop();
     }
   }
   std::lock_guard<std::mutex> lock(g_mu);
-  g_tiled.emplace(std::move(key), te);
+  auto ins = g_tiled.emplace(std::move(key), te);
+  if (!ins.second) {  // planned meanwhile by another thread: keep that one
+    for (auto& d : te->epochs) {
+      (void)hipFree(d.tile_q);
+      (void)hipFree(d.outer_q);
+    }
+    delete te;
+    return ins.first->second;
+  }
   return te;
 }
 
@@ -636,6 +652,7 @@ bool tuned_for_call(const qs_circuit& c, int dtype, int64_t B, int flags, void* 
 }  // namespace
 
 namespace qs {
+void free_programs();  // prog_api.cpp
 struct ProgEnginePlan {
   SvDevPlan* dev;
 };
@@ -1295,6 +1312,7 @@ int qs_plan_dump(const qs_circuit* c, int dtype, int64_t B, int flags, int adjoi
 }
 
 void qs_shutdown(void) {
+  qs::free_programs();  // they reference the engine plans released below
   std::lock_guard<std::mutex> lock(g_mu);
   for (auto& kv : g_cache) {
     free_dev(kv.second->dev);

@@ -823,6 +823,28 @@ def test_graph_replay_uneven_with_side_streams():
         torch.cuda.synchronize()
 
 
+def test_shutdown_then_replan_gives_the_same_results():
+    """qs_shutdown releases every cached plan, program plans (which point into
+    the engine plans) included; the next calls plan again and agree with the
+    first (batched, uneven, and uneven with side streams)."""
+    torch.cuda.synchronize()
+    w = Dt.make_workload("c2", 32)
+    d = sim.to_device(w)
+    a = sim.step(d)
+    ub = Dt.uneven_batch(12, seed=4, n_lo=12, n_hi=14, d_lo=1, d_hi=2)
+    dev = sim.UnevenDevice(ub, dtype="c128")
+    u = dev.step()
+    torch.cuda.synchronize()
+    ref = [a["expz"].clone(), a["grad_params"].clone(), u["expz"].clone(),
+           u["grad_params"].clone()]
+    N.qs_shutdown()
+    a = sim.step(d)
+    u = dev.step()
+    torch.cuda.synchronize()
+    for x, y in zip(ref, [a["expz"], a["grad_params"], u["expz"], u["grad_params"]]):
+        assert torch.allclose(x, y, rtol=0, atol=1e-12)
+
+
 # ------------------------------------------------------------- autotuner
 def test_autotune_picks_a_config_and_results_stay_exact(tmp_path, monkeypatch):
     cache = tmp_path / "tune.txt"
