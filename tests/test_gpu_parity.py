@@ -585,6 +585,14 @@ def test_large_state_auto_path(n):
     _run_expz_case(c, "c64", "auto", 2, seed=n)
 
 
+def test_c128_14_qubits_auto_path():
+    rng = np.random.default_rng(714)
+    c = C.random_circuit(14, 70, rng, n_params=6, n_features=2)
+    assert N.qs_plan_info_get(N.CircuitHandle(c), N.QS_C128, 3)["path"] == N.QS_PATH_HBM
+    _run_expz_case(c, "c128", "auto", 3, seed=14)
+    _run_expz_case(c, "c128", "auto", 2, seed=15, per_sample=True)
+
+
 def test_tiled_checkpoints(tile_qubits):
     tile_qubits(6)
     w = Dt.make_workload("c2", 3)

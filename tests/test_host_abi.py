@@ -186,6 +186,12 @@ def test_large_circuits_take_the_tiled_path():
     assert 40 <= info["n_segments"] <= 80
     plain = N.qs_plan_info_get(N.CircuitHandle(c), N.QS_C64, 1, N.QS_PATH_PLAIN)
     assert plain["path"] == N.QS_PATH_PLAIN
+    # complex128 at 14 qubits does not fit one workgroup's registers and LDS:
+    # the automatic path gathers 12-qubit tiles rather than going gate by gate
+    h14 = N.CircuitHandle(C.hea_ry_rz_ring(14, 2))
+    assert N.qs_plan_info_get(h14, N.QS_C64, 4)["path"] == N.QS_PATH_FUSED
+    info = N.qs_plan_info_get(h14, N.QS_C128, 4)
+    assert info["path"] == N.QS_PATH_HBM and info["log2_threads"] == 12
 
 
 def test_explicit_fused_path_refuses_states_that_do_not_fit():
