@@ -22,8 +22,9 @@
  * memory that must stay valid until the stream reaches the call; (host)
  * pointers are read before the call returns. Input buffers must not alias
  * output buffers, except `state`, which is in/out by design. The library owns
- * only its plan cache (device copies of planned gate programs), released by
- * qs_shutdown().
+ * only its plan caches (device copies of planned gate programs; for uneven
+ * batches also a queue counter, an adjoint workspace and up to three side
+ * streams with their events), released by qs_shutdown().
  *
  * Errors. Every call returns a qs_status; nothing throws across the ABI.
  * Launch-side calls are asynchronous on the given stream (a hipStream_t
@@ -45,7 +46,7 @@ extern "C" {
 typedef enum qs_status {
   QS_OK = 0,
   QS_ERR_INVALID = -1,     /* bad descriptor, shape, pointer or flag        */
-  QS_ERR_UNSUPPORTED = -2, /* valid request this build does not implement   */
+  QS_ERR_UNSUPPORTED = -2, /* valid request the library does not implement */
   QS_ERR_WORKSPACE = -3,   /* workspace missing or smaller than required    */
   QS_ERR_ZERO_NORM = -4,   /* amplitude input row with norm 0               */
   QS_ERR_LAUNCH = -5,      /* a HIP runtime call or kernel launch failed    */
@@ -357,7 +358,9 @@ typedef struct qs_tune_info {
 int qs_autotune(const qs_circuit* circuit, int dtype, int64_t B, int flags,
                 void* stream, qs_tune_info* out);
 
-/* Release the plan cache (device memory). Safe to call more than once. */
+/* Release the plan caches (device memory, and the side streams and events of
+ * uneven-batch programs). No call may be in flight on any stream. Safe to
+ * call more than once; later calls plan again. */
 void qs_shutdown(void);
 
 #ifdef __cplusplus

@@ -20,7 +20,10 @@ from the textbook definitions of the operations:
   trash qubits are reset to |0> (Romero, Olson & Aspuru-Guzik,
   *Quantum Sci. Technol.* 2, 045001, 2017), or measured with only the
   all-zero outcome kept (post-selection, renormalised; Nielsen & Chuang
-  §2.2.3, the projective-measurement postulate);
+  §2.2.3, the projective-measurement postulate), or one quantum trajectory of
+  the reset channel (the trash qubits measured with an outcome drawn from the
+  Born probabilities, then reset; Dalibard, Castin & Molmer, *Phys. Rev.
+  Lett.* 68, 580, 1992, for the unravelling of a channel into trajectories);
 * gradients three ways: the adjoint (reverse state propagation) method
   (Jones & Gacon, arXiv:2009.02823, §3), the parameter-shift rule
   (Mitarai et al., *Phys. Rev. A* 98, 032309, 2018; Schuld et al.,
@@ -35,6 +38,8 @@ from .statevector import (  # noqa: F401
     encode_amplitude, encode_zero, run_circuit, expz, fidelity_reset,
     fidelity_reset_direct, reset_channel_fidelity_cotangents,
     fidelity_postselect, postselect_fidelity_cotangents, fidelity_postselect_direct,
+    trajectory_outcome, fidelity_trajectory, trajectory_fidelity_cotangents,
+    fidelity_trajectory_direct,
 )
 from .gradients import (  # noqa: F401
     adjoint_vjp, param_shift_theta_jacobian, theta_to_param_grads,

@@ -232,6 +232,74 @@ def postselect_fidelity_cotangents(psi, chi, c, p, dF, n_trash: int):
     return lam.reshape(B, N) * dF, mu.reshape(B, N) * dF
 
 
+def trajectory_outcome(p_m: np.ndarray, u: np.ndarray) -> np.ndarray:
+    """Outcome of one measurement of the trash qubits, drawn by inverse CDF
+    from a uniform u in [0, 1): the smallest m with u * sum_j p_j < sum_{j<=m}
+    p_j, the sums running over m = 0, 1, ... in FP64 (m = the last outcome
+    with p_m > 0 if rounding leaves none)."""
+    B, M = p_m.shape
+    out = np.empty(B, dtype=np.int64)
+    for b in range(B):
+        tot = float(np.sum(p_m[b]))
+        acc = 0.0
+        pick = -1
+        for m in range(M):
+            acc += float(p_m[b, m])
+            if u[b] * tot < acc:
+                pick = m
+                break
+        if pick < 0:
+            nz = np.nonzero(p_m[b] > 0)[0]
+            pick = int(nz[-1]) if len(nz) else 0
+        out[b] = pick
+    return out
+
+
+def fidelity_trajectory(psi: np.ndarray, chi: np.ndarray, n_trash: int, u: np.ndarray):
+    """One quantum trajectory of the reset channel: the trash qubits are
+    measured (outcome m with probability p_m = ||psi_m||^2 / ||psi||^2, drawn
+    from u by ``trajectory_outcome``) and then reset, so the kept state is
+    |0>_t (x) psi_m / sqrt(p_m') with p_m' = ||psi_m||^2, and its fidelity is
+        F_traj = |<chi_0 | psi_m>|^2 / ||psi_m||^2.
+    Averaged over outcomes (weights p_m) it is the reset-channel fidelity
+    sum_m |c_m|^2 (for a normalised psi). Returns (F [B], m [B], c [B], p [B])
+    with c = <chi_0|psi_m> and p = ||psi_m||^2 of the drawn outcome.
+    """
+    B, N = psi.shape
+    k = (N.bit_length() - 1) - n_trash
+    pr = psi.reshape(B, 1 << n_trash, 1 << k)
+    chi0 = chi.reshape(B, 1 << n_trash, 1 << k)[:, 0, :]
+    p_all = np.sum(np.abs(pr) ** 2, axis=2)
+    m = trajectory_outcome(p_all, np.asarray(u, dtype=np.float64))
+    psim = pr[np.arange(B), m, :]
+    c = np.sum(np.conj(chi0) * psim, axis=1)
+    p = p_all[np.arange(B), m]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        F = np.abs(c) ** 2 / p
+    return F, m, c, p
+
+
+def trajectory_fidelity_cotangents(psi, chi, m, c, p, dF, n_trash: int):
+    """State cotangents of F_traj for the drawn (fixed) outcome m, convention
+    dL = 2 Re<lam|d psi>, scaled by dF[b]: the post-selection formulas on
+    slice m,
+        lam = (c/p) |m>|chi_0> - (F/p) |m>|psi_m>   (zero on the other slices),
+        mu  = (conj(c)/p) |0>|psi_m>                (zero on the other slices).
+    """
+    B, N = psi.shape
+    k = (N.bit_length() - 1) - n_trash
+    pr = psi.reshape(B, 1 << n_trash, 1 << k)
+    chi0 = chi.reshape(B, 1 << n_trash, 1 << k)[:, 0, :]
+    psim = pr[np.arange(B), m, :]
+    F = np.abs(c) ** 2 / p
+    lam = np.zeros((B, 1 << n_trash, 1 << k), dtype=np.complex128)
+    mu = np.zeros_like(lam)
+    lam[np.arange(B), m, :] = (c / p)[:, None] * chi0 - (F / p)[:, None] * psim
+    mu[:, 0, :] = (np.conj(c) / p)[:, None] * psim
+    dF = np.asarray(dF, dtype=np.float64)[:, None]
+    return lam.reshape(B, N) * dF, mu.reshape(B, N) * dF
+
+
 def circuit_unitary(circuit, params, feats_row=None) -> np.ndarray:
     """Full 2^n x 2^n matrix of a circuit for one sample, column j = the
     circuit applied to basis state |j>."""
@@ -293,6 +361,33 @@ def fidelity_postselect_direct(x_state, enc, params_enc, dec, params_dec,
         psi = U @ x
         rho = np.outer(psi, np.conj(psi))
         kept = Pi @ rho @ Pi
+        rho_p = kept / np.real(np.trace(kept))
+        rho2 = D @ rho_p @ D.conj().T
+        out[b] = np.real(np.conj(x) @ rho2 @ x)
+    return out
+
+
+def fidelity_trajectory_direct(x_state, enc, params_enc, dec, params_dec,
+                               n_trash: int, m: np.ndarray) -> np.ndarray:
+    """One trajectory from its definition, for a given outcome m per sample:
+    rho = U|x><x|U^dagger; the measurement keeps Pi_m rho Pi_m / tr(Pi_m rho)
+    (Pi_m the projector on trash bits = m); the reset K_m = |0><m| then moves
+    it to the trash-0 slice; rho'' = D rho' D^dagger, F = <x|rho''|x>. For
+    small n only."""
+    B, N = x_state.shape
+    n = N.bit_length() - 1
+    k = n - n_trash
+    U = circuit_unitary(enc, params_enc)
+    D = circuit_unitary(dec, params_dec)
+    out = np.empty(B)
+    for b in range(B):
+        x = x_state[b]
+        psi = U @ x
+        rho = np.outer(psi, np.conj(psi))
+        K = np.zeros((N, N), dtype=np.complex128)
+        for j in range(1 << k):
+            K[j, (int(m[b]) << k) | j] = 1.0   # |0>_t|j> <m|_t<j|  (= K_m Pi_m)
+        kept = K @ rho @ K.conj().T
         rho_p = kept / np.real(np.trace(kept))
         rho2 = D @ rho_p @ D.conj().T
         out[b] = np.real(np.conj(x) @ rho2 @ x)

@@ -11,7 +11,10 @@
   for the reset channel and for post-selection on the all-zero trash outcome
   (plus a hand value, its reduction to the reset fidelity when only that
   outcome is populated, scale invariance, Cauchy-Schwarz bounds, and its
-  state cotangents against finite differences entry by entry);
+  state cotangents against finite differences entry by entry), and for one
+  trajectory of the reset channel (hand values of the outcome draw, its
+  outcome-weighted average equal to the reset fidelity, outcome 0 equal to
+  post-selection, cotangents against finite differences);
 * gradients: adjoint = parameter shift (exact) = central finite differences.
 """
 import json
@@ -384,6 +387,73 @@ def test_postselect_parameter_gradients_adjoint_vs_fd(rng):
                                atol=1e-8)
     np.testing.assert_allclose(d_ph, O.finite_difference(lambda v: L(th, v), ph.copy()),
                                atol=1e-8)
+
+
+# --------------------------------------------- trajectory of the reset channel
+def _mid_u(psi, n_trash, m):
+    """u in the middle of outcome m's CDF interval (far from any boundary)."""
+    B, N = psi.shape
+    k = (N.bit_length() - 1) - n_trash
+    p = np.sum(np.abs(psi.reshape(B, 1 << n_trash, 1 << k)) ** 2, axis=2)
+    cum = np.cumsum(p, axis=1) / p.sum(axis=1, keepdims=True)
+    lo = np.where(m > 0, cum[np.arange(B), np.maximum(m - 1, 0)], 0.0)
+    return (lo + cum[np.arange(B), m]) / 2
+
+
+def test_trajectory_outcome_hand_values():
+    p = np.array([[0.2, 0.0, 0.5, 0.3]] * 6)
+    u = np.array([0.1, 0.2, 0.69, 0.7, 0.999, 0.0])
+    np.testing.assert_array_equal(O.trajectory_outcome(p, u), [0, 2, 2, 3, 3, 0])
+    # unnormalised probabilities: u scales with their sum
+    np.testing.assert_array_equal(O.trajectory_outcome(p * 4, u), [0, 2, 2, 3, 3, 0])
+
+
+@pytest.mark.parametrize("n,t", [(3, 1), (4, 2), (5, 3)])
+def test_trajectory_average_is_the_reset_fidelity(n, t, rng):
+    """Sum over outcomes m of p_m F_traj(m) = the reset-channel fidelity."""
+    enc = C.ry_rz_chain(n, 2)
+    B = 3
+    th = rng.uniform(-np.pi, np.pi, enc.n_params)
+    ph = rng.uniform(-np.pi, np.pi, enc.n_params)
+    x = O.encode_amplitude(rng.standard_normal((B, 1 << n)), n)
+    psi = O.run_circuit(enc, th, None, x)
+    chi = O.run_circuit(enc, ph, None, x)
+    avg = np.zeros(B)
+    for m in range(1 << t):
+        mm = np.full(B, m)
+        F, got, c, p = O.fidelity_trajectory(psi, chi, t, _mid_u(psi, t, mm))
+        np.testing.assert_array_equal(got, mm)
+        avg += p * F
+        np.testing.assert_allclose(
+            F, O.fidelity_trajectory_direct(x, enc, th, C.inverse_structure(enc), ph, t, mm),
+            atol=1e-12)
+    np.testing.assert_allclose(avg, O.fidelity_reset(psi, chi, t)[0], atol=1e-12)
+    # outcome 0 is the post-selected fidelity
+    F0 = O.fidelity_trajectory(psi, chi, t, _mid_u(psi, t, np.zeros(B, int)))[0]
+    np.testing.assert_allclose(F0, O.fidelity_postselect(psi, chi, t)[0], atol=1e-13)
+
+
+def test_trajectory_cotangents_match_finite_differences(rng):
+    n, t, B = 3, 1, 2
+    psi = O.encode_amplitude(rng.standard_normal((B, 8)), n) * (0.9 - 0.2j)
+    chi = O.encode_amplitude(rng.standard_normal((B, 8)), n) * np.exp(-0.3j)
+    m = np.array([1, 0])
+    u = _mid_u(psi, t, m)
+    F, got, c, p = O.fidelity_trajectory(psi, chi, t, u)
+    np.testing.assert_array_equal(got, m)
+    lam, mu = O.trajectory_fidelity_cotangents(psi, chi, got, c, p, np.ones(B), t)
+    h = 1e-6
+    for which, st, cot in (("psi", psi, lam), ("chi", chi, mu)):
+        for i in range(8):
+            for unit in (1.0, 1j):
+                e = np.zeros_like(st)
+                e[:, i] = unit * h
+                a = (st + e, chi) if which == "psi" else (psi, st + e)
+                b_ = (st - e, chi) if which == "psi" else (psi, st - e)
+                fd = (O.fidelity_trajectory(*a, t, u)[0] -
+                      O.fidelity_trajectory(*b_, t, u)[0]) / (2 * h)
+                want = 2 * (cot[:, i].real if unit == 1.0 else cot[:, i].imag)
+                np.testing.assert_allclose(fd, want, atol=1e-8)
 
 
 # ---------------------------------------------------------------- gradients
