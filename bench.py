@@ -57,6 +57,11 @@ def workload_text(key, dtype, loss=None):
         t = t.replace("4 trash qubits reset, loss 1 - fidelity",
                       "4 trash qubits measured with only the all-zero outcome kept "
                       "(renormalised in FP64), loss 1 - post-selected fidelity")
+    elif loss == "fidelity_trajectory":
+        t = t.replace("4 trash qubits reset, loss 1 - fidelity",
+                      "4 trash qubits reset along one sampled trajectory per sample "
+                      "(measurement outcome drawn from seeded uniforms), loss 1 - "
+                      "trajectory fidelity")
     return t.replace("complex64 forward", "complex128 forward") if dtype == "c128" else t
 
 
@@ -232,9 +237,11 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--dtype", choices=["c64", "c128"], default=None,
                     help="run the workload in this complex type (default: its own)")
-    ap.add_argument("--fidelity", choices=["reset", "postselect"], default="reset",
-                    help="c4: trash qubits reset (default), or measured with only "
-                         "the all-zero outcome kept and renormalised")
+    ap.add_argument("--fidelity", choices=["reset", "postselect", "trajectory"],
+                    default="reset",
+                    help="c4: trash qubits reset (default), measured with only "
+                         "the all-zero outcome kept and renormalised, or reset "
+                         "along one sampled trajectory per sample")
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--cpu-rows", type=int, default=256,
                     help="oracle rows per host process for cpu_baseline")
@@ -261,6 +268,7 @@ def main():
     from paper_2509_25075_amd import sim
     from paper_2509_25075_amd import _native as N
     from workloads import make_workload, uneven_batch
+    from workloads.data import trajectory_uniforms
 
     if args.copy_calibration:
         n = args.copy_calibration << 18  # float32 elements
@@ -305,8 +313,9 @@ def main():
         w = make_workload(key)
         if args.dtype:
             w = dataclasses.replace(w, dtype=args.dtype)
-        if key == "c4" and args.fidelity == "postselect":
-            w = dataclasses.replace(w, loss="fidelity_postselect")
+        if key == "c4" and args.fidelity != "reset":
+            w = dataclasses.replace(w, loss="fidelity_" + args.fidelity)
+        traj_u = trajectory_uniforms(w.batch) if w.loss == "fidelity_trajectory" else None
         tuned = None
         if not args.no_tune:
             # The library's autotuner times the register-split candidates of
@@ -326,7 +335,7 @@ def main():
             torch.cuda.synchronize()
         ck = 4 if key == "c5b" else 0
         # automatic path: register/LDS engine when it fits, else tiled HBM
-        d = sim.to_device(w, flags=0, ckpt_every_layers=ck)
+        d = sim.to_device(w, flags=0, ckpt_every_layers=ck, traj_u=traj_u)
         path = {1: "fused", 2: "plain", 3: "tiled_hbm"}[d.sim.plan_info(w.batch)["path"]]
         updates = w.updates_per_step()
         sim.Simulator.adjoint = timer.wrap(sim.Simulator.adjoint)
@@ -360,7 +369,7 @@ def main():
         if roof is not None:
             roof["frac"] = roof["achieved"] / roof["peak"]
         if not args.no_plain and w.loss != "none" and path == "fused":
-            dp = sim.to_device(w, flags=N.QS_PATH_PLAIN)
+            dp = sim.to_device(w, flags=N.QS_PATH_PLAIN, traj_u=traj_u)
             sim.step(dp)
             torch.cuda.synchronize()
             p0 = torch.cuda.Event(enable_timing=True)

@@ -215,6 +215,32 @@ int qs_fidelity_postselect(int dtype, int n_qubits, int n_trash, int64_t B,
                            const double* dfid, void* lam_psi, void* lam_chi,
                            void* stream);
 
+/* One quantum trajectory of the reset channel (its unravelling into
+ * measurement outcomes: Dalibard, Castin & Molmer, PRL 68, 580, 1992): the
+ * top n_trash qubits are measured, outcome m drawn from the Born
+ * probabilities by the caller's uniform u_b in [0, 1), then reset to |0>.
+ * With psi_m the slice of psi whose trash bits equal m, in FP64:
+ *   p_m = ||psi_m||^2,  m_b = the smallest m with u_b sum_j p_j < p_0 + ... + p_m
+ *   (the sums in m order; the last m with p_m > 0 if rounding leaves none),
+ *   c = <chi_0|psi_m>,  F_b = |c|^2 / p_m.
+ * Its average over outcomes (weights p_m / sum p) is the reset-channel
+ * fidelity of qs_fidelity_reset. A row of zeros gives NaN (outcome 0).
+ *   psi, chi (device) [B][2^n] complex, read only; 0 <= n_trash <= 6, < n
+ *   u        (device) [B] double uniforms (the random numbers are inputs)
+ *   fid      (device) [B] double output
+ *   outcome  (device, optional) [B] int32 output, the drawn m_b
+ *   dfid     (device, optional) [B] double dL/dF_b; when given, the state
+ *            cotangents for the drawn outcome (dL = 2 Re<lam|d psi>)
+ *              lam_psi = dfid_b ((c/p) chi_0 - (F/p) psi_m) on slice m,
+ *              lam_chi = dfid_b (conj(c)/p) psi_m on slice 0,
+ *            zero elsewhere, are written (both [B][2^n] complex, device).
+ * B = 0 does nothing. Returns QS_ERR_INVALID for a bad dtype or size, or a
+ * missing pointer when B > 0. */
+int qs_fidelity_trajectory(int dtype, int n_qubits, int n_trash, int64_t B,
+                           const void* psi, const void* chi, const double* u,
+                           double* fid, int32_t* outcome, const double* dfid,
+                           void* lam_psi, void* lam_chi, void* stream);
+
 /* ------------------------------------------------------- uneven batches */
 /* Many circuits of uneven qubit count and depth in one persistent launch.
  * Circuits are grouped into classes of identical structure (same gate list);

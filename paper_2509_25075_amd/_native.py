@@ -116,6 +116,9 @@ def lib() -> ctypes.CDLL:
         "qs_fidelity_postselect": (ctypes.c_int, [ctypes.c_int, ctypes.c_int,
                                                   ctypes.c_int, i64, vp, vp, vp, vp,
                                                   vp, vp, vp]),
+        "qs_fidelity_trajectory": (ctypes.c_int, [ctypes.c_int, ctypes.c_int,
+                                                  ctypes.c_int, i64, vp, vp, vp, vp,
+                                                  vp, vp, vp, vp, vp]),
         "qs_plan_info_get": (ctypes.c_int, [cp, ctypes.c_int, i64, ctypes.c_int,
                                             ctypes.POINTER(QsPlanInfo)]),
         "qs_plan_export": (ctypes.c_int, [cp, ctypes.c_int, i64, ctypes.c_int,
@@ -261,6 +264,16 @@ def qs_fidelity_postselect(dtype: int, n_qubits: int, n_trash: int, psi, chi, fi
                                         _ptr(psi), _ptr(chi), _ptr(fid), _ptr(dfid),
                                         _ptr(lam_psi), _ptr(lam_chi),
                                         _stream(stream)), "qs_fidelity_postselect")
+
+
+def qs_fidelity_trajectory(dtype: int, n_qubits: int, n_trash: int, psi, chi, u, fid,
+                           outcome=None, dfid=None, lam_psi=None, lam_chi=None,
+                           stream=None):
+    _check(lib().qs_fidelity_trajectory(dtype, n_qubits, n_trash, psi.shape[0],
+                                        _ptr(psi), _ptr(chi), _ptr(u), _ptr(fid),
+                                        _ptr(outcome), _ptr(dfid), _ptr(lam_psi),
+                                        _ptr(lam_chi), _stream(stream)),
+           "qs_fidelity_trajectory")
 
 
 def qs_plan_info_get(h: CircuitHandle, dtype: int, B: int, flags: int = 0) -> dict:

@@ -6,7 +6,9 @@
 // fidelity with reset trash qubits F = sum_m |<chi_0|psi_m>|^2 (Romero, Olson
 // & Aspuru-Guzik 2017), the post-selected variant F' = |<chi_0|psi_0>|^2 /
 // ||psi_0||^2 (trash qubits measured, only the all-zero outcome kept and
-// renormalised), and their state cotangents.
+// renormalised), one trajectory of the reset channel (outcome m drawn from
+// the Born probabilities by a given uniform, F = |<chi_0|psi_m>|^2 /
+// ||psi_m||^2), and their state cotangents.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -236,6 +238,90 @@ fidelity_postselect_kernel(int n, int nt, const real* psi, const real* chi, doub
   }
 }
 
+// One trajectory of the reset channel, one block per sample (nt <= 6). In
+// FP64: p_m = ||psi_m||^2 for every outcome m (slice m = amplitudes
+// [m K, (m+1) K)), the outcome = the smallest m with u * sum p < p_0 + ... +
+// p_m (summed in m order; the last m with p_m > 0 if rounding leaves none),
+// c = <chi_0|psi_m>, F = |c|^2 / p_m. Cotangents scaled by d = dL/dF for that
+// outcome: lam_psi = d ((c/p) chi_0 - (F/p) psi_m) on slice m, lam_chi =
+// d (conj(c)/p) psi_m on slice 0, zero elsewhere.
+template <typename real>
+__global__ void __launch_bounds__(kBlock)
+fidelity_trajectory_kernel(int n, int nt, const real* psi, const real* chi, const double* u,
+                           double* fid, int32_t* outcome, const double* dfid,
+                           real* lam_psi, real* lam_chi) {
+  __shared__ double sh[kBlock / 64];
+  __shared__ double pm[64];
+  __shared__ int pick_sh;
+  const int64_t b = blockIdx.x;
+  const int64_t K = 1ll << (n - nt), M = 1ll << nt, N = 1ll << n;
+  const real* p = psi + 2 * b * N;
+  const real* c = chi + 2 * b * N;
+  for (int64_t m = 0; m < M; ++m) {
+    double s = 0;
+    for (int64_t j = threadIdx.x; j < K; j += blockDim.x) {
+      const double yr = p[2 * (m * K + j)], yi = p[2 * (m * K + j) + 1];
+      s += yr * yr + yi * yi;
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) pm[m] = s;
+  }
+  if (threadIdx.x == 0) {
+    double tot = 0;
+    for (int64_t m = 0; m < M; ++m) tot += pm[m];
+    const double target = u[b] * tot;
+    double acc = 0;
+    int pick = -1, last = 0;
+    for (int64_t m = 0; m < M; ++m) {
+      acc += pm[m];
+      if (pm[m] > 0) last = (int)m;
+      if (pick < 0 && target < acc) pick = (int)m;
+    }
+    pick_sh = pick < 0 ? last : pick;
+  }
+  __syncthreads();
+  const int64_t m = pick_sh;
+  double ar = 0, ai = 0;
+  for (int64_t j = threadIdx.x; j < K; j += blockDim.x) {
+    const double xr = c[2 * j], xi = c[2 * j + 1];
+    const double yr = p[2 * (m * K + j)], yi = p[2 * (m * K + j) + 1];
+    ar += xr * yr + xi * yi;  // conj(x) y
+    ai += xr * yi - xi * yr;
+  }
+  ar = block_sum(ar, sh);
+  ai = block_sum(ai, sh);
+  const double pp = pm[m];
+  const double F = (ar * ar + ai * ai) / pp;
+  if (threadIdx.x == 0) {
+    fid[b] = F;
+    if (outcome != nullptr) outcome[b] = (int32_t)m;
+  }
+  if (dfid == nullptr) return;
+  const double d = dfid[b];
+  const double gr = d * ar / pp, gi = d * ai / pp, gf = d * F / pp;
+  real* lp = lam_psi + 2 * b * N;
+  real* lc = lam_chi + 2 * b * N;
+  for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
+    const int64_t s = i / K, j = i - s * K;
+    double pr = 0, pi = 0, cr = 0, ci = 0;
+    if (s == m) {
+      const double xr = c[2 * j], xi = c[2 * j + 1];
+      const double yr = p[2 * i], yi = p[2 * i + 1];
+      pr = gr * xr - gi * xi - gf * yr;
+      pi = gr * xi + gi * xr - gf * yi;
+    }
+    if (s == 0) {
+      const double yr = p[2 * (m * K + j)], yi = p[2 * (m * K + j) + 1];
+      cr = gr * yr + gi * yi;
+      ci = gr * yi - gi * yr;
+    }
+    lp[2 * i] = (real)pr;
+    lp[2 * i + 1] = (real)pi;
+    lc[2 * i] = (real)cr;
+    lc[2 * i + 1] = (real)ci;
+  }
+}
+
 // out[col_param[c]] (+)= sum_r partials[r][c] in FP64: one block per column,
 // threads stride over rows with four independent sums each, then a block
 // reduction. The order of the additions is fixed, so the result is
@@ -401,6 +487,23 @@ int launch_fidelity_postselect(int dtype, int n, int n_trash, int64_t B, const v
     hipLaunchKernelGGL(fidelity_postselect_kernel<double>, dim3((unsigned)B), kBlock, 0, st,
                        n, n_trash, (const double*)psi, (const double*)chi, fid, dfid,
                        (double*)lam_psi, (double*)lam_chi);
+  return ok();
+}
+
+int launch_fidelity_trajectory(int dtype, int n, int n_trash, int64_t B, const void* psi,
+                               const void* chi, const double* u, double* fid,
+                               int32_t* outcome, const double* dfid, void* lam_psi,
+                               void* lam_chi, void* stream) {
+  if (B == 0) return QS_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dtype == QS_C64)
+    hipLaunchKernelGGL(fidelity_trajectory_kernel<float>, dim3((unsigned)B), kBlock, 0, st,
+                       n, n_trash, (const float*)psi, (const float*)chi, u, fid, outcome,
+                       dfid, (float*)lam_psi, (float*)lam_chi);
+  else
+    hipLaunchKernelGGL(fidelity_trajectory_kernel<double>, dim3((unsigned)B), kBlock, 0, st,
+                       n, n_trash, (const double*)psi, (const double*)chi, u, fid, outcome,
+                       dfid, (double*)lam_psi, (double*)lam_chi);
   return ok();
 }
 

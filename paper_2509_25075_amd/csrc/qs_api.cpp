@@ -1207,6 +1207,19 @@ int qs_fidelity_postselect(int dtype, int n, int n_trash, int64_t B, const void*
                                     lam_chi, stream);
 }
 
+int qs_fidelity_trajectory(int dtype, int n, int n_trash, int64_t B, const void* psi,
+                           const void* chi, const double* u, double* fid, int32_t* outcome,
+                           const double* dfid, void* lam_psi, void* lam_chi,
+                           void* stream) {
+  if ((dtype != QS_C64 && dtype != QS_C128) || n < 1 || n > 30 || B < 0 ||
+      B > 0x7fffffff || n_trash < 0 || n_trash > 6 || n_trash >= n)
+    return QS_ERR_INVALID;
+  if (B == 0) return QS_OK;
+  if (!psi || !chi || !u || !fid || (dfid && (!lam_psi || !lam_chi))) return QS_ERR_INVALID;
+  return launch_fidelity_trajectory(dtype, n, n_trash, B, psi, chi, u, fid, outcome, dfid,
+                                    lam_psi, lam_chi, stream);
+}
+
 int qs_plan_info_get(const qs_circuit* c, int dtype, int64_t B, int flags,
                      qs_plan_info* out) {
   int rc = validate(c);

@@ -199,6 +199,10 @@ int launch_fidelity(int dtype, int n, int n_trash, int64_t B, const void* psi,
 int launch_fidelity_postselect(int dtype, int n, int n_trash, int64_t B, const void* psi,
                                const void* chi, double* fid, const double* dfid,
                                void* lam_psi, void* lam_chi, void* stream);
+int launch_fidelity_trajectory(int dtype, int n, int n_trash, int64_t B, const void* psi,
+                               const void* chi, const double* u, double* fid,
+                               int32_t* outcome, const double* dfid, void* lam_psi,
+                               void* lam_chi, void* stream);
 // out[col_param[j]] (+)= sum over rows of partials[row][j], j < cols.
 int launch_reduce_partials(int dtype, const void* partials, int64_t rows,
                            int cols, const int32_t* col_param, double* out,

@@ -144,9 +144,15 @@ class DeviceWorkload:
     ckpt_gates: list | None = None   # gate counts after which psi is stored
     ckpt: torch.Tensor | None = None  # [n_ckpt, B, 2^n] stored states
     dz: torch.Tensor | None = None    # [B, n] float64 upstream gradient buffer
+    u: torch.Tensor | None = None     # [B] float64 trajectory uniforms
 
 
-def to_device(w, flags: int = 0, device="cuda", ckpt_every_layers: int = 0) -> DeviceWorkload:
+def to_device(w, flags: int = 0, device="cuda", ckpt_every_layers: int = 0,
+              traj_u=None) -> DeviceWorkload:
+    """``traj_u``: [B] uniforms in [0, 1) that draw the measurement outcome of
+    each sample's reset-channel trajectory (loss "fidelity_trajectory")."""
+    if w.loss == "fidelity_trajectory" and traj_u is None:
+        raise ValueError("the trajectory loss needs its uniforms (traj_u)")
     sim = Simulator(w.circuit, w.dtype, flags)
     rd = sim.rdtype
     B = w.batch
@@ -177,7 +183,8 @@ def to_device(w, flags: int = 0, device="cuda", ckpt_every_layers: int = 0) -> D
         state=state, state_dec=sim.empty_state(B, device) if sim_dec else None,
         ws=sim.workspace(B, device, flags),
         ws_dec=sim_dec.workspace(B, device, flags) if sim_dec else None,
-        flags=flags, ckpt_gates=ckpt_gates, ckpt=ckpt, dz=dz)
+        flags=flags, ckpt_gates=ckpt_gates, ckpt=ckpt, dz=dz,
+        u=t(traj_u, torch.float64) if w.loss == "fidelity_trajectory" else None)
 
 
 def step(d: DeviceWorkload, backward: bool = True) -> dict:
@@ -190,7 +197,7 @@ def step(d: DeviceWorkload, backward: bool = True) -> dict:
     else:
         sim.zero_state(B, d.state.device, out=d.state)
     out = {}
-    if w.loss in ("fidelity_reset", "fidelity_postselect"):
+    if w.loss in ("fidelity_reset", "fidelity_postselect", "fidelity_trajectory"):
         sim.encode_amplitude(d.x, out=d.state_dec)
         sim.forward(d.params, d.feats, d.state, want_expz=False)
         d.sim_dec.forward(d.params_dec, d.feats, d.state_dec, want_expz=False)
@@ -198,11 +205,18 @@ def step(d: DeviceWorkload, backward: bool = True) -> dict:
         dfid = torch.full((B,), -1.0 / B, dtype=torch.float64, device=d.state.device)
         lam_psi = torch.empty_like(d.state)
         lam_chi = torch.empty_like(d.state)
-        fn = N.qs_fidelity_reset if w.loss == "fidelity_reset" else N.qs_fidelity_postselect
-        fn(sim.qs_dtype, sim.n, w.n_trash, d.state, d.state_dec,
-           fid, dfid if backward else None,
-           lam_psi if backward else None,
-           lam_chi if backward else None)
+        if w.loss == "fidelity_trajectory":
+            N.qs_fidelity_trajectory(sim.qs_dtype, sim.n, w.n_trash, d.state, d.state_dec,
+                                     d.u, fid, None, dfid if backward else None,
+                                     lam_psi if backward else None,
+                                     lam_chi if backward else None)
+        else:
+            fn = (N.qs_fidelity_reset if w.loss == "fidelity_reset"
+                  else N.qs_fidelity_postselect)
+            fn(sim.qs_dtype, sim.n, w.n_trash, d.state, d.state_dec,
+               fid, dfid if backward else None,
+               lam_psi if backward else None,
+               lam_chi if backward else None)
         out["fid"] = fid
         out["loss"] = 1.0 - fid.mean()
         if backward:

@@ -193,7 +193,11 @@ def _fidelity_oracle(w, rows, B_total):
     psi = O.run_circuit(w.circuit, w.params, None, x)
     chi = O.run_circuit(w.decoder, w.params_dec, None, x)
     dF = -np.ones(len(idx)) / B_total
-    if w.loss == "fidelity_postselect":
+    if w.loss == "fidelity_trajectory":
+        u = Dt.trajectory_uniforms(w.batch)[idx]
+        F, m, c, p = O.fidelity_trajectory(psi, chi, w.n_trash, u)
+        lam, mu = O.trajectory_fidelity_cotangents(psi, chi, m, c, p, dF, w.n_trash)
+    elif w.loss == "fidelity_postselect":
         F, c, p = O.fidelity_postselect(psi, chi, w.n_trash)
         lam, mu = O.postselect_fidelity_cotangents(psi, chi, c, p, dF, w.n_trash)
     else:
@@ -231,6 +235,77 @@ def test_autoencoder_postselect_step_vs_oracle(dtype, B):
     np.testing.assert_allclose(float(out["loss"]), 1.0 - F.mean(), atol=tol["z"])
     np.testing.assert_allclose(out["grad_params"].cpu().numpy(), gth, atol=tol["grad"])
     np.testing.assert_allclose(out["grad_params_dec"].cpu().numpy(), gph, atol=tol["grad"])
+
+
+@pytest.mark.parametrize("dtype,B", [("c64", 5), ("c128", 3)])
+def test_autoencoder_trajectory_step_vs_oracle(dtype, B):
+    w = dataclasses.replace(Dt.make_workload("c4", B), dtype=dtype,
+                            loss="fidelity_trajectory")
+    _announce(f"workload c4 trajectory B={B} {dtype}")
+    d = sim.to_device(w, traj_u=Dt.trajectory_uniforms(B))
+    out = sim.step(d)
+    torch.cuda.synchronize()
+    F, gth, gph = _fidelity_oracle(w, None, w.batch)
+    tol = TOL[dtype]
+    np.testing.assert_allclose(out["fid"].cpu().numpy(), F, atol=tol["z"])
+    np.testing.assert_allclose(out["grad_params"].cpu().numpy(), gth, atol=tol["grad"])
+    np.testing.assert_allclose(out["grad_params_dec"].cpu().numpy(), gph, atol=tol["grad"])
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("n,t,B", [(1, 0, 3), (4, 2, 9), (7, 6, 5), (10, 3, 40), (12, 4, 6),
+                                   (15, 1, 2), (3, 1, 0)])
+def test_trajectory_fidelity_kernel_vs_oracle(dtype, n, t, B):
+    """The kernel alone on seeded random (unnormalised) states with some
+    empty slices and one all-zero row: the drawn outcome (exact; the uniforms
+    sit mid-interval of a seeded target outcome, away from any boundary), F,
+    and both cotangents element by element."""
+    _announce(f"trajectory fidelity kernel n={n} t={t} B={B} {dtype}")
+    rng = np.random.default_rng(2000 + 37 * n + t)
+    N_, M, K = 1 << n, 1 << t, 1 << (n - t)
+    cd = torch.complex64 if dtype == "c64" else torch.complex128
+    qd = N.QS_C64 if dtype == "c64" else N.QS_C128
+    psi = (rng.standard_normal((B, N_)) + 1j * rng.standard_normal((B, N_))) * 0.6
+    chi = rng.standard_normal((B, N_)) + 1j * rng.standard_normal((B, N_))
+    if B > 1 and M > 1:
+        psi[0, K:2 * K] = 0          # outcome 1 impossible in row 0
+    if B > 2:
+        psi[2] = 0                   # nothing at all: NaN, outcome 0
+    P = torch.as_tensor(psi).to("cuda", cd).contiguous()
+    X = torch.as_tensor(chi).to("cuda", cd).contiguous()
+    psi_r, chi_r = P.cpu().numpy().astype(np.complex128), X.cpu().numpy().astype(np.complex128)
+    pm = np.sum(np.abs(psi_r.reshape(B, M, K)) ** 2, axis=2)
+    u = np.zeros(B)
+    for b in range(B):
+        ok_m = np.nonzero(pm[b] > 0)[0]
+        if len(ok_m) == 0:
+            u[b] = 0.5
+            continue
+        m = int(rng.choice(ok_m))
+        cum = np.cumsum(pm[b]) / pm[b].sum()
+        u[b] = ((cum[m - 1] if m > 0 else 0.0) + cum[m]) / 2
+    dF = rng.uniform(-1, 1, B)
+    fid = torch.full((B,), 7.0, dtype=torch.float64, device="cuda")
+    out_m = torch.full((B,), -5, dtype=torch.int32, device="cuda")
+    lp = torch.full_like(P, 3.0)
+    lc = torch.full_like(P, 3.0)
+    N.qs_fidelity_trajectory(qd, n, t, P, X, _dev(u, torch.float64), fid, out_m,
+                             _dev(dF, torch.float64), lp, lc)
+    torch.cuda.synchronize()
+    if B == 0:
+        return
+    F, m, c, p = O.fidelity_trajectory(psi_r, chi_r, t, u)
+    np.testing.assert_array_equal(out_m.cpu().numpy(), m)
+    ok = p > 0
+    f = fid.cpu().numpy()
+    assert np.all(np.isnan(f[~ok]))
+    rt = 1e-5 if dtype == "c64" else 1e-12
+    np.testing.assert_allclose(f[ok], F[ok], rtol=rt, atol=rt)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        lam, mu = O.trajectory_fidelity_cotangents(psi_r, chi_r, m, c, p, dF, t)
+    scale = np.abs(lam[ok]).max() + np.abs(mu[ok]).max()
+    np.testing.assert_allclose(lp.cpu().numpy()[ok], lam[ok], atol=rt * scale, rtol=0)
+    np.testing.assert_allclose(lc.cpu().numpy()[ok], mu[ok], atol=rt * scale, rtol=0)
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])

@@ -19,7 +19,7 @@ import numpy as np
 from .circuits import (Circuit, hea_ry_rz_ring, rxyz_cz_ring,
                        reupload_ry_rz_chain, ry_rz_chain)
 
-STREAM_X, STREAM_P, STREAM_Y, STREAM_P2, STREAM_SPEC = 1, 2, 3, 4, 5
+STREAM_X, STREAM_P, STREAM_Y, STREAM_P2, STREAM_SPEC, STREAM_U = 1, 2, 3, 4, 5, 6
 
 
 def _rng(seed: int, stream: int) -> np.random.Generator:
@@ -67,7 +67,9 @@ class Workload:
     "mse_z0" (mean (<Z_0> - y)^2), "fidelity_reset" (1 - mean fidelity after
     resetting the trash qubits), "fidelity_postselect" (1 - mean fidelity when
     the trash qubits are measured and only the all-zero outcome is kept,
-    renormalised), "weighted_z" (sum_b sum_q g_q <Z_q>_b).
+    renormalised), "fidelity_trajectory" (1 - mean fidelity of one trajectory
+    of the reset channel per sample, its measurement outcome drawn from the
+    uniforms ``trajectory_uniforms``), "weighted_z" (sum_b sum_q g_q <Z_q>_b).
     """
 
     name: str
@@ -228,3 +230,10 @@ def uneven_batch_spec(n_circuits: int = 10000, seed: int = 0,
     n = rng.integers(n_lo, n_hi + 1, size=n_circuits)
     d = rng.integers(d_lo, d_hi + 1, size=n_circuits)
     return n.astype(np.int64), d.astype(np.int64)
+
+
+def trajectory_uniforms(B: int, seed: int = 0) -> np.ndarray:
+    """Uniforms in [0, 1), one per sample, that draw the measurement outcome
+    of a reset-channel trajectory (the random numbers are inputs, so both
+    sides of a comparison see the same draw)."""
+    return _rng(seed, STREAM_U).random(B)
