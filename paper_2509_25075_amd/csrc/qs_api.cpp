@@ -675,16 +675,14 @@ float time_ms(hipStream_t st, const std::function<int()>& fn, int reps, int* rc)
     *rc = QS_ERR_LAUNCH;
     return 0.f;
   }
-  // The first run warms plans and caches and sizes the samples: each sample
-  // times k back-to-back calls (k such that a sample lasts about 2 ms, at most
-  // 16), so that short kernels are timed in steady state rather than one
-  // launch after an idle gap; the result is the best sample's time per call.
+  // The first run warms plans and caches; the result is the best of the
+  // following `reps` calls, each synchronised on its own. (Timing a call
+  // repeated back to back was tried: it favoured a smaller forward block
+  // that then ran slower inside the training step.)
   float best = 1e30f;
-  int k = 1;
   for (int i = 0; i <= reps; ++i) {
     (void)hipEventRecord(a, st);
-    int r = QS_OK;
-    for (int j = 0; j < (i == 0 ? 1 : k) && r == QS_OK; ++j) r = fn();
+    int r = fn();
     (void)hipEventRecord(b, st);
     (void)hipEventSynchronize(b);
     if (r != QS_OK) {
@@ -694,11 +692,7 @@ float time_ms(hipStream_t st, const std::function<int()>& fn, int reps, int* rc)
     }
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, a, b);
-    if (i == 0) {
-      k = ms > 0.f ? (int)std::min(16.f, std::max(1.f, 2.f / ms)) : 16;
-    } else if (ms / k < best) {
-      best = ms / k;
-    }
+    if (i > 0 && ms < best) best = ms;
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
@@ -818,17 +812,17 @@ int qs_autotune(const qs_circuit* c, int dtype, int64_t B, int flags, void* stre
               const size_t wsb = fused_ws_bytes(*c, dtype, sh, B, ps);
               void* ws = sc.get(wsb);
               if (!ws) { force_r = force_s = 0; force_h = -1; return QS_ERR_NOMEM; }
-              ms = time_ms(st, [&]() { return adj(ws, wsb); }, 3, &rc);
+              ms = time_ms(st, [&]() { return adj(ws, wsb); }, 5, &rc);
             } else {
-              ms = time_ms(st, fwd, 3, &rc);
+              ms = time_ms(st, fwd, 5, &rc);
             }
             force_r = force_s = 0;
             force_h = -1;
             info.n_candidates++;
             if (rc != QS_OK) return rc;
-            // A smaller block or half staging must win clearly: within timing
-            // noise the LDS-limited default is kept.
-            if (ms < ((cap || half) ? 0.98f : 1.0f) * bt) {
+            // A smaller block or half staging must win clearly (by 5 %): within
+            // timing noise the LDS-limited default is kept.
+            if (ms < ((cap || half) ? 0.95f : 1.0f) * bt) {
               bt = ms;
               (adjoint ? best.adj_r : best.fwd_r) = r;
               (adjoint ? best.adj_s : best.fwd_s) = cap;
