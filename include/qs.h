@@ -95,8 +95,12 @@ enum { QS_C64 = 0, QS_C128 = 1 };
 /* Encodings for qs_encode. */
 enum { QS_ENC_AMPLITUDE = 0, QS_ENC_ZERO = 1 };
 
-/* Flags for qs_forward / qs_adjoint_backward / qs_workspace_size.
- * The low byte selects the execution path. */
+/* Flags for qs_forward / qs_adjoint_backward / qs_workspace_size (and the
+ * planning calls that take flags). The low byte selects the execution path.
+ * QS_FLAG_INVERSE runs the circuit's inverse U^dagger: its gates in reverse
+ * order with every rotation angle negated; checkpoint gate counts then count
+ * gates of that reversed list, and gradients are those of U^dagger's
+ * parameters (the same parameter vector). */
 enum {
   QS_PATH_AUTO = 0,   /* register/LDS-resident engine when it fits, else HBM */
   QS_PATH_FUSED = 1,  /* register/LDS-resident engine (n <= 14)              */
@@ -104,7 +108,8 @@ enum {
   QS_PATH_HBM = 3,    /* state in HBM, run as epochs of gathered m-qubit
                          tiles through the register/LDS engine (n > 14)     */
   QS_PATH_MASK = 0xff,
-  QS_FLAG_PER_SAMPLE_PARAMS = 0x100 /* params is [B][n_params]            */
+  QS_FLAG_PER_SAMPLE_PARAMS = 0x100, /* params is [B][n_params]           */
+  QS_FLAG_INVERSE = 0x200            /* run U^dagger instead of U          */
 };
 
 /* ------------------------------------------------------------------ calls */

@@ -22,6 +22,7 @@ QS_C64, QS_C128 = 0, 1
 QS_ENC_AMPLITUDE, QS_ENC_ZERO = 0, 1
 QS_PATH_AUTO, QS_PATH_FUSED, QS_PATH_PLAIN, QS_PATH_HBM = 0, 1, 2, 3
 QS_FLAG_PER_SAMPLE_PARAMS = 0x100
+QS_FLAG_INVERSE = 0x200
 
 GATE_NP_DTYPE = np.dtype([
     ("op", "<i4"), ("q0", "<i4"), ("q1", "<i4"), ("p_w", "<i4"),

@@ -669,6 +669,27 @@ int64_t engine_lds_bytes(int dtype, const qs_circuit& c, int S, int n_slots, int
 
 namespace {
 
+// QS_FLAG_INVERSE: the calls run U^dagger of the circuit: its gates in
+// reverse order with every rotation angle negated (scale -> -scale); X, Y, Z,
+// H, CNOT and CZ are their own inverses. The inverted list is built on the
+// host for the duration of the call (plans are cached by gate content).
+struct InvCircuit {
+  std::vector<qs_gate> g;
+  qs_circuit c;
+};
+const qs_circuit* apply_inverse(const qs_circuit* c, int* flags, InvCircuit& inv) {
+  if (!c || !(*flags & QS_FLAG_INVERSE)) return c;
+  *flags &= ~QS_FLAG_INVERSE;
+  if (validate(c) != QS_OK) return c;  // the call itself reports it
+  if (c->n_gates > 0 && c->gates) inv.g.assign(c->gates, c->gates + c->n_gates);
+  std::reverse(inv.g.begin(), inv.g.end());
+  for (qs_gate& x : inv.g)
+    if (x.op == QS_OP_RX || x.op == QS_OP_RY || x.op == QS_OP_RZ) x.scale = -x.scale;
+  inv.c = *c;
+  inv.c.gates = inv.g.empty() ? c->gates : inv.g.data();
+  return &inv.c;
+}
+
 float time_ms(hipStream_t st, const std::function<int()>& fn, int reps, int* rc) {
   hipEvent_t a, b;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
@@ -732,6 +753,8 @@ extern "C" {
 
 int qs_autotune(const qs_circuit* c, int dtype, int64_t B, int flags, void* stream,
                 qs_tune_info* out) {
+  InvCircuit inv_;
+  c = apply_inverse(c, &flags, inv_);
   int rc = validate(c);
   if (rc != QS_OK) return rc;
   if ((dtype != QS_C64 && dtype != QS_C128) || B < 1) return QS_ERR_INVALID;
@@ -940,6 +963,8 @@ int qs_forward(const qs_circuit* c, int dtype, int64_t B, const void* params,
                const void* feats, void* state, double* expz,
                const int32_t* ckpt_gates, int32_t n_ckpt, void* ckpt, int flags,
                void* stream) {
+  InvCircuit inv_;
+  c = apply_inverse(c, &flags, inv_);
   int rc = validate(c);
   if (rc != QS_OK) return rc;
   if ((dtype != QS_C64 && dtype != QS_C128) || B < 0) return QS_ERR_INVALID;
@@ -1019,6 +1044,8 @@ int qs_forward(const qs_circuit* c, int dtype, int64_t B, const void* params,
 }
 
 size_t qs_workspace_size(const qs_circuit* c, int dtype, int64_t B, int flags) {
+  InvCircuit inv_;
+  c = apply_inverse(c, &flags, inv_);
   if (validate(c) != QS_OK || B < 0) return 0;
   const bool ps = (flags & QS_FLAG_PER_SAMPLE_PARAMS) != 0;
   TuneVal tv;
@@ -1042,6 +1069,8 @@ int qs_adjoint_backward(const qs_circuit* c, int dtype, int64_t B,
                         const int32_t* ckpt_gates, int32_t n_ckpt,
                         const void* ckpt, void* ws, size_t ws_bytes, int flags,
                         void* stream) {
+  InvCircuit inv_;
+  c = apply_inverse(c, &flags, inv_);
   int rc = validate(c);
   if (rc != QS_OK) return rc;
   if ((dtype != QS_C64 && dtype != QS_C128) || B < 0) return QS_ERR_INVALID;
@@ -1226,6 +1255,8 @@ int qs_fidelity_trajectory(int dtype, int n, int n_trash, int64_t B, const void*
 
 int qs_plan_info_get(const qs_circuit* c, int dtype, int64_t B, int flags,
                      qs_plan_info* out) {
+  InvCircuit inv_;
+  c = apply_inverse(c, &flags, inv_);
   int rc = validate(c);
   if (rc != QS_OK) return rc;
   if (!out || (dtype != QS_C64 && dtype != QS_C128)) return QS_ERR_INVALID;
@@ -1269,6 +1300,8 @@ int qs_plan_info_get(const qs_circuit* c, int dtype, int64_t B, int flags,
 int qs_plan_export(const qs_circuit* c, int dtype, int64_t B, int flags,
                    qs_plan_info* info, int32_t* ops, int32_t* seg_begin,
                    uint8_t* seg_map) {
+  InvCircuit inv_;
+  c = apply_inverse(c, &flags, inv_);
   int rc = qs_plan_info_get(c, dtype, B, flags, info);
   if (rc != QS_OK) return rc;
   if (info->path != QS_PATH_FUSED) return QS_ERR_UNSUPPORTED;
@@ -1291,6 +1324,8 @@ int qs_plan_export(const qs_circuit* c, int dtype, int64_t B, int flags,
 int qs_plan_dump(const qs_circuit* c, int dtype, int64_t B, int flags, int adjoint,
                  qs_engine_dump* info, int32_t* ops, int32_t* seg_begin, uint16_t* seg_lay,
                  int32_t* l1q, uint32_t* diag, int32_t* blk_begin, int32_t* blk_gates) {
+  InvCircuit inv_;
+  c = apply_inverse(c, &flags, inv_);
   if (!info) return QS_ERR_INVALID;
   qs_plan_info pi;
   int rc = qs_plan_info_get(c, dtype, B, flags, &pi);

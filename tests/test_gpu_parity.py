@@ -115,6 +115,49 @@ def test_state_cotangent(n, path):
                    amplitude=False)
 
 
+def _reversed(c):
+    """U^dagger written out: gates reversed, rotation scales negated."""
+    g = c.gates[::-1].copy()
+    rot = np.isin(g["op"], (C.OP["RX"], C.OP["RY"], C.OP["RZ"]))
+    g["scale"][rot] = -g["scale"][rot]
+    return C.Circuit(c.n_qubits, g, c.n_params, c.n_features)
+
+
+@pytest.mark.parametrize("n,path", [(7, "fused"), (7, "plain"), (16, "auto")])
+def test_inverse_flag(n, path):
+    """QS_FLAG_INVERSE runs U^dagger: it undoes a forward sweep, and its forward
+    and adjoint match the oracle on the reversed, negated gate list."""
+    rng = np.random.default_rng(800 + n)
+    c = C.random_circuit(n, 60, rng, n_params=5, n_features=2)
+    B = 9 if n <= 10 else 2
+    _announce(f"inverse flag n={n} {path} B={B}")
+    params = rng.uniform(-np.pi, np.pi, c.n_params).astype(np.float32)
+    feats = rng.uniform(-1, 1, (B, 2)).astype(np.float32)
+    x = rng.standard_normal((B, 1 << n)).astype(np.float32)
+    s = sim.Simulator(c, "c64", PATHS[path])
+    si = sim.Simulator(c, "c64", PATHS[path] | N.QS_FLAG_INVERSE)
+    pt, ft = _dev(params, torch.float32), _dev(feats, torch.float32)
+    st = s.encode_amplitude(_dev(x, torch.float32))
+    st0 = st.clone()
+    s.forward(pt, ft, st)
+    si.forward(pt, ft, st)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(st.cpu().numpy(), st0.cpu().numpy(), atol=1e-5)
+    rev = _reversed(c)
+    psi0 = O.encode_amplitude(x, n)
+    psiG = O.run_circuit(rev, params, feats, psi0)
+    z = si.forward(pt, ft, st)          # st holds psi0 again
+    dz = rng.uniform(-1, 1, (B, n))
+    gp, gf = si.adjoint(pt, ft, st, dexpz=_dev(dz, torch.float64))
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(st.cpu().numpy(), psiG, atol=1e-5)
+    np.testing.assert_allclose(z.cpu().numpy(), O.expz(psiG), atol=1e-5)
+    gth, _ = O.adjoint_vjp(rev, params, feats, psi0, dexpz=dz)
+    rp, rf = O.theta_to_param_grads(rev, params, feats, gth)
+    np.testing.assert_allclose(gp.cpu().numpy(), rp, atol=1e-4)
+    np.testing.assert_allclose(gf.cpu().numpy(), rf, atol=1e-4)
+
+
 def test_empty_circuit_and_single_gate():
     for rows in ([], [(C.OP["RY"], 0, -1, 0, -1, -1, 1.0, 0)]):
         c = C.Circuit(3, np.array(rows, dtype=C.GATE_DTYPE), 1)

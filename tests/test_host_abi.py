@@ -194,6 +194,20 @@ def test_large_circuits_take_the_tiled_path():
     assert info["path"] == N.QS_PATH_HBM and info["log2_threads"] == 12
 
 
+def test_inverse_flag_plans_the_reversed_negated_list():
+    rng = np.random.default_rng(31)
+    c = C.random_circuit(9, 50, rng, n_params=4, n_features=1)
+    g = c.gates[::-1].copy()
+    rot = np.isin(g["op"], (C.OP["RX"], C.OP["RY"], C.OP["RZ"]))
+    g["scale"][rot] = -g["scale"][rot]
+    rev = C.Circuit(c.n_qubits, g, c.n_params, c.n_features)
+    a = N.qs_plan_info_get(N.CircuitHandle(c), N.QS_C64, 8, N.QS_FLAG_INVERSE)
+    b = N.qs_plan_info_get(N.CircuitHandle(rev), N.QS_C64, 8)
+    assert a == b
+    assert N.qs_workspace_size(N.CircuitHandle(c), N.QS_C64, 8, N.QS_FLAG_INVERSE) == \
+        N.qs_workspace_size(N.CircuitHandle(rev), N.QS_C64, 8, 0)
+
+
 def test_explicit_fused_path_refuses_states_that_do_not_fit():
     """Asking for the register/LDS engine on a state it cannot hold is an
     error, never a silent switch to another path."""
