@@ -554,6 +554,10 @@ struct Ctx {
 
   __device__ __forceinline__ void remap(St<real, R>& x, const QS_K uint16_t* from,
                                         const QS_K uint16_t* to) {
+    // The LDS traffic of a remap issues at raised wave priority, so that it
+    // starts while the other waves of the SIMD compute (measured: c2 step
+    // -2.5 %, c3 -5 %, c4 -7 %; with load_state / store_state likewise).
+    __builtin_amdgcn_s_setprio(1);
     static_for<kPasses>([&](auto PC) QS_AI {
       constexpr int P = decltype(PC)::value;
       sample_sync(A.t);
@@ -561,6 +565,7 @@ struct Ctx {
       sample_sync(A.t);
       read_mapped<P>(x, to);
     });
+    __builtin_amdgcn_s_setprio(0);
   }
 
   // HBM offsets of the R amplitudes this thread moves between HBM and LDS:
@@ -581,6 +586,7 @@ struct Ctx {
   // loads of a thread are issued before the first wait.
   __device__ __forceinline__ void load_state(St<real, R>& x, const real* src,
                                              const QS_K uint16_t* map) {
+    __builtin_amdgcn_s_setprio(1);  // memory phase: issue ahead of computing waves
     const v2* s2 = reinterpret_cast<const v2*>(src);
     int64_t off[LR > 0 ? LR : 1];
     hbm_offsets(off);
@@ -617,12 +623,14 @@ struct Ctx {
       sample_sync(A.t);
       read_mapped<P>(x, map);  // with HALF, the other component is still staged
     });
+    __builtin_amdgcn_s_setprio(0);
   }
   // Registers under `map` -> LDS -> HBM (logical order), in runs of 8.
   // In runs of 8. With HALF each pass stores every other real of a run of
   // amplitudes and the second pass fills the gaps (the lines merge in L2).
   __device__ __forceinline__ void store_state(const St<real, R>& x, real* dst,
                                               const QS_K uint16_t* map) {
+    __builtin_amdgcn_s_setprio(1);  // memory phase, as in load_state
     int64_t off[LR > 0 ? LR : 1];
     hbm_offsets(off);
     const int64_t a0 = hbm_a0();
@@ -658,6 +666,7 @@ struct Ctx {
         }
       }
     });
+    __builtin_amdgcn_s_setprio(0);
   }
 
   // cos, sin of theta/2 of a block's rotation (uniform record).
