@@ -838,6 +838,9 @@ struct Ctx {
       const G3<real> pg =
           pauli_and_apply<j>(psi, lam, u_dag(block_or_id(bid, r.w[kL1QFused + j])));
       if (bid >= 0) {  // reads pg only: no state copies at the join
+        // The gradient sums (wave reductions, LDS adds) also run at raised
+        // priority: they then overlap the other waves' block arithmetic.
+        __builtin_amdgcn_s_setprio(1);
         const int b0 = kc(A.blk_begin)[bid], b1 = kc(A.blk_begin)[bid + 1];
         const int gen = kc(A.blk_gen)[bid];
         if (SHARED || gen >= 0) {
@@ -862,6 +865,7 @@ struct Ctx {
             if (i > b0) m.conj_by(kind, c, sn);
           }
         }
+        __builtin_amdgcn_s_setprio(0);
       }
     });
     apply_signs(psi, lam, r.w[kL1QPreDiag]);
