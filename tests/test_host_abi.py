@@ -47,6 +47,25 @@ def test_header_constants_match_descriptor_format():
     assert C.GATE_DTYPE.itemsize == 32
 
 
+def test_fidelity_calls_validate_before_touching_the_gpu():
+    """Bad sizes are rejected and B = 0 is a no-op, before any device work
+    (so these run without a GPU)."""
+    L = N.lib()
+    nul = [None] * 7
+    # n_trash must be < n (and <= 6 where the kernel keeps per-outcome sums)
+    assert L.qs_fidelity_postselect(N.QS_C64, 4, 4, 1, *nul) == N.QS_ERR_INVALID
+    assert L.qs_fidelity_trajectory(N.QS_C64, 10, 7, 1, *nul, None, None) == N.QS_ERR_INVALID
+    assert L.qs_fidelity_reset(N.QS_C64, 10, 7, 1, *nul) == N.QS_ERR_INVALID
+    assert L.qs_fidelity_postselect(3, 4, 1, 1, *nul) == N.QS_ERR_INVALID     # dtype
+    assert L.qs_fidelity_trajectory(N.QS_C128, 31, 1, 1, *nul, None, None) == N.QS_ERR_INVALID
+    # missing buffers with B > 0
+    assert L.qs_fidelity_postselect(N.QS_C64, 4, 1, 2, *nul) == N.QS_ERR_INVALID
+    assert L.qs_fidelity_trajectory(N.QS_C64, 4, 1, 2, *nul, None, None) == N.QS_ERR_INVALID
+    # B = 0: nothing to do, no buffers needed
+    assert L.qs_fidelity_postselect(N.QS_C64, 4, 1, 0, *nul) == N.QS_OK
+    assert L.qs_fidelity_trajectory(N.QS_C128, 4, 2, 0, *nul, None, None) == N.QS_OK
+
+
 def test_status_strings():
     for s in [0, -1, -2, -3, -4, -5, -6, 7]:
         assert isinstance(N.status_string(s), str) and N.status_string(s)
