@@ -50,7 +50,11 @@ typedef enum qs_status {
   QS_ERR_WORKSPACE = -3,   /* workspace missing or smaller than required    */
   QS_ERR_ZERO_NORM = -4,   /* amplitude input row with norm 0               */
   QS_ERR_LAUNCH = -5,      /* a HIP runtime call or kernel launch failed    */
-  QS_ERR_NOMEM = -6        /* the plan cache could not allocate             */
+  QS_ERR_NOMEM = -6,       /* the plan cache could not allocate             */
+  QS_ERR_CAPTURE = -7      /* a new plan would have to be uploaded while the
+                              call's stream is being captured into a graph:
+                              nothing was enqueued and the capture stays
+                              valid; run the call once before capturing     */
 } qs_status;
 
 /* ------------------------------------------------------------- descriptor */
@@ -136,10 +140,19 @@ int qs_validate(const qs_circuit* circuit);
  *   state    (device) [B][2^n] complex output.
  *   bad_rows (device, optional) int32 counter; the number of zero-norm rows
  *            is ADDED to it (those rows become NaN). The host cannot see this
- *            without a sync, so the call itself returns QS_OK for them. */
+ *            without a sync, so the call itself returns QS_OK for them;
+ *            qs_encode_check reads the counter. */
 int qs_encode(int enc, int dtype, int n_qubits, int64_t B, int64_t D,
               int x_is_f64, const void* x, int64_t x_stride, void* state,
               int32_t* bad_rows, void* stream);
+
+/* Synchronous: waits for `stream`, then reads the bad_rows counter that
+ * qs_encode / qs_program_encode added to (device, int32). Returns
+ * QS_ERR_ZERO_NORM when it is non-zero (some amplitude input row had norm 0
+ * and became NaN), QS_OK when it is zero, QS_ERR_INVALID for a NULL counter,
+ * QS_ERR_CAPTURE while the stream is being captured (a capture cannot wait),
+ * QS_ERR_LAUNCH when the wait or the copy fails. */
+int qs_encode_check(const int32_t* bad_rows, void* stream);
 
 /* Forward sweep: state[b] <- U_G(theta_G(b)) ... U_1(theta_1(b)) state[b].
  *   params   (device) [n_params] or [B][n_params] (QS_FLAG_PER_SAMPLE_PARAMS)
@@ -193,7 +206,9 @@ int qs_expz(int dtype, int n_qubits, int64_t B, const void* state,
  *   dfid     (device, optional) [B] double dL/dF_b; when given, the state
  *            cotangents lam_psi = dfid_b sum_m c_m |m>|chi_0> and
  *            lam_chi = dfid_b |0> sum_m conj(c_m) psi_m are written
- *            (both [B][2^n] complex, device). */
+ *            (both [B][2^n] complex, device).
+ * 0 <= n_trash <= 6, < n. B = 0 does nothing. Returns QS_ERR_INVALID for a
+ * bad dtype or size, or a missing pointer when B > 0. */
 int qs_fidelity_reset(int dtype, int n_qubits, int n_trash, int64_t B,
                       const void* psi, const void* chi, double* fid,
                       const double* dfid, void* lam_psi, void* lam_chi,
@@ -318,6 +333,24 @@ typedef struct qs_plan_info {
 /* Fill `out` with the plan the engine would use (host only, no GPU). */
 int qs_plan_info_get(const qs_circuit* circuit, int dtype, int64_t B,
                      int flags, qs_plan_info* out);
+
+/* Host only: what the large-state path (QS_PATH_HBM) runs for this circuit
+ * with these checkpoints (the same gate counts qs_forward and
+ * qs_adjoint_backward take; ckpt_gates may be NULL when n_ckpt == 0).
+ * Returns QS_ERR_UNSUPPORTED when the circuit does not take that path. */
+typedef struct qs_hbm_info {
+  int32_t path;              /* QS_PATH_HBM                                  */
+  int32_t n_passes;          /* epochs: kernel launches over the whole state
+                                per direction                                */
+  int32_t tile_qubits;       /* qubits held by one tile-sample (m)           */
+  int32_t reserved;
+  int64_t max_partial_bytes; /* largest gradient partial-sum area any adjoint
+                                epoch of this plan writes                    */
+  int64_t ws_bytes;          /* qs_workspace_size() for these flags: covers
+                                every checkpoint placement                   */
+} qs_hbm_info;
+int qs_hbm_info_get(const qs_circuit* circuit, int dtype, int64_t B, int flags,
+                    const int32_t* ckpt_gates, int32_t n_ckpt, qs_hbm_info* out);
 
 /* Host only: export the fused engine's plan for inspection (tests, tools).
  * Fills `info` like qs_plan_info_get; then, when the arrays are non-NULL,

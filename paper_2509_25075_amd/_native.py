@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libqs.so")
 # status codes / enums (mirrors include/qs.h)
 QS_OK, QS_ERR_INVALID, QS_ERR_UNSUPPORTED = 0, -1, -2
 QS_ERR_WORKSPACE, QS_ERR_ZERO_NORM, QS_ERR_LAUNCH, QS_ERR_NOMEM = -3, -4, -5, -6
+QS_ERR_CAPTURE = -7
 QS_C64, QS_C128 = 0, 1
 QS_ENC_AMPLITUDE, QS_ENC_ZERO = 0, 1
 QS_PATH_AUTO, QS_PATH_FUSED, QS_PATH_PLAIN, QS_PATH_HBM = 0, 1, 2, 3
@@ -53,6 +54,12 @@ class QsPlanInfo(ctypes.Structure):
                 ("adj_log2_regs", ctypes.c_int32),
                 ("adj_samples_per_block", ctypes.c_int32),
                 ("adj_block_threads", ctypes.c_int32), ("n_engine_ops", ctypes.c_int32)]
+
+
+class QsHbmInfo(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int32), ("n_passes", ctypes.c_int32),
+                ("tile_qubits", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_partial_bytes", ctypes.c_int64), ("ws_bytes", ctypes.c_int64)]
 
 
 class QsProgram(ctypes.Structure):
@@ -104,6 +111,7 @@ def lib() -> ctypes.CDLL:
         "qs_validate": (ctypes.c_int, [cp]),
         "qs_encode": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, i64,
                                      i64, ctypes.c_int, vp, i64, vp, vp, vp]),
+        "qs_encode_check": (ctypes.c_int, [vp, vp]),
         "qs_forward": (ctypes.c_int, [cp, ctypes.c_int, i64, vp, vp, vp, vp,
                                       i32p, i32, vp, ctypes.c_int, vp]),
         "qs_workspace_size": (sz, [cp, ctypes.c_int, i64, ctypes.c_int]),
@@ -122,6 +130,8 @@ def lib() -> ctypes.CDLL:
                                                   vp, vp, vp, vp, vp]),
         "qs_plan_info_get": (ctypes.c_int, [cp, ctypes.c_int, i64, ctypes.c_int,
                                             ctypes.POINTER(QsPlanInfo)]),
+        "qs_hbm_info_get": (ctypes.c_int, [cp, ctypes.c_int, i64, ctypes.c_int, i32p,
+                                           i32, ctypes.POINTER(QsHbmInfo)]),
         "qs_plan_export": (ctypes.c_int, [cp, ctypes.c_int, i64, ctypes.c_int,
                                           ctypes.POINTER(QsPlanInfo), vp, vp, vp]),
         "qs_program_layout": (ctypes.c_int, [ctypes.POINTER(QsProgram), vp, vp, vp, vp]),
@@ -219,6 +229,12 @@ def qs_encode(enc: int, dtype: int, n_qubits: int, x, state, bad_rows=None,
            "qs_encode")
 
 
+def qs_encode_check(bad_rows, stream=None):
+    """Waits for the stream and raises QsError(QS_ERR_ZERO_NORM) when the
+    bad-row counter of earlier encodes is non-zero."""
+    _check(lib().qs_encode_check(_ptr(bad_rows), _stream(stream)), "qs_encode_check")
+
+
 def qs_forward(h: CircuitHandle, dtype: int, params, feats, state, expz=None,
                ckpt_gates=None, ckpt=None, flags: int = 0, stream=None):
     arr, n_ck, keep = _ckpt_arr(ckpt_gates)
@@ -275,6 +291,15 @@ def qs_fidelity_trajectory(dtype: int, n_qubits: int, n_trash: int, psi, chi, u,
                                         _ptr(outcome), _ptr(dfid), _ptr(lam_psi),
                                         _ptr(lam_chi), _stream(stream)),
            "qs_fidelity_trajectory")
+
+
+def qs_hbm_info_get(h: CircuitHandle, dtype: int, B: int, flags: int = 0,
+                    ckpt_gates=None) -> dict:
+    arr, n, _ = _ckpt_arr(ckpt_gates)
+    info = QsHbmInfo()
+    _check(lib().qs_hbm_info_get(h.ptr, dtype, B, flags, arr, n, ctypes.byref(info)),
+           "qs_hbm_info_get")
+    return {k: getattr(info, k) for k, _ in QsHbmInfo._fields_}
 
 
 def qs_plan_info_get(h: CircuitHandle, dtype: int, B: int, flags: int = 0) -> dict:

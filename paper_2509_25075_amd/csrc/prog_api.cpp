@@ -137,6 +137,10 @@ ProgPlan* get_prog(const qs_program* p, int dtype, int* rc) {
     auto it = g_prog.find(key);
     if (it != g_prog.end()) return it->second;
   }
+  if (call_stream_capturing()) {
+    *rc = QS_ERR_CAPTURE;
+    return nullptr;
+  }
   const int r = dtype == QS_C64 ? 5 : 4;
   std::vector<int64_t> so, po, eo;
   int64_t tot[3];
@@ -379,6 +383,7 @@ int qs_program_layout(const qs_program* p, int64_t* state_off, int64_t* param_of
 
 int qs_program_encode(const qs_program* p, int dtype, const void* x, int x_is_f64,
                       void* states, int32_t* bad_rows, void* stream) {
+  CallStream call_(stream);
   int rc = check_program(p, dtype);
   if (rc != QS_OK) return rc;
   if (!x || !states) return QS_ERR_INVALID;
@@ -391,6 +396,7 @@ int qs_program_encode(const qs_program* p, int dtype, const void* x, int x_is_f6
 
 int qs_program_forward(const qs_program* p, int dtype, const void* params,
                        void* states, double* expz, void* stream) {
+  CallStream call_(stream);
   int rc = check_program(p, dtype);
   if (rc != QS_OK) return rc;
   if (!states || !params) return QS_ERR_INVALID;
@@ -400,6 +406,7 @@ int qs_program_forward(const qs_program* p, int dtype, const void* params,
 int qs_program_adjoint(const qs_program* p, int dtype, const void* params,
                        const void* states, const double* dexpz, double* grad_params,
                        void* stream) {
+  CallStream call_(stream);
   int rc = check_program(p, dtype);
   if (rc != QS_OK) return rc;
   if (!states || !params || !dexpz || !grad_params) return QS_ERR_INVALID;

@@ -13,7 +13,29 @@
 
 namespace qs {
 int sv_max_threads(int dtype, int r, int adjoint);
+
+namespace {
+thread_local void* t_call_stream = nullptr;
+thread_local bool t_in_call = false;
+}  // namespace
+
+CallStream::CallStream(void* stream) : prev(t_call_stream), prev_in_call(t_in_call) {
+  t_call_stream = stream;
+  t_in_call = true;
 }
+CallStream::~CallStream() {
+  t_call_stream = prev;
+  t_in_call = prev_in_call;
+}
+
+bool call_stream_capturing() {
+  if (!t_in_call) return false;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(static_cast<hipStream_t>(t_call_stream), &cs) != hipSuccess)
+    return false;
+  return cs != hipStreamCaptureStatusNone;
+}
+}  // namespace qs
 
 using namespace qs;
 
@@ -330,6 +352,10 @@ Entry* get_plan(const qs_circuit& c, int r, bool ps, const int32_t* ck, int n_ck
   std::lock_guard<std::mutex> lock(g_mu);
   auto it = g_cache.find(key);
   if (it != g_cache.end()) return it->second;
+  if (call_stream_capturing()) {
+    *rc = QS_ERR_CAPTURE;
+    return nullptr;
+  }
   Entry* e = new Entry();
   e->device = device;
   e->host = plan_sv(c, r, ps, ck, n_ck);
@@ -413,6 +439,10 @@ qs_gate* get_dev_gates(const qs_circuit& c, int* rc) {
   std::lock_guard<std::mutex> lock(g_mu);
   auto it = g_gate_cache.find(key);
   if (it != g_gate_cache.end()) return it->second;
+  if (call_stream_capturing()) {
+    *rc = QS_ERR_CAPTURE;
+    return nullptr;
+  }
   qs_gate* d = nullptr;
   if (!upload(&d, c.gates, (size_t)c.n_gates)) {
     *rc = QS_ERR_NOMEM;
@@ -480,6 +510,10 @@ TiledEntry* get_tiled(const qs_circuit& c, int dtype, bool ps, const int32_t* ck
     auto it = g_tiled.find(key);
     if (it != g_tiled.end()) return it->second;
   }
+  if (call_stream_capturing()) {
+    *rc = QS_ERR_CAPTURE;
+    return nullptr;
+  }
   const int low_keep = m >= 6 ? 4 : (m >= 4 ? m - 2 : 0);
   std::vector<TiledEpoch> eps = plan_tiled(c, m, low_keep, ck, n_ck);
   TiledEntry* te = new TiledEntry();
@@ -537,18 +571,24 @@ TiledEntry* get_tiled(const qs_circuit& c, int dtype, bool ps, const int32_t* ck
 }
 
 // Host-only view of the tiled plan: tile size, epochs, largest adjoint grid
-// and largest per-block gradient-sum array (blocks x gradient columns).
+// and a bound on the per-block gradient-sum array (blocks x gradient columns)
+// that holds for every checkpoint placement: checkpoints move the epoch
+// boundaries, so the bound takes the largest possible grid (one tile-sample
+// per workgroup) times the gradient columns of the whole circuit, which no
+// epoch can exceed.
+// max_part_plan is the largest array of the plan for the given checkpoints.
 struct TiledHostInfo {
   int m = 0, n_epochs = 0;
-  int64_t max_grid = 1, max_part = 1;
+  int64_t max_grid = 1, max_part = 1, max_part_plan = 0;
   bool ok = true;
 };
 TiledHostInfo tiled_host_info(const qs_circuit& c, int dtype, int64_t B, bool ps,
-                              const TileCfg& tc) {
+                              const TileCfg& tc, const int32_t* ck = nullptr,
+                              int n_ck = 0) {
   TiledHostInfo h;
   h.m = tile_qubits(dtype, c.n_qubits, tc.m_pref);
   const int low_keep = h.m >= 6 ? 4 : (h.m >= 4 ? h.m - 2 : 0);
-  std::vector<TiledEpoch> eps = plan_tiled(c, h.m, low_keep, nullptr, 0);
+  std::vector<TiledEpoch> eps = plan_tiled(c, h.m, low_keep, ck, n_ck);
   h.n_epochs = (int)eps.size();
   const int64_t samples = B << (c.n_qubits - h.m);
   for (const TiledEpoch& e : eps) {
@@ -563,8 +603,9 @@ TiledHostInfo tiled_host_info(const qs_circuit& c, int dtype, int64_t B, bool ps
     const int64_t g = (samples + a.samples_per_block - 1) / a.samples_per_block;
     if (g > h.max_grid) h.max_grid = g;
     const int64_t cols = (int64_t)grad_columns(sub, ps).size();
-    if (g * cols > h.max_part) h.max_part = g * cols;
+    if (g * cols > h.max_part_plan) h.max_part_plan = g * cols;
   }
+  h.max_part = std::max<int64_t>(1, samples * (int64_t)grad_columns(c, ps).size());
   return h;
 }
 
@@ -937,6 +978,9 @@ const char* qs_status_string(int s) {
     case QS_ERR_ZERO_NORM: return "amplitude input row with zero norm";
     case QS_ERR_LAUNCH: return "HIP runtime or kernel launch failure";
     case QS_ERR_NOMEM: return "device allocation for the plan cache failed";
+    case QS_ERR_CAPTURE:
+      return "this shape has no plan yet and its upload is not allowed inside a stream "
+             "capture: run the call once before capturing";
     default: return "unknown status";
   }
 }
@@ -959,10 +1003,24 @@ int qs_encode(int enc, int dtype, int n, int64_t B, int64_t D, int x_is_f64,
                        bad_rows, stream);
 }
 
+int qs_encode_check(const int32_t* bad_rows, void* stream) {
+  if (!bad_rows) return QS_ERR_INVALID;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess) return QS_ERR_LAUNCH;
+  if (cs != hipStreamCaptureStatusNone) return QS_ERR_CAPTURE;
+  if (hipStreamSynchronize(st) != hipSuccess) return QS_ERR_LAUNCH;
+  int32_t h = 0;
+  if (hipMemcpy(&h, bad_rows, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
+    return QS_ERR_LAUNCH;
+  return h != 0 ? QS_ERR_ZERO_NORM : QS_OK;
+}
+
 int qs_forward(const qs_circuit* c, int dtype, int64_t B, const void* params,
                const void* feats, void* state, double* expz,
                const int32_t* ckpt_gates, int32_t n_ckpt, void* ckpt, int flags,
                void* stream) {
+  CallStream call_(stream);
   InvCircuit inv_;
   c = apply_inverse(c, &flags, inv_);
   int rc = validate(c);
@@ -1069,6 +1127,7 @@ int qs_adjoint_backward(const qs_circuit* c, int dtype, int64_t B,
                         const int32_t* ckpt_gates, int32_t n_ckpt,
                         const void* ckpt, void* ws, size_t ws_bytes, int flags,
                         void* stream) {
+  CallStream call_(stream);
   InvCircuit inv_;
   c = apply_inverse(c, &flags, inv_);
   int rc = validate(c);
@@ -1103,6 +1162,15 @@ int qs_adjoint_backward(const qs_circuit* c, int dtype, int64_t B,
     if (!te) return rc;
     const int64_t per = B << c->n_qubits;
     const size_t cs = dtype == QS_C64 ? 8 : 16;
+    const int64_t samples = B << (c->n_qubits - te->m);
+    if (!ps) {  // every epoch's partial sums must fit behind the two states
+      const size_t acc = dtype == QS_C64 ? 4 : 8;
+      for (const TiledEpochDev& d : te->epochs) {
+        const int64_t g = (samples + d.ashape.samples_per_block - 1) / d.ashape.samples_per_block;
+        if (2 * cs * (size_t)per + (size_t)g * d.adj->dev.n_acc * acc > ws_bytes)
+          return QS_ERR_WORKSPACE;
+      }
+    }
     char* psi_w = static_cast<char*>(ws);
     char* lam_w = psi_w + cs * per;
     void* part = lam_w + cs * per;
@@ -1115,7 +1183,6 @@ int qs_adjoint_backward(const qs_circuit* c, int dtype, int64_t B,
     if (c->n_features && grad_feats &&
         (rc = launch_fill_f64(grad_feats, B * c->n_features, stream)) != QS_OK)
       return rc;
-    const int64_t samples = B << (c->n_qubits - te->m);
     for (int i = (int)te->epochs.size() - 1; i >= 0; --i) {
       const TiledEpochDev& d = te->epochs[i];
       if (d.ckpt_after >= 0 && ckpt) {  // psi after this epoch = the checkpoint
@@ -1221,9 +1288,10 @@ int qs_fidelity_reset(int dtype, int n, int n_trash, int64_t B, const void* psi,
                       const void* chi, double* fid, const double* dfid,
                       void* lam_psi, void* lam_chi, void* stream) {
   if ((dtype != QS_C64 && dtype != QS_C128) || n < 1 || n > 30 || B < 0 ||
-      n_trash < 0 || n_trash > 6 || n_trash >= n || !psi || !chi || !fid)
+      B > 0x7fffffff || n_trash < 0 || n_trash > 6 || n_trash >= n)
     return QS_ERR_INVALID;
-  if (dfid && (!lam_psi || !lam_chi)) return QS_ERR_INVALID;
+  if (B == 0) return QS_OK;
+  if (!psi || !chi || !fid || (dfid && (!lam_psi || !lam_chi))) return QS_ERR_INVALID;
   return launch_fidelity(dtype, n, n_trash, B, psi, chi, fid, dfid, lam_psi,
                          lam_chi, stream);
 }
@@ -1295,6 +1363,35 @@ int qs_plan_info_get(const qs_circuit* c, int dtype, int64_t B, int flags,
   out->lds_bytes = shape.lds_bytes;
   (void)B;
   return QS_OK;
+}
+
+int qs_hbm_info_get(const qs_circuit* c, int dtype, int64_t B, int flags,
+                    const int32_t* ckpt_gates, int32_t n_ckpt, qs_hbm_info* out) {
+  InvCircuit inv_;
+  c = apply_inverse(c, &flags, inv_);
+  int rc = validate(c);
+  if (rc != QS_OK) return rc;
+  if (!out || (dtype != QS_C64 && dtype != QS_C128) || B < 0) return QS_ERR_INVALID;
+  static const char dummy = 0;  // check_ckpt wants a buffer; none is touched here
+  if ((rc = check_ckpt(c, ckpt_gates, n_ckpt, &dummy)) != QS_OK) return rc;
+  const bool ps = (flags & QS_FLAG_PER_SAMPLE_PARAMS) != 0;
+  TuneVal tv;
+  const bool tuned = tuned_lookup(*c, dtype, B, flags, &tv);
+  SvShape shape;
+  const int path = pick_path(*c, dtype, flags, &shape, count_slots(*c, ps), true,
+                             tuned ? &tv : nullptr, ckpt_gates, n_ckpt);
+  if (path < 0) return path;
+  if (path != QS_PATH_HBM) return QS_ERR_UNSUPPORTED;
+  std::memset(out, 0, sizeof(*out));
+  out->path = path;
+  const TileCfg tc = tile_cfg(tuned, tv);
+  TiledHostInfo h = tiled_host_info(*c, dtype, B, ps, tc, ckpt_gates, n_ckpt);
+  if (!h.ok) return QS_ERR_UNSUPPORTED;
+  out->n_passes = h.n_epochs;
+  out->tile_qubits = h.m;
+  out->max_partial_bytes = h.max_part_plan * (dtype == QS_C64 ? 4 : 8);
+  out->ws_bytes = (int64_t)tiled_ws_bytes(*c, dtype, B, ps, tc, &rc);
+  return rc;
 }
 
 int qs_plan_export(const qs_circuit* c, int dtype, int64_t B, int flags,

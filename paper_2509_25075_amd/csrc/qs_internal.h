@@ -284,6 +284,19 @@ struct PlainLaunch {
   void* stream;
 };
 size_t plain_workspace_bytes(const qs_circuit& c, int dtype, int64_t B);
+
+// The stream of the launch-side call running on this thread, set for the
+// call's duration by its entry point (nested calls restore the outer one).
+// Plan caches upload with synchronous allocations and copies, which a stream
+// capture does not allow: on a cache miss they first ask whether that stream
+// is capturing and, if so, return QS_ERR_CAPTURE instead of breaking it.
+struct CallStream {
+  explicit CallStream(void* stream);
+  ~CallStream();
+  void* prev;
+  bool prev_in_call;
+};
+bool call_stream_capturing();
 int run_plain_forward(const PlainLaunch& L);
 int run_plain_adjoint(const PlainLaunch& L);
 

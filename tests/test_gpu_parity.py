@@ -542,6 +542,50 @@ def test_zero_norm_rows_are_counted_and_nan():
     assert torch.isfinite(st[[0, 1, 3]].real).all()
 
 
+def test_encode_check_reports_zero_norm_rows():
+    """The counter of zero-norm rows becomes a host-visible status."""
+    bad = torch.zeros(1, dtype=torch.int32, device="cuda")
+    st = torch.empty(3, 8, dtype=torch.complex64, device="cuda")
+    x = torch.randn(3, 8, device="cuda")
+    N.qs_encode(N.QS_ENC_AMPLITUDE, N.QS_C64, 3, x, st, bad)
+    N.qs_encode_check(bad)  # no zero row: no error
+    x[1] = 0
+    N.qs_encode(N.QS_ENC_AMPLITUDE, N.QS_C64, 3, x, st, bad)
+    with pytest.raises(N.QsError) as e:
+        N.qs_encode_check(bad)
+    assert e.value.status == N.QS_ERR_ZERO_NORM
+    assert int(bad.item()) == 1
+
+
+@pytest.mark.parametrize("path", ["fused", "hbm"])
+def test_first_call_inside_a_capture_returns_a_status_and_keeps_the_capture(path):
+    """A shape with no plan yet inside a stream capture: the call returns
+    QS_ERR_CAPTURE without enqueueing anything, the capture ends normally and
+    its graph replays; outside the capture the same call plans and runs."""
+    n = 7 if path == "fused" else 15
+    c = C.hea_ry_rz_ring(n, 3)
+    # a parameter layout no other test uses, so this shape is not planned yet
+    c.gates["scale"] = np.where(np.isin(c.gates["op"], list(C.ROTATIONS)), 0.731, 1.0)
+    s = sim.Simulator(c, "c64", 0 if path == "fused" else PATHS["hbm"])
+    p = torch.full((c.n_params,), 0.3, device="cuda")
+    st = s.zero_state(2)
+    out = torch.zeros(2, n, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        with pytest.raises(N.QsError) as e:
+            N.qs_forward(s.h, s.qs_dtype, p, None, st, out)
+        out.add_(1.0)
+    assert e.value.status == N.QS_ERR_CAPTURE
+    g.replay()
+    torch.cuda.synchronize()
+    assert torch.all(out == 1.0)
+    z = s.forward(p, None, st)  # plans outside the capture
+    torch.cuda.synchronize()
+    ref = O.expz(O.run_circuit(c, np.full(c.n_params, 0.3), None, O.encode_zero(2, n)))
+    np.testing.assert_allclose(z.cpu().numpy(), ref, atol=1e-5)
+
+
 def test_zero_batch_is_a_no_op():
     c = C.hea_ry_rz_ring(4, 1)
     for path in (1, 2):
@@ -732,6 +776,86 @@ def test_tiled_checkpoints(tile_qubits):
     gth, _ = O.adjoint_vjp(c, w.params, None, psi0, dexpz=dz.cpu().numpy())
     np.testing.assert_allclose(gp.cpu().numpy(),
                                O.theta_to_param_grads(c, w.params, None, gth)[0], atol=1e-4)
+
+
+def test_26q_structure_at_18_qubits_with_checkpoints_and_weighted_loss():
+    """The 26-qubit workload's structure at a size the oracle carries: 18
+    qubits (five outer bits around the default 13-qubit tile), 20
+    hardware-efficient layers with ring CNOTs (CNOT folding across tile and
+    outer bits), checkpoints every 4 layers, loss sum_q g_q <Z_q> with its
+    gradient, one whole step on the automatic (tiled) path. Deep random
+    circuits have small gradients, so the gradient is also held to a
+    relative-norm bound."""
+    n = 18
+    _announce(f"26-qubit structure at n={n}, checkpoints every 4 layers")
+    c = C.hea_ry_rz_ring(n, 20)
+    w = Dt.Workload("hea ring n18 L20", n, 1, c, "c64", "zero", "weighted_z",
+                    params=Dt.uniform_params(c.n_params, 0),
+                    weights=Dt.upstream_weights(n, 0))
+    d = sim.to_device(w, ckpt_every_layers=4)
+    assert d.sim.plan_info(1)["path"] == N.QS_PATH_HBM
+    assert d.ckpt_gates == [c.layer_end[l - 1] for l in (4, 8, 12, 16)]
+    out = sim.step(d)
+    torch.cuda.synchronize()
+    p64 = w.params.astype(np.float64)
+    psi0 = O.encode_zero(1, n)
+    z = O.expz(O.run_circuit(c, p64, None, psi0))
+    L, dz = O.loss_and_dexpz("weighted_z", z, None, w.weights)
+    gth, _ = O.adjoint_vjp(c, p64, None, psi0, dexpz=dz)
+    gp = O.theta_to_param_grads(c, p64, None, gth)[0]
+    np.testing.assert_allclose(out["expz"].cpu().numpy(), z, atol=1e-5)
+    assert abs(out["loss"].item() - L) < 1e-5 * n
+    got = out["grad_params"].cpu().numpy()
+    np.testing.assert_allclose(got, gp, atol=1e-4)
+    assert np.linalg.norm(got - gp) <= 1e-3 * np.linalg.norm(gp)
+    for i, g in enumerate(d.ckpt_gates):  # the stored states themselves
+        ref = O.run_circuit(C.Circuit(n, c.gates[:g], c.n_params), p64, None, psi0)
+        np.testing.assert_allclose(d.ckpt[i].cpu().numpy(), ref, atol=1e-5)
+
+
+def test_tiled_checkpoints_that_widen_an_epochs_gradient_columns():
+    """Shared-parameter circuits whose checkpoints give some epoch more
+    gradient columns than any epoch of the plan without them: the workspace
+    qs_workspace_size reports holds them, and the gradients match the oracle."""
+    rng = np.random.default_rng(2024)
+    found = 0
+    for trial in range(200):
+        n = int(rng.integers(15, 18))
+        G = int(rng.integers(60, 240))
+        P = int(rng.integers(2, 12))
+        c = C.random_circuit(n, G, rng, n_params=P, n_features=0)
+        B = int(rng.choice([1, 8, 32]))
+        ck = sorted(set(int(v) for v in rng.integers(1, G, size=int(rng.integers(1, 5)))))
+        if n > 16 or B < 8:
+            continue
+        h = N.CircuitHandle(c)
+        a = N.qs_hbm_info_get(h, N.QS_C64, B, N.QS_PATH_HBM, ck)
+        b = N.qs_hbm_info_get(h, N.QS_C64, B, N.QS_PATH_HBM)
+        if a["max_partial_bytes"] <= b["max_partial_bytes"]:
+            continue
+        _announce(f"widened epoch: n={n} G={G} P={P} B={B} ckpt={ck}")
+        s = sim.Simulator(c, "c64", PATHS["hbm"])
+        x = rng.standard_normal((B, 1 << n)).astype(np.float32)
+        st = s.encode_amplitude(_dev(x, torch.float32))
+        buf = torch.empty((len(ck),) + tuple(st.shape), dtype=st.dtype, device="cuda")
+        params = rng.uniform(-np.pi, np.pi, P).astype(np.float32)
+        pt = _dev(params, torch.float32)
+        s.forward(pt, None, st, ckpt_gates=ck, ckpt=buf)
+        dz = rng.uniform(-1, 1, (B, n))
+        ws = s.workspace(B)
+        assert ws.numel() >= 2 * (B << n) * 8 + a["max_partial_bytes"]
+        gp, _ = s.adjoint(pt, None, st, dexpz=_dev(dz, torch.float64), ws=ws,
+                          ckpt_gates=ck, ckpt=buf)
+        torch.cuda.synchronize()
+        psi0 = O.encode_amplitude(x, n)
+        gth, _ = O.adjoint_vjp(c, params, None, psi0, dexpz=dz)
+        np.testing.assert_allclose(gp.cpu().numpy(),
+                                   O.theta_to_param_grads(c, params, None, gth)[0],
+                                   atol=1e-4)
+        found += 1
+        if found == 2:
+            break
+    assert found >= 1
 
 
 def _product_circuit(n, layers, rng):

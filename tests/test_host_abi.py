@@ -62,13 +62,23 @@ def test_fidelity_calls_validate_before_touching_the_gpu():
     assert L.qs_fidelity_postselect(N.QS_C64, 4, 1, 2, *nul) == N.QS_ERR_INVALID
     assert L.qs_fidelity_trajectory(N.QS_C64, 4, 1, 2, *nul, None, None) == N.QS_ERR_INVALID
     # B = 0: nothing to do, no buffers needed
+    assert L.qs_fidelity_reset(N.QS_C64, 4, 1, 2, *nul) == N.QS_ERR_INVALID
+    assert L.qs_fidelity_reset(N.QS_C64, 4, 1, 1 << 31, *nul) == N.QS_ERR_INVALID  # B bound
+    assert L.qs_fidelity_postselect(N.QS_C64, 4, 1, 1 << 31, *nul) == N.QS_ERR_INVALID
+    # B = 0: nothing to do, no buffers needed
     assert L.qs_fidelity_postselect(N.QS_C64, 4, 1, 0, *nul) == N.QS_OK
     assert L.qs_fidelity_trajectory(N.QS_C128, 4, 2, 0, *nul, None, None) == N.QS_OK
+    assert L.qs_fidelity_reset(N.QS_C64, 4, 1, 0, *nul) == N.QS_OK
 
 
 def test_status_strings():
-    for s in [0, -1, -2, -3, -4, -5, -6, 7]:
+    for s in [0, -1, -2, -3, -4, -5, -6, -7, 7]:
         assert isinstance(N.status_string(s), str) and N.status_string(s)
+    assert "capture" in N.status_string(N.QS_ERR_CAPTURE)
+    assert N.status_string(-7) != N.status_string(7)
+    txt = open(HEADER).read()
+    assert int(re.search(r"QS_ERR_CAPTURE\s*=\s*(-\d+)", txt).group(1)) == N.QS_ERR_CAPTURE
+    assert N.lib().qs_encode_check(None, None) == N.QS_ERR_INVALID
 
 
 def _circ(n, rows, n_params=4, n_features=2):
@@ -211,6 +221,61 @@ def test_large_circuits_take_the_tiled_path():
     assert N.qs_plan_info_get(h14, N.QS_C64, 4)["path"] == N.QS_PATH_FUSED
     info = N.qs_plan_info_get(h14, N.QS_C128, 4)
     assert info["path"] == N.QS_PATH_HBM and info["log2_threads"] == 12
+
+
+@pytest.mark.parametrize("dtype", [N.QS_C64, N.QS_C128])
+def test_tiled_workspace_covers_checkpointed_plans(dtype):
+    """Checkpoints move the large-state path's epoch boundaries, so an epoch
+    can read more shared-parameter gradient columns than any epoch of the
+    plan without them; the workspace qs_workspace_size reports (the same for
+    every checkpoint set) must hold the partial sums of every epoch of every
+    such plan."""
+    rng = np.random.default_rng(2024)
+    checked = grew = 0
+    for trial in range(60):
+        n = int(rng.integers(15, 18))
+        G = int(rng.integers(60, 240))
+        P = int(rng.integers(2, 12))  # few parameters, shared by many rotations
+        c = C.random_circuit(n, G, rng, n_params=P, n_features=0)
+        h = N.CircuitHandle(c)
+        B = int(rng.choice([1, 8, 32]))
+        k = int(rng.integers(1, 5))
+        ck = sorted(set(int(v) for v in rng.integers(1, G, size=k)))
+        try:
+            info = N.qs_hbm_info_get(h, dtype, B, N.QS_PATH_HBM, ck)
+        except N.QsError as e:
+            assert e.status == N.QS_ERR_UNSUPPORTED
+            continue
+        base = N.qs_hbm_info_get(h, dtype, B, N.QS_PATH_HBM)
+        ws = N.qs_workspace_size(h, dtype, B, N.QS_PATH_HBM)
+        assert ws == info["ws_bytes"] == base["ws_bytes"]
+        states = 2 * (B << n) * (8 if dtype == N.QS_C64 else 16)
+        assert ws >= states + info["max_partial_bytes"], (trial, ck)
+        assert ws >= states + base["max_partial_bytes"]
+        assert info["n_passes"] >= base["n_passes"] - len(ck)
+        grew += info["max_partial_bytes"] > base["max_partial_bytes"]
+        checked += 1
+    assert checked >= 40
+    assert grew >= 1  # some checkpointed plans need more than the plain plan
+
+
+def test_hbm_info_counts_the_epochs_the_checkpointed_plan_runs():
+    w = Dt.make_workload("c5b")
+    h = N.CircuitHandle(w.circuit)
+    L = 78  # gates per hardware-efficient layer on 26 qubits
+    ck = [4 * L * i for i in range(1, 5)]
+    a = N.qs_hbm_info_get(h, N.QS_C64, 1)
+    b = N.qs_hbm_info_get(h, N.QS_C64, 1, 0, ck)
+    assert a["path"] == b["path"] == N.QS_PATH_HBM and a["tile_qubits"] == 13
+    assert a["n_passes"] == N.qs_plan_info_get(h, N.QS_C64, 1)["n_segments"]
+    # a checkpoint closes the epoch it falls in: never fewer epochs
+    assert b["n_passes"] >= a["n_passes"]
+    with pytest.raises(N.QsError) as e:  # not increasing
+        N.qs_hbm_info_get(h, N.QS_C64, 1, 0, [10, 5])
+    assert e.value.status == N.QS_ERR_INVALID
+    with pytest.raises(N.QsError) as e:  # the fused path is not a large-state path
+        N.qs_hbm_info_get(N.CircuitHandle(C.hea_ry_rz_ring(10, 2)), N.QS_C64, 4)
+    assert e.value.status == N.QS_ERR_UNSUPPORTED
 
 
 def test_inverse_flag_plans_the_reversed_negated_list():

@@ -501,6 +501,43 @@ def test_mse_loss_gradient_matches_fd(rng):
     np.testing.assert_allclose(dp, O.finite_difference(loss, params.copy()), atol=1e-8)
 
 
+def test_weighted_z_loss_hand_value_and_gradient():
+    """The readout loss of the uneven batch and of the 26-qubit circuit is the
+    plain sum L = sum_b sum_q g_q <Z_q>_b (not a mean): two samples, two
+    qubits, worked by hand: (2 * 0.5 - 4 * -0.25) + (2 * 1.0 - 4 * 0.0) = 4."""
+    z = np.array([[0.5, -0.25], [1.0, 0.0]])
+    g = np.array([2.0, -4.0])
+    L, d = O.loss_and_dexpz("weighted_z", z, None, g)
+    assert L == 4.0
+    np.testing.assert_array_equal(d, [[2.0, -4.0], [2.0, -4.0]])
+    # dL/dz against central differences of the returned loss
+    fd = O.finite_difference(lambda v: O.loss_and_dexpz("weighted_z", v, None, g)[0],
+                             z.copy())
+    np.testing.assert_allclose(d, fd, atol=1e-9)
+
+
+def test_weighted_z_gradient_through_the_26_qubit_structure_matches_fd(rng):
+    """The 26-qubit workload's structure (RY, RZ on every qubit + ring CNOT)
+    at 5 qubits with its weighted readout loss: adjoint = parameter shift =
+    central differences of the loss."""
+    c = C.hea_ry_rz_ring(5, 3)
+    params = rng.uniform(-np.pi, np.pi, c.n_params)
+    g = rng.uniform(-1, 1, 5)
+    psi0 = O.encode_zero(2, 5)
+
+    def loss(p):
+        return O.loss_and_dexpz("weighted_z", O.expz(O.run_circuit(c, p, None, psi0)),
+                                None, g)[0]
+
+    z = O.expz(O.run_circuit(c, params, None, psi0))
+    _, dz = O.loss_and_dexpz("weighted_z", z, None, g)
+    gth, _ = O.adjoint_vjp(c, params, None, psi0, dexpz=dz)
+    dp, _ = O.theta_to_param_grads(c, params, None, gth)
+    np.testing.assert_allclose(dp, O.finite_difference(loss, params.copy()), atol=1e-8)
+    J = O.param_shift_theta_jacobian(c, params, None, psi0, O.expz)
+    np.testing.assert_allclose(gth, np.einsum("bgk,k->bg", J, g), atol=1e-12)
+
+
 def test_fidelity_gradients_adjoint_shift_fd(rng):
     n, t, B = 4, 2, 2
     enc = C.ry_rz_chain(n, 2)
