@@ -51,10 +51,12 @@ typedef enum qs_status {
   QS_ERR_ZERO_NORM = -4,   /* amplitude input row with norm 0               */
   QS_ERR_LAUNCH = -5,      /* a HIP runtime call or kernel launch failed    */
   QS_ERR_NOMEM = -6,       /* the plan cache could not allocate             */
-  QS_ERR_CAPTURE = -7      /* a new plan would have to be uploaded while the
+  QS_ERR_CAPTURE = -7,     /* a new plan would have to be uploaded while the
                               call's stream is being captured into a graph:
                               nothing was enqueued and the capture stays
                               valid; run the call once before capturing     */
+  QS_ERR_NOT_PLANNED = -8  /* a call that may not allocate met a shape with
+                              no cached plan; nothing was enqueued          */
 } qs_status;
 
 /* ------------------------------------------------------------- descriptor */
@@ -191,6 +193,31 @@ int qs_adjoint_backward(const qs_circuit* circuit, int dtype, int64_t B,
                         double* grad_feats, const int32_t* ckpt_gates,
                         int32_t n_ckpt, const void* ckpt, void* ws,
                         size_t ws_bytes, int flags, void* stream);
+
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): qs_adjoint_backward
+ * without a workspace argument. The per-block gradient partial sums go to a
+ * library-owned device array of QS_NOALLOC_SCRATCH_BYTES per GPU (a static
+ * device global, held until the process ends); the call allocates nothing.
+ * Same arguments, results and errors as qs_adjoint_backward, plus:
+ *   - only the register/LDS engine path runs (QS_PATH_AUTO choosing it, or
+ *     QS_PATH_FUSED); another path gives QS_ERR_UNSUPPORTED;
+ *   - the partial sums of this shape must fit QS_NOALLOC_SCRATCH_BYTES
+ *     (qs_workspace_size() <= that), else QS_ERR_WORKSPACE;
+ *   - the shape's plan must already be cached by an earlier allocating call
+ *     (qs_adjoint_backward with the same circuit, dtype, flags and
+ *     checkpoints), else QS_ERR_NOT_PLANNED; the autotuner never runs.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (different streams, or host threads) race on it and must not be
+ * issued. Calls ordered on one stream are safe. */
+#define QS_NOALLOC_SCRATCH_BYTES (32u << 20)
+int qs_adjoint_backward_noalloc(const qs_circuit* circuit, int dtype, int64_t B,
+                                const void* params, const void* feats,
+                                const void* state, const double* dexpz,
+                                const void* dstate, double* grad_params,
+                                double* grad_feats, const int32_t* ckpt_gates,
+                                int32_t n_ckpt, const void* ckpt, int flags,
+                                void* stream);
 
 /* Readout alone: expz[b][q] = <Z_q>_b of state [B][2^n], FP64 sums. */
 int qs_expz(int dtype, int n_qubits, int64_t B, const void* state,

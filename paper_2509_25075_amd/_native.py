@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libqs.so")
 # status codes / enums (mirrors include/qs.h)
 QS_OK, QS_ERR_INVALID, QS_ERR_UNSUPPORTED = 0, -1, -2
 QS_ERR_WORKSPACE, QS_ERR_ZERO_NORM, QS_ERR_LAUNCH, QS_ERR_NOMEM = -3, -4, -5, -6
-QS_ERR_CAPTURE = -7
+QS_ERR_CAPTURE, QS_ERR_NOT_PLANNED = -7, -8
+QS_NOALLOC_SCRATCH_BYTES = 32 << 20
 QS_C64, QS_C128 = 0, 1
 QS_ENC_AMPLITUDE, QS_ENC_ZERO = 0, 1
 QS_PATH_AUTO, QS_PATH_FUSED, QS_PATH_PLAIN, QS_PATH_HBM = 0, 1, 2, 3
@@ -118,6 +119,9 @@ def lib() -> ctypes.CDLL:
         "qs_adjoint_backward": (ctypes.c_int, [cp, ctypes.c_int, i64, vp, vp, vp,
                                                vp, vp, vp, vp, i32p, i32, vp, vp,
                                                sz, ctypes.c_int, vp]),
+        "qs_adjoint_backward_noalloc": (ctypes.c_int, [cp, ctypes.c_int, i64, vp, vp, vp,
+                                                       vp, vp, vp, vp, i32p, i32, vp,
+                                                       ctypes.c_int, vp]),
         "qs_expz": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, i64, vp, vp, vp]),
         "qs_fidelity_reset": (ctypes.c_int, [ctypes.c_int, ctypes.c_int,
                                              ctypes.c_int, i64, vp, vp, vp, vp,
@@ -259,6 +263,20 @@ def qs_adjoint_backward(h: CircuitHandle, dtype: int, params, feats, state,
         _ptr(dexpz), _ptr(dstate), _ptr(grad_params), _ptr(grad_feats), arr,
         n_ck, _ptr(ckpt), _ptr(ws), ws_bytes, flags, _stream(stream)),
         "qs_adjoint_backward")
+    del keep
+
+
+def qs_adjoint_backward_noalloc(h: CircuitHandle, dtype: int, params, feats, state,
+                                dexpz=None, dstate=None, grad_params=None,
+                                grad_feats=None, ckpt_gates=None, ckpt=None,
+                                flags: int = 0, stream=None):
+    """qs_adjoint_backward with the library's own device scratch array in
+    place of a workspace (no device allocation; the shape must be planned)."""
+    arr, n_ck, keep = _ckpt_arr(ckpt_gates)
+    _check(lib().qs_adjoint_backward_noalloc(
+        h.ptr, dtype, state.shape[0], _ptr(params), _ptr(feats), _ptr(state),
+        _ptr(dexpz), _ptr(dstate), _ptr(grad_params), _ptr(grad_feats), arr,
+        n_ck, _ptr(ckpt), flags, _stream(stream)), "qs_adjoint_backward_noalloc")
     del keep
 
 

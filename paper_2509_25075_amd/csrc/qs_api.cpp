@@ -7,12 +7,14 @@
 #include <functional>
 #include <cstring>
 #include <mutex>
+#include <optional>
 #include <unordered_map>
 
 #include "qs_internal.h"
 
 namespace qs {
 int sv_max_threads(int dtype, int r, int adjoint);
+bool no_alloc_call();
 
 namespace {
 thread_local void* t_call_stream = nullptr;
@@ -27,6 +29,20 @@ CallStream::~CallStream() {
   t_call_stream = prev;
   t_in_call = prev_in_call;
 }
+
+namespace {
+thread_local bool t_no_alloc = false;
+}  // namespace
+
+NoAllocCall::NoAllocCall() : prev(t_no_alloc) { t_no_alloc = true; }
+NoAllocCall::~NoAllocCall() { t_no_alloc = prev; }
+
+int plan_upload_status() {
+  if (t_no_alloc) return QS_ERR_NOT_PLANNED;
+  return call_stream_capturing() ? QS_ERR_CAPTURE : QS_OK;
+}
+
+bool no_alloc_call() { return t_no_alloc; }
 
 bool call_stream_capturing() {
   if (!t_in_call) return false;
@@ -352,8 +368,8 @@ Entry* get_plan(const qs_circuit& c, int r, bool ps, const int32_t* ck, int n_ck
   std::lock_guard<std::mutex> lock(g_mu);
   auto it = g_cache.find(key);
   if (it != g_cache.end()) return it->second;
-  if (call_stream_capturing()) {
-    *rc = QS_ERR_CAPTURE;
+  if (const int up = plan_upload_status(); up != QS_OK) {
+    *rc = up;
     return nullptr;
   }
   Entry* e = new Entry();
@@ -439,8 +455,8 @@ qs_gate* get_dev_gates(const qs_circuit& c, int* rc) {
   std::lock_guard<std::mutex> lock(g_mu);
   auto it = g_gate_cache.find(key);
   if (it != g_gate_cache.end()) return it->second;
-  if (call_stream_capturing()) {
-    *rc = QS_ERR_CAPTURE;
+  if (const int up = plan_upload_status(); up != QS_OK) {
+    *rc = up;
     return nullptr;
   }
   qs_gate* d = nullptr;
@@ -510,8 +526,8 @@ TiledEntry* get_tiled(const qs_circuit& c, int dtype, bool ps, const int32_t* ck
     auto it = g_tiled.find(key);
     if (it != g_tiled.end()) return it->second;
   }
-  if (call_stream_capturing()) {
-    *rc = QS_ERR_CAPTURE;
+  if (const int up = plan_upload_status(); up != QS_OK) {
+    *rc = up;
     return nullptr;
   }
   const int low_keep = m >= 6 ? 4 : (m >= 4 ? m - 2 : 0);
@@ -779,7 +795,7 @@ bool tuned_for_call(const qs_circuit& c, int dtype, int64_t B, int flags, void* 
                     TuneVal* out) {
   if (g_in_tune) return false;
   if (tuned_lookup(c, dtype, B, flags, out)) return true;
-  if (env_int("QS_AUTOTUNE", 0) != 1) return false;
+  if (env_int("QS_AUTOTUNE", 0) != 1 || no_alloc_call()) return false;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(static_cast<hipStream_t>(stream), &cs) == hipSuccess &&
       cs != hipStreamCaptureStatusNone)
@@ -981,6 +997,9 @@ const char* qs_status_string(int s) {
     case QS_ERR_CAPTURE:
       return "this shape has no plan yet and its upload is not allowed inside a stream "
              "capture: run the call once before capturing";
+    case QS_ERR_NOT_PLANNED:
+      return "this shape has no plan yet and the call may not allocate one: run the "
+             "allocating call once first";
     default: return "unknown status";
   }
 }
@@ -1127,7 +1146,23 @@ int qs_adjoint_backward(const qs_circuit* c, int dtype, int64_t B,
                         const int32_t* ckpt_gates, int32_t n_ckpt,
                         const void* ckpt, void* ws, size_t ws_bytes, int flags,
                         void* stream) {
+  return adjoint_backward_impl(c, dtype, B, params, feats, state, dexpz, dstate, grad_params,
+                               grad_feats, ckpt_gates, n_ckpt, ckpt, ws, ws_bytes, flags,
+                               stream, false);
+}
+
+}  // extern "C"
+
+namespace qs {
+int adjoint_backward_impl(const qs_circuit* c, int dtype, int64_t B, const void* params,
+                          const void* feats, const void* state, const double* dexpz,
+                          const void* dstate, double* grad_params, double* grad_feats,
+                          const int32_t* ckpt_gates, int32_t n_ckpt, const void* ckpt,
+                          void* ws, size_t ws_bytes, int flags, void* stream,
+                          bool no_alloc) {
   CallStream call_(stream);
+  std::optional<NoAllocCall> na_;
+  if (no_alloc) na_.emplace();
   InvCircuit inv_;
   c = apply_inverse(c, &flags, inv_);
   int rc = validate(c);
@@ -1151,6 +1186,7 @@ int qs_adjoint_backward(const qs_circuit* c, int dtype, int64_t B,
   const int path = pick_path(*c, dtype, flags, &shape, count_slots(*c, ps), true,
                              tuned ? &tv : nullptr, ckpt_gates, n_ckpt);
   if (path < 0) return path;
+  if (no_alloc && path != QS_PATH_FUSED) return QS_ERR_UNSUPPORTED;
   const TileCfg tcfg = tile_cfg(tuned, tv);
   const size_t need = path == QS_PATH_PLAIN ? plain_workspace_bytes(*c, dtype, B)
                      : path == QS_PATH_HBM ? tiled_ws_bytes(*c, dtype, B, ps, tcfg, &rc)
@@ -1275,6 +1311,10 @@ int qs_adjoint_backward(const qs_circuit* c, int dtype, int64_t B,
   }
   return rc;
 }
+
+}  // namespace qs
+
+extern "C" {
 
 int qs_expz(int dtype, int n, int64_t B, const void* state, double* expz,
             void* stream) {

@@ -297,6 +297,29 @@ struct CallStream {
   bool prev_in_call;
 };
 bool call_stream_capturing();
+
+// Set for the duration of a call that must not allocate device memory: plan
+// caches then refuse a miss with QS_ERR_NOT_PLANNED, and the autotuner does
+// not run.
+struct NoAllocCall {
+  NoAllocCall();
+  ~NoAllocCall();
+  bool prev;
+};
+// QS_OK when a plan cache may upload a new plan now; otherwise the status to
+// return (QS_ERR_NOT_PLANNED in a no-allocation call, QS_ERR_CAPTURE while
+// the call's stream is being captured).
+int plan_upload_status();
+
+// The body of qs_adjoint_backward. With no_alloc, only the register/LDS
+// engine path runs (its workspace is the caller's `ws`), plans must already
+// be cached, and nothing allocates.
+int adjoint_backward_impl(const qs_circuit* c, int dtype, int64_t B, const void* params,
+                          const void* feats, const void* state, const double* dexpz,
+                          const void* dstate, double* grad_params, double* grad_feats,
+                          const int32_t* ckpt_gates, int32_t n_ckpt, const void* ckpt,
+                          void* ws, size_t ws_bytes, int flags, void* stream,
+                          bool no_alloc);
 int run_plain_forward(const PlainLaunch& L);
 int run_plain_adjoint(const PlainLaunch& L);
 

@@ -72,7 +72,7 @@ def test_fidelity_calls_validate_before_touching_the_gpu():
 
 
 def test_status_strings():
-    for s in [0, -1, -2, -3, -4, -5, -6, -7, 7]:
+    for s in [0, -1, -2, -3, -4, -5, -6, -7, -8, 7]:
         assert isinstance(N.status_string(s), str) and N.status_string(s)
     assert "capture" in N.status_string(N.QS_ERR_CAPTURE)
     assert N.status_string(-7) != N.status_string(7)
