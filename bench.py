@@ -350,9 +350,15 @@ def main():
         elif path == "tiled_hbm":
             # Each epoch's adjoint launch reads psi and lam and writes them
             # back (4 complex amplitudes of 8 or 16 B); the timed call runs
-            # all epochs.
-            n_ep = d.sim.plan_info(w.batch)["n_segments"]
-            bytes_call = n_ep * 4 * (8 if w.dtype == "c64" else 16) * amps
+            # all epochs of the plan with the step's checkpoints, plus its own
+            # state copies: psi_G into the workspace (read + write), lam
+            # formed from it (read + write) and one re-anchoring copy per
+            # checkpoint (read + write).
+            hi = N.qs_hbm_info_get(d.sim.h, d.sim.qs_dtype, w.batch, 0, d.ckpt_gates)
+            n_ep = hi["n_passes"]
+            cs = 8 if w.dtype == "c64" else 16
+            n_ck = len(d.ckpt_gates or [])
+            bytes_call = (n_ep * 4 + 4 + 2 * n_ck) * cs * amps
             roof = {"bound": "hbm", "achieved": bytes_call / (adj_ms * 1e-3) / 1e9,
                     "peak": PEAK_HBM_GBPS, "unit": "GB/s", "traffic": None,
                     "kernel": "sv_adjoint (tiled epochs)", "kernel_ms": adj_ms,
