@@ -325,18 +325,20 @@ def main():
                 if c is None:
                     continue
                 s0 = sim.Simulator(c, w.dtype)
-                if s0.plan_info(w.batch)["path"] not in (N.QS_PATH_FUSED, N.QS_PATH_HBM):
+                if s0.plan_info(w.batch)["path"] not in (N.QS_PATH_FUSED, N.QS_PATH_HBM,
+                                                         N.QS_PATH_MFMA):
                     continue
                 t = N.qs_autotune(s0.h, s0.qs_dtype, w.batch, 0)
-                tuned[name] = {k: t[k] for k in ("fwd_log2_regs", "adj_log2_regs",
+                tuned[name] = {k: t[k] for k in ("path", "fwd_log2_regs", "adj_log2_regs",
                                                  "tile_qubits", "fwd_samples_cap",
                                                  "adj_samples_cap", "fwd_half_staging",
-                                                 "adj_half_staging")}
+                                                 "adj_half_staging", "fwd_ms", "adj_ms")}
             torch.cuda.synchronize()
         ck = 4 if key == "c5b" else 0
         # automatic path: register/LDS engine when it fits, else tiled HBM
         d = sim.to_device(w, flags=0, ckpt_every_layers=ck, traj_u=traj_u)
-        path = {1: "fused", 2: "plain", 3: "tiled_hbm"}[d.sim.plan_info(w.batch)["path"]]
+        path = {1: "fused", 2: "plain", 3: "tiled_hbm", 4: "mfma_blocks"}[
+            d.sim.plan_info(w.batch)["path"]]
         updates = w.updates_per_step()
         sim.Simulator.adjoint = timer.wrap(sim.Simulator.adjoint)
         ms, wall = timed_loop(torch, stream, lambda: sim.step(d), args.steps,
@@ -363,6 +365,23 @@ def main():
                     "peak": PEAK_HBM_GBPS, "unit": "GB/s", "traffic": None,
                     "kernel": "sv_adjoint (tiled epochs)", "kernel_ms": adj_ms,
                     "launches_per_step": n_ep, "algorithmic_bytes_per_call": bytes_call}
+        elif path == "mfma_blocks":
+            # Each block's adjoint pass reads psi and lam and writes them back
+            # (32 B per complex64 amplitude) and does 768 MFMA flops per
+            # amplitude: M^dagger applied to psi and to lam (256 each, the real
+            # embedding of a 32 x 32 complex matrix) and rho = sum psi lam^dagger
+            # (256); plus the call's state copies as on the tiled path.
+            hi = N.qs_hbm_info_get(d.sim.h, d.sim.qs_dtype, w.batch, 0, d.ckpt_gates)
+            n_bl = hi["n_passes"]
+            n_ck = len(d.ckpt_gates or [])
+            bytes_call = (n_bl * 4 + 4 + 2 * n_ck) * 8 * amps
+            mfma_flops = n_bl * 768 * amps
+            roof = {"bound": "hbm", "achieved": bytes_call / (adj_ms * 1e-3) / 1e9,
+                    "peak": PEAK_HBM_GBPS, "unit": "GB/s", "traffic": None,
+                    "kernel": "db_adjoint (dense 5-qubit blocks on MFMA)", "kernel_ms": adj_ms,
+                    "launches_per_step": n_bl, "algorithmic_bytes_per_call": bytes_call,
+                    "mfma_tflops": mfma_flops / (adj_ms * 1e-3) / 1e12,
+                    "mfma_frac": mfma_flops / (adj_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
         else:
             flops_adj = FLOPS_ROT_ADJ * rot * amps
             roof = {"bound": "alu", "achieved": flops_adj / (adj_ms * 1e-3) / 1e12,

@@ -113,6 +113,11 @@ enum {
   QS_PATH_PLAIN = 2,  /* one kernel launch per gate, state in HBM            */
   QS_PATH_HBM = 3,    /* state in HBM, run as epochs of gathered m-qubit
                          tiles through the register/LDS engine (n > 14)     */
+  QS_PATH_MFMA = 4,   /* state in HBM, gates fused into dense 5-qubit blocks,
+                         each applied in one pass as a complex matrix product
+                         on MFMA (complex64, angles shared by the batch,
+                         n >= 10); QS_PATH_AUTO takes it for large states
+                         when qs_autotune found it faster than QS_PATH_HBM */
   QS_PATH_MASK = 0xff,
   QS_FLAG_PER_SAMPLE_PARAMS = 0x100, /* params is [B][n_params]           */
   QS_FLAG_INVERSE = 0x200            /* run U^dagger instead of U          */
@@ -361,23 +366,39 @@ typedef struct qs_plan_info {
 int qs_plan_info_get(const qs_circuit* circuit, int dtype, int64_t B,
                      int flags, qs_plan_info* out);
 
-/* Host only: what the large-state path (QS_PATH_HBM) runs for this circuit
- * with these checkpoints (the same gate counts qs_forward and
+/* Host only: what a large-state path (QS_PATH_HBM or QS_PATH_MFMA) runs for
+ * this circuit with these checkpoints (the same gate counts qs_forward and
  * qs_adjoint_backward take; ckpt_gates may be NULL when n_ckpt == 0).
- * Returns QS_ERR_UNSUPPORTED when the circuit does not take that path. */
+ * Returns QS_ERR_UNSUPPORTED when the circuit takes neither path. */
 typedef struct qs_hbm_info {
-  int32_t path;              /* QS_PATH_HBM                                  */
-  int32_t n_passes;          /* epochs: kernel launches over the whole state
-                                per direction                                */
-  int32_t tile_qubits;       /* qubits held by one tile-sample (m)           */
+  int32_t path;              /* QS_PATH_HBM or QS_PATH_MFMA                  */
+  int32_t n_passes;          /* epochs (QS_PATH_HBM) or dense blocks
+                                (QS_PATH_MFMA): kernel launches over the
+                                whole state per direction                    */
+  int32_t tile_qubits;       /* qubits of a tile-sample (m), or of a block  */
   int32_t reserved;
   int64_t max_partial_bytes; /* largest gradient partial-sum area any adjoint
-                                epoch of this plan writes                    */
+                                pass of this plan writes                     */
   int64_t ws_bytes;          /* qs_workspace_size() for these flags: covers
                                 every checkpoint placement                   */
 } qs_hbm_info;
 int qs_hbm_info_get(const qs_circuit* circuit, int dtype, int64_t B, int flags,
                     const int32_t* ckpt_gates, int32_t n_ckpt, qs_hbm_info* out);
+
+/* Host only: the dense-block plan of QS_PATH_MFMA, for inspection and for
+ * checking the planner on the CPU. Call with NULL arrays to get *n_blocks;
+ * then, with arrays of these sizes, fills
+ *   blk_qubits [n_blocks][5] the block's qubits, ascending (local bit i of
+ *              the block's 32 x 32 matrix = qubit blk_qubits[b][i]),
+ *   blk_begin  [n_blocks + 1] ranges of blk_gates,
+ *   blk_gates  [n_gates] descriptor gate indices in the order each block
+ *              multiplies them (every gate exactly once),
+ *   blk_ckpt   [n_blocks] checkpoint slot stored after the block, or -1.
+ * Returns QS_ERR_UNSUPPORTED when the circuit cannot take QS_PATH_MFMA. */
+int qs_block_plan_export(const qs_circuit* circuit, int dtype, int flags,
+                         const int32_t* ckpt_gates, int32_t n_ckpt, int32_t* n_blocks,
+                         int32_t* blk_qubits, int32_t* blk_begin, int32_t* blk_gates,
+                         int32_t* blk_ckpt);
 
 /* Host only: export the fused engine's plan for inspection (tests, tools).
  * Fills `info` like qs_plan_info_get; then, when the arrays are non-NULL,

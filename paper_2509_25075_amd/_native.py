@@ -22,7 +22,7 @@ QS_ERR_CAPTURE, QS_ERR_NOT_PLANNED = -7, -8
 QS_NOALLOC_SCRATCH_BYTES = 32 << 20
 QS_C64, QS_C128 = 0, 1
 QS_ENC_AMPLITUDE, QS_ENC_ZERO = 0, 1
-QS_PATH_AUTO, QS_PATH_FUSED, QS_PATH_PLAIN, QS_PATH_HBM = 0, 1, 2, 3
+QS_PATH_AUTO, QS_PATH_FUSED, QS_PATH_PLAIN, QS_PATH_HBM, QS_PATH_MFMA = 0, 1, 2, 3, 4
 QS_FLAG_PER_SAMPLE_PARAMS = 0x100
 QS_FLAG_INVERSE = 0x200
 
@@ -136,6 +136,8 @@ def lib() -> ctypes.CDLL:
                                             ctypes.POINTER(QsPlanInfo)]),
         "qs_hbm_info_get": (ctypes.c_int, [cp, ctypes.c_int, i64, ctypes.c_int, i32p,
                                            i32, ctypes.POINTER(QsHbmInfo)]),
+        "qs_block_plan_export": (ctypes.c_int, [cp, ctypes.c_int, ctypes.c_int, i32p, i32,
+                                                i32p, vp, vp, vp, vp]),
         "qs_plan_export": (ctypes.c_int, [cp, ctypes.c_int, i64, ctypes.c_int,
                                           ctypes.POINTER(QsPlanInfo), vp, vp, vp]),
         "qs_program_layout": (ctypes.c_int, [ctypes.POINTER(QsProgram), vp, vp, vp, vp]),
@@ -318,6 +320,25 @@ def qs_hbm_info_get(h: CircuitHandle, dtype: int, B: int, flags: int = 0,
     _check(lib().qs_hbm_info_get(h.ptr, dtype, B, flags, arr, n, ctypes.byref(info)),
            "qs_hbm_info_get")
     return {k: getattr(info, k) for k, _ in QsHbmInfo._fields_}
+
+
+def qs_block_plan_export(h: CircuitHandle, dtype: int = QS_C64, flags: int = 0,
+                         ckpt_gates=None):
+    """The dense-block plan: (qubits [nb, 5], begin [nb + 1], gates [G],
+    ckpt [nb]) as int32 arrays."""
+    arr, n, _ = _ckpt_arr(ckpt_gates)
+    nb = ctypes.c_int32(0)
+    L = lib()
+    _check(L.qs_block_plan_export(h.ptr, dtype, flags, arr, n, ctypes.byref(nb),
+                                  None, None, None, None), "qs_block_plan_export")
+    q = np.zeros((nb.value, 5), np.int32)
+    b = np.zeros(nb.value + 1, np.int32)
+    g = np.zeros(max(h.n_gates, 1), np.int32)
+    k = np.zeros(nb.value, np.int32)
+    _check(L.qs_block_plan_export(h.ptr, dtype, flags, arr, n, ctypes.byref(nb),
+                                  q.ctypes.data, b.ctypes.data, g.ctypes.data,
+                                  k.ctypes.data), "qs_block_plan_export")
+    return q, b, g[:h.n_gates], k
 
 
 def qs_plan_info_get(h: CircuitHandle, dtype: int, B: int, flags: int = 0) -> dict:

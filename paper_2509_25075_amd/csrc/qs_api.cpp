@@ -110,6 +110,7 @@ struct TuneVal {
   int fwd_r = 0, adj_r = 0, m = 0;
   int fwd_s = 0, adj_s = 0;  // samples-per-block caps (0: the LDS-limited default)
   int fwd_h = 0, adj_h = 0;  // 1: stage one state component at a time in LDS
+  int large = 0;             // large states: 0 tiled engine, 1 dense blocks on MFMA
 };
 std::mutex g_tmu;
 std::mutex g_tune_run_mu;  // one tuning run at a time (overrides are global)
@@ -118,6 +119,7 @@ bool g_tune_loaded = false;
 int g_force_fwd_r = 0, g_force_adj_r = 0, g_force_m = 0;
 int g_force_fwd_s = 0, g_force_adj_s = 0;
 int g_force_fwd_h = -1, g_force_adj_h = -1;  // -1: not forced
+int g_force_large = -1;                       // -1: not forced
 thread_local bool g_in_tune = false;  // calls made by the tuner itself
 
 int batch_class(int64_t B) {
@@ -148,15 +150,16 @@ void load_tune_file_locked() {
   if (!path || !*path) return;
   FILE* f = std::fopen(path, "r");
   if (!f) return;
-  // One line per tuned key: key fwd_r adj_r m [fwd_s adj_s [fwd_h adj_h]].
+  // One line per tuned key: key fwd_r adj_r m [fwd_s adj_s [fwd_h adj_h [large]]].
   char line[256], key[64];
   while (std::fgets(line, sizeof(line), f)) {
     TuneVal v;
-    const int k = std::sscanf(line, "%63s %d %d %d %d %d %d %d", key, &v.fwd_r, &v.adj_r,
-                              &v.m, &v.fwd_s, &v.adj_s, &v.fwd_h, &v.adj_h);
-    if (k != 4 && k != 6 && k != 8) continue;
+    const int k = std::sscanf(line, "%63s %d %d %d %d %d %d %d %d", key, &v.fwd_r, &v.adj_r,
+                              &v.m, &v.fwd_s, &v.adj_s, &v.fwd_h, &v.adj_h, &v.large);
+    if (k != 4 && k != 6 && k != 8 && k != 9) continue;
     if (k < 6) v.fwd_s = v.adj_s = 0;
     if (k < 8) v.fwd_h = v.adj_h = 0;
+    if (k < 9) v.large = 0;
     g_tune[key] = v;
   }
   std::fclose(f);
@@ -586,6 +589,177 @@ TiledEntry* get_tiled(const qs_circuit& c, int dtype, bool ps, const int32_t* ck
   return te;
 }
 
+// -------------------------------------------------------- dense-block plans
+// Large states on MFMA: complex64, angles shared by the whole batch (no
+// per-sample parameters, no rotation reading a feature), 2^(n-5) >= 32
+// columns per state.
+constexpr int kDbK = 5;
+constexpr int kDbGrid = 512;  // persistent workgroups (two per CU of 256)
+
+bool db_supported(const qs_circuit& c, int dtype, bool ps) {
+  if (dtype != QS_C64 || ps || c.n_qubits < kDbK + 5) return false;
+  for (int g = 0; g < c.n_gates; ++g)
+    if (is_rotation(c.gates[g].op) && c.gates[g].feat >= 0) return false;
+  return true;
+}
+
+struct DbEntry {
+  std::vector<DenseBlock> blocks;
+  std::vector<int32_t> h_blk_q;  // [n_blocks][kDbGeoWords] block geometry
+  int32_t* blk_begin = nullptr;
+  DbGate* gates = nullptr;
+  int32_t* blk_q = nullptr;
+  int32_t* p_begin = nullptr;    // [n_params + 1] rotations reading each parameter
+  int32_t* p_gate = nullptr;
+  float* p_scale = nullptr;
+};
+std::unordered_map<Key, DbEntry*, KeyHash> g_db;
+
+void free_db(DbEntry* e) {
+  (void)hipFree(e->blk_begin);
+  (void)hipFree(e->gates);
+  (void)hipFree(e->blk_q);
+  (void)hipFree(e->p_begin);
+  (void)hipFree(e->p_gate);
+  (void)hipFree(e->p_scale);
+  delete e;
+}
+
+// The host side of a dense-block plan (no device memory): blocks, device
+// records, per-parameter rotation lists. False when the blocks do not cover
+// every gate once.
+bool db_host_plan(const qs_circuit& c, const int32_t* ck, int n_ck, DbEntry& e,
+                  std::vector<int32_t>& begin, std::vector<DbGate>& recs,
+                  std::vector<int32_t>& pb, std::vector<int32_t>& pg,
+                  std::vector<float>& psc) {
+  e.blocks = plan_blocks(c, kDbK, ck, n_ck);
+  std::vector<char> seen(c.n_gates, 0);
+  begin.assign(1, 0);
+  e.h_blk_q.clear();
+  for (const DenseBlock& b : e.blocks) {
+    if ((int)b.qubits.size() != kDbK) return false;
+    std::vector<int> local(c.n_qubits, -1);
+    for (int i = 0; i < kDbK; ++i) local[b.qubits[i]] = i;
+    for (int g : b.gates) {
+      if (g < 0 || g >= c.n_gates || seen[g]) return false;
+      seen[g] = 1;
+      const qs_gate& x = c.gates[g];
+      DbGate r{};
+      r.op = x.op;
+      r.q0 = local[x.q0];
+      r.q1 = x.q1 >= 0 ? local[x.q1] : -1;
+      if (r.q0 < 0 || (x.q1 >= 0 && r.q1 < 0)) return false;
+      r.p_w = x.p_w;
+      r.p_b = x.p_b;
+      r.scale = x.scale;
+      r.g = g;
+      recs.push_back(r);
+    }
+    begin.push_back((int32_t)recs.size());
+    // Geometry of the block's tiles (see DbGeo): the block qubits, the 10
+    // address bits of a 32-column tile (block qubits and the 5 lowest other
+    // positions, ascending) and the rank of each block and column bit there.
+    int32_t geo[kDbGeoWords] = {};
+    std::vector<int> pos(b.qubits.begin(), b.qubits.end()), low;
+    for (int q = 0; q < c.n_qubits && (int)low.size() < 5; ++q)
+      if (std::find(b.qubits.begin(), b.qubits.end(), q) == b.qubits.end()) low.push_back(q);
+    if ((int)low.size() < 5) return false;
+    pos.insert(pos.end(), low.begin(), low.end());
+    std::sort(pos.begin(), pos.end());
+    auto rank = [&](int q) { return (int)(std::find(pos.begin(), pos.end(), q) - pos.begin()); };
+    for (int i = 0; i < kDbK; ++i) {
+      geo[i] = b.qubits[i];
+      geo[15 + i] = rank(b.qubits[i]);
+      geo[20 + i] = rank(low[i]);
+    }
+    for (int i = 0; i < 10; ++i) geo[5 + i] = pos[i];
+    e.h_blk_q.insert(e.h_blk_q.end(), geo, geo + kDbGeoWords);
+  }
+  for (char v : seen)
+    if (!v) return false;
+  // theta = scale (w + bias): dtheta/dw = dtheta/dbias = scale
+  std::vector<std::vector<std::pair<int, float>>> lists(c.n_params);
+  for (int g = 0; g < c.n_gates; ++g) {
+    const qs_gate& x = c.gates[g];
+    if (!is_rotation(x.op)) continue;
+    if (x.p_w >= 0) lists[x.p_w].push_back({g, x.scale});
+    if (x.p_b >= 0) lists[x.p_b].push_back({g, x.scale});
+  }
+  pb.assign(1, 0);
+  for (int p = 0; p < c.n_params; ++p) {
+    for (auto& t : lists[p]) {
+      pg.push_back(t.first);
+      psc.push_back(t.second);
+    }
+    pb.push_back((int32_t)pg.size());
+  }
+  return true;
+}
+
+DbEntry* get_db(const qs_circuit& c, const int32_t* ck, int n_ck, int* rc) {
+  int device = 0;
+  (void)hipGetDevice(&device);
+  Key key = make_key(c, -5000 - kDbK, false, ck, n_ck, device);
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_db.find(key);
+    if (it != g_db.end()) return it->second;
+  }
+  if (const int up = plan_upload_status(); up != QS_OK) {
+    *rc = up;
+    return nullptr;
+  }
+  DbEntry* e = new DbEntry();
+  std::vector<int32_t> begin, pb, pg;
+  std::vector<DbGate> recs;
+  std::vector<float> psc;
+  if (!db_host_plan(c, ck, n_ck, *e, begin, recs, pb, pg, psc)) {
+    delete e;
+    *rc = QS_ERR_UNSUPPORTED;
+    return nullptr;
+  }
+  if (!upload(&e->blk_begin, begin.data(), begin.size()) ||
+      !upload(&e->gates, recs.data(), recs.size()) ||
+      !upload(&e->blk_q, e->h_blk_q.data(), e->h_blk_q.size()) ||
+      !upload(&e->p_begin, pb.data(), pb.size()) || !upload(&e->p_gate, pg.data(), pg.size()) ||
+      !upload(&e->p_scale, psc.data(), psc.size())) {
+    free_db(e);
+    *rc = QS_ERR_NOMEM;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_mu);
+  auto ins = g_db.emplace(std::move(key), e);
+  if (!ins.second) {  // planned meanwhile by another thread: keep that one
+    free_db(e);
+    return ins.first->second;
+  }
+  return e;
+}
+
+// Adjoint workspace of the dense-block path: psi and lam copies, one pass's
+// per-workgroup rho partial sums, every block's rho (FP64) and the per-gate
+// gradients (FP64), each 256-byte aligned.
+struct DbWs {
+  size_t psi = 0, lam = 0, part = 0, rho = 0, gth = 0, total = 0;
+};
+DbWs db_ws_layout(const qs_circuit& c, int64_t B, int n_blocks) {
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  DbWs w;
+  const size_t st = al(((size_t)B << c.n_qubits) * 8);
+  w.psi = 0;
+  w.lam = st;
+  w.part = 2 * st;
+  w.rho = w.part + al((size_t)kDbGrid * 2 * 32 * 32 * sizeof(float));
+  w.gth = w.rho + al((size_t)n_blocks * 2 * 32 * 32 * sizeof(double));
+  w.total = w.gth + al((size_t)std::max(c.n_gates, 1) * sizeof(double));
+  return w;
+}
+// Sized for as many blocks as gates (every block holds a gate), so it covers
+// every checkpoint placement.
+size_t db_ws_bytes(const qs_circuit& c, int64_t B) {
+  return db_ws_layout(c, B, std::max(c.n_gates, 1)).total;
+}
+
 // Host-only view of the tiled plan: tile size, epochs, largest adjoint grid
 // and a bound on the per-block gradient-sum array (blocks x gradient columns)
 // that holds for every checkpoint placement: checkpoints move the epoch
@@ -663,9 +837,19 @@ int pick_path(const qs_circuit& c, int dtype, int flags, SvShape* shape,
       path = c.n_qubits > kMaxQubitsFused || tile_qubits(dtype, c.n_qubits) < c.n_qubits
                  ? QS_PATH_HBM
                  : QS_PATH_PLAIN;
+    if (path == QS_PATH_HBM) {
+      // large states: the tiled engine, or dense blocks on MFMA where the
+      // tuner found them faster (the tuner's trial, then the environment)
+      int large = g_force_large;
+      if (large < 0) large = env_int("QS_LARGE_PATH_MFMA", -1);
+      if (large < 0) large = tv ? tv->large : 0;
+      if (large == 1 && db_supported(c, dtype, ps)) path = QS_PATH_MFMA;
+    }
   } else if (path == QS_PATH_FUSED) {
     if (!choose_shape(dtype, c, n_slots, rf, adjoint, shape, ps, ck, n_ck, true, sc, hf > 0))
       return QS_ERR_UNSUPPORTED;
+  } else if (path == QS_PATH_MFMA) {
+    if (!db_supported(c, dtype, ps)) return QS_ERR_UNSUPPORTED;
   } else if (path != QS_PATH_PLAIN && path != QS_PATH_HBM) {
     return QS_ERR_INVALID;
   }
@@ -918,6 +1102,7 @@ int qs_autotune(const qs_circuit* c, int dtype, int64_t B, int flags, void* stre
     const int hi = std::min(c->n_qubits, dtype == QS_C64 ? kMaxQubitsFused : 13);
     const int rmax = dtype == QS_C64 ? 5 : 4;
     float bt = 1e30f;
+    g_force_large = 0;  // the tiled engine first
     for (int m = std::max(6, hi - 3); m <= hi; ++m) {
       g_force_m = m;
       float mf = 1e30f, ma = 1e30f;
@@ -954,7 +1139,32 @@ int qs_autotune(const qs_circuit* c, int dtype, int64_t B, int flags, void* stre
         best.adj_r = ra_best;
       }
     }
+    g_force_large = -1;
     if (best.m == 0) return QS_ERR_UNSUPPORTED;
+    // Dense blocks on MFMA against the best tiled configuration (forward +
+    // adjoint); the faster becomes the automatic path's choice.
+    if ((flags & QS_PATH_MASK) == QS_PATH_AUTO && db_supported(*c, dtype, ps)) {
+      g_force_large = 1;
+      const float tf = time_ms(st, fwd, 1, &rc);
+      float ta = 0.f;
+      if (rc == QS_OK) {
+        const size_t wsb = db_ws_bytes(*c, B);
+        void* ws = sc.get(wsb);
+        if (!ws) rc = QS_ERR_NOMEM;
+        else ta = time_ms(st, [&]() { return adj(ws, wsb); }, 1, &rc);
+      }
+      g_force_large = -1;
+      if (rc == QS_OK) {
+        info.n_candidates += 2;
+        if (tf + ta < bf + ba) {
+          best.large = 1;
+          bf = tf;
+          ba = ta;
+        }
+      }
+      rc = QS_OK;
+    }
+    if (best.large) info.path = QS_PATH_MFMA;
   }
   info.fwd_log2_regs = best.fwd_r;
   info.adj_log2_regs = best.adj_r;
@@ -973,8 +1183,8 @@ int qs_autotune(const qs_circuit* c, int dtype, int64_t B, int flags, void* stre
     const char* path_env = std::getenv("QS_AUTOTUNE_CACHE");
     if (path_env && *path_env) {
       if (FILE* f = std::fopen(path_env, "a")) {
-        std::fprintf(f, "%s %d %d %d %d %d %d %d\n", key.c_str(), best.fwd_r, best.adj_r,
-                     best.m, best.fwd_s, best.adj_s, best.fwd_h, best.adj_h);
+        std::fprintf(f, "%s %d %d %d %d %d %d %d %d\n", key.c_str(), best.fwd_r, best.adj_r,
+                     best.m, best.fwd_s, best.adj_s, best.fwd_h, best.adj_h, best.large);
         std::fclose(f);
       }
     }
@@ -1074,6 +1284,22 @@ int qs_forward(const qs_circuit* c, int dtype, int64_t B, const void* params,
     L.stream = stream;
     return run_plain_forward(L);
   }
+  if (path == QS_PATH_MFMA) {
+    DbEntry* e = get_db(*c, ckpt_gates, n_ckpt, &rc);
+    if (!e) return rc;
+    const DbLaunch L{kDbK, c->n_qubits, B, e->blk_begin, e->gates, e->blk_q,
+                     e->h_blk_q.data(), params, kDbGrid, stream};
+    const int64_t per = B << c->n_qubits;
+    for (size_t i = 0; i < e->blocks.size(); ++i) {
+      if ((rc = launch_db_forward(L, (int)i, state)) != QS_OK) return rc;
+      const int slot = e->blocks[i].ckpt_after;
+      if (slot >= 0 &&
+          (rc = launch_copy_state(dtype, state, static_cast<char*>(ckpt) + 8 * per * slot, per,
+                                  stream)) != QS_OK)
+        return rc;
+    }
+    return expz ? launch_expz(dtype, c->n_qubits, B, state, expz, stream) : QS_OK;
+  }
   if (path == QS_PATH_HBM) {
     TiledEntry* te = get_tiled(*c, dtype, ps, ckpt_gates, n_ckpt, tile_cfg(tuned, tv), &rc);
     if (!te) return rc;
@@ -1136,6 +1362,7 @@ size_t qs_workspace_size(const qs_circuit* c, int dtype, int64_t B, int flags) {
     int rc = QS_OK;
     return tiled_ws_bytes(*c, dtype, B, ps, tile_cfg(tuned, tv), &rc);
   }
+  if (path == QS_PATH_MFMA) return db_ws_bytes(*c, B);
   return 0;
 }
 
@@ -1189,10 +1416,48 @@ int adjoint_backward_impl(const qs_circuit* c, int dtype, int64_t B, const void*
   if (no_alloc && path != QS_PATH_FUSED) return QS_ERR_UNSUPPORTED;
   const TileCfg tcfg = tile_cfg(tuned, tv);
   const size_t need = path == QS_PATH_PLAIN ? plain_workspace_bytes(*c, dtype, B)
-                     : path == QS_PATH_HBM ? tiled_ws_bytes(*c, dtype, B, ps, tcfg, &rc)
-                                           : fused_ws_bytes(*c, dtype, shape, B, ps);
+                     : path == QS_PATH_HBM   ? tiled_ws_bytes(*c, dtype, B, ps, tcfg, &rc)
+                     : path == QS_PATH_MFMA  ? db_ws_bytes(*c, B)
+                                             : fused_ws_bytes(*c, dtype, shape, B, ps);
   if (rc != QS_OK) return rc;
   if (need > 0 && (!ws || ws_bytes < need)) return QS_ERR_WORKSPACE;
+  if (path == QS_PATH_MFMA) {
+    DbEntry* e = get_db(*c, ckpt_gates, n_ckpt, &rc);
+    if (!e) return rc;
+    const DbLaunch L{kDbK, c->n_qubits, B, e->blk_begin, e->gates, e->blk_q,
+                     e->h_blk_q.data(), params, kDbGrid, stream};
+    const int nb = (int)e->blocks.size();
+    const DbWs lay = db_ws_layout(*c, B, nb);
+    if (lay.total > ws_bytes) return QS_ERR_WORKSPACE;
+    const int64_t per = B << c->n_qubits;
+    char* w = static_cast<char*>(ws);
+    void* psi_w = w + lay.psi;
+    void* lam_w = w + lay.lam;
+    float* part = reinterpret_cast<float*>(w + lay.part);
+    double* rho = reinterpret_cast<double*>(w + lay.rho);
+    double* gth = reinterpret_cast<double*>(w + lay.gth);
+    if ((rc = launch_copy_state(dtype, state, psi_w, per, stream)) != QS_OK) return rc;
+    rc = dstate ? launch_copy_state(dtype, dstate, lam_w, per, stream)
+                : launch_obs_cot(dtype, c->n_qubits, B, dexpz, psi_w, lam_w, stream);
+    if (rc != QS_OK) return rc;
+    for (int i = nb - 1; i >= 0; --i) {
+      const int slot = e->blocks[i].ckpt_after;
+      if (slot >= 0 && ckpt &&  // psi after this block = the stored checkpoint
+          (rc = launch_copy_state(dtype, static_cast<const char*>(ckpt) + 8 * per * slot,
+                                  psi_w, per, stream)) != QS_OK)
+        return rc;
+      if ((rc = launch_db_adjoint(L, i, psi_w, lam_w, part)) != QS_OK) return rc;
+      if ((rc = launch_db_reduce(L, part, rho + (size_t)i * 2 * 32 * 32)) != QS_OK) return rc;
+    }
+    if ((rc = launch_fill_f64(gth, std::max(c->n_gates, 1), stream)) != QS_OK) return rc;
+    if ((rc = launch_db_grads(L, nb, rho, gth)) != QS_OK) return rc;
+    if ((rc = launch_db_chain(c->n_params, e->p_begin, e->p_gate, e->p_scale, gth,
+                              grad_params, stream)) != QS_OK)
+      return rc;
+    if (c->n_features && grad_feats)  // no rotation reads a feature on this path
+      rc = launch_fill_f64(grad_feats, B * c->n_features, stream);
+    return rc;
+  }
   if (path == QS_PATH_HBM) {
     TiledEntry* te = get_tiled(*c, dtype, ps, ckpt_gates, n_ckpt, tcfg, &rc);
     if (!te) return rc;
@@ -1384,6 +1649,11 @@ int qs_plan_info_get(const qs_circuit* c, int dtype, int64_t B, int flags,
     out->log2_threads = h.m;       // tile qubits
     return QS_OK;
   }
+  if (path == QS_PATH_MFMA) {
+    out->n_segments = (int32_t)plan_blocks(*c, kDbK, nullptr, 0).size();  // blocks
+    out->log2_threads = kDbK;                                             // block qubits
+    return QS_OK;
+  }
   if (path != QS_PATH_FUSED) return QS_OK;
   if (pick_path(*c, dtype, flags, &ashape, count_slots(*c, ps), true,
                 tuned ? &tv : nullptr) == QS_PATH_FUSED) {
@@ -1421,6 +1691,21 @@ int qs_hbm_info_get(const qs_circuit* c, int dtype, int64_t B, int flags,
   const int path = pick_path(*c, dtype, flags, &shape, count_slots(*c, ps), true,
                              tuned ? &tv : nullptr, ckpt_gates, n_ckpt);
   if (path < 0) return path;
+  if (path == QS_PATH_MFMA) {
+    std::memset(out, 0, sizeof(*out));
+    out->path = path;
+    DbEntry e;
+    std::vector<int32_t> b0, pb, pg;
+    std::vector<DbGate> recs;
+    std::vector<float> psc;
+    if (!db_host_plan(*c, ckpt_gates, n_ckpt, e, b0, recs, pb, pg, psc))
+      return QS_ERR_UNSUPPORTED;
+    out->n_passes = (int32_t)e.blocks.size();
+    out->tile_qubits = kDbK;
+    out->max_partial_bytes = (int64_t)kDbGrid * 2 * 32 * 32 * sizeof(float);
+    out->ws_bytes = (int64_t)db_ws_bytes(*c, B);
+    return QS_OK;
+  }
   if (path != QS_PATH_HBM) return QS_ERR_UNSUPPORTED;
   std::memset(out, 0, sizeof(*out));
   out->path = path;
@@ -1432,6 +1717,36 @@ int qs_hbm_info_get(const qs_circuit* c, int dtype, int64_t B, int flags,
   out->max_partial_bytes = h.max_part_plan * (dtype == QS_C64 ? 4 : 8);
   out->ws_bytes = (int64_t)tiled_ws_bytes(*c, dtype, B, ps, tc, &rc);
   return rc;
+}
+
+int qs_block_plan_export(const qs_circuit* c, int dtype, int flags, const int32_t* ckpt_gates,
+                         int32_t n_ckpt, int32_t* n_blocks, int32_t* blk_qubits,
+                         int32_t* blk_begin, int32_t* blk_gates, int32_t* blk_ckpt) {
+  InvCircuit inv_;
+  c = apply_inverse(c, &flags, inv_);
+  int rc = validate(c);
+  if (rc != QS_OK) return rc;
+  if (!n_blocks) return QS_ERR_INVALID;
+  static const char dummy = 0;  // check_ckpt wants a buffer; none is touched here
+  if ((rc = check_ckpt(c, ckpt_gates, n_ckpt, &dummy)) != QS_OK) return rc;
+  if (!db_supported(*c, dtype, (flags & QS_FLAG_PER_SAMPLE_PARAMS) != 0))
+    return QS_ERR_UNSUPPORTED;
+  DbEntry e;
+  std::vector<int32_t> begin, pb, pg;
+  std::vector<DbGate> recs;
+  std::vector<float> psc;
+  if (!db_host_plan(*c, ckpt_gates, n_ckpt, e, begin, recs, pb, pg, psc))
+    return QS_ERR_UNSUPPORTED;
+  *n_blocks = (int32_t)e.blocks.size();
+  for (size_t b = 0; b < e.blocks.size(); ++b) {
+    if (blk_qubits)
+      for (int i = 0; i < kDbK; ++i) blk_qubits[b * kDbK + i] = e.blocks[b].qubits[i];
+    if (blk_ckpt) blk_ckpt[b] = e.blocks[b].ckpt_after;
+  }
+  if (blk_begin) std::memcpy(blk_begin, begin.data(), sizeof(int32_t) * begin.size());
+  if (blk_gates)
+    for (size_t i = 0; i < recs.size(); ++i) blk_gates[i] = recs[i].g;
+  return QS_OK;
 }
 
 int qs_plan_export(const qs_circuit* c, int dtype, int64_t B, int flags,
@@ -1518,6 +1833,8 @@ void qs_shutdown(void) {
     delete kv.second;
   }
   g_tiled.clear();
+  for (auto& kv : g_db) free_db(kv.second);
+  g_db.clear();
 }
 
 }  // extern "C"

@@ -129,6 +129,65 @@ struct TiledEpoch {
 std::vector<TiledEpoch> plan_tiled(const qs_circuit& c, int m, int low_keep,
                                    const int32_t* ckpt_gates, int n_ckpt);
 
+// Large states on the dense-block path: the gate list cut into blocks of K
+// qubits; each block's gates (descriptor indices, in an order that keeps
+// every qubit's gate order) multiply into one 2^K x 2^K unitary applied in
+// one pass over the state.
+struct DenseBlock {
+  std::vector<int> qubits;    // the K qubits, ascending (local bit i = qubits[i])
+  std::vector<int> gates;     // descriptor gates, application order
+  int ckpt_after = -1;        // checkpoint stored after this block
+};
+std::vector<DenseBlock> plan_blocks(const qs_circuit& c, int K, const int32_t* ckpt_gates,
+                                    int n_ckpt);
+
+// Device records of a dense-block plan. A block gate: kind, local qubits,
+// angle rule (as in qs_gate, no features).
+struct DbGate {
+  int32_t op, q0, q1, p_w, p_b;
+  float scale;
+  int32_t g;        // descriptor gate (gradient slot)
+  int32_t pad;
+};
+static_assert(sizeof(DbGate) == 32, "DbGate layout");
+// Per-block tile geometry, kDbGeoWords int32 per block: [0, 5) the block
+// qubits (ascending), [5, 15) the 10 address bits of a tile of 32 columns
+// (the block qubits and the 5 lowest other positions, ascending; the first 5
+// are always 0..4), [15, 20) the rank among those 10 of each block qubit,
+// [20, 25) the rank of each column bit (column bit j sits at the j-th lowest
+// position outside the block).
+constexpr int kDbGeoWords = 32;
+struct DbLaunch {
+  int K;                      // block qubits (5)
+  int n;                      // qubits of a state
+  int64_t B;
+  const int32_t* blk_begin;   // device [n_blocks + 1] ranges of gates
+  const DbGate* gates;        // device
+  const int32_t* blk_q;       // device [n_blocks][kDbGeoWords] tile geometry
+  const int32_t* h_blk_q;     // host copy of blk_q
+  const void* params;         // device float (complex64 states)
+  int grid;                   // persistent workgroups of the pass kernels
+  void* stream;
+};
+// Forward pass of block i over the state (in place): every workgroup builds
+// the block's unitary M in FP64 from the parameters and applies it to its
+// share of the state's columns on MFMA.
+int launch_db_forward(const DbLaunch& L, int i, void* state);
+// Adjoint pass of block i: psi <- M^dagger psi, lam <- M^dagger lam (in
+// place), and per-workgroup partial sums of rho = sum psi lam^dagger over the
+// state's columns (taken before the update) into `partials`
+// [grid][2][2^K][2^K] float (real part, then imaginary part).
+int launch_db_adjoint(const DbLaunch& L, int i, void* psi, void* lam, float* partials);
+// rho (FP64, [2][2^K][2^K]) = sum over workgroups of the partials.
+int launch_db_reduce(const DbLaunch& L, const float* partials, double* rho);
+// Per-gate adjoint gradients dL/dtheta_g (FP64, gtheta[g] for every rotation
+// g of the n_blocks blocks) from each block's rho, walking its gates
+// backwards.
+int launch_db_grads(const DbLaunch& L, int n_blocks, const double* rho, double* gtheta);
+// grad[p] = sum of scale * gtheta over the rotations reading p (p_w or p_b).
+int launch_db_chain(int n_params, const int32_t* p_begin, const int32_t* p_gate,
+                    const float* p_scale, const double* gtheta, double* grad, void* stream);
+
 // Device copy of a plan plus its launch shape.
 struct SvDevPlan {
   int n, r, t, nseg, n_gates, n_slots, n_params, n_features;

@@ -123,6 +123,64 @@ def expz(params, feats, state0, sim: Simulator):
     return CircuitExpZ.apply(params, feats, state0, sim)
 
 
+_FIDELITY = {"reset": "qs_fidelity_reset", "postselect": "qs_fidelity_postselect",
+             "trajectory": "qs_fidelity_trajectory"}
+
+
+class AutoencoderFidelity(torch.autograd.Function):
+    """Per-sample autoencoder fidelity F_b of an encoder U(params_enc) and a
+    decoder V(params_dec)^dagger on the encoded inputs state0, with the
+    n_trash top qubits reset ("reset"), measured with only the all-zero
+    outcome kept ("postselect"), or reset along one trajectory drawn by the
+    uniforms u ("trajectory"); differentiable in both parameter sets through
+    the library's fidelity cotangents and adjoint."""
+
+    @staticmethod
+    def forward(ctx, params_enc, params_dec, state0, enc: Simulator, dec: Simulator,
+                n_trash: int, kind: str = "reset", u=None):
+        psi = state0.clone()
+        chi = state0.clone()
+        enc.forward(params_enc.detach(), None, psi, want_expz=False)
+        dec.forward(params_dec.detach(), None, chi, want_expz=False)
+        fid = torch.empty(state0.shape[0], dtype=torch.float64, device=state0.device)
+        ctx.enc, ctx.dec, ctx.n_trash, ctx.kind = enc, dec, n_trash, kind
+        ctx.save_for_backward(params_enc, params_dec, psi, chi,
+                              u if u is not None else fid)
+        _fidelity_call(enc, kind, n_trash, psi, chi, fid, u=u)
+        return fid
+
+    @staticmethod
+    def backward(ctx, gfid):
+        params_enc, params_dec, psi, chi, u = ctx.saved_tensors
+        u = u if ctx.kind == "trajectory" else None
+        fid = torch.empty(psi.shape[0], dtype=torch.float64, device=psi.device)
+        lam_psi = torch.empty_like(psi)
+        lam_chi = torch.empty_like(chi)
+        _fidelity_call(ctx.enc, ctx.kind, ctx.n_trash, psi, chi, fid, u=u,
+                       dfid=gfid.contiguous().to(torch.float64), lam_psi=lam_psi,
+                       lam_chi=lam_chi)
+        ge, _ = ctx.enc.adjoint(params_enc.detach(), None, psi, dstate=lam_psi)
+        gd, _ = ctx.dec.adjoint(params_dec.detach(), None, chi, dstate=lam_chi)
+        return ge.to(params_enc.dtype), gd.to(params_dec.dtype), None, None, None, None, \
+            None, None
+
+
+def _fidelity_call(sim: Simulator, kind, n_trash, psi, chi, fid, u=None, dfid=None,
+                   lam_psi=None, lam_chi=None):
+    if kind == "trajectory":
+        N.qs_fidelity_trajectory(sim.qs_dtype, sim.n, n_trash, psi, chi, u, fid, None,
+                                 dfid, lam_psi, lam_chi)
+    else:
+        getattr(N, _FIDELITY[kind])(sim.qs_dtype, sim.n, n_trash, psi, chi, fid, dfid,
+                                    lam_psi, lam_chi)
+
+
+def autoencoder_fidelity(params_enc, params_dec, state0, enc: Simulator, dec: Simulator,
+                         n_trash: int, kind: str = "reset", u=None):
+    return AutoencoderFidelity.apply(params_enc, params_dec, state0, enc, dec, n_trash,
+                                     kind, u)
+
+
 # ---------------------------------------------------------------- workloads
 @dataclass
 class DeviceWorkload:

@@ -24,7 +24,7 @@ if torch.cuda.is_available():
 
 TOL = {"c64": dict(z=1e-5, state=1e-5, grad=1e-4),
        "c128": dict(z=1e-10, state=1e-10, grad=1e-10)}
-PATHS = {"fused": 1, "plain": 2, "hbm": 3, "auto": 0}
+PATHS = {"fused": 1, "plain": 2, "hbm": 3, "auto": 0, "mfma": 4}
 
 
 def _dev(a, dt):
@@ -707,6 +707,135 @@ def test_autograd_function_matches_oracle():
     np.testing.assert_allclose(feats.grad.cpu().numpy(), rf, atol=1e-4)
 
 
+# ------------------------------------- finite differences on the GPU itself
+@pytest.mark.parametrize("key", ["c2", "c3"])
+def test_adjoint_matches_gpu_central_differences_c128(key):
+    """The complex128 adjoint against central differences of the complex128
+    forward, both on the GPU (no oracle in the loop): L = sum_b,q w_bq <Z_q>_b,
+    h = 1e-5 on every parameter (and every feature of the re-uploading
+    circuit)."""
+    w = Dt.make_workload(key, 3)
+    c = w.circuit
+    _announce(f"GPU central differences {key} c128")
+    rng = np.random.default_rng(41)
+    s = sim.Simulator(c, "c128")
+    B, n = 3, c.n_qubits
+    params = torch.tensor(rng.uniform(-np.pi, np.pi, c.n_params), device="cuda")
+    feats = (torch.tensor(rng.uniform(-1, 1, (B, c.n_features)), device="cuda")
+             if c.n_features else None)
+    if w.encoding == "amplitude":
+        st0 = s.encode_amplitude(_dev(rng.standard_normal((B, 1 << n)), torch.float64))
+    else:
+        st0 = s.zero_state(B)
+    wts = torch.tensor(rng.uniform(-1, 1, (B, n)), device="cuda")
+
+    def loss(p, f):
+        st = st0.clone()
+        return float((s.forward(p, f, st) * wts).sum().item())
+
+    st = st0.clone()
+    s.forward(params, feats, st, want_expz=False)
+    gp, gf = s.adjoint(params, feats, st, dexpz=wts)
+    gp = gp.cpu().numpy()
+    h = 1e-5
+    fd = np.zeros(c.n_params)
+    for i in range(c.n_params):
+        pp, pm = params.clone(), params.clone()
+        pp[i] += h
+        pm[i] -= h
+        fd[i] = (loss(pp, feats) - loss(pm, feats)) / (2 * h)
+    np.testing.assert_allclose(gp, fd, atol=1e-8)
+    if feats is not None:
+        fdf = np.zeros((B, c.n_features))
+        for b in range(B):
+            for k in range(c.n_features):
+                fp, fm = feats.clone(), feats.clone()
+                fp[b, k] += h
+                fm[b, k] -= h
+                fdf[b, k] = (loss(params, fp) - loss(params, fm)) / (2 * h)
+        np.testing.assert_allclose(gf.cpu().numpy(), fdf, atol=1e-8)
+
+
+def test_autograd_gradcheck_c128():
+    """torch.autograd.gradcheck (its own finite differences) through the
+    <Z> Function in complex128, parameters and features."""
+    rng = np.random.default_rng(43)
+    c = C.random_circuit(4, 30, rng, n_params=5, n_features=2)
+    s = sim.Simulator(c, "c128")
+    st0 = s.encode_amplitude(_dev(rng.standard_normal((2, 16)), torch.float64))
+    p = torch.tensor(rng.uniform(-2, 2, 5), device="cuda", requires_grad=True)
+    f = torch.tensor(rng.uniform(-1, 1, (2, 2)), device="cuda", requires_grad=True)
+    assert torch.autograd.gradcheck(lambda a, b: sim.expz(a, b, st0, s), (p, f),
+                                    eps=1e-6, atol=1e-7, rtol=1e-5)
+
+
+def _fidelity_setup(dtype, rng, n=6, t=2, B=4):
+    enc = C.ry_rz_chain(n, 3)
+    rd = np.float32 if dtype == "c64" else np.float64
+    th = rng.uniform(-np.pi, np.pi, enc.n_params).astype(rd)
+    ph = rng.uniform(-np.pi, np.pi, enc.n_params).astype(rd)
+    x = rng.standard_normal((B, 1 << n)).astype(rd)
+    return enc, th, ph, x
+
+
+@pytest.mark.parametrize("kind", ["reset", "postselect", "trajectory"])
+def test_fidelity_autograd_matches_oracle(kind):
+    """The fidelity losses through torch.autograd (complex64) against the
+    oracle's cotangents and adjoint, and a complex128 gradcheck."""
+    rng = np.random.default_rng(47)
+    n, t, B = 6, 2, 4
+    enc, th, ph, x = _fidelity_setup("c64", rng, n, t, B)
+    psi0 = O.encode_amplitude(x, n)
+    psi = O.run_circuit(enc, th, None, psi0)
+    chi = O.run_circuit(enc, ph, None, psi0)
+    u = None
+    if kind == "trajectory":  # mid-interval uniforms: the outcome is 1 for every row
+        pm = np.abs(psi.reshape(B, 1 << t, -1)) ** 2
+        pm = pm.sum(axis=2)
+        u = (pm[:, 0] + 0.5 * pm[:, 1]) / pm.sum(axis=1)
+    dF = -np.ones(B) / B
+    if kind == "reset":
+        F, cm = O.fidelity_reset(psi, chi, t)
+        lam, mu = O.reset_channel_fidelity_cotangents(psi, chi, cm, dF, t)
+    elif kind == "postselect":
+        F, cc, pp = O.fidelity_postselect(psi, chi, t)
+        lam, mu = O.postselect_fidelity_cotangents(psi, chi, cc, pp, dF, t)
+    else:
+        F, m, cc, pp = O.fidelity_trajectory(psi, chi, t, u)
+        assert np.all(m == 1)
+        lam, mu = O.trajectory_fidelity_cotangents(psi, chi, m, cc, pp, dF, t)
+    g1, _ = O.adjoint_vjp(enc, th, None, psi0, lam_final=lam)
+    g2, _ = O.adjoint_vjp(enc, ph, None, psi0, lam_final=mu)
+    ref_th = O.theta_to_param_grads(enc, th, None, g1)[0]
+    ref_ph = O.theta_to_param_grads(enc, ph, None, g2)[0]
+    se, sd = sim.Simulator(enc, "c64"), sim.Simulator(enc, "c64")
+    st0 = se.encode_amplitude(_dev(x, torch.float32))
+    pt = torch.tensor(th, device="cuda", requires_grad=True)
+    pd = torch.tensor(ph, device="cuda", requires_grad=True)
+    ut = None if u is None else _dev(u, torch.float64)
+    fid = sim.autoencoder_fidelity(pt, pd, st0, se, sd, t, kind, ut)
+    loss = 1.0 - fid.mean()
+    loss.backward()
+    np.testing.assert_allclose(fid.detach().cpu().numpy(), F, atol=1e-5)
+    np.testing.assert_allclose(pt.grad.cpu().numpy(), ref_th, atol=1e-4)
+    np.testing.assert_allclose(pd.grad.cpu().numpy(), ref_ph, atol=1e-4)
+    # complex128: gradcheck through the same Function
+    enc2, th2, ph2, x2 = _fidelity_setup("c128", rng, 5, 1, 2)
+    s2e, s2d = sim.Simulator(enc2, "c128"), sim.Simulator(enc2, "c128")
+    st2 = s2e.encode_amplitude(_dev(x2, torch.float64))
+    u2 = None
+    if kind == "trajectory":
+        q = np.abs(O.run_circuit(enc2, th2, None, O.encode_amplitude(x2, 5))
+                   .reshape(2, 2, -1)) ** 2
+        q = q.sum(axis=2)
+        u2 = _dev(0.5 * q[:, 0] / q.sum(axis=1), torch.float64)  # outcome 0
+    a = torch.tensor(th2, device="cuda", requires_grad=True)
+    b = torch.tensor(ph2, device="cuda", requires_grad=True)
+    assert torch.autograd.gradcheck(
+        lambda p1, p2: sim.autoencoder_fidelity(p1, p2, st2, s2e, s2d, 1, kind, u2),
+        (a, b), eps=1e-6, atol=1e-7, rtol=1e-5)
+
+
 # ------------------------------------------------ large states: tiled path
 @pytest.fixture
 def tile_qubits(monkeypatch):
@@ -856,6 +985,116 @@ def test_tiled_checkpoints_that_widen_an_epochs_gradient_columns():
         if found == 2:
             break
     assert found >= 1
+
+
+# ------------------------------------- large states: dense blocks on MFMA
+@pytest.mark.parametrize("n,G,B", [(10, 150, 3), (11, 90, 2), (13, 200, 2), (15, 120, 1)])
+def test_mfma_block_path_random_circuits(n, G, B):
+    """Every gate kind, shared parameters (including parameters read by
+    several rotations and as biases), states, <Z> and gradients against the
+    oracle; then a state cotangent."""
+    rng = np.random.default_rng(1000 + n)
+    c = C.random_circuit(n, G, rng, n_params=9, n_features=0)
+    _run_expz_case(c, "c64", "mfma", B, seed=n)
+    _run_expz_case(c, "c64", "mfma", B, seed=n + 1, dstate_mode=True, amplitude=False)
+
+
+def test_mfma_block_path_checkpoints_and_inverse():
+    rng = np.random.default_rng(1017)
+    n, G, B = 12, 160, 2
+    c = C.random_circuit(n, G, rng, n_params=8, n_features=0)
+    ck = [17, 60, 61, 140]
+    s = sim.Simulator(c, "c64", PATHS["mfma"])
+    x = rng.standard_normal((B, 1 << n)).astype(np.float32)
+    st = s.encode_amplitude(_dev(x, torch.float32))
+    buf = torch.empty((len(ck),) + tuple(st.shape), dtype=st.dtype, device="cuda")
+    params = rng.uniform(-np.pi, np.pi, c.n_params).astype(np.float32)
+    pt = _dev(params, torch.float32)
+    z = s.forward(pt, None, st, ckpt_gates=ck, ckpt=buf)
+    dz = rng.uniform(-1, 1, (B, n))
+    gp, _ = s.adjoint(pt, None, st, dexpz=_dev(dz, torch.float64), ckpt_gates=ck, ckpt=buf)
+    torch.cuda.synchronize()
+    psi0 = O.encode_amplitude(x, n)
+    for i, g in enumerate(ck):
+        ref = O.run_circuit(C.Circuit(n, c.gates[:g], c.n_params), params, None, psi0)
+        np.testing.assert_allclose(buf[i].cpu().numpy(), ref, atol=1e-5)
+    np.testing.assert_allclose(z.cpu().numpy(), O.expz(O.run_circuit(c, params, None, psi0)),
+                               atol=1e-5)
+    gth, _ = O.adjoint_vjp(c, params, None, psi0, dexpz=dz)
+    np.testing.assert_allclose(gp.cpu().numpy(),
+                               O.theta_to_param_grads(c, params, None, gth)[0], atol=1e-4)
+    # the inverse flag runs U^dagger: back to the input
+    s.forward(pt, None, st, want_expz=False, flags=PATHS["mfma"] | N.QS_FLAG_INVERSE)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(st.cpu().numpy(), psi0, atol=1e-5)
+
+
+def test_26q_structure_at_18_qubits_on_mfma_blocks():
+    """The 18-qubit version of the 26-qubit workload (see the tiled-path test
+    above) on the dense-block MFMA path."""
+    n = 18
+    _announce(f"26-qubit structure at n={n} on MFMA blocks")
+    c = C.hea_ry_rz_ring(n, 20)
+    w = Dt.Workload("hea ring n18 L20", n, 1, c, "c64", "zero", "weighted_z",
+                    params=Dt.uniform_params(c.n_params, 0),
+                    weights=Dt.upstream_weights(n, 0))
+    d = sim.to_device(w, flags=PATHS["mfma"], ckpt_every_layers=4)
+    out = sim.step(d)
+    torch.cuda.synchronize()
+    p64 = w.params.astype(np.float64)
+    psi0 = O.encode_zero(1, n)
+    z = O.expz(O.run_circuit(c, p64, None, psi0))
+    L, dz = O.loss_and_dexpz("weighted_z", z, None, w.weights)
+    gth, _ = O.adjoint_vjp(c, p64, None, psi0, dexpz=dz)
+    gp = O.theta_to_param_grads(c, p64, None, gth)[0]
+    np.testing.assert_allclose(out["expz"].cpu().numpy(), z, atol=1e-5)
+    got = out["grad_params"].cpu().numpy()
+    np.testing.assert_allclose(got, gp, atol=1e-4)
+    assert np.linalg.norm(got - gp) <= 1e-3 * np.linalg.norm(gp)
+
+
+def test_full_size_26q_on_mfma_blocks_closed_forms_and_inverse():
+    """26 qubits on the MFMA path: the product circuit's per-qubit closed
+    forms and gradients, and the hardware-efficient circuit then its inverse
+    returning |0...0>."""
+    _announce("26-qubit product state on MFMA blocks")
+    n = 26
+    rng = np.random.default_rng(826)
+    c = _product_circuit(n, 3, rng)
+    params = rng.uniform(-np.pi, np.pi, c.n_params).astype(np.float32)
+    g = rng.uniform(-1, 1, n)
+    s = sim.Simulator(c, "c64", PATHS["mfma"])
+    st = s.zero_state(1)
+    pt = _dev(params, torch.float32)
+    z = s.forward(pt, None, st)
+    gp, _ = s.adjoint(pt, None, st, dexpz=_dev(g[None, :], torch.float64))
+    torch.cuda.synchronize()
+    z = z.cpu().numpy()[0]
+    gp = gp.cpu().numpy()
+    for q in range(n):
+        sel = [i for i, gt in enumerate(c.gates) if gt["q0"] == q]
+        g1 = c.gates[sel].copy()
+        g1["q0"] = 0
+        c1 = C.Circuit(1, g1, c.n_params)
+        psi = O.run_circuit(c1, params, None, O.encode_zero(1, 1))
+        assert abs(z[q] - O.expz(psi)[0, 0]) < 1e-5
+        gth, _ = O.adjoint_vjp(c1, params, None, O.encode_zero(1, 1),
+                               dexpz=np.array([[g[q]]]))
+        ref = O.theta_to_param_grads(c1, params, None, gth)[0]
+        idx = np.unique(g1["p_w"])
+        np.testing.assert_allclose(gp[idx], ref[idx], atol=1e-4)
+    del st
+    _announce("26-qubit U then U^dagger on MFMA blocks")
+    w = Dt.make_workload("c5b")
+    s = sim.Simulator(w.circuit, "c64", PATHS["mfma"])
+    st = s.zero_state(1)
+    pt = _dev(w.params, torch.float32)
+    s.forward(pt, None, st, want_expz=False)
+    s.forward(pt, None, st, want_expz=False, flags=PATHS["mfma"] | N.QS_FLAG_INVERSE)
+    torch.cuda.synchronize()
+    assert abs(st[0, 0].item() - 1.0) < 1e-3
+    norm = float((st.abs().double() ** 2).sum().item())
+    assert abs(norm - 1.0) < 1e-3
 
 
 def _product_circuit(n, layers, rng):

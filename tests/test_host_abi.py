@@ -454,3 +454,98 @@ def test_engine_program_cnot_patterns(kind):
 def test_engine_program_of_workloads(key):
     w = Dt.make_workload(key, 2)
     _engine_program_case(w.circuit, seed=1, B=2)
+
+
+# ------------------------------------------------- dense-block plans (MFMA)
+def _apply_block(psi, n, qubits, U):
+    """psi [2^n] <- (U on the given qubits, local bit i = qubits[i]) psi."""
+    k = len(qubits)
+    t = psi.reshape([2] * n)  # axis n - 1 - q holds qubit q
+    axes = [n - 1 - q for q in qubits[::-1]]  # local bit k-1 .. 0
+    Ut = U.reshape([2] * (2 * k))
+    out = np.tensordot(Ut, t, axes=(list(range(k, 2 * k)), axes))
+    return np.moveaxis(out, list(range(k)), axes).reshape(-1)
+
+
+def _check_block_plan(c, ckpt=None):
+    h = N.CircuitHandle(c)
+    q, b, g, k = N.qs_block_plan_export(h, N.QS_C64, 0, ckpt)
+    G = c.n_gates
+    assert sorted(g.tolist()) == list(range(G))  # every gate exactly once
+    assert b[0] == 0 and b[-1] == G and np.all(np.diff(b) >= 1)
+    for blk in range(len(q)):
+        assert len(set(q[blk].tolist())) == 5 and np.all(np.diff(q[blk]) > 0)
+        for gi in g[b[blk]:b[blk + 1]]:
+            gt = c.gates[gi]
+            assert gt["q0"] in q[blk] and (gt["q1"] < 0 or gt["q1"] in q[blk])
+    # each qubit sees its gates in descriptor order
+    for qq in range(c.n_qubits):
+        seq = [int(x) for x in g if c.gates[x]["q0"] == qq or c.gates[x]["q1"] == qq]
+        assert seq == sorted(seq), qq
+    # blocks never straddle a checkpoint; the last block of each segment
+    # stores its slot
+    bounds = list(ckpt or []) + [G]
+    seg_of = np.searchsorted(np.asarray(bounds), g, side="right")
+    for blk in range(len(q)):
+        assert len(set(seg_of[b[blk]:b[blk + 1]].tolist())) == 1
+    assert [int(x) for x in k if x >= 0] == list(range(len(ckpt or [])))
+    return q, b, g
+
+
+@pytest.mark.parametrize("n,G", [(10, 120), (11, 200), (12, 90)])
+def test_block_plan_executes_the_circuit(n, G):
+    """The exported dense-block plan, run in NumPy block by block (each
+    block's 32 x 32 unitary from the oracle's own gate matrices), equals the
+    oracle's gate-by-gate run."""
+    import oracle as O
+    from oracle.statevector import circuit_unitary
+    rng = np.random.default_rng(900 + n)
+    c = C.random_circuit(n, G, rng, n_params=7, n_features=0)
+    ck = sorted(set(int(v) for v in rng.integers(1, G, size=3)))
+    for cks in (None, ck):
+        q, b, g = _check_block_plan(c, cks)
+        p = rng.uniform(-np.pi, np.pi, c.n_params)
+        psi0 = O.encode_amplitude(rng.standard_normal((1, 1 << n)), n)
+        ref = O.run_circuit(c, p, None, psi0)[0]
+        psi = psi0[0].copy()
+        for blk in range(len(q)):
+            loc = {int(x): i for i, x in enumerate(q[blk])}
+            rows = c.gates[g[b[blk]:b[blk + 1]]].copy()
+            rows["q0"] = [loc[int(x)] for x in rows["q0"]]
+            rows["q1"] = [loc[int(x)] if x >= 0 else -1 for x in rows["q1"]]
+            U = circuit_unitary(C.Circuit(5, rows, c.n_params), p)
+            psi = _apply_block(psi, n, [int(x) for x in q[blk]], U)
+        np.testing.assert_allclose(psi, ref, atol=1e-12)
+
+
+def test_block_plan_of_the_26_qubit_circuit():
+    w = Dt.make_workload("c5b")
+    c = w.circuit
+    ck = [c.layer_end[l - 1] for l in (4, 8, 12, 16)]
+    q, b, g = _check_block_plan(c)
+    q2, b2, g2 = _check_block_plan(c, ck)
+    # 20 layers of 78 gates on 26 qubits: about 14 gates per 5-qubit block
+    assert 80 <= len(q) <= 160 and len(q2) >= len(q)
+    h = N.CircuitHandle(c)
+    info = N.qs_hbm_info_get(h, N.QS_C64, 1, N.QS_PATH_MFMA, ck)
+    assert info["path"] == N.QS_PATH_MFMA and info["n_passes"] == len(q2)
+    assert info["ws_bytes"] == N.qs_workspace_size(h, N.QS_C64, 1, N.QS_PATH_MFMA)
+    assert info["ws_bytes"] >= 2 * (1 << 26) * 8
+
+
+def test_block_path_refuses_what_it_does_not_run():
+    h = N.CircuitHandle(C.hea_ry_rz_ring(16, 1))
+    for dt, fl in [(N.QS_C128, N.QS_PATH_MFMA),
+                   (N.QS_C64, N.QS_PATH_MFMA | N.QS_FLAG_PER_SAMPLE_PARAMS)]:
+        with pytest.raises(N.QsError) as e:
+            N.qs_plan_info_get(h, dt, 2, fl)
+        assert e.value.status == N.QS_ERR_UNSUPPORTED
+    # a rotation reading a feature: its angle differs per sample
+    hf = N.CircuitHandle(C.reupload_ry_rz_chain(12, 2, 4))
+    with pytest.raises(N.QsError):
+        N.qs_plan_info_get(hf, N.QS_C64, 2, N.QS_PATH_MFMA)
+    # fewer than 32 columns per state
+    with pytest.raises(N.QsError):
+        N.qs_plan_info_get(N.CircuitHandle(C.hea_ry_rz_ring(9, 1)), N.QS_C64, 2,
+                           N.QS_PATH_MFMA)
+    assert N.qs_plan_info_get(h, N.QS_C64, 2, N.QS_PATH_MFMA)["path"] == N.QS_PATH_MFMA
