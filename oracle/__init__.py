@@ -24,6 +24,11 @@ from the textbook definitions of the operations:
   the reset channel (the trash qubits measured with an outcome drawn from the
   Born probabilities, then reset; Dalibard, Castin & Molmer, *Phys. Rev.
   Lett.* 68, 580, 1992, for the unravelling of a channel into trajectories);
+* mid-circuit channels on one qubit: one trajectory of a Z-basis measurement
+  (outcome drawn from the Born probabilities by a given uniform), the state
+  renormalised and kept or reset to |0> (Nielsen & Chuang §2.2.3 and §8.3 for
+  the measurement and reset channels; trajectories as above), with the
+  pathwise cotangent through the renormalisation;
 * gradients three ways: the adjoint (reverse state propagation) method
   (Jones & Gacon, arXiv:2009.02823, §3), the parameter-shift rule
   (Mitarai et al., *Phys. Rev. A* 98, 032309, 2018; Schuld et al.,
@@ -39,7 +44,7 @@ from .statevector import (  # noqa: F401
     fidelity_reset_direct, reset_channel_fidelity_cotangents,
     fidelity_postselect, postselect_fidelity_cotangents, fidelity_postselect_direct,
     trajectory_outcome, fidelity_trajectory, trajectory_fidelity_cotangents,
-    fidelity_trajectory_direct,
+    fidelity_trajectory_direct, channel_probabilities, apply_channel, channel_cotangent,
 )
 from .gradients import (  # noqa: F401
     adjoint_vjp, param_shift_theta_jacobian, theta_to_param_grads,

@@ -12,9 +12,10 @@ import numpy as np
 from workloads.circuits import OP
 
 from .statevector import (apply_gate, gate_angles, pauli_of, run_circuit,
-                          apply_1q, expz)
+                          apply_1q, expz, apply_channel, channel_cotangent)
 
 _ROT = (OP["RX"], OP["RY"], OP["RZ"])
+_CHANNELS = (OP["RESET"], OP["MEASURE"])
 
 
 def observable_cotangent(psi: np.ndarray, dexpz: np.ndarray) -> np.ndarray:
@@ -35,17 +36,39 @@ def adjoint_vjp(circuit, params, feats, psi0, lam_final=None, dexpz=None):
     Runs the circuit forward, forms lam at the output, then walks the gates
     backwards: at gate g, with psi and lam both taken just after g,
     dL/dtheta_g = Im <lam | P_g | psi> for R_P(theta) = exp(-i theta P / 2);
-    then psi <- U_g^dagger psi and lam <- U_g^dagger lam.
+    then psi <- U_g^dagger psi and lam <- U_g^dagger lam. At a mid-circuit
+    channel (one trajectory, outcome held fixed) psi is restored to the state
+    the forward saw in front of it and lam goes through ``channel_cotangent``.
     Returns (dL/dtheta [B, G], final state psi_G).
     """
     B = psi0.shape[0]
-    psi_G = run_circuit(circuit, params, feats, psi0)
+    channels = [g for g, gate in enumerate(circuit.gates) if int(gate["op"]) in _CHANNELS]
+    if channels:
+        # A channel cannot be un-applied: keep the state in front of each one.
+        pre, psi = {}, psi0.copy()
+        for g, gate in enumerate(circuit.gates):
+            op = int(gate["op"])
+            if op in _CHANNELS:
+                pre[g] = psi.copy()
+                u = np.asarray(feats, dtype=np.float64)[:, int(gate["feat"])]
+                psi = apply_channel(psi, gate, u)[0]
+            else:
+                th = gate_angles(gate, params, feats, B) if op in _ROT else None
+                psi = apply_gate(psi, gate, th)
+        psi_G = psi
+    else:
+        psi_G = run_circuit(circuit, params, feats, psi0)
     lam = observable_cotangent(psi_G, dexpz) if dexpz is not None \
         else np.asarray(lam_final, dtype=np.complex128).copy()
     psi = psi_G.copy()
     gtheta = np.zeros((B, circuit.n_gates))
     for g in range(circuit.n_gates - 1, -1, -1):
         gate = circuit.gates[g]
+        if int(gate["op"]) in _CHANNELS:  # outcome held fixed: no gradient here
+            u = np.asarray(feats, dtype=np.float64)[:, int(gate["feat"])]
+            lam, _ = channel_cotangent(pre[g], gate, u, lam)
+            psi = pre[g].copy()
+            continue
         theta = None
         if int(gate["op"]) in _ROT:
             theta = gate_angles(gate, params, feats, B)

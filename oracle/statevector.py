@@ -14,6 +14,7 @@ from workloads.circuits import OP
 _RX, _RY, _RZ = OP["RX"], OP["RY"], OP["RZ"]
 _X, _Y, _Z, _H = OP["X"], OP["Y"], OP["Z"], OP["H"]
 _CNOT, _CZ = OP["CNOT"], OP["CZ"]
+_RESET, _MEASURE = OP["RESET"], OP["MEASURE"]
 
 
 def gate_matrix(op: int, theta=None) -> np.ndarray:
@@ -129,14 +130,71 @@ def encode_zero(B: int, n: int) -> np.ndarray:
     return psi
 
 
+def channel_probabilities(psi: np.ndarray, q: int) -> np.ndarray:
+    """p[b, m] = sum of |psi_bi|^2 over the amplitudes whose bit q is m (FP64)."""
+    B, N = psi.shape
+    v = psi.reshape(B, N >> (q + 1), 2, 1 << q)
+    return np.sum(np.abs(v) ** 2, axis=(1, 3))
+
+
+def apply_channel(psi: np.ndarray, gate, u: np.ndarray):
+    """One trajectory of a mid-circuit measurement of qubit q0 in the Z basis
+    (projective-measurement postulate, Nielsen & Chuang sec. 2.2.3): outcome
+    m drawn from the Born probabilities p_m by the uniform u (inverse CDF,
+    ``trajectory_outcome``), the state projected on bit q0 = m and
+    renormalised by sqrt(p_m); RESET then moves it to bit q0 = 0 (the reset
+    channel's Kraus operator |0><m|), MEASURE keeps it. A row of zeros gives
+    outcome 0 and NaN. Returns (psi' [B, N], m [B], p_m [B])."""
+    B, N = psi.shape
+    q = int(gate["q0"])
+    p = channel_probabilities(psi, q)
+    m = trajectory_outcome(p, np.asarray(u, dtype=np.float64))
+    rows = np.arange(B)
+    v = psi.reshape(B, N >> (q + 1), 2, 1 << q)
+    pm = p[rows, m]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        kept = v[rows, :, m, :] / np.sqrt(pm)[:, None, None]
+    out = np.zeros_like(v)
+    dst = np.zeros(B, dtype=np.int64) if int(gate["op"]) == _RESET else m
+    out[rows, :, dst, :] = kept
+    return out.reshape(B, N), m, pm
+
+
+def channel_cotangent(psi_pre: np.ndarray, gate, u: np.ndarray, lam: np.ndarray):
+    """Cotangent before a channel from the cotangent ``lam`` after it, the
+    drawn outcome m held fixed (pathwise; convention dL = 2 Re<lam|d psi>).
+    With phi = K psi (K = |0><m| or Pi_m on qubit q0), r = ||phi|| =
+    sqrt(p_m) and psi' = phi / r: d psi' = d phi / r - psi' Re<psi'|d phi> / r,
+    so the cotangent of phi is (lam - Re<lam|psi'> psi') / r and that of psi
+    is K^dagger of it. Returns (lam_pre [B, N], psi' [B, N])."""
+    B, N = psi_pre.shape
+    q = int(gate["q0"])
+    post, m, pm = apply_channel(psi_pre, gate, u)
+    c = np.real(np.sum(np.conj(lam) * post, axis=1))
+    g = (lam - c[:, None] * post) / np.sqrt(pm)[:, None]
+    rows = np.arange(B)
+    gv = g.reshape(B, N >> (q + 1), 2, 1 << q)
+    src = np.zeros(B, dtype=np.int64) if int(gate["op"]) == _RESET else m
+    out = np.zeros_like(gv)
+    out[rows, :, m, :] = gv[rows, :, src, :]  # K^dagger: slice src of g -> slice m
+    return out.reshape(B, N), post
+
+
 def run_circuit(circuit, params, feats, psi, theta_override=None):
-    """psi_G = U_G ... U_1 psi, gates in descriptor order. ``theta_override``
-    maps a gate index to a replacement angle array (parameter shift)."""
+    """psi_G = U_G ... U_1 psi, gates in descriptor order (a channel gate is
+    one trajectory, ``apply_channel``, its uniform read from feats).
+    ``theta_override`` maps a gate index to a replacement angle array
+    (parameter shift)."""
     B = psi.shape[0]
     psi = psi.copy()
     for g, gate in enumerate(circuit.gates):
+        op = int(gate["op"])
+        if op in (_RESET, _MEASURE):
+            u = np.asarray(feats, dtype=np.float64)[:, int(gate["feat"])]
+            psi = apply_channel(psi, gate, u)[0]
+            continue
         theta = None
-        if int(gate["op"]) in (_RX, _RY, _RZ):
+        if op in (_RX, _RY, _RZ):
             theta = gate_angles(gate, params, feats, B)
             if theta_override is not None and g in theta_override:
                 theta = theta_override[g]

@@ -538,6 +538,131 @@ def test_weighted_z_gradient_through_the_26_qubit_structure_matches_fd(rng):
     np.testing.assert_allclose(gth, np.einsum("bgk,k->bg", J, g), atol=1e-12)
 
 
+# ------------------------------------------------- mid-circuit channels
+def _chan_circuit(rows, n, n_params=0, n_features=1):
+    return C.Circuit(n, np.array(rows, dtype=C.GATE_DTYPE), n_params, n_features)
+
+
+def test_channel_hand_values():
+    gv = GOLD["channel_plus"]
+    for kind in ("reset", "measure"):
+        c = _chan_circuit([(OPS["H"], 0, -1, -1, -1, -1, 0.0, 0),
+                           (OPS[kind.upper()], 0, -1, -1, 0, -1, 0.0, 0)], 1)
+        for u, want in zip(gv["u"], gv[kind]):
+            out = O.run_circuit(c, np.zeros(0), np.array([[u]]), O.encode_zero(1, 1))
+            np.testing.assert_allclose(out[0], want, atol=1e-12)
+    gv = GOLD["channel_ry"]
+    c = _chan_circuit([(OPS["RY"], 0, -1, -1, -1, -1, gv["theta"], 0),
+                       (OPS["MEASURE"], 0, -1, -1, 0, -1, 0.0, 0)], 1)
+    for u, want in zip(gv["u"], gv["measure"]):
+        out = O.run_circuit(c, np.zeros(0), np.array([[u]]), O.encode_zero(1, 1))
+        np.testing.assert_allclose(out[0], want, atol=1e-12)
+    gv = GOLD["channel_bell"]
+    for kind, idx in (("MEASURE", gv["measure_index"]), ("RESET", gv["reset_index"])):
+        c = _chan_circuit([(OPS["H"], 0, -1, -1, -1, -1, 0.0, 0),
+                           (OPS["CNOT"], 0, 1, -1, -1, -1, 0.0, 0),
+                           (OPS[kind], 1, -1, -1, 0, -1, 0.0, 0)], 2)
+        out = O.run_circuit(c, np.zeros(0), np.array([[gv["u"]]]), O.encode_zero(1, 2))
+        want = np.zeros(4)
+        want[idx] = 1.0
+        np.testing.assert_allclose(out[0], want, atol=1e-12)
+
+
+@pytest.mark.parametrize("kind", ["RESET", "MEASURE"])
+@pytest.mark.parametrize("n,q", [(1, 0), (3, 0), (3, 2), (4, 1)])
+def test_channel_trajectories_average_to_the_kraus_channel(n, q, kind, rng):
+    """Averaged over outcomes (weights p_m), the trajectory states are the
+    channel applied to the density matrix, with Kraus operators |0><m| (reset)
+    or |m><m| (measurement) built by Kronecker products."""
+    from _brute import embed
+    psi = O.encode_amplitude(rng.standard_normal((1, 1 << n)), n)
+    psi = psi * np.exp(1j * rng.uniform(0, 2 * np.pi, psi.shape))
+    rho = np.outer(psi[0], np.conj(psi[0]))
+    ket = [np.array([[1, 0], [0, 0]], complex), np.array([[0, 0], [0, 1]], complex)]
+    lower = np.array([[0, 1], [0, 0]], complex)  # |0><1|
+    K = [embed(n, q, ket[0]), embed(n, q, lower if kind == "RESET" else ket[1])]
+    want = sum(k @ rho @ k.conj().T for k in K)
+    g = np.array([(OPS[kind], q, -1, -1, 0, -1, 0.0, 0)], dtype=C.GATE_DTYPE)[0]
+    p = np.array([np.real(np.vdot(psi[0], embed(n, q, ket[m]) @ psi[0])) for m in (0, 1)])
+    got = np.zeros_like(rho)
+    for m in (0, 1):
+        if p[m] <= 0:
+            continue
+        u = (p[:m].sum() + 0.5 * p[m]) / p.sum()  # inside outcome m's interval
+        out, mm, pm = O.apply_channel(psi, g, np.array([u]))
+        assert mm[0] == m and abs(pm[0] - p[m]) < 1e-12
+        got += p[m] * np.outer(out[0], np.conj(out[0]))
+    np.testing.assert_allclose(got, want, atol=1e-12)
+
+
+def test_channel_on_a_qubit_in_zero_is_the_identity(rng):
+    n, q = 4, 2
+    c = _chan_circuit([(OPS["RESET"], q, -1, -1, 0, -1, 0.0, 0),
+                       (OPS["MEASURE"], q, -1, -1, 1, -1, 0.0, 0)], n, n_features=2)
+    psi = O.encode_amplitude(rng.standard_normal((3, 1 << n)), n)
+    idx = np.arange(1 << n)
+    psi[:, (idx >> q) & 1 == 1] = 0
+    psi /= np.linalg.norm(psi, axis=1, keepdims=True)
+    out = O.run_circuit(c, np.zeros(0), rng.uniform(0, 1, (3, 2)), psi)
+    np.testing.assert_allclose(out, psi, atol=1e-13)
+
+
+def _stable_uniforms(c, params, feats, psi0, first_u):
+    """Sets each channel's uniform (columns first_u ...) to the middle of the
+    interval of the outcome it draws, so that small parameter changes keep
+    every outcome (the pathwise gradient then equals finite differences)."""
+    feats = feats.copy()
+    B = psi0.shape[0]
+    for g, gate in enumerate(c.gates):
+        if int(gate["op"]) not in C.CHANNELS:
+            continue
+        pre = O.run_circuit(C.Circuit(c.n_qubits, c.gates[:g], c.n_params, c.n_features),
+                            params, feats, psi0)
+        p = O.channel_probabilities(pre, int(gate["q0"]))
+        m = O.trajectory_outcome(p, np.full(B, 0.5))
+        tot = p.sum(axis=1)
+        lo = np.where(m == 1, p[:, 0], 0.0)
+        feats[:, int(gate["feat"])] = (lo + 0.5 * p[np.arange(B), m]) / tot
+    return feats
+
+
+@pytest.mark.parametrize("per_sample", [False, True])
+def test_channel_gradients_adjoint_vs_fd(rng, per_sample):
+    """Rotations before, between and after two channels (one reset, one
+    measurement), with features: the adjoint through the channels (outcomes
+    held fixed) equals central differences of the loss, for a <Z> loss and for
+    a state cotangent."""
+    n, B = 4, 3
+    base = C.random_circuit(n, 36, rng, n_params=6, n_features=2)
+    c = C.with_channels(base, [12, 25], rng)
+    P = c.n_params
+    params = rng.uniform(-np.pi, np.pi, (B, P) if per_sample else P)
+    psi0 = O.encode_amplitude(rng.standard_normal((B, 1 << n)), n)
+    feats = np.concatenate([rng.uniform(-1, 1, (B, 2)), np.full((B, 2), 0.5)], axis=1)
+    feats = _stable_uniforms(c, params, feats, psi0, 2)
+    wts = rng.uniform(-1, 1, (B, n))
+
+    def loss(p, f):
+        return float(np.sum(wts * O.expz(O.run_circuit(c, p, f, psi0))))
+
+    gth, _ = O.adjoint_vjp(c, params, feats, psi0, dexpz=wts)
+    dp, df = O.theta_to_param_grads(c, params, feats, gth)
+    np.testing.assert_allclose(dp, O.finite_difference(lambda p: loss(p, feats), params.copy()),
+                               atol=1e-7)
+    fd_f = O.finite_difference(lambda f: loss(params, f), feats.copy())
+    np.testing.assert_allclose(df[:, :2], fd_f[:, :2], atol=1e-7)
+    assert np.all(df[:, 2:] == 0)
+    # a state cotangent: L = 2 Re <a | psi_G>
+    a = rng.standard_normal((B, 1 << n)) + 1j * rng.standard_normal((B, 1 << n))
+
+    def loss2(p):
+        return float(2 * np.real(np.sum(np.conj(a) * O.run_circuit(c, p, feats, psi0))))
+
+    gth2, _ = O.adjoint_vjp(c, params, feats, psi0, lam_final=a)
+    dp2, _ = O.theta_to_param_grads(c, params, feats, gth2)
+    np.testing.assert_allclose(dp2, O.finite_difference(loss2, params.copy()), atol=1e-7)
+
+
 def test_fidelity_gradients_adjoint_shift_fd(rng):
     n, t, B = 4, 2, 2
     enc = C.ry_rz_chain(n, 2)

@@ -30,9 +30,12 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-# Gate kinds. The numbering is part of the descriptor format.
+# Gate kinds. The numbering is part of the descriptor format. RESET and
+# MEASURE are mid-circuit channels on qubit q0: one trajectory, its outcome
+# drawn from the uniform X[b, feat] (then reset to |0>, or kept).
 OP = {"RX": 0, "RY": 1, "RZ": 2, "X": 3, "Y": 4, "Z": 5, "H": 6,
-      "CNOT": 7, "CZ": 8}
+      "CNOT": 7, "CZ": 8, "RESET": 9, "MEASURE": 10}
+CHANNELS = (OP["RESET"], OP["MEASURE"])
 OP_NAMES = {v: k for k, v in OP.items()}
 ROTATIONS = (OP["RX"], OP["RY"], OP["RZ"])
 
@@ -84,6 +87,10 @@ class _Builder:
 
     def fixed(self, kind: str, q0: int, q1: int = -1):
         self.rows.append((OP[kind], q0, q1, -1, -1, -1, 0.0, 0))
+
+    def channel(self, kind: str, q: int, feat: int):
+        """A mid-circuit RESET or MEASURE of qubit q; its uniform is X[b, feat]."""
+        self.rows.append((OP[kind], q, -1, -1, feat, -1, 0.0, 0))
 
     def end_layer(self):
         self.layer_end.append(len(self.rows))
@@ -223,3 +230,23 @@ def random_circuit(n: int, n_gates: int, rng: np.random.Generator,
         else:
             b.fixed(k, int(rng.integers(n)))
     return b.build(n_features=n_features, name=f"random{n}q{n_gates}g")
+
+
+def with_channels(c: Circuit, where, rng: np.random.Generator,
+                  kinds=("RESET", "MEASURE")) -> Circuit:
+    """A copy of ``c`` with a channel inserted before each gate index in
+    ``where`` (ascending), each on a seeded random qubit, alternating
+    ``kinds``; each channel reads its uniform from a new feature column
+    appended after the circuit's own (so n_features grows by len(where))."""
+    rows = [tuple(r) for r in c.gates.tolist()]
+    out, k = [], 0
+    for g in range(len(rows) + 1):
+        while k < len(where) and where[k] == g:
+            q = int(rng.integers(c.n_qubits))
+            out.append((OP[kinds[k % len(kinds)]], q, -1, -1, c.n_features + k, -1, 0.0, 0))
+            k += 1
+        if g < len(rows):
+            out.append(rows[g])
+    g = np.array(out, dtype=GATE_DTYPE)
+    return Circuit(c.n_qubits, g, c.n_params, c.n_features + len(where), [],
+                   c.name + "+channels")
