@@ -66,8 +66,29 @@ enum {
   QS_OP_X = 3, QS_OP_Y = 4, QS_OP_Z = 5,    /* Paulis                        */
   QS_OP_H = 6,                              /* Hadamard                      */
   QS_OP_CNOT = 7,                           /* q0 = control, q1 = target     */
-  QS_OP_CZ = 8                              /* symmetric in q0, q1           */
+  QS_OP_CZ = 8,                             /* symmetric in q0, q1           */
+  QS_OP_RESET = 9,   /* mid-circuit channels on qubit q0, see below          */
+  QS_OP_MEASURE = 10
 };
+
+/* Mid-circuit channels (one quantum trajectory per sample; the projective
+ * measurement postulate, Nielsen & Chuang sec. 2.2.3). Qubit q0 is measured
+ * in the Z basis: with p_m the FP64 sum of |psi_i|^2 over the amplitudes
+ * whose bit q0 is m, the outcome is the smallest m with
+ * u (p_0 + p_1) < p_0 + ... + p_m (else the last m with p_m > 0), u being
+ * the sample's uniform feats[b][feat] in [0, 1) (random numbers are inputs);
+ * the state is projected on bit q0 = m and divided by sqrt(p_m), and
+ * QS_OP_RESET then moves it to bit q0 = 0 (Kraus operator |0><m|) while
+ * QS_OP_MEASURE keeps it. Gradients hold the drawn outcome fixed (pathwise):
+ * through the renormalisation, the cotangent in front of the channel is
+ * K^dagger (lam' - Re<lam'|psi'> psi') / sqrt(p_m); no gradient reaches u.
+ * A channel gate needs q1 = -1 and 0 <= feat < n_features (p_w, p_b, scale
+ * are ignored). Circuits with channels run on the register/LDS engine
+ * (QS_PATH_AUTO or QS_PATH_FUSED; other paths, QS_FLAG_INVERSE, the planning
+ * and tuning calls and uneven-batch programs return QS_ERR_UNSUPPORTED or
+ * QS_ERR_INVALID), and qs_forward / qs_adjoint_backward need a checkpoint at
+ * every channel's gate index (the state in front of it, which the adjoint
+ * restarts from; QS_ERR_INVALID otherwise). */
 
 /* One gate, 32 bytes. The angle of a rotation on sample b is
  *   theta_b = scale * (w * f + bias),
@@ -167,8 +188,9 @@ int qs_encode_check(const int32_t* bad_rows, void* stream);
  *   state    (device) [B][2^n] complex, in: encoded input, out: final state
  *   expz     (device, optional) [B][n] double, receives <Z_q>_b summed in FP64
  *   ckpt_gates (host, optional) n_ckpt strictly increasing gate counts in
- *            (0, n_gates); after the first ckpt_gates[i] gates the state is
- *            copied to ckpt + i * B * 2^n (complex elements)
+ *            (0, n_gates) (0 is allowed when gate 0 is a channel); after the
+ *            first ckpt_gates[i] gates the state is copied to
+ *            ckpt + i * B * 2^n (complex elements)
  *   ckpt     (device) [n_ckpt][B][2^n] complex, required when n_ckpt > 0
  *   flags    path selection (QS_PATH_*) | QS_FLAG_PER_SAMPLE_PARAMS */
 int qs_forward(const qs_circuit* circuit, int dtype, int64_t B,

@@ -102,6 +102,101 @@ encode_zero(int n, int64_t total, real* state) {
   }
 }
 
+// Mid-circuit measurement of qubit q in the Z basis, one trajectory per
+// sample (projective-measurement postulate, Nielsen & Chuang sec. 2.2.3):
+// p_m = sum of |psi_i|^2 over the amplitudes whose bit q is m (FP64), the
+// outcome m drawn from the uniform u by inverse CDF (the smallest m with
+// u (p_0 + p_1) < p_0 + ... + p_m, else the last m with p_m > 0), the state
+// projected on bit q = m and divided by sqrt(p_m); a reset then moves it to
+// bit q = 0. One workgroup per sample; amplitude pairs (i0, i0 | 1 << q).
+struct ChanDraw {
+  int m;
+  double inv;  // 1 / sqrt(p_m)
+};
+
+template <typename real>
+__device__ ChanDraw channel_draw(int n, int q, const real* s, double u, double* sh) {
+  const int64_t half = 1ll << (n - 1);
+  const int64_t lo = (1ll << q) - 1;
+  double p0 = 0, p1 = 0;
+  for (int64_t k = threadIdx.x; k < half; k += blockDim.x) {
+    const int64_t i0 = ((k & ~lo) << 1) | (k & lo), i1 = i0 | (1ll << q);
+    const double a = s[2 * i0], b = s[2 * i0 + 1], c = s[2 * i1], d = s[2 * i1 + 1];
+    p0 += a * a + b * b;
+    p1 += c * c + d * d;
+  }
+  p0 = block_sum(p0, sh);
+  p1 = block_sum(p1, sh);
+  const double x = u * (p0 + p1);
+  int m = x < p0 ? 0 : (x < p0 + p1 ? 1 : (p1 > 0 ? 1 : 0));
+  const double pm = m ? p1 : p0;
+  return ChanDraw{m, 1.0 / sqrt(pm)};  // p_m = 0 only for a zero row: NaN
+}
+
+template <typename real>
+__global__ void __launch_bounds__(kBlock)
+channel_forward(int n, int q, int reset, const real* feats, int n_feats, int feat,
+                real* state) {
+  __shared__ double sh[kBlock / 64];
+  const int64_t b = blockIdx.x;
+  real* s = state + 2 * b * (1ll << n);
+  const ChanDraw d = channel_draw(n, q, s, (double)feats[b * n_feats + feat], sh);
+  const int64_t half = 1ll << (n - 1), lo = (1ll << q) - 1;
+  for (int64_t k = threadIdx.x; k < half; k += blockDim.x) {
+    const int64_t i0 = ((k & ~lo) << 1) | (k & lo), i1 = i0 | (1ll << q);
+    const int64_t src = d.m ? i1 : i0;
+    const double re = (double)s[2 * src] * d.inv, im = (double)s[2 * src + 1] * d.inv;
+    const int64_t dst = reset ? i0 : src, other = dst == i0 ? i1 : i0;
+    s[2 * dst] = (real)re;
+    s[2 * dst + 1] = (real)im;
+    s[2 * other] = 0;
+    s[2 * other + 1] = 0;
+  }
+}
+
+// Backward through the channel with its outcome held fixed (pathwise; state
+// cotangents with dL = 2 Re<lam|d psi>): from the stored state in front of
+// the channel, psi' = K psi / r (K = |0><m| or the projector on m, r =
+// sqrt(p_m)); the cotangent in front is K^dagger (lam' - Re<lam'|psi'> psi')
+// / r. lam is updated in place, psi_out receives the state in front.
+template <typename real>
+__global__ void __launch_bounds__(kBlock)
+channel_adjoint(int n, int q, int reset, const real* feats, int n_feats, int feat,
+                const real* psi_pre, real* lam, real* psi_out) {
+  __shared__ double sh[kBlock / 64];
+  const int64_t b = blockIdx.x, N = 1ll << n;
+  const real* s = psi_pre + 2 * b * N;
+  real* l = lam + 2 * b * N;
+  const ChanDraw d = channel_draw(n, q, s, (double)feats[b * n_feats + feat], sh);
+  const int64_t half = 1ll << (n - 1), lo = (1ll << q) - 1;
+  // psi' is nonzero only at dst = (reset ? i0 : the outcome's index)
+  double c = 0;
+  for (int64_t k = threadIdx.x; k < half; k += blockDim.x) {
+    const int64_t i0 = ((k & ~lo) << 1) | (k & lo), i1 = i0 | (1ll << q);
+    const int64_t src = d.m ? i1 : i0, dst = reset ? i0 : src;
+    const double pr = (double)s[2 * src] * d.inv, pi = (double)s[2 * src + 1] * d.inv;
+    c += (double)l[2 * dst] * pr + (double)l[2 * dst + 1] * pi;
+  }
+  c = block_sum(c, sh);
+  for (int64_t k = threadIdx.x; k < half; k += blockDim.x) {
+    const int64_t i0 = ((k & ~lo) << 1) | (k & lo), i1 = i0 | (1ll << q);
+    const int64_t src = d.m ? i1 : i0, dst = reset ? i0 : src;
+    const double pr = (double)s[2 * src] * d.inv, pi = (double)s[2 * src + 1] * d.inv;
+    const double gr = ((double)l[2 * dst] - c * pr) * d.inv;
+    const double gi = ((double)l[2 * dst + 1] - c * pi) * d.inv;
+    const int64_t other = src == i0 ? i1 : i0;  // K^dagger: slice dst -> slice src
+    l[2 * src] = (real)gr;
+    l[2 * src + 1] = (real)gi;
+    l[2 * other] = 0;
+    l[2 * other + 1] = 0;
+    real* o = psi_out + 2 * b * N;
+    o[2 * i0] = s[2 * i0];
+    o[2 * i0 + 1] = s[2 * i0 + 1];
+    o[2 * i1] = s[2 * i1];
+    o[2 * i1 + 1] = s[2 * i1 + 1];
+  }
+}
+
 // <Z_q> for q < 32: grid (blocks_per_sample, B); partial sums in registers
 // (compile-time indexed), block sums, FP64 atomics into a zeroed expz.
 template <typename real>
@@ -429,6 +524,35 @@ int launch_program_encode(int dtype, int n_classes, const int64_t* cum,
       hipLaunchKernelGGL((encode_program<double, float>), g, kBlock, 0, st, n_classes,
                          cum, nq, state_off, (const float*)x, (double*)states, bad_rows);
   }
+  return ok();
+}
+
+int launch_channel(int dtype, int n, int q, int reset, int64_t B, const void* feats,
+                   int n_feats, int feat, void* state, void* stream) {
+  if (B == 0) return QS_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dtype == QS_C64)
+    hipLaunchKernelGGL(channel_forward<float>, dim3((unsigned)B), kBlock, 0, st, n, q, reset,
+                       (const float*)feats, n_feats, feat, (float*)state);
+  else
+    hipLaunchKernelGGL(channel_forward<double>, dim3((unsigned)B), kBlock, 0, st, n, q, reset,
+                       (const double*)feats, n_feats, feat, (double*)state);
+  return ok();
+}
+
+int launch_channel_adjoint(int dtype, int n, int q, int reset, int64_t B, const void* feats,
+                           int n_feats, int feat, const void* psi_pre, void* lam,
+                           void* psi_out, void* stream) {
+  if (B == 0) return QS_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dtype == QS_C64)
+    hipLaunchKernelGGL(channel_adjoint<float>, dim3((unsigned)B), kBlock, 0, st, n, q, reset,
+                       (const float*)feats, n_feats, feat, (const float*)psi_pre,
+                       (float*)lam, (float*)psi_out);
+  else
+    hipLaunchKernelGGL(channel_adjoint<double>, dim3((unsigned)B), kBlock, 0, st, n, q, reset,
+                       (const double*)feats, n_feats, feat, (const double*)psi_pre,
+                       (double*)lam, (double*)psi_out);
   return ok();
 }
 

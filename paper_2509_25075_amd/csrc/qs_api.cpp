@@ -69,7 +69,12 @@ int validate(const qs_circuit* c) {
   if (c->n_gates > 0 && !c->gates) return QS_ERR_INVALID;
   for (int g = 0; g < c->n_gates; ++g) {
     const qs_gate& x = c->gates[g];
-    if (x.op < QS_OP_RX || x.op > QS_OP_CZ || x.flags != 0) return QS_ERR_INVALID;
+    if (x.op < QS_OP_RX || x.op > QS_OP_MEASURE || x.flags != 0) return QS_ERR_INVALID;
+    if (x.op == QS_OP_RESET || x.op == QS_OP_MEASURE) {  // uniform = feats[b][feat]
+      if (x.q0 < 0 || x.q0 >= c->n_qubits || x.q1 != -1) return QS_ERR_INVALID;
+      if (x.feat < 0 || x.feat >= c->n_features) return QS_ERR_INVALID;
+      continue;
+    }
     if (x.q0 < 0 || x.q0 >= c->n_qubits) return QS_ERR_INVALID;
     if (x.op == QS_OP_CNOT || x.op == QS_OP_CZ) {
       if (x.q1 < 0 || x.q1 >= c->n_qubits || x.q1 == x.q0) return QS_ERR_INVALID;
@@ -85,13 +90,23 @@ int validate(const qs_circuit* c) {
   return QS_OK;
 }
 
+bool is_channel(int op) { return op == QS_OP_RESET || op == QS_OP_MEASURE; }
+
+bool has_channels(const qs_circuit& c) {
+  for (int g = 0; g < c.n_gates; ++g)
+    if (is_channel(c.gates[g].op)) return true;
+  return false;
+}
+
 int check_ckpt(const qs_circuit* c, const int32_t* ck, int32_t n_ck,
                const void* buf) {
   if (n_ck < 0) return QS_ERR_INVALID;
   if (n_ck == 0) return QS_OK;
   if (!ck || !buf) return QS_ERR_INVALID;
   for (int i = 0; i < n_ck; ++i) {
-    if (ck[i] <= 0 || ck[i] >= c->n_gates) return QS_ERR_INVALID;
+    // count 0 (the input state) only in front of a channel at gate 0
+    const bool zero_ok = ck[i] == 0 && c->n_gates > 0 && is_channel(c->gates[0].op);
+    if ((ck[i] <= 0 && !zero_ok) || ck[i] >= c->n_gates) return QS_ERR_INVALID;
     if (i > 0 && ck[i] <= ck[i - 1]) return QS_ERR_INVALID;
   }
   return QS_OK;
@@ -597,7 +612,7 @@ constexpr int kDbK = 5;
 constexpr int kDbGrid = 512;  // persistent workgroups (two per CU of 256)
 
 bool db_supported(const qs_circuit& c, int dtype, bool ps) {
-  if (dtype != QS_C64 || ps || c.n_qubits < kDbK + 5) return false;
+  if (dtype != QS_C64 || ps || c.n_qubits < kDbK + 5 || has_channels(c)) return false;
   for (int g = 0; g < c.n_gates; ++g)
     if (is_rotation(c.gates[g].op) && c.gates[g].feat >= 0) return false;
   return true;
@@ -890,6 +905,154 @@ size_t fused_ws_bytes(const qs_circuit& c, int dtype, const SvShape& s, int64_t 
 bool tuned_for_call(const qs_circuit& c, int dtype, int64_t B, int flags, void* stream,
                     TuneVal* out);
 
+// ------------------------------------- circuits with mid-circuit channels
+// A circuit with RESET / MEASURE gates runs as unitary runs between them:
+// each run through the register/LDS engine, each channel as its own kernel
+// (one trajectory per sample). The state in front of every channel must be
+// stored as a checkpoint (a checkpoint at the channel's gate index): the
+// adjoint cannot un-apply a channel, it restarts from that state.
+struct Run {
+  int b, e, ch;  // gates [b, e), then channel gate ch (-1 after the last run)
+};
+std::vector<Run> unitary_runs(const qs_circuit& c) {
+  std::vector<Run> runs;
+  int b = 0;
+  for (int g = 0; g < c.n_gates; ++g)
+    if (is_channel(c.gates[g].op)) {
+      runs.push_back({b, g, g});
+      b = g + 1;
+    }
+  runs.push_back({b, c.n_gates, -1});
+  return runs;
+}
+int slot_of(const int32_t* ck, int n_ck, int count) {
+  for (int i = 0; i < n_ck; ++i)
+    if (ck[i] == count) return i;
+  return -1;
+}
+qs_circuit run_circuit_of(const qs_circuit& c, const Run& r) {
+  return qs_circuit{c.n_qubits, r.e - r.b, c.n_params, c.n_features,
+                    r.e > r.b ? c.gates + r.b : nullptr};
+}
+// Checkpoints strictly inside run r, as gate counts of the run, and the slot
+// of the first of them.
+void run_ckpts(const int32_t* ck, int n_ck, const Run& r, std::vector<int32_t>& rel,
+               int* first) {
+  rel.clear();
+  *first = 0;
+  for (int i = 0; i < n_ck; ++i)
+    if (ck[i] > r.b && ck[i] < r.e) {
+      if (rel.empty()) *first = i;
+      rel.push_back(ck[i] - r.b);
+    }
+}
+// Register/LDS engine only (the adjoint needs each run's cotangent at its
+// start), no inverse, a checkpoint at every channel.
+int channels_check(const qs_circuit& c, int flags, const int32_t* ck, int n_ck) {
+  const int path = flags & QS_PATH_MASK;
+  if (path != QS_PATH_AUTO && path != QS_PATH_FUSED) return QS_ERR_UNSUPPORTED;
+  for (const Run& r : unitary_runs(c))
+    if (r.ch >= 0 && slot_of(ck, n_ck, r.ch) < 0) return QS_ERR_INVALID;
+  return QS_OK;
+}
+// Adjoint workspace: psi and lam of the whole batch, then the largest run's
+// partial-sum area.
+size_t channel_ws_bytes(const qs_circuit& c, int dtype, int64_t B, int flags) {
+  const int path = flags & QS_PATH_MASK;
+  if (path != QS_PATH_AUTO && path != QS_PATH_FUSED) return 0;
+  const bool ps = (flags & QS_FLAG_PER_SAMPLE_PARAMS) != 0;
+  size_t part = 0;
+  for (const Run& r : unitary_runs(c)) {
+    if (r.e == r.b) continue;
+    const qs_circuit sub = run_circuit_of(c, r);
+    SvShape sh;
+    if (pick_path(sub, dtype, (flags & ~QS_PATH_MASK) | QS_PATH_FUSED, &sh,
+                  count_slots(sub, ps), true) != QS_PATH_FUSED)
+      return 0;
+    part = std::max(part, fused_ws_bytes(sub, dtype, sh, B, ps));
+  }
+  const size_t st = (((size_t)B << c.n_qubits) * (dtype == QS_C64 ? 8 : 16) + 255) & ~(size_t)255;
+  return 2 * st + part;
+}
+
+int adjoint_channels(const qs_circuit& c, int dtype, int64_t B, const void* params,
+                     const void* feats, const void* state, const double* dexpz,
+                     const void* dstate, double* grad_params, double* grad_feats,
+                     const int32_t* ck, int n_ck, const void* ckpt, void* ws, int flags,
+                     void* stream) {
+  const bool ps = (flags & QS_FLAG_PER_SAMPLE_PARAMS) != 0;
+  const int sub_flags = (flags & ~QS_PATH_MASK) | QS_PATH_FUSED;
+  const int64_t per = B << c.n_qubits;
+  const size_t cs = dtype == QS_C64 ? 8 : 16;
+  const size_t st = (per * cs + 255) & ~(size_t)255;
+  char* psi_w = static_cast<char*>(ws);
+  char* lam_w = psi_w + st;
+  void* part = lam_w + st;
+  const char* cb = static_cast<const char*>(ckpt);
+  int rc = launch_copy_state(dtype, state, psi_w, per, stream);
+  if (rc != QS_OK) return rc;
+  rc = dstate ? launch_copy_state(dtype, dstate, lam_w, per, stream)
+              : launch_obs_cot(dtype, c.n_qubits, B, dexpz, psi_w, lam_w, stream);
+  if (rc != QS_OK) return rc;
+  if (c.n_params && (rc = launch_fill_f64(grad_params, ps ? B * c.n_params : c.n_params,
+                                          stream)) != QS_OK)
+    return rc;
+  if (c.n_features && grad_feats &&
+      (rc = launch_fill_f64(grad_feats, B * c.n_features, stream)) != QS_OK)
+    return rc;
+  const std::vector<Run> runs = unitary_runs(c);
+  std::vector<int32_t> rel;
+  for (int k = (int)runs.size() - 1; k >= 0; --k) {
+    const Run& r = runs[k];
+    if (r.e > r.b) {  // the run backwards, psi and lam in place at its start
+      const qs_circuit sub = run_circuit_of(c, r);
+      int first = 0;
+      run_ckpts(ck, n_ck, r, rel, &first);
+      const int32_t* rk = rel.empty() ? nullptr : rel.data();
+      TuneVal tv;
+      const bool tuned = tuned_for_call(sub, dtype, B, sub_flags, stream, &tv);
+      SvShape shape;
+      if (pick_path(sub, dtype, sub_flags, &shape, count_slots(sub, ps), true,
+                    tuned ? &tv : nullptr, rk, (int)rel.size()) != QS_PATH_FUSED)
+        return QS_ERR_UNSUPPORTED;
+      Entry* e = get_plan(sub, shape.r, ps, rk, (int)rel.size(), &rc);
+      if (!e) return rc;
+      if (!tables_fit(*e, dtype, sub, shape, ps, true)) return QS_ERR_UNSUPPORTED;
+      SvLaunch L{};
+      L.p = &e->dev;
+      L.shape = shape;
+      L.B = B;
+      L.per_sample_params = ps;
+      L.params = params;
+      L.feats = feats;
+      L.state = psi_w;
+      L.dstate = lam_w;
+      L.out_psi = psi_w;
+      L.out_lam = lam_w;
+      L.ckpt = rel.empty() ? nullptr : const_cast<char*>(cb) + cs * per * first;
+      L.ws_partials = part;
+      L.grad_params = grad_params;
+      L.grad_feats = c.n_features ? grad_feats : nullptr;
+      L.accum_feats = 1;
+      L.stream = stream;
+      if ((rc = launch_sv_adjoint(dtype, L)) != QS_OK) return rc;
+      if (!ps && e->dev.n_acc &&
+          (rc = launch_reduce_partials(dtype, part, grid_of(shape, B), e->dev.n_acc,
+                                       e->dev.grad_cols, grad_params, 1, stream)) != QS_OK)
+        return rc;
+    }
+    if (k == 0) break;
+    // the channel in front of this run: restart from the state stored there
+    const int ch = runs[k - 1].ch;
+    const qs_gate& g = c.gates[ch];
+    rc = launch_channel_adjoint(dtype, c.n_qubits, g.q0, g.op == QS_OP_RESET, B, feats,
+                                c.n_features, g.feat, cb + cs * per * slot_of(ck, n_ck, ch),
+                                lam_w, psi_w, stream);
+    if (rc != QS_OK) return rc;
+  }
+  return QS_OK;
+}
+
 }  // namespace
 
 namespace qs {
@@ -920,8 +1083,10 @@ struct InvCircuit {
 };
 const qs_circuit* apply_inverse(const qs_circuit* c, int* flags, InvCircuit& inv) {
   if (!c || !(*flags & QS_FLAG_INVERSE)) return c;
-  *flags &= ~QS_FLAG_INVERSE;
   if (validate(c) != QS_OK) return c;  // the call itself reports it
+  // A channel has no inverse: the flag stays set and the call rejects it.
+  if (has_channels(*c)) return c;
+  *flags &= ~QS_FLAG_INVERSE;
   if (c->n_gates > 0 && c->gates) inv.g.assign(c->gates, c->gates + c->n_gates);
   std::reverse(inv.g.begin(), inv.g.end());
   for (qs_gate& x : inv.g)
@@ -998,6 +1163,7 @@ int qs_autotune(const qs_circuit* c, int dtype, int64_t B, int flags, void* stre
   c = apply_inverse(c, &flags, inv_);
   int rc = validate(c);
   if (rc != QS_OK) return rc;
+  if (has_channels(*c)) return QS_ERR_UNSUPPORTED;  // runs of the engine, planned per call
   if ((dtype != QS_C64 && dtype != QS_C128) || B < 1) return QS_ERR_INVALID;
   if (flags & ~(QS_PATH_MASK | QS_FLAG_PER_SAMPLE_PARAMS)) return QS_ERR_INVALID;
   const bool ps = (flags & QS_FLAG_PER_SAMPLE_PARAMS) != 0;
@@ -1262,6 +1428,42 @@ int qs_forward(const qs_circuit* c, int dtype, int64_t B, const void* params,
   if (c->n_features > 0 && !feats) return QS_ERR_INVALID;
   if ((rc = check_ckpt(c, ckpt_gates, n_ckpt, ckpt)) != QS_OK) return rc;
   const bool ps = (flags & QS_FLAG_PER_SAMPLE_PARAMS) != 0;
+  if (has_channels(*c)) {  // unitary runs through the engine, channels between them
+    if ((rc = channels_check(*c, flags, ckpt_gates, n_ckpt)) != QS_OK) return rc;
+    const int64_t per = B << c->n_qubits;
+    const size_t cs = dtype == QS_C64 ? 8 : 16;
+    char* cb = static_cast<char*>(ckpt);
+    const std::vector<Run> runs = unitary_runs(*c);
+    std::vector<int32_t> rel;
+    for (size_t k = 0; k < runs.size(); ++k) {
+      const Run& r = runs[k];
+      const bool last = k + 1 == runs.size();
+      if (r.e > r.b) {
+        const qs_circuit sub = run_circuit_of(*c, r);
+        int first = 0;
+        run_ckpts(ckpt_gates, n_ckpt, r, rel, &first);
+        rc = qs_forward(&sub, dtype, B, params, feats, state, last ? expz : nullptr,
+                        rel.empty() ? nullptr : rel.data(), (int32_t)rel.size(),
+                        rel.empty() ? nullptr : cb + cs * per * first,
+                        (flags & ~QS_PATH_MASK) | QS_PATH_FUSED, stream);
+      } else if (last && expz) {
+        rc = launch_expz(dtype, c->n_qubits, B, state, expz, stream);
+      }
+      if (rc != QS_OK) return rc;
+      if (r.ch < 0) continue;
+      const qs_gate& g = c->gates[r.ch];
+      rc = launch_copy_state(dtype, state, cb + cs * per * slot_of(ckpt_gates, n_ckpt, r.ch),
+                             per, stream);
+      if (rc == QS_OK)
+        rc = launch_channel(dtype, c->n_qubits, g.q0, g.op == QS_OP_RESET, B, feats,
+                            c->n_features, g.feat, state, stream);
+      const int after = slot_of(ckpt_gates, n_ckpt, r.ch + 1);  // state just after it
+      if (rc == QS_OK && after >= 0)
+        rc = launch_copy_state(dtype, state, cb + cs * per * after, per, stream);
+      if (rc != QS_OK) return rc;
+    }
+    return QS_OK;
+  }
   TuneVal tv;
   const bool tuned = tuned_for_call(*c, dtype, B, flags, stream, &tv);
   SvShape shape;
@@ -1350,6 +1552,7 @@ size_t qs_workspace_size(const qs_circuit* c, int dtype, int64_t B, int flags) {
   InvCircuit inv_;
   c = apply_inverse(c, &flags, inv_);
   if (validate(c) != QS_OK || B < 0) return 0;
+  if (has_channels(*c)) return channel_ws_bytes(*c, dtype, B, flags);
   const bool ps = (flags & QS_FLAG_PER_SAMPLE_PARAMS) != 0;
   TuneVal tv;
   const bool tuned = tuned_lookup(*c, dtype, B, flags, &tv);
@@ -1407,6 +1610,15 @@ int adjoint_backward_impl(const qs_circuit* c, int dtype, int64_t B, const void*
   if (c->n_params > 0 && (!params || !grad_params)) return QS_ERR_INVALID;
   if (c->n_features > 0 && !feats) return QS_ERR_INVALID;
   if ((rc = check_ckpt(c, ckpt_gates, n_ckpt, ckpt)) != QS_OK) return rc;
+  if (has_channels(*c)) {
+    if (no_alloc) return QS_ERR_UNSUPPORTED;
+    if ((rc = channels_check(*c, flags, ckpt_gates, n_ckpt)) != QS_OK) return rc;
+    const size_t need = channel_ws_bytes(*c, dtype, B, flags);
+    if (need == 0) return QS_ERR_UNSUPPORTED;
+    if (!ws || ws_bytes < need) return QS_ERR_WORKSPACE;
+    return adjoint_channels(*c, dtype, B, params, feats, state, dexpz, dstate, grad_params,
+                            grad_feats, ckpt_gates, n_ckpt, ckpt, ws, flags, stream);
+  }
   TuneVal tv;
   const bool tuned = tuned_for_call(*c, dtype, B, flags, stream, &tv);
   SvShape shape;
@@ -1632,6 +1844,7 @@ int qs_plan_info_get(const qs_circuit* c, int dtype, int64_t B, int flags,
   c = apply_inverse(c, &flags, inv_);
   int rc = validate(c);
   if (rc != QS_OK) return rc;
+  if (has_channels(*c)) return QS_ERR_UNSUPPORTED;  // runs of the engine, planned per call
   if (!out || (dtype != QS_C64 && dtype != QS_C128)) return QS_ERR_INVALID;
   const bool ps = (flags & QS_FLAG_PER_SAMPLE_PARAMS) != 0;
   TuneVal tv;
@@ -1681,6 +1894,7 @@ int qs_hbm_info_get(const qs_circuit* c, int dtype, int64_t B, int flags,
   c = apply_inverse(c, &flags, inv_);
   int rc = validate(c);
   if (rc != QS_OK) return rc;
+  if (has_channels(*c)) return QS_ERR_UNSUPPORTED;  // runs of the engine, planned per call
   if (!out || (dtype != QS_C64 && dtype != QS_C128) || B < 0) return QS_ERR_INVALID;
   static const char dummy = 0;  // check_ckpt wants a buffer; none is touched here
   if ((rc = check_ckpt(c, ckpt_gates, n_ckpt, &dummy)) != QS_OK) return rc;

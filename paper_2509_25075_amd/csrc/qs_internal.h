@@ -242,6 +242,8 @@ struct SvLaunch {
   const uint8_t* outer_q = nullptr;  // device [ob] global qubit per outer bit
   void* out_psi = nullptr;           // adjoint: final psi (may alias state)
   void* out_lam = nullptr;           // adjoint: final lam (may alias dstate)
+  int accum_feats = 0;               // adjoint: add to grad_feats (segments of a
+                                     // circuit with mid-circuit channels)
   void* stream;
 };
 int launch_sv_forward(int dtype, const SvLaunch& L);
@@ -269,6 +271,13 @@ int launch_reduce_partials(int dtype, const void* partials, int64_t rows,
 int launch_obs_cot(int dtype, int n, int64_t B, const double* dexpz,
                    const void* psi, void* lam, void* stream);
 int launch_fill_f64(double* p, int64_t n, void* stream);
+// Mid-circuit channel on qubit q (reset or measurement), one trajectory per
+// sample, its uniform at feats[b][feat]; and its backward pass.
+int launch_channel(int dtype, int n, int q, int reset, int64_t B, const void* feats,
+                   int n_feats, int feat, void* state, void* stream);
+int launch_channel_adjoint(int dtype, int n, int q, int reset, int64_t B, const void* feats,
+                           int n_feats, int feat, const void* psi_pre, void* lam,
+                           void* psi_out, void* stream);
 int launch_copy_state(int dtype, const void* src, void* dst, int64_t n_amp,
                       void* stream);
 

@@ -396,6 +396,7 @@ struct Args {
   const uint8_t* outer_q;  // tiled: [ob] global qubit of each outer bit
   real* out_psi;           // adjoint: store the final psi here (or null)
   real* out_lam;           // adjoint: store the final lam here (or null)
+  int accum_feats;         // adjoint: add to grad_feats instead of writing
   const real* params;
   const real* feats;
   real* state;
@@ -1158,6 +1159,8 @@ __device__ __forceinline__ void adjoint_body(const Args<real>& A, unsigned char*
       double* dst = &A.grad_feats[(size_t)(bb >> A.ob) * A.n_feats + f];
       if (A.tile_q != nullptr)
         atomicAdd(dst, (double)t);  // several tiles share a batch row
+      else if (A.accum_feats)
+        *dst += t;  // one writer per entry; earlier segments' sums are in place
       else
         *dst = t;
     }
@@ -1231,6 +1234,7 @@ sv_program(const ProgClass* classes, const ProgItem* items, int n_items,
     A.outer_q = nullptr;
     A.out_psi = nullptr;
     A.out_lam = nullptr;
+    A.accum_feats = 0;
     const int64_t first = w.first;
     A.params = params + cd.param_off + first * cd.n_params;
     A.feats = nullptr;
@@ -1299,6 +1303,7 @@ Args<real> make_args(const SvLaunch& L) {
   A.ws_partials = static_cast<real*>(L.ws_partials);
   A.grad_params = L.grad_params;
   A.grad_feats = L.grad_feats;
+  A.accum_feats = L.accum_feats;
   return A;
 }
 

@@ -14,6 +14,7 @@ import oracle as O
 from workloads import circuits as C
 from workloads import data as Dt
 from _patterns import cnot_pattern
+from _channels import stable_uniforms, channel_gates
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -705,6 +706,88 @@ def test_autograd_function_matches_oracle():
     rp, rf = O.theta_to_param_grads(c, p64, f64, gth)
     np.testing.assert_allclose(params.grad.cpu().numpy(), rp, atol=1e-4)
     np.testing.assert_allclose(feats.grad.cpu().numpy(), rf, atol=1e-4)
+
+
+# ------------------------------------------------- mid-circuit channels
+def _run_channel_case(c, dtype, B, seed, per_sample=False, dstate_mode=False,
+                      extra_ckpt=()):
+    """Forward (state, <Z>, the stored states in front of the channels) and
+    adjoint of a circuit with RESET / MEASURE gates, against the oracle."""
+    _announce(f"channels n={c.n_qubits} G={c.n_gates} B={B} {dtype} ps={per_sample} "
+              f"dstate={dstate_mode}")
+    rng = np.random.default_rng(seed)
+    n = c.n_qubits
+    rd = np.float32 if dtype == "c64" else np.float64
+    P = c.n_params
+    params = rng.uniform(-np.pi, np.pi, (B, P) if per_sample else P).astype(rd)
+    x = rng.standard_normal((B, 1 << n)).astype(rd)
+    psi0 = O.encode_amplitude(x, n)
+    feats = rng.uniform(-1, 1, (B, c.n_features))
+    feats = stable_uniforms(c, params, feats, psi0).astype(rd)
+    ck = sorted(set(channel_gates(c)) | set(extra_ckpt))
+    flags = N.QS_FLAG_PER_SAMPLE_PARAMS if per_sample else 0
+    s = sim.Simulator(c, dtype, flags)
+    st = s.encode_amplitude(_dev(x, s.rdtype))
+    buf = torch.empty((len(ck),) + tuple(st.shape), dtype=st.dtype, device="cuda")
+    pt, ft = _dev(params, s.rdtype), _dev(feats, s.rdtype)
+    z = s.forward(pt, ft, st, ckpt_gates=ck, ckpt=buf)
+    torch.cuda.synchronize()
+    tol = TOL[dtype]
+    psiG = O.run_circuit(c, params, feats, psi0)
+    np.testing.assert_allclose(st.cpu().numpy(), psiG, atol=tol["state"])
+    np.testing.assert_allclose(z.cpu().numpy(), O.expz(psiG), atol=tol["z"])
+    for i, g in enumerate(ck):
+        ref = O.run_circuit(C.Circuit(n, c.gates[:g], P, c.n_features), params, feats, psi0)
+        np.testing.assert_allclose(buf[i].cpu().numpy(), ref, atol=tol["state"])
+    if dstate_mode:
+        lam = (rng.standard_normal((B, 1 << n)) + 1j * rng.standard_normal((B, 1 << n))) * 0.3
+        gp, gf = s.adjoint(pt, ft, st, dstate=_dev(lam, s.cdtype), ckpt_gates=ck, ckpt=buf)
+        gth, _ = O.adjoint_vjp(c, params, feats, psi0, lam_final=lam)
+    else:
+        dz = rng.uniform(-1, 1, (B, n))
+        gp, gf = s.adjoint(pt, ft, st, dexpz=_dev(dz, torch.float64), ckpt_gates=ck, ckpt=buf)
+        gth, _ = O.adjoint_vjp(c, params, feats, psi0, dexpz=dz)
+    torch.cuda.synchronize()
+    rp, rf = O.theta_to_param_grads(c, params, feats, gth)
+    np.testing.assert_allclose(gp.cpu().numpy(), rp, atol=tol["grad"])
+    np.testing.assert_allclose(gf.cpu().numpy(), rf, atol=tol["grad"])
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("n,G,where", [(1, 12, [3, 8]), (3, 40, [0, 17, 17, 40]),
+                                       (6, 80, [25, 50]), (10, 120, [30, 61, 90]),
+                                       (13, 90, [44])])
+def test_mid_circuit_channels_vs_oracle(n, G, where, dtype):
+    """Reset and measurement channels inside random circuits (every gate
+    kind, features, shared parameters), including channels at the start, at
+    the end and back to back, with extra checkpoints between them: states,
+    <Z>, the stored states, parameter and feature gradients."""
+    rng = np.random.default_rng(1300 + n)
+    c = C.with_channels(C.random_circuit(n, G, rng, n_params=7, n_features=2), where, rng)
+    extra = [g + 1 for g in channel_gates(c) if g + 1 < c.n_gates][:1] + [2]
+    _run_channel_case(c, dtype, 5, seed=n, extra_ckpt=[e for e in extra if 0 < e < c.n_gates])
+    _run_channel_case(c, dtype, 3, seed=n + 1, per_sample=True)
+    _run_channel_case(c, dtype, 3, seed=n + 2, dstate_mode=True)
+
+
+def test_mid_circuit_channel_calls_refuse_what_they_cannot_run():
+    rng = np.random.default_rng(1399)
+    c = C.with_channels(C.hea_ry_rz_ring(6, 2), [5, 20], rng)
+    s = sim.Simulator(c, "c64")
+    st = s.zero_state(2)
+    p = torch.zeros(c.n_params, device="cuda")
+    f = torch.full((2, c.n_features), 0.5, device="cuda")
+    ck = channel_gates(c)
+    buf = torch.empty((len(ck),) + tuple(st.shape), dtype=st.dtype, device="cuda")
+    with pytest.raises(N.QsError) as e:  # no checkpoint in front of the second channel
+        s.forward(p, f, st, ckpt_gates=ck[:1], ckpt=buf)
+    assert e.value.status == N.QS_ERR_INVALID
+    with pytest.raises(N.QsError) as e:  # a channel has no inverse
+        s.forward(p, f, st, ckpt_gates=ck, ckpt=buf, flags=N.QS_FLAG_INVERSE)
+    assert e.value.status == N.QS_ERR_INVALID
+    with pytest.raises(N.QsError) as e:  # gate by gate: not for channels
+        s.forward(p, f, st, ckpt_gates=ck, ckpt=buf, flags=N.QS_PATH_PLAIN)
+    assert e.value.status == N.QS_ERR_UNSUPPORTED
 
 
 # ------------------------------------- finite differences on the GPU itself

@@ -549,3 +549,29 @@ def test_block_path_refuses_what_it_does_not_run():
         N.qs_plan_info_get(N.CircuitHandle(C.hea_ry_rz_ring(9, 1)), N.QS_C64, 2,
                            N.QS_PATH_MFMA)
     assert N.qs_plan_info_get(h, N.QS_C64, 2, N.QS_PATH_MFMA)["path"] == N.QS_PATH_MFMA
+
+
+def test_channel_gates_validate_and_plan_only_per_call():
+    """RESET / MEASURE need q1 = -1 and a feature column for their uniform;
+    circuits with them are not planned by the planning calls (they run as
+    engine runs between the channels) but have a workspace size."""
+    base = C.hea_ry_rz_ring(5, 2)
+    rng = np.random.default_rng(3)
+    c = C.with_channels(base, [7, 15], rng)
+    h = N.CircuitHandle(c)
+    assert N.lib().qs_validate(h.ptr) == N.QS_OK
+    bad = c.gates.copy()
+    g = int(np.nonzero(np.isin(c.gates["op"], C.CHANNELS))[0][0])
+    bad[g]["feat"] = -1
+    assert N.lib().qs_validate(N.CircuitHandle(C.Circuit(5, bad, c.n_params, c.n_features)).ptr) \
+        == N.QS_ERR_INVALID
+    bad = c.gates.copy()
+    bad[g]["q1"] = 2
+    assert N.lib().qs_validate(N.CircuitHandle(C.Circuit(5, bad, c.n_params, c.n_features)).ptr) \
+        == N.QS_ERR_INVALID
+    with pytest.raises(N.QsError) as e:
+        N.qs_plan_info_get(h, N.QS_C64, 4)
+    assert e.value.status == N.QS_ERR_UNSUPPORTED
+    ws = N.qs_workspace_size(h, N.QS_C64, 4)
+    assert ws >= 2 * 4 * 32 * 8  # psi and lam of the batch, then partial sums
+    assert N.qs_workspace_size(h, N.QS_C64, 4, N.QS_PATH_PLAIN) == 0

@@ -30,6 +30,7 @@ from workloads import circuits as C
 from workloads import data as Dt
 
 from _brute import circuit_full, gate_full, angle
+from _channels import stable_uniforms
 
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
                                    "hand_values.json")))
@@ -607,25 +608,6 @@ def test_channel_on_a_qubit_in_zero_is_the_identity(rng):
     np.testing.assert_allclose(out, psi, atol=1e-13)
 
 
-def _stable_uniforms(c, params, feats, psi0, first_u):
-    """Sets each channel's uniform (columns first_u ...) to the middle of the
-    interval of the outcome it draws, so that small parameter changes keep
-    every outcome (the pathwise gradient then equals finite differences)."""
-    feats = feats.copy()
-    B = psi0.shape[0]
-    for g, gate in enumerate(c.gates):
-        if int(gate["op"]) not in C.CHANNELS:
-            continue
-        pre = O.run_circuit(C.Circuit(c.n_qubits, c.gates[:g], c.n_params, c.n_features),
-                            params, feats, psi0)
-        p = O.channel_probabilities(pre, int(gate["q0"]))
-        m = O.trajectory_outcome(p, np.full(B, 0.5))
-        tot = p.sum(axis=1)
-        lo = np.where(m == 1, p[:, 0], 0.0)
-        feats[:, int(gate["feat"])] = (lo + 0.5 * p[np.arange(B), m]) / tot
-    return feats
-
-
 @pytest.mark.parametrize("per_sample", [False, True])
 def test_channel_gradients_adjoint_vs_fd(rng, per_sample):
     """Rotations before, between and after two channels (one reset, one
@@ -639,7 +621,7 @@ def test_channel_gradients_adjoint_vs_fd(rng, per_sample):
     params = rng.uniform(-np.pi, np.pi, (B, P) if per_sample else P)
     psi0 = O.encode_amplitude(rng.standard_normal((B, 1 << n)), n)
     feats = np.concatenate([rng.uniform(-1, 1, (B, 2)), np.full((B, 2), 0.5)], axis=1)
-    feats = _stable_uniforms(c, params, feats, psi0, 2)
+    feats = stable_uniforms(c, params, feats, psi0)
     wts = rng.uniform(-1, 1, (B, n))
 
     def loss(p, f):
