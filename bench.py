@@ -126,6 +126,10 @@ import numpy as np
 import oracle as O
 from workloads import make_workload
 w = make_workload({key!r}, {rows})
+if {gates}:  # one state too large to split: the first gates of the circuit on all of it
+    from workloads import circuits as C
+    w = w.__class__(**{{**w.__dict__, "circuit": C.Circuit(w.n_qubits, w.circuit.gates[:{gates}],
+                                                        w.circuit.n_params)}})
 k, W = {part}, {parts}
 sl = slice(k, None, W)
 x = w.x[sl] if w.x is not None else None
@@ -158,16 +162,37 @@ print(json.dumps({{"seconds": dt, "updates": passes * B * (1 << w.n_qubits) * G}
 """
 
 
-def cpu_baseline(key: str, rows_per_worker: int) -> dict:
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# The CPU share of one GPU on the GPU hosts these benchmarks run on is 16
+# cores; the oracle's worker processes stay within it.
+CPU_SHARE = 16
+
+
+def cpu_baseline(key: str, rows_per_worker: int, gates: int = 0) -> dict:
     """The FP64 oracle, as it stands, on a bounded sample of the workload:
-    one process per available host core (at most 16), each with one
-    BLAS/OpenMP thread, each on its own rows of the sample."""
-    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    one process per available host core (at most the 16-core share of one
+    GPU), each with one BLAS/OpenMP thread, each on its own rows of the
+    sample. With ``gates`` > 0 (a single state too large to split), one
+    process runs the first ``gates`` gates of the circuit on the whole state,
+    forward with readout and adjoint."""
+    avail = len(os.sched_getaffinity(0))
+    workers = 1 if gates else max(1, min(CPU_SHARE, avail))
     rows = rows_per_worker * workers
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1",
                MKL_NUM_THREADS="1", NUMEXPR_NUM_THREADS="1")
     procs = [subprocess.Popen([sys.executable, "-c", _CPU_WORKER.format(
-        root=ROOT, key=key, rows=rows, part=k, parts=workers)],
+        root=ROOT, key=key, rows=None if gates else rows, part=k, parts=workers,
+        gates=gates)],
         stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env)
         for k in range(workers)]
     res = []
@@ -178,11 +203,15 @@ def cpu_baseline(key: str, rows_per_worker: int) -> dict:
         res.append(json.loads(out.strip().splitlines()[-1]))
     wall = max(r["seconds"] for r in res)
     updates = sum(r["updates"] for r in res)
+    sample = (f"the first {gates} gates of the circuit on the whole state (forward with "
+              f"readout, loss and adjoint; 1 process x 1 thread), {wall:.1f} s wall"
+              if gates else
+              f"{rows} rows of the batch ({rows_per_worker} per process, {workers} "
+              f"processes x 1 thread), forward + adjoint, {wall:.1f} s wall")
     return {"value": updates / wall, "unit": "gate-amp updates/s",
-            "cores": workers, "kind": "oracle",
-            "sample": f"{rows} rows of the batch ({rows_per_worker} per process, "
-                      f"{workers} processes x 1 thread), forward + adjoint, "
-                      f"{wall:.1f} s wall"}
+            "cores": workers, "kind": "oracle", "sample": sample,
+            "host": {"cpu_model": cpu_model(), "cores_visible": avail,
+                     "cores_online": os.cpu_count(), "process_cap": CPU_SHARE}}
 
 
 # ---------------------------------------------------------------- timing
@@ -426,6 +455,8 @@ def main():
     cpu = None
     if not args.no_cpu_baseline and key == "c2":
         cpu = cpu_baseline(key, args.cpu_rows)
+    elif not args.no_cpu_baseline and key == "c5b":
+        cpu = cpu_baseline(key, 1, gates=2)
     rec = {
         "metric": METRIC, "value": value, "unit": "gate-amp updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
