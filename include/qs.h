@@ -198,6 +198,38 @@ int qs_forward(const qs_circuit* circuit, int dtype, int64_t B,
                double* expz, const int32_t* ckpt_gates, int32_t n_ckpt,
                void* ckpt, int flags, void* stream);
 
+/* Amplitude encoding and forward sweep in one call (the input of the
+ * sweep's first step, then the sweep): state[b] <- U(theta(b)) pad(x[b]) /
+ * ||x[b]||_2, with qs_encode's QS_ENC_AMPLITUDE definition of the encoded
+ * state (squared norm summed in FP64, zero padding to 2^n). The encoded
+ * state is never stored: the register/LDS engine normalises each sample as
+ * it loads it when x is in the state's precision (float32 for QS_C64,
+ * float64 for QS_C128); every other case runs qs_encode into `state` first.
+ *   x, x_is_f64, D, x_stride  as qs_encode (device [B][x_stride] reals, the
+ *            first D <= 2^n of each row used)
+ *   bad_rows (device, optional) int32 counter; zero-norm rows become NaN and
+ *            add one each, as in qs_encode (read it with qs_encode_check)
+ *   state    (device) [B][2^n] complex output: the final state only
+ *   other arguments and errors as qs_forward; QS_ERR_INVALID also for a
+ *   NULL x, D outside [1, 2^n] or x_stride < D when B > 0. */
+int qs_forward_amplitude(const qs_circuit* circuit, int dtype, int64_t B,
+                         const void* params, const void* feats, const void* x,
+                         int x_is_f64, int64_t D, int64_t x_stride, int32_t* bad_rows,
+                         void* state, double* expz, const int32_t* ckpt_gates,
+                         int32_t n_ckpt, void* ckpt, int flags, void* stream);
+
+/* Mean-squared-error loss on one qubit's readout and its upstream gradient
+ * (the regression loss of the training step; one kernel):
+ *   loss[0]        = (1/B) sum_b (expz[b][q] - y[b])^2, FP64, summed in a
+ *                    fixed order (bitwise reproducible)
+ *   dexpz[b][k]    = (2/B)(expz[b][q] - y[b]) for k == q, 0 for k != q
+ *   expz  (device) [B][n] double, y (device) [B] double,
+ *   dexpz (device) [B][n] double output (may be NULL), loss (device) [1]
+ *   double output (may be NULL). QS_ERR_INVALID for n < 1, q outside
+ *   [0, n), B < 0 or a NULL expz / y when B > 0. B == 0 writes loss = 0. */
+int qs_loss_mse_z(int n_qubits, int64_t B, int q, const double* expz, const double* y,
+                  double* dexpz, double* loss, void* stream);
+
 /* Bytes of device workspace qs_adjoint_backward needs for this shape. */
 size_t qs_workspace_size(const qs_circuit* circuit, int dtype, int64_t B,
                          int flags);

@@ -115,6 +115,11 @@ def lib() -> ctypes.CDLL:
         "qs_encode_check": (ctypes.c_int, [vp, vp]),
         "qs_forward": (ctypes.c_int, [cp, ctypes.c_int, i64, vp, vp, vp, vp,
                                       i32p, i32, vp, ctypes.c_int, vp]),
+        "qs_forward_amplitude": (ctypes.c_int, [cp, ctypes.c_int, i64, vp, vp, vp,
+                                                ctypes.c_int, i64, i64, vp, vp, vp,
+                                                i32p, i32, vp, ctypes.c_int, vp]),
+        "qs_loss_mse_z": (ctypes.c_int, [ctypes.c_int, i64, ctypes.c_int, vp, vp, vp, vp,
+                                         vp]),
         "qs_workspace_size": (sz, [cp, ctypes.c_int, i64, ctypes.c_int]),
         "qs_adjoint_backward": (ctypes.c_int, [cp, ctypes.c_int, i64, vp, vp, vp,
                                                vp, vp, vp, vp, i32p, i32, vp, vp,
@@ -248,6 +253,28 @@ def qs_forward(h: CircuitHandle, dtype: int, params, feats, state, expz=None,
                             _ptr(feats), _ptr(state), _ptr(expz), arr, n_ck,
                             _ptr(ckpt), flags, _stream(stream)), "qs_forward")
     del keep
+
+
+def qs_forward_amplitude(h: CircuitHandle, dtype: int, params, feats, x, state,
+                         expz=None, bad_rows=None, ckpt_gates=None, ckpt=None,
+                         flags: int = 0, stream=None):
+    """x: [B, D] float32/float64 device tensor (row stride may exceed D);
+    state: [B, 2^n] complex device tensor, receives the final state."""
+    arr, n_ck, keep = _ckpt_arr(ckpt_gates)
+    D, xs, f64 = x.shape[1], x.stride(0), int(x.dtype.itemsize == 8)
+    _check(lib().qs_forward_amplitude(h.ptr, dtype, state.shape[0], _ptr(params),
+                                      _ptr(feats), _ptr(x), f64, D, xs, _ptr(bad_rows),
+                                      _ptr(state), _ptr(expz), arr, n_ck, _ptr(ckpt),
+                                      flags, _stream(stream)), "qs_forward_amplitude")
+    del keep
+
+
+def qs_loss_mse_z(q: int, expz, y, dexpz=None, loss=None, stream=None):
+    """expz: [B, n] float64, y: [B] float64; dexpz [B, n] and loss [1] float64
+    device outputs (either may be None)."""
+    B, n = expz.shape
+    _check(lib().qs_loss_mse_z(n, B, q, _ptr(expz), _ptr(y), _ptr(dexpz), _ptr(loss),
+                               _stream(stream)), "qs_loss_mse_z")
 
 
 def qs_workspace_size(h: CircuitHandle, dtype: int, B: int, flags: int = 0) -> int:

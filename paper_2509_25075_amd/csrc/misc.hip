@@ -464,6 +464,53 @@ unsigned grid_for(int64_t n) {
 
 int ok() { return hipGetLastError() == hipSuccess ? QS_OK : QS_ERR_LAUNCH; }
 
+// Mean-squared error on qubit q's readout: every workgroup writes its share
+// of the upstream gradient rows (2/B)(z_b - y_b) e_q; workgroup 0 also sums
+// the squared residuals, each thread over a fixed stride of rows and then
+// the workgroup in a fixed order, so the loss is bitwise reproducible.
+constexpr int kLossBlock = 1024;
+__global__ void __launch_bounds__(kLossBlock)
+loss_mse_z(int n, int64_t B, int q, const double* expz, const double* y, double* dexpz,
+           double* loss) {
+  __shared__ double sh[kLossBlock / 64];
+  const double inv_b = B > 0 ? 1.0 / (double)B : 0.0;
+  if (dexpz != nullptr) {
+    // row-major [B][n]: element i is row i / n, column i % n (32-bit
+    // division while the index fits, which it does for any batch in HBM)
+    const int64_t total = B * n;
+    const bool small = total < (1ll << 31);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t b = small ? (int64_t)((uint32_t)i / (uint32_t)n) : i / n;
+      const int k = (int)(i - b * n);
+      dexpz[i] = k == q ? 2.0 * inv_b * (expz[b * n + q] - y[b]) : 0.0;
+    }
+  }
+  if (blockIdx.x != 0 || loss == nullptr) return;
+  // Rows tid, tid + T, ... of this thread, added in that order; the loads of
+  // eight rows are in flight together.
+  double s = 0;
+  const int64_t T = blockDim.x;
+  for (int64_t b0 = threadIdx.x; b0 < B; b0 += 8 * T) {
+    double r[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t b = b0 + u * T;
+      r[u] = b < B ? expz[b * n + q] - y[b] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += r[u] * r[u];
+  }
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+    loss[0] = t * inv_b;
+  }
+}
+
 }  // namespace
 
 int launch_encode(int enc, int dtype, int n, int64_t B, int64_t D, int x_is_f64,
@@ -560,6 +607,17 @@ int launch_fill_f64(double* p, int64_t n, void* stream) {
   if (n <= 0) return QS_OK;
   hipLaunchKernelGGL(fill_f64, grid_for(n), kBlock, 0,
                      static_cast<hipStream_t>(stream), p, n);
+  return ok();
+}
+
+int launch_loss_mse_z(int n, int64_t B, int q, const double* expz, const double* y,
+                      double* dexpz, double* loss, void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int64_t g = (B * n + kLossBlock * 4 - 1) / (kLossBlock * 4);
+  if (g < 1) g = 1;
+  if (g > 1024) g = 1024;
+  hipLaunchKernelGGL(loss_mse_z, dim3((unsigned)g), kLossBlock, 0, st, n, B, q, expz, y,
+                     dexpz, loss);
   return ok();
 }
 

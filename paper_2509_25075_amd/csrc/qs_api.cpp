@@ -1411,11 +1411,58 @@ int qs_encode_check(const int32_t* bad_rows, void* stream) {
   return h != 0 ? QS_ERR_ZERO_NORM : QS_OK;
 }
 
+namespace {
+
+// The amplitude-encoded input of qs_forward_amplitude.
+struct EncIn {
+  const void* x;
+  int x_is_f64;
+  int64_t D, x_stride;
+  int32_t* bad_rows;
+};
+
+// Encodes into `state` with its own kernel (every path but the fused engine
+// with x in the state's precision, which encodes while it loads).
+int encode_first(const EncIn* enc, int dtype, int n, int64_t B, void* state, void* stream) {
+  if (!enc) return QS_OK;
+  return launch_encode(QS_ENC_AMPLITUDE, dtype, n, B, enc->D, enc->x_is_f64, enc->x,
+                       enc->x_stride, state, enc->bad_rows, stream);
+}
+
+int forward_impl(const qs_circuit* c, int dtype, int64_t B, const void* params,
+                 const void* feats, void* state, double* expz, const int32_t* ckpt_gates,
+                 int32_t n_ckpt, void* ckpt, int flags, void* stream, const EncIn* enc);
+
+}  // namespace
+
 int qs_forward(const qs_circuit* c, int dtype, int64_t B, const void* params,
                const void* feats, void* state, double* expz,
                const int32_t* ckpt_gates, int32_t n_ckpt, void* ckpt, int flags,
                void* stream) {
   CallStream call_(stream);
+  return forward_impl(c, dtype, B, params, feats, state, expz, ckpt_gates, n_ckpt, ckpt,
+                      flags, stream, nullptr);
+}
+
+int qs_forward_amplitude(const qs_circuit* c, int dtype, int64_t B, const void* params,
+                         const void* feats, const void* x, int x_is_f64, int64_t D,
+                         int64_t x_stride, int32_t* bad_rows, void* state, double* expz,
+                         const int32_t* ckpt_gates, int32_t n_ckpt, void* ckpt, int flags,
+                         void* stream) {
+  CallStream call_(stream);
+  if (!c || c->n_qubits < 1 || c->n_qubits > 30) return QS_ERR_INVALID;
+  if (B > 0 && (!x || D < 1 || D > (1ll << c->n_qubits) || x_stride < D))
+    return QS_ERR_INVALID;
+  const EncIn enc{x, x_is_f64 ? 1 : 0, D, x_stride, bad_rows};
+  return forward_impl(c, dtype, B, params, feats, state, expz, ckpt_gates, n_ckpt, ckpt,
+                      flags, stream, &enc);
+}
+
+namespace {
+
+int forward_impl(const qs_circuit* c, int dtype, int64_t B, const void* params,
+                 const void* feats, void* state, double* expz, const int32_t* ckpt_gates,
+                 int32_t n_ckpt, void* ckpt, int flags, void* stream, const EncIn* enc) {
   InvCircuit inv_;
   c = apply_inverse(c, &flags, inv_);
   int rc = validate(c);
@@ -1430,6 +1477,7 @@ int qs_forward(const qs_circuit* c, int dtype, int64_t B, const void* params,
   const bool ps = (flags & QS_FLAG_PER_SAMPLE_PARAMS) != 0;
   if (has_channels(*c)) {  // unitary runs through the engine, channels between them
     if ((rc = channels_check(*c, flags, ckpt_gates, n_ckpt)) != QS_OK) return rc;
+    if ((rc = encode_first(enc, dtype, c->n_qubits, B, state, stream)) != QS_OK) return rc;
     const int64_t per = B << c->n_qubits;
     const size_t cs = dtype == QS_C64 ? 8 : 16;
     char* cb = static_cast<char*>(ckpt);
@@ -1470,6 +1518,10 @@ int qs_forward(const qs_circuit* c, int dtype, int64_t B, const void* params,
   const int path = pick_path(*c, dtype, flags, &shape, count_slots(*c, ps), false,
                              tuned ? &tv : nullptr, ckpt_gates, n_ckpt);
   if (path < 0) return path;
+  // The fused engine encodes while it loads when x is in the state's precision.
+  const bool fuse_enc = enc && path == QS_PATH_FUSED && (enc->x_is_f64 != 0) == (dtype == QS_C128);
+  if (!fuse_enc && (rc = encode_first(enc, dtype, c->n_qubits, B, state, stream)) != QS_OK)
+    return rc;
   if (path == QS_PATH_PLAIN) {
     PlainLaunch L{};
     L.c = c;
@@ -1545,8 +1597,16 @@ int qs_forward(const qs_circuit* c, int dtype, int64_t B, const void* params,
   L.expz = expz;
   L.ckpt = ckpt;
   L.stream = stream;
+  if (fuse_enc) {
+    L.x_in = enc->x;
+    L.x_stride = enc->x_stride;
+    L.x_D = enc->D;
+    L.bad_rows = enc->bad_rows;
+  }
   return launch_sv_forward(dtype, L);
 }
+
+}  // namespace
 
 size_t qs_workspace_size(const qs_circuit* c, int dtype, int64_t B, int flags) {
   InvCircuit inv_;
@@ -1799,6 +1859,14 @@ int qs_expz(int dtype, int n, int64_t B, const void* state, double* expz,
       !expz)
     return QS_ERR_INVALID;
   return launch_expz(dtype, n, B, state, expz, stream);
+}
+
+int qs_loss_mse_z(int n, int64_t B, int q, const double* expz, const double* y,
+                  double* dexpz, double* loss, void* stream) {
+  if (n < 1 || n > 30 || q < 0 || q >= n || B < 0) return QS_ERR_INVALID;
+  if (B > 0 && (!expz || !y)) return QS_ERR_INVALID;
+  if (!dexpz && !loss) return QS_OK;
+  return launch_loss_mse_z(n, B, q, expz, y, dexpz, loss, stream);
 }
 
 int qs_fidelity_reset(int dtype, int n, int n_trash, int64_t B, const void* psi,

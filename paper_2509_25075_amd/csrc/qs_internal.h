@@ -244,6 +244,11 @@ struct SvLaunch {
   void* out_lam = nullptr;           // adjoint: final lam (may alias dstate)
   int accum_feats = 0;               // adjoint: add to grad_feats (segments of a
                                      // circuit with mid-circuit channels)
+  // Forward: amplitude encoding fused into the state load (batched layout,
+  // x in the state's real type); x_in null reads `state`.
+  const void* x_in = nullptr;
+  int64_t x_stride = 0, x_D = 0;
+  int32_t* bad_rows = nullptr;
   void* stream;
 };
 int launch_sv_forward(int dtype, const SvLaunch& L);
@@ -254,6 +259,8 @@ int launch_encode(int enc, int dtype, int n, int64_t B, int64_t D,
                   int32_t* bad_rows, void* stream);
 int launch_expz(int dtype, int n, int64_t B, const void* state, double* expz,
                 void* stream);
+int launch_loss_mse_z(int n, int64_t B, int q, const double* expz, const double* y,
+                      double* dexpz, double* loss, void* stream);
 int launch_fidelity(int dtype, int n, int n_trash, int64_t B, const void* psi,
                     const void* chi, double* fid, const double* dfid,
                     void* lam_psi, void* lam_chi, void* stream);

@@ -407,6 +407,14 @@ struct Args {
   real* ws_partials;
   double* grad_params;
   double* grad_feats;
+  // Forward with amplitude encoding fused into the state load (batched
+  // layout only): sample b starts as pad(x[b]) / ||x[b]||, x[b] being the
+  // first x_D of the x_stride reals at x_in + b x_stride; the squared norm is
+  // summed in FP64 over the sample's threads in a fixed order. A zero row
+  // becomes NaN and adds one to *bad_rows (when given). Null: read `state`.
+  const real* x_in;
+  int64_t x_stride, x_D;
+  int32_t* bad_rows;
 };
 
 template <typename real>
@@ -584,27 +592,68 @@ struct Ctx {
                                    : ((int64_t)1 << kc(A.tile_q)[A.t + j]);
   }
 
+  // Amplitude encoding of this thread's R elements (logical index tau + u T,
+  // as load_state holds them) from the sample's input row; see Args::x_in.
+  // The squared norm is summed in FP64: over the thread's elements, over the
+  // sample's lanes of each wave, then over its waves through the staging
+  // region (which the staging passes after this overwrite).
+  __device__ __forceinline__ void load_encoded(St<real, R>& x) {
+    const real* xr = A.x_in + (active ? b : 0) * A.x_stride;
+    double ss = 0;
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int64_t i = tau + ((int64_t)u << A.t);
+      const real v = (active && i < A.x_D) ? xr[i] : (real)0;
+      x.re[u] = v;
+      ss += (double)v * v;
+    }
+    const int Tw = (1 << A.t) < 64 ? (1 << A.t) : 64;
+    ss = group_sum(ss, Tw);
+    if (wps > 1) {
+      double* red = reinterpret_cast<double*>(ldr);
+      if ((tau & 63) == 0) red[tau >> 6] = ss;
+      sample_sync(A.t);
+      ss = 0;
+      for (int w = 0; w < wps; ++w) ss += red[w];
+    }
+    // (threads past the batch end hold zeros and stay finite)
+    const bool zero = active && !(ss > 0);
+    const double inv = zero ? (double)NAN : ss > 0 ? 1.0 / sqrt(ss) : 0.0;
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int64_t i = tau + ((int64_t)u << A.t);
+      x.re[u] = (real)(i < A.x_D ? (double)x.re[u] * inv : (zero ? (double)NAN : 0.0));
+      x.im[u] = zero ? (real)NAN : (real)0;
+    }
+    if (zero && active && tau == 0 && A.bad_rows != nullptr) atomicAdd(A.bad_rows, 1);
+  }
+
   // HBM (logical order) -> LDS -> registers under placement `map`. All R
   // loads of a thread are issued before the first wait.
   __device__ __forceinline__ void load_state(St<real, R>& x, const real* src,
-                                             const QS_K uint16_t* map) {
+                                             const QS_K uint16_t* map,
+                                             bool encode = false) {
     __builtin_amdgcn_s_setprio(1);  // memory phase: issue ahead of computing waves
-    const v2* s2 = reinterpret_cast<const v2*>(src);
-    int64_t off[LR > 0 ? LR : 1];
-    hbm_offsets(off);
-    const int64_t a0 = hbm_a0();
+    if (encode) {
+      load_encoded(x);
+    } else {
+      const v2* s2 = reinterpret_cast<const v2*>(src);
+      int64_t off[LR > 0 ? LR : 1];
+      hbm_offsets(off);
+      const int64_t a0 = hbm_a0();
 #pragma unroll
-    for (int u = 0; u < R; ++u) {
-      int64_t o = 0;
+      for (int u = 0; u < R; ++u) {
+        int64_t o = 0;
 #pragma unroll
-      for (int j = 0; j < LR; ++j)
-        if (u & (1 << j)) o += off[j];
-      v2 v;
-      v.x = 0;
-      v.y = 0;
-      if (active) v = s2[a0 + o];
-      x.re[u] = v.x;  // staging only: read_mapped below sets the placement
-      x.im[u] = v.y;
+        for (int j = 0; j < LR; ++j)
+          if (u & (1 << j)) o += off[j];
+        v2 v;
+        v.x = 0;
+        v.y = 0;
+        if (active) v = s2[a0 + o];
+        x.re[u] = v.x;  // staging only: read_mapped below sets the placement
+        x.im[u] = v.y;
+      }
     }
     const uint32_t tb = opaque((uint32_t)tau);
     static_for<kPasses>([&](auto PC) QS_AI {
@@ -906,7 +955,11 @@ __device__ __forceinline__ void setup(Ctx<real, LR, FLY, SHARED, HALF>& C,
   real* st = reinterpret_cast<real*>(smem);
   C.ldr = st + (size_t)C.sl * N * comps;
   C.lds = reinterpret_cast<typename V2<real>::T*>(C.ldr);
-  C.salt = ((uint32_t)C.sl << A.t) & 31u & (uint32_t)(N - 1);
+  // Samples sharing a wave get different salts, so that one LDS access of
+  // the wave spreads over all banks: 32 slot values cover the 64 banks when
+  // a slot is a complex pair; with one component staged (4-byte slots) the
+  // salt takes 64 values.
+  C.salt = ((uint32_t)C.sl << A.t) & (HALF ? 63u : 31u) & (uint32_t)(N - 1);
   real* tail = st + (size_t)A.S * N * comps;
   C.ang_sh = tail;
   C.ang_ps = C.ang_sh + 2 * (size_t)A.n_gates;
@@ -1016,7 +1069,7 @@ __device__ __forceinline__ void forward_body(const Args<real>& A, unsigned char*
   setup(C, A, smem, false, blk);
 
   St<real, R> x;
-  C.load_state(x, A.state, rlay(A, 0));
+  C.load_state(x, A.state, rlay(A, 0), !FLY && A.x_in != nullptr);
   const int nseg = A.nseg;
   const QS_K int32_t* seg_begin = kc(A.seg_begin);
   for (int s = 0; s < nseg; ++s) {
@@ -1304,6 +1357,10 @@ Args<real> make_args(const SvLaunch& L) {
   A.grad_params = L.grad_params;
   A.grad_feats = L.grad_feats;
   A.accum_feats = L.accum_feats;
+  A.x_in = static_cast<const real*>(L.x_in);
+  A.x_stride = L.x_stride;
+  A.x_D = L.x_D;
+  A.bad_rows = L.bad_rows;
   return A;
 }
 

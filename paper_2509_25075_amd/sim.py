@@ -55,13 +55,21 @@ class Simulator:
 
     # ------------------------------------------------------------- sweeps
     def forward(self, params, feats, state, want_expz=True, ckpt_gates=None,
-                ckpt=None, flags=None):
-        """In-place forward on ``state``; returns <Z> [B, n] (float64) or None."""
+                ckpt=None, flags=None, x=None, bad_rows=None):
+        """In-place forward on ``state``; returns <Z> [B, n] (float64) or None.
+        With ``x`` ([B, D] real amplitude inputs), the sweep starts from their
+        amplitude encoding instead (one call: qs_forward_amplitude) and
+        ``state`` only receives the final state."""
         B = state.shape[0]
         expz = torch.empty((B, self.n), dtype=torch.float64,
                            device=state.device) if want_expz else None
-        N.qs_forward(self.h, self.qs_dtype, params, feats, state, expz,
-                     ckpt_gates, ckpt, self.flags if flags is None else flags)
+        fl = self.flags if flags is None else flags
+        if x is None:
+            N.qs_forward(self.h, self.qs_dtype, params, feats, state, expz,
+                         ckpt_gates, ckpt, fl)
+        else:
+            N.qs_forward_amplitude(self.h, self.qs_dtype, params, feats, x, state, expz,
+                                   bad_rows, ckpt_gates, ckpt, fl)
         return expz
 
     def workspace(self, B: int, device="cuda", flags=None):
@@ -203,6 +211,8 @@ class DeviceWorkload:
     ckpt: torch.Tensor | None = None  # [n_ckpt, B, 2^n] stored states
     dz: torch.Tensor | None = None    # [B, n] float64 upstream gradient buffer
     u: torch.Tensor | None = None     # [B] float64 trajectory uniforms
+    loss_buf: torch.Tensor | None = None  # [1] float64 loss of the last step
+    dfid: torch.Tensor | None = None  # [B] float64 dL/dF_b = -1/B (fidelity losses)
 
 
 def to_device(w, flags: int = 0, device="cuda", ckpt_every_layers: int = 0,
@@ -229,11 +239,13 @@ def to_device(w, flags: int = 0, device="cuda", ckpt_every_layers: int = 0,
             ckpt_gates = None
     # Upstream gradient dL/d<Z>: MSE on qubit 0 writes column 0 each step
     # (the others stay zero); a weighted sum has a constant one.
-    dz = None
+    dz, dfid = None, None
     if w.loss == "mse_z0":
         dz = torch.zeros((B, w.n_qubits), dtype=torch.float64, device=device)
     elif w.loss == "weighted_z":
         dz = t(w.weights, torch.float64)[None, :].expand(B, w.n_qubits).contiguous()
+    elif w.loss.startswith("fidelity"):
+        dfid = torch.full((B,), -1.0 / B, dtype=torch.float64, device=device)
     return DeviceWorkload(
         w=w, sim=sim, sim_dec=sim_dec, x=t(w.x), feats=t(w.feats),
         params=t(w.params), params_dec=t(w.params_dec),
@@ -242,7 +254,8 @@ def to_device(w, flags: int = 0, device="cuda", ckpt_every_layers: int = 0,
         ws=sim.workspace(B, device, flags),
         ws_dec=sim_dec.workspace(B, device, flags) if sim_dec else None,
         flags=flags, ckpt_gates=ckpt_gates, ckpt=ckpt, dz=dz,
-        u=t(traj_u, torch.float64) if w.loss == "fidelity_trajectory" else None)
+        u=t(traj_u, torch.float64) if w.loss == "fidelity_trajectory" else None,
+        loss_buf=torch.zeros(1, dtype=torch.float64, device=device), dfid=dfid)
 
 
 def step(d: DeviceWorkload, backward: bool = True) -> dict:
@@ -250,17 +263,18 @@ def step(d: DeviceWorkload, backward: bool = True) -> dict:
     adjoint backward. Returns the device tensors it produced."""
     w, sim = d.w, d.sim
     B = w.batch
-    if w.encoding == "amplitude":
-        sim.encode_amplitude(d.x, out=d.state)
-    else:
+    # Amplitude inputs are encoded by the forward call itself.
+    x = d.x if w.encoding == "amplitude" else None
+    if x is None:
         sim.zero_state(B, d.state.device, out=d.state)
     out = {}
     if w.loss in ("fidelity_reset", "fidelity_postselect", "fidelity_trajectory"):
-        sim.encode_amplitude(d.x, out=d.state_dec)
-        sim.forward(d.params, d.feats, d.state, want_expz=False)
-        d.sim_dec.forward(d.params_dec, d.feats, d.state_dec, want_expz=False)
+        if x is None:
+            sim.zero_state(B, d.state.device, out=d.state_dec)
+        sim.forward(d.params, d.feats, d.state, want_expz=False, x=x)
+        d.sim_dec.forward(d.params_dec, d.feats, d.state_dec, want_expz=False, x=x)
         fid = torch.empty(B, dtype=torch.float64, device=d.state.device)
-        dfid = torch.full((B,), -1.0 / B, dtype=torch.float64, device=d.state.device)
+        dfid = d.dfid
         lam_psi = torch.empty_like(d.state)
         lam_chi = torch.empty_like(d.state)
         if w.loss == "fidelity_trajectory":
@@ -284,15 +298,14 @@ def step(d: DeviceWorkload, backward: bool = True) -> dict:
                 d.params_dec, d.feats, d.state_dec, dstate=lam_chi, ws=d.ws_dec)
         return out
     z = sim.forward(d.params, d.feats, d.state, want_expz=True,
-                    ckpt_gates=d.ckpt_gates, ckpt=d.ckpt)
+                    ckpt_gates=d.ckpt_gates, ckpt=d.ckpt, x=x)
     out["expz"] = z
     if w.loss == "none" or not backward:
         return out
     dz = d.dz
     if w.loss == "mse_z0":
-        r = z[:, 0] - d.labels
-        out["loss"] = (r * r).mean()
-        torch.mul(r, 2.0 / B, out=dz[:, 0])
+        N.qs_loss_mse_z(0, z, d.labels, dexpz=dz, loss=d.loss_buf)
+        out["loss"] = d.loss_buf[0]
     elif w.loss == "weighted_z":
         out["loss"] = (z * d.weights[None, :]).sum()
     else:

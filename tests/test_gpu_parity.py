@@ -543,6 +543,94 @@ def test_zero_norm_rows_are_counted_and_nan():
     assert torch.isfinite(st[[0, 1, 3]].real).all()
 
 
+@pytest.mark.parametrize("dtype,xbits", [("c64", 32), ("c128", 64), ("c64", 64)])
+@pytest.mark.parametrize("n", [1, 3, 5, 8, 10, 12, 13, 14])
+def test_forward_amplitude_vs_oracle(n, dtype, xbits):
+    """Encoding fused into the engine's state load (x in the state's
+    precision) and the encode-then-forward fallback (x in the other one):
+    final states and <Z> against the oracle, on a zero-padded input read
+    through a row stride wider than D, with one zero row that must come out
+    NaN and be counted; other rows are unaffected by it."""
+    rng = np.random.default_rng(1500 + n)
+    c = C.random_circuit(n, 60, rng, n_params=6, n_features=2)
+    B = 13 if n <= 10 else 3
+    _announce(f"forward_amplitude n={n} {dtype} x{xbits} B={B}")
+    rd = np.float32 if xbits == 32 else np.float64
+    D = max(1, (1 << n) - (1 << n) // 5)
+    wide = rng.standard_normal((B, D + 3)).astype(rd)
+    zero_row = B // 2
+    wide[zero_row] = 0
+    s = sim.Simulator(c, dtype, PATHS["auto"])
+    params = rng.uniform(-np.pi, np.pi, c.n_params)
+    feats = rng.uniform(-1, 1, (B, c.n_features))
+    pt, ft = _dev(params, s.rdtype), _dev(feats, s.rdtype)
+    xt = _dev(wide, torch.float32 if xbits == 32 else torch.float64)[:, :D]
+    bad = torch.zeros(1, dtype=torch.int32, device="cuda")
+    st = s.empty_state(B)
+    z = s.forward(pt, ft, st, x=xt, bad_rows=bad)
+    torch.cuda.synchronize()
+    assert int(bad.item()) == 1
+    assert torch.isnan(st[zero_row].real).all() and torch.isnan(st[zero_row].imag).all()
+    keep = [b for b in range(B) if b != zero_row]
+    x_used = wide[keep, :D].astype(np.float64)
+    psi0 = O.encode_amplitude(x_used, n)
+    rn = np.float32 if dtype == "c64" else np.float64  # what the GPU was given
+    pc = params.astype(rn).astype(np.float64)
+    fc = feats[keep].astype(rn).astype(np.float64)
+    psiG = O.run_circuit(c, pc, fc, psi0)
+    tol = TOL[dtype]
+    np.testing.assert_allclose(st.cpu().numpy()[keep], psiG, atol=tol["state"])
+    np.testing.assert_allclose(z.cpu().numpy()[keep], O.expz(psiG), atol=tol["z"])
+
+
+def test_forward_amplitude_with_checkpoints_matches_encode_then_forward():
+    """With checkpoints the fused forward stores the same states as qs_encode
+    followed by qs_forward, and ends in the same final state."""
+    rng = np.random.default_rng(1600)
+    c = C.hea_ry_rz_ring(9, 6)
+    B = 33
+    s = sim.Simulator(c, "c64", PATHS["fused"])
+    pt = _dev(rng.uniform(-np.pi, np.pi, c.n_params), torch.float32)
+    xt = _dev(rng.standard_normal((B, 512)), torch.float32)
+    ck_g = [c.layer_end[1], c.layer_end[3]]
+    ck_a = torch.empty((2, B, 512), dtype=torch.complex64, device="cuda")
+    ck_b = torch.empty_like(ck_a)
+    st_a = s.empty_state(B)
+    za = s.forward(pt, None, st_a, ckpt_gates=ck_g, ckpt=ck_a, x=xt)
+    st_b = s.encode_amplitude(xt)
+    zb = s.forward(pt, None, st_b, ckpt_gates=ck_g, ckpt=ck_b)
+    torch.cuda.synchronize()
+    for a, b in ((st_a, st_b), (ck_a, ck_b), (za, zb)):
+        np.testing.assert_allclose(a.cpu().numpy(), b.cpu().numpy(), atol=2e-6)
+
+
+@pytest.mark.parametrize("B,n,q", [(1, 1, 0), (37, 10, 0), (4096, 10, 0), (777, 8, 7),
+                                   (65536, 8, 0), (0, 3, 1)])
+def test_loss_mse_z(B, n, q):
+    """The loss kernel's upstream gradient is (2/B)(z - y) in column q and 0
+    elsewhere (the same FP64 operations as written here, so bit for bit);
+    its loss is the mean squared residual, summed in a fixed order."""
+    rng = np.random.default_rng(1700 + B)
+    z = rng.uniform(-1, 1, (B, n))
+    y = rng.choice([-1.0, 1.0], B)
+    zt, yt = _dev(z, torch.float64), _dev(y, torch.float64)
+    dz = torch.full((B, n), 7.0, dtype=torch.float64, device="cuda")
+    loss = torch.full((1,), 7.0, dtype=torch.float64, device="cuda")
+    N.qs_loss_mse_z(q, zt, yt, dexpz=dz, loss=loss)
+    torch.cuda.synchronize()
+    want = np.zeros((B, n))
+    if B:
+        want[:, q] = 2.0 * (1.0 / B) * (z[:, q] - y)
+    np.testing.assert_array_equal(dz.cpu().numpy(), want)
+    ref = float(np.mean((z[:, q] - y) ** 2)) if B else 0.0
+    assert abs(float(loss.item()) - ref) <= 1e-13 * max(1.0, ref)
+    # bitwise reproducible from call to call
+    loss2 = torch.zeros_like(loss)
+    N.qs_loss_mse_z(q, zt, yt, loss=loss2)
+    torch.cuda.synchronize()
+    assert float(loss2.item()) == float(loss.item())
+
+
 def test_encode_check_reports_zero_norm_rows():
     """The counter of zero-norm rows becomes a host-visible status."""
     bad = torch.zeros(1, dtype=torch.int32, device="cuda")

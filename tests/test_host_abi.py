@@ -4,6 +4,7 @@ workload generator's, descriptor validation rejects malformed input, and the
 planner's programs respect the circuit (same per-qubit gate order, every
 pair-mixing gate on a register-resident qubit)."""
 import os
+import ctypes
 import re
 
 import numpy as np
@@ -69,6 +70,28 @@ def test_fidelity_calls_validate_before_touching_the_gpu():
     assert L.qs_fidelity_postselect(N.QS_C64, 4, 1, 0, *nul) == N.QS_OK
     assert L.qs_fidelity_trajectory(N.QS_C128, 4, 2, 0, *nul, None, None) == N.QS_OK
     assert L.qs_fidelity_reset(N.QS_C64, 4, 1, 0, *nul) == N.QS_OK
+
+
+def test_forward_amplitude_and_loss_validate_before_touching_the_gpu():
+    """Bad encoding arguments and bad loss shapes are rejected, and B = 0 is a
+    no-op, before any device work."""
+    L = N.lib()
+    h = N.CircuitHandle(C.hea_ry_rz_ring(3, 1))
+    x = ctypes.c_void_p(16)  # never dereferenced: every call below returns first
+    args = lambda B, xp, D, xs: (h.ptr, N.QS_C64, B, x, None, xp, 0, D, xs, None, x,
+                                 None, None, 0, None, 0, None)
+    assert L.qs_forward_amplitude(*args(2, None, 8, 8)) == N.QS_ERR_INVALID   # no x
+    assert L.qs_forward_amplitude(*args(2, x, 0, 8)) == N.QS_ERR_INVALID      # D < 1
+    assert L.qs_forward_amplitude(*args(2, x, 9, 9)) == N.QS_ERR_INVALID      # D > 2^n
+    assert L.qs_forward_amplitude(*args(2, x, 8, 7)) == N.QS_ERR_INVALID      # stride < D
+    assert L.qs_forward_amplitude(*args(0, None, 0, 0)) == N.QS_OK            # B = 0
+    assert L.qs_loss_mse_z(0, 4, 0, x, x, x, x, None) == N.QS_ERR_INVALID     # n < 1
+    assert L.qs_loss_mse_z(3, 4, 3, x, x, x, x, None) == N.QS_ERR_INVALID     # q >= n
+    assert L.qs_loss_mse_z(3, 4, -1, x, x, x, x, None) == N.QS_ERR_INVALID
+    assert L.qs_loss_mse_z(3, -1, 0, x, x, x, x, None) == N.QS_ERR_INVALID    # B < 0
+    assert L.qs_loss_mse_z(3, 4, 0, None, x, x, x, None) == N.QS_ERR_INVALID  # no expz
+    assert L.qs_loss_mse_z(3, 4, 0, x, None, x, x, None) == N.QS_ERR_INVALID  # no y
+    assert L.qs_loss_mse_z(3, 4, 0, x, x, None, None, None) == N.QS_OK        # no outputs
 
 
 def test_status_strings():
