@@ -36,6 +36,7 @@ namespace {
 
 constexpr int kBlock = 512;
 constexpr int64_t kMaxLds = 160 * 1024;
+constexpr int64_t kStaticLds = 256;  // the persistent kernel's own __shared__ words
 
 struct ProgPlan {
   ProgClass* d_classes = nullptr;
@@ -151,6 +152,7 @@ ProgPlan* get_prog(const qs_program* p, int dtype, int* rc) {
   struct Cand { ProgItem it; double cost; };
   std::vector<Cand> items;
   int64_t lds = 0, lds_half = 0;
+  std::vector<int64_t> table_lds(p->n_classes, 0), table_lds_half(p->n_classes, 0);
   std::vector<int> overflow;
   size_t ws_bytes = 0;
   for (int k = 0; k < p->n_classes; ++k) {
@@ -198,6 +200,8 @@ ProgPlan* get_prog(const qs_program* p, int dtype, int* rc) {
     d.expz_off = eo[k];
     lds = std::max(lds, engine_lds_bytes(dtype, c, d.S, 0, kBlock, true, true, false));
     lds_half = std::max(lds_half, engine_lds_bytes(dtype, c, d.S, 0, kBlock, true, true, true));
+    table_lds[k] = engine_lds_bytes(dtype, c, d.S, d.n_slots, kBlock, true, true, false);
+    table_lds_half[k] = engine_lds_bytes(dtype, c, d.S, d.n_slots, kBlock, true, true, true);
     for (int64_t f = 0; f < d.count; f += d.S) {
       const int64_t m = std::min<int64_t>(d.S, d.count - f);
       items.push_back({{k, (int32_t)f}, (double)m * (double)(1ll << d.n) *
@@ -214,6 +218,20 @@ ProgPlan* get_prog(const qs_program* p, int dtype, int* rc) {
   if (lds > kMaxLds) {
     *rc = QS_ERR_UNSUPPORTED;
     return nullptr;
+  }
+  // Classes whose per-circuit angle table fits next to the staging (within
+  // the one workgroup per CU the staging already implies) take the table
+  // path; the launch's LDS grows to the largest such class.
+  const int64_t per_cu_fly = std::max<int64_t>(1, std::min<int64_t>(4, kMaxLds / std::max<int64_t>(lds, 1)));
+  const int64_t budget = kMaxLds / per_cu_fly - kStaticLds;
+  if (lds <= budget) {
+    for (int k = 0; k < p->n_classes; ++k) {
+      const int64_t need = half ? table_lds_half[k] : table_lds[k];
+      if (cls[k].S > 0 && cls[k].n_slots > 0 && need <= budget) {
+        cls[k].table = 1;
+        lds = std::max(lds, need);
+      }
+    }
   }
   std::stable_sort(items.begin(), items.end(),
                    [](const Cand& a, const Cand& b) { return a.cost > b.cost; });

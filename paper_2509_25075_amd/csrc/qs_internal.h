@@ -306,6 +306,9 @@ struct ProgClass {
   const int32_t* blk_fu;
   const int32_t* blk_gen;
   int32_t n, t, nseg, n_gates, n_slots, n_params, S, n_blocks, n_fu, n_gen;
+  int32_t table;       // 1: the item's angles go to an LDS table (sines and
+                       // cosines once per gate and circuit); 0: each thread
+                       // computes the angles of its circuit where it uses them
   int64_t count;       // circuits in the class
   int64_t state_off;   // complex-element offset of the class's first state
   int64_t param_off;   // element offset of the class's parameters [count][P]

@@ -1299,10 +1299,24 @@ sv_program(const ProgClass* classes, const ProgItem* items, int n_items,
     A.ws_partials = nullptr;
     A.grad_params = grad_params ? grad_params + cd.param_off + first * cd.n_params : nullptr;
     A.grad_feats = nullptr;
-    if (ADJ)
-      adjoint_body<real, LR, true, false, HALF>(A, smem, 0);
-    else
-      forward_body<real, LR, true, false, HALF>(A, smem, 0);
+    A.x_in = nullptr;
+    A.x_stride = 0;
+    A.x_D = 0;
+    A.bad_rows = nullptr;
+    // Classes whose per-circuit angle table fits the LDS budget next to the
+    // staging take the table path (sines and cosines once per gate and
+    // circuit, in the prologue); the others compute angles where they use them.
+    if (cd.table) {
+      if (ADJ)
+        adjoint_body<real, LR, false, false, HALF>(A, smem, 0);
+      else
+        forward_body<real, LR, false, false, HALF>(A, smem, 0);
+    } else {
+      if (ADJ)
+        adjoint_body<real, LR, true, false, HALF>(A, smem, 0);
+      else
+        forward_body<real, LR, true, false, HALF>(A, smem, 0);
+    }
     __syncthreads();  // the next item reuses the LDS
   }
 }

@@ -1377,6 +1377,28 @@ def test_uneven_batch_small_all_circuits():
             np.testing.assert_allclose(gp[ps], go, atol=1e-4)
 
 
+def test_uneven_batch_table_and_on_the_fly_classes():
+    """Deep 11- and 12-qubit classes: the persistent kernel keeps an LDS
+    angle table for the classes where it fits beside the staging (12 qubits:
+    4 circuits per workgroup) and computes angles in place for the others
+    (11 qubits at depth 32: 8 circuits x 704 angles do not fit); every
+    circuit of both kinds matches the oracle."""
+    ub = Dt.uneven_batch(10, seed=13, n_lo=11, n_hi=12, d_lo=20, d_hi=32)
+    assert any(n == 11 and d > 24 for n, d, _, _ in ub.classes)
+    _announce(f"uneven batch table/fly: {ub.n_circuits} circuits, {len(ub.classes)} classes")
+    dev = sim.UnevenDevice(ub)
+    out = dev.step()
+    torch.cuda.synchronize()
+    z = out["expz"].cpu().numpy()
+    gp = out["grad_params"].cpu().numpy()
+    for k, (n, d, c, idx) in enumerate(ub.classes):
+        for j in range(len(idx)):
+            zo, go = _oracle_program_circuit(ub, k, j)
+            _, ps, es = ub.circuit_slices(k, j)
+            np.testing.assert_allclose(z[es], zo, atol=1e-5)
+            np.testing.assert_allclose(gp[ps], go, atol=1e-4)
+
+
 def test_uneven_batch_c128():
     ub = Dt.uneven_batch(40, seed=5, n_lo=4, n_hi=9, d_lo=1, d_hi=3)
     _announce(f"uneven batch c128: {ub.n_circuits} circuits, {len(ub.classes)} classes")
