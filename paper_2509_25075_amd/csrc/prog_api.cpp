@@ -224,7 +224,7 @@ ProgPlan* get_prog(const qs_program* p, int dtype, int* rc) {
   // path; the launch's LDS grows to the largest such class.
   const int64_t per_cu_fly = std::max<int64_t>(1, std::min<int64_t>(4, kMaxLds / std::max<int64_t>(lds, 1)));
   const int64_t budget = kMaxLds / per_cu_fly - kStaticLds;
-  if (lds <= budget) {
+  if (lds <= budget && dtype == QS_C64) {
     for (int k = 0; k < p->n_classes; ++k) {
       const int64_t need = half ? table_lds_half[k] : table_lds[k];
       if (cls[k].S > 0 && cls[k].n_slots > 0 && need <= budget) {

@@ -747,6 +747,14 @@ struct Ctx {
       return U2<real>{p[0], p[1], p[2], p[3], p[4], p[5], p[6], p[7]};
     }
     const int b0 = kc(A.blk_begin)[bid], b1 = kc(A.blk_begin)[bid + 1];
+    if (b1 - b0 == 2) {
+      // the common two-gate block: both records and angles fetched together
+      const BGate g0 = kload(A.blk_rec, b0), g1 = kload(A.blk_rec, b0 + 1);
+      real c0 = 1, s0 = 0, c1 = 1, s1 = 0;
+      if (bg_kind(g0) <= QS_OP_RZ) gate_cs(g0, c0, s0);
+      if (bg_kind(g1) <= QS_OP_RZ) gate_cs(g1, c1, s1);
+      return gate_lmul(bg_kind(g1), c1, s1, gate_u<real>(bg_kind(g0), c0, s0));
+    }
     U2<real> u{1, 0, 0, 0, 0, 0, 1, 0};
     for (int i = b0; i < b1; ++i) {
       const BGate bg = kload(A.blk_rec, i);
@@ -885,15 +893,47 @@ struct Ctx {
     static_for<LR>([&](auto J) QS_AI {
       constexpr int j = decltype(J)::value;
       const int bid = r.w[j];
-      const G3<real> pg =
-          pauli_and_apply<j>(psi, lam, u_dag(block_or_id(bid, r.w[kL1QFused + j])));
+      const int fu = r.w[kL1QFused + j];
+      // A per-sample block of two gates (RY then RZ, say): its two records
+      // and angles are fetched once, together, for the matrix and again
+      // for the generator frames.
+      bool two = false;
+      BGate g0{}, g1{};
+      real c0 = 1, s0 = 0, c1 = 1, s1 = 0;
+      U2<real> u;
+      if constexpr (!SHARED && sizeof(real) == 4) {  // complex128: no registers to spare
+        if (bid >= 0 && fu < 0) {
+          const int b0 = kc(A.blk_begin)[bid];
+          two = kc(A.blk_begin)[bid + 1] - b0 == 2;
+          if (two) {
+            g0 = kload(A.blk_rec, b0);
+            g1 = kload(A.blk_rec, b0 + 1);
+            if (bg_kind(g0) <= QS_OP_RZ) gate_cs(g0, c0, s0);
+            if (bg_kind(g1) <= QS_OP_RZ) gate_cs(g1, c1, s1);
+            u = gate_lmul(bg_kind(g1), c1, s1, gate_u<real>(bg_kind(g0), c0, s0));
+          }
+        }
+      }
+      if (!two) u = block_or_id(bid, fu);
+      const G3<real> pg = pauli_and_apply<j>(psi, lam, u_dag(u));
       if (bid >= 0) {  // reads pg only: no state copies at the join
         // The gradient sums (wave reductions, LDS adds) also run at raised
         // priority: they then overlap the other waves' block arithmetic.
         __builtin_amdgcn_s_setprio(1);
         const int b0 = kc(A.blk_begin)[bid], b1 = kc(A.blk_begin)[bid + 1];
         const int gen = kc(A.blk_gen)[bid];
-        if (SHARED || gen >= 0) {
+        if (two) {
+          // frames of the two gates, last gate first (as in the walk below)
+          P3<real> m;
+          const int k1 = bg_kind(g1), k0 = bg_kind(g0);
+          if (k1 <= QS_OP_RZ)
+            accum(g1, k1 == QS_OP_RX ? m.dot(0, pg) : k1 == QS_OP_RY ? m.dot(1, pg) : m.dot(2, pg),
+                  lane, wave, Tw);
+          m.conj_by(k1, c1, s1);
+          if (k0 <= QS_OP_RZ)
+            accum(g0, k0 == QS_OP_RX ? m.dot(0, pg) : k0 == QS_OP_RY ? m.dot(1, pg) : m.dot(2, pg),
+                  lane, wave, Tw);
+        } else if (SHARED || gen >= 0) {
           for (int i = b0; i < b1; ++i) {
             const BGate gt = kload(A.blk_rec, i);
             if (bg_kind(gt) > QS_OP_RZ) continue;
@@ -1303,10 +1343,14 @@ sv_program(const ProgClass* classes, const ProgItem* items, int n_items,
     A.x_stride = 0;
     A.x_D = 0;
     A.bad_rows = nullptr;
-    // Classes whose per-circuit angle table fits the LDS budget next to the
-    // staging take the table path (sines and cosines once per gate and
-    // circuit, in the prologue); the others compute angles where they use them.
-    if (cd.table) {
+    // Complex64 classes whose per-circuit angle table fits the LDS budget
+    // next to the staging take the table path (sines and cosines once per
+    // gate and circuit, in the prologue); the others compute angles where
+    // they use them. (Complex128 keeps one path: its adjoint has no
+    // registers to spare for a second.)
+    bool table = false;
+    if constexpr (sizeof(real) == 4) table = cd.table != 0;  // complex64 only
+    if (table) {
       if (ADJ)
         adjoint_body<real, LR, false, false, HALF>(A, smem, 0);
       else
