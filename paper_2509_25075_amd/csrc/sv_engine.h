@@ -753,7 +753,7 @@ struct Ctx {
       real c0 = 1, s0 = 0, c1 = 1, s1 = 0;
       if (bg_kind(g0) <= QS_OP_RZ) gate_cs(g0, c0, s0);
       if (bg_kind(g1) <= QS_OP_RZ) gate_cs(g1, c1, s1);
-      return gate_lmul(bg_kind(g1), c1, s1, gate_u<real>(bg_kind(g0), c0, s0));
+      return two_u(bg_kind(g0), c0, s0, bg_kind(g1), c1, s1);
     }
     U2<real> u{1, 0, 0, 0, 0, 0, 1, 0};
     for (int i = b0; i < b1; ++i) {
@@ -764,6 +764,19 @@ struct Ctx {
       u = i == b0 ? gate_u<real>(kind, c, s) : gate_lmul(kind, c, s, u);
     }
     return u;
+  }
+
+  // The matrix of a two-gate block G1 G0. RZ(b) RY(a), the block of
+  // hardware-efficient layers, is written out: with (c0, s0) of a/2 and
+  // (c1, s1) of b/2 it is [[c0 (c1 - i s1), -s0 (c1 - i s1)],
+  // [s0 (c1 + i s1), c0 (c1 + i s1)]].
+  __device__ __forceinline__ static U2<real> two_u(int k0, real c0, real s0, int k1, real c1,
+                                                   real s1) {
+    if (k0 == QS_OP_RY && k1 == QS_OP_RZ) {
+      const real a = c0 * c1, b = c0 * s1, d = s0 * c1, e = s0 * s1;
+      return U2<real>{a, -b, -d, e, d, e, a, b};
+    }
+    return gate_lmul(k1, c1, s1, gate_u<real>(k0, c0, s0));
   }
 
   // The block's matrix, the identity for bid < 0. Register bits without a
@@ -856,7 +869,6 @@ struct Ctx {
     const real* P = param_row(A, active ? row : 0);
     const real f = (gt.feat >= 0 && active) ? A.feats[(size_t)row * A.n_feats + gt.feat]
                                              : (real)1;
-    const real w = gt.p_w >= 0 ? P[gt.p_w] : (real)1;
     if (A.per_sample_params) {
       if (leader) {
         double* gp = A.grad_params + (size_t)row * A.n_params;
@@ -874,9 +886,11 @@ struct Ctx {
         if (lane == 0) atomicAdd(&gacc[(size_t)wave * A.n_acc + gt.col_b], v);
       }
     }
-    if (gt.feat >= 0 && leader)
+    if (gt.feat >= 0 && leader) {
+      const real w = gt.p_w >= 0 ? P[gt.p_w] : (real)1;
       atomicAdd(&facc[((size_t)sl * wps + (tau >> 6)) * A.n_feats + gt.feat],
                 gth * scale * w);
+    }
   }
 
   // Backward through an L1Q op: its second sign pattern un-applied (a sign
@@ -910,7 +924,7 @@ struct Ctx {
             g1 = kload(A.blk_rec, b0 + 1);
             if (bg_kind(g0) <= QS_OP_RZ) gate_cs(g0, c0, s0);
             if (bg_kind(g1) <= QS_OP_RZ) gate_cs(g1, c1, s1);
-            u = gate_lmul(bg_kind(g1), c1, s1, gate_u<real>(bg_kind(g0), c0, s0));
+            u = two_u(bg_kind(g0), c0, s0, bg_kind(g1), c1, s1);
           }
         }
       }
@@ -924,15 +938,21 @@ struct Ctx {
         const int gen = kc(A.blk_gen)[bid];
         if (two) {
           // frames of the two gates, last gate first (as in the walk below)
-          P3<real> m;
           const int k1 = bg_kind(g1), k0 = bg_kind(g0);
-          if (k1 <= QS_OP_RZ)
-            accum(g1, k1 == QS_OP_RX ? m.dot(0, pg) : k1 == QS_OP_RY ? m.dot(1, pg) : m.dot(2, pg),
-                  lane, wave, Tw);
-          m.conj_by(k1, c1, s1);
-          if (k0 <= QS_OP_RZ)
-            accum(g0, k0 == QS_OP_RX ? m.dot(0, pg) : k0 == QS_OP_RY ? m.dot(1, pg) : m.dot(2, pg),
-                  lane, wave, Tw);
+          real p0, p1;
+          if (k0 == QS_OP_RY && k1 == QS_OP_RZ) {
+            // RZ's frame is Z itself; RY's is Y turned about Z by RZ's angle
+            const real co = c1 * c1 - s1 * s1, si = 2 * c1 * s1;
+            p1 = pg.z;
+            p0 = co * pg.y - si * pg.x;
+          } else {
+            P3<real> m;
+            p1 = k1 == QS_OP_RX ? m.dot(0, pg) : k1 == QS_OP_RY ? m.dot(1, pg) : m.dot(2, pg);
+            m.conj_by(k1, c1, s1);
+            p0 = k0 == QS_OP_RX ? m.dot(0, pg) : k0 == QS_OP_RY ? m.dot(1, pg) : m.dot(2, pg);
+          }
+          if (k1 <= QS_OP_RZ) accum(g1, p1, lane, wave, Tw);
+          if (k0 <= QS_OP_RZ) accum(g0, p0, lane, wave, Tw);
         } else if (SHARED || gen >= 0) {
           for (int i = b0; i < b1; ++i) {
             const BGate gt = kload(A.blk_rec, i);
