@@ -2,23 +2,32 @@
 #include "sv_engine.h"
 
 namespace qs {
+namespace {
+// The specialisation for the plan: shared angles only (fused matrices and
+// generator frames from LDS, no per-sample block code) or not.
+template <int LR, int MAXT, bool ADJ>
+int launch_sel(const SvLaunch& L) {
+  return L.p->n_fu == L.p->n_blocks ? launch_one<double, LR, MAXT, ADJ, true>(L)
+                                     : launch_one<double, LR, MAXT, ADJ, false>(L);
+}
+}  // namespace
 
 int sv_c128_forward(const SvLaunch& L) {
   switch (L.shape.r) {
-    case 1: return launch_one<double, 1, 1024, false>(L);
-    case 2: return launch_one<double, 2, 1024, false>(L);
-    case 3: return launch_one<double, 3, 1024, false>(L);
-    case 4: return launch_one<double, 4, 512, false>(L);
+    case 1: return launch_sel<1, 1024, false>(L);
+    case 2: return launch_sel<2, 1024, false>(L);
+    case 3: return launch_sel<3, 1024, false>(L);
+    case 4: return launch_sel<4, 512, false>(L);
     default: return QS_ERR_UNSUPPORTED;
   }
 }
 
 int sv_c128_adjoint(const SvLaunch& L) {
   switch (L.shape.r) {
-    case 1: return launch_one<double, 1, 1024, true>(L);
-    case 2: return launch_one<double, 2, 1024, true>(L);
-    case 3: return launch_one<double, 3, 1024, true>(L);
-    case 4: return launch_one<double, 4, 512, true>(L);
+    case 1: return launch_sel<1, 1024, true>(L);
+    case 2: return launch_sel<2, 1024, true>(L);
+    case 3: return launch_sel<3, 1024, true>(L);
+    case 4: return launch_sel<4, 512, true>(L);
     default: return QS_ERR_UNSUPPORTED;
   }
 }
