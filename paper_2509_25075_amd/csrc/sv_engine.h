@@ -81,8 +81,25 @@ __device__ __forceinline__ float xor32_sum(float v) {
                                                   false, false);
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
-__device__ __forceinline__ double xor16_sum(double v) { return v + __shfl_xor(v, 16); }
-__device__ __forceinline__ double xor32_sum(double v) { return v + __shfl_xor(v, 32); }
+// The same for a double: its two 32-bit halves are swapped separately.
+__device__ __forceinline__ double xor16_sum(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)u, hi = (unsigned)(u >> 32);
+  const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  const double x = __longlong_as_double((long long)(((unsigned long long)b[0] << 32) | a[0]));
+  const double y = __longlong_as_double((long long)(((unsigned long long)b[1] << 32) | a[1]));
+  return x + y;
+}
+__device__ __forceinline__ double xor32_sum(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)u, hi = (unsigned)(u >> 32);
+  const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  const double x = __longlong_as_double((long long)(((unsigned long long)b[0] << 32) | a[0]));
+  const double y = __longlong_as_double((long long)(((unsigned long long)b[1] << 32) | a[1]));
+  return x + y;
+}
 
 // Sum over the lanes l, l ^ G, l ^ 2G, ... (G a power of two, uniform): with
 // every lane of each aligned group of G lanes holding that group's value,
