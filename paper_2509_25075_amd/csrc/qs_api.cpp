@@ -223,9 +223,9 @@ int64_t lds_bytes(int dtype, const qs_circuit& c, int S, int n_slots, int block,
   b += 8 * rs * (n_fu + 1);                         // fused block matrices, identity
   if (adjoint) b += 3 * rs * n_gen;                 // generator frames
   b += 2 * rs * (int64_t)n_slots * S;               // per-sample angle table
-  if (adjoint)                                      // gradient sums
+  if (adjoint)                                      // gradient sums, features
     b += rs * (waves * (int64_t)grad_columns(c, ps).size() +
-               (int64_t)S * wps * c.n_features);
+               (int64_t)S * wps * c.n_features + (int64_t)S * c.n_features);
   return (b + 15) & ~15ll;
 }
 

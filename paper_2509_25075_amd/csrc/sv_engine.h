@@ -510,6 +510,7 @@ struct Ctx {
   real* gen_sh;      // [n_gen][3] generator frames of their gates (adjoint)
   real* gacc;        // [waves][n_acc] shared-parameter gradient sums
   real* facc;        // [S * wps][n_feats] feature gradient sums
+  real* fsh;         // [S][n_feats] the block's features (adjoint)
   int wps;           // waves per sample (1 when a wave holds whole samples)
 
   __device__ Ctx(const Args<real>& a) : A(a) {}
@@ -884,8 +885,7 @@ struct Ctx {
     const real gth = group_sum(part, Tw);  // this sample (this wave's share)
     const bool leader = (tau & (Tw - 1)) == 0 && active;
     const real* P = param_row(A, active ? row : 0);
-    const real f = (gt.feat >= 0 && active) ? A.feats[(size_t)row * A.n_feats + gt.feat]
-                                             : (real)1;
+    const real f = (gt.feat >= 0 && active) ? fsh[(size_t)sl * A.n_feats + gt.feat] : (real)1;
     if (A.per_sample_params) {
       if (leader) {
         double* gp = A.grad_params + (size_t)row * A.n_params;
@@ -1046,6 +1046,7 @@ __device__ __forceinline__ void setup(Ctx<real, LR, FLY, SHARED, HALF>& C,
   C.wps = A.t > 6 ? (1 << (A.t - 6)) : 1;
   const int waves = blockDim.x >> 6;
   C.facc = C.gacc + (A.per_sample_params ? 0 : (size_t)waves * A.n_acc);
+  C.fsh = C.facc + (adjoint ? (size_t)A.S * C.wps * A.n_feats : 0);
 
   // Shared angles, by gate.
   for (int g = tid; g < A.n_gates; g += blockDim.x) {
@@ -1074,6 +1075,11 @@ __device__ __forceinline__ void setup(Ctx<real, LR, FLY, SHARED, HALF>& C,
     if (!A.per_sample_params)
       for (int i = tid; i < waves * A.n_acc; i += blockDim.x) C.gacc[i] = 0;
     for (int i = tid; i < A.S * C.wps * A.n_feats; i += blockDim.x) C.facc[i] = 0;
+    // the features the gradient sums scale by, read from HBM once per sample
+    for (int i = tid; i < A.S * A.n_feats; i += blockDim.x) {
+      const int64_t bb = blk + i / A.n_feats;
+      C.fsh[i] = bb < A.B ? A.feats[(size_t)(bb >> A.ob) * A.n_feats + i % A.n_feats] : (real)0;
+    }
   }
   __syncthreads();
   // Fused matrices of the blocks whose angles are shared; slot n_fu holds the
