@@ -416,6 +416,11 @@ Entry* get_plan(const qs_circuit& c, int r, bool ps, const int32_t* ck, int n_ck
   d.n_fu = P.n_fu;
   d.n_gen = P.n_gen;
   d.n_acc = (int)P.grad_cols.size();
+  d.ryrz = d.n_blocks > 0;
+  for (int b = 0; b < d.n_blocks && d.ryrz; ++b)
+    d.ryrz = P.blk_begin[b + 1] - P.blk_begin[b] == 2 &&
+             c.gates[P.blk_gates[P.blk_begin[b]]].op == QS_OP_RY &&
+             c.gates[P.blk_gates[P.blk_begin[b] + 1]].op == QS_OP_RZ;
   std::vector<BGate> rec(P.blk_gates.size());
   for (size_t i = 0; i < rec.size(); ++i) {
     const int g = P.blk_gates[i];

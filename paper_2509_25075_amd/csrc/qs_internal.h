@@ -208,6 +208,7 @@ struct SvDevPlan {
   int32_t* blk_gen;
   int32_t* grad_cols;  // [n_acc] parameter of each gradient column
   int n_blocks, n_fu, n_acc, n_gen;
+  int ryrz = 0;        // every block is RY then RZ (hardware-efficient layers)
 };
 
 // Launch geometry of the engine for a plan.

@@ -7,6 +7,17 @@ namespace {
 // staging mode.
 template <int LR, int MAXT>
 int launch_sel(const SvLaunch& L, bool shared) {
+  // Plans whose every block is RY then RZ take the gate-at-a-time pass
+  // (register tiles 2^4 and 2^5, the ones such plans are tuned to).
+  if constexpr (LR >= 4) {
+    if (L.p->ryrz) {
+      if (L.shape.half)
+        return shared ? launch_one<float, LR, MAXT, true, true, true, true>(L)
+                      : launch_one<float, LR, MAXT, true, false, true, true>(L);
+      return shared ? launch_one<float, LR, MAXT, true, true, false, true>(L)
+                    : launch_one<float, LR, MAXT, true, false, false, true>(L);
+    }
+  }
   if (L.shape.half)
     return shared ? launch_one<float, LR, MAXT, true, true, true>(L)
                   : launch_one<float, LR, MAXT, true, false, true>(L);
