@@ -187,6 +187,7 @@ ProgPlan* get_prog(const qs_program* p, int dtype, int* rc) {
     d.n_blocks = ep.dev->n_blocks;
     d.n_fu = ep.dev->n_fu;
     d.n_gen = ep.dev->n_gen;
+    d.ryrz = dtype == QS_C64 ? ep.dev->ryrz : 0;
     d.n = c.n_qubits;
     d.t = c.n_qubits - r;
     d.nseg = ep.dev->nseg;

@@ -307,6 +307,7 @@ struct ProgClass {
   const int32_t* blk_fu;
   const int32_t* blk_gen;
   int32_t n, t, nseg, n_gates, n_slots, n_params, S, n_blocks, n_fu, n_gen;
+  int32_t ryrz;        // every block is RY then RZ (the adjoint's gate-at-a-time pass)
   int32_t table;       // 1: the item's angles go to an LDS table (sines and
                        // cosines once per gate and circuit); 0: each thread
                        // computes the angles of its circuit where it uses them

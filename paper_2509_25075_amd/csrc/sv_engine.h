@@ -1468,16 +1468,28 @@ sv_program(const ProgClass* classes, const ProgItem* items, int n_items,
     // registers to spare for a second.)
     bool table = false;
     if constexpr (sizeof(real) == 4) table = cd.table != 0;  // complex64 only
+    // Complex64 classes whose blocks are all RY then RZ take the adjoint's
+    // gate-at-a-time pass.
+    bool ryrz = false;
+    if constexpr (sizeof(real) == 4 && ADJ) ryrz = cd.ryrz != 0;
     if (table) {
-      if (ADJ)
-        adjoint_body<real, LR, false, false, HALF>(A, smem, 0);
-      else
+      if constexpr (ADJ) {
+        if (ryrz)
+          adjoint_body<real, LR, false, false, HALF, true>(A, smem, 0);
+        else
+          adjoint_body<real, LR, false, false, HALF>(A, smem, 0);
+      } else {
         forward_body<real, LR, false, false, HALF>(A, smem, 0);
+      }
     } else {
-      if (ADJ)
-        adjoint_body<real, LR, true, false, HALF>(A, smem, 0);
-      else
+      if constexpr (ADJ) {
+        if (ryrz)
+          adjoint_body<real, LR, true, false, HALF, true>(A, smem, 0);
+        else
+          adjoint_body<real, LR, true, false, HALF>(A, smem, 0);
+      } else {
         forward_body<real, LR, true, false, HALF>(A, smem, 0);
+      }
     }
     __syncthreads();  // the next item reuses the LDS
   }
