@@ -7,8 +7,16 @@ namespace {
 // generator frames from LDS, no per-sample block code) or not.
 template <int LR, int MAXT, bool ADJ>
 int launch_sel(const SvLaunch& L) {
-  return L.p->n_fu == L.p->n_blocks ? launch_one<double, LR, MAXT, ADJ, true>(L)
-                                     : launch_one<double, LR, MAXT, ADJ, false>(L);
+  const bool shared = L.p->n_fu == L.p->n_blocks;
+  // Plans whose every block is RY then RZ: the adjoint's gate-at-a-time pass
+  // (register tile 2^4).
+  if constexpr (ADJ && LR == 4) {
+    if (L.p->ryrz)
+      return shared ? launch_one<double, LR, MAXT, ADJ, true, false, true>(L)
+                    : launch_one<double, LR, MAXT, ADJ, false, false, true>(L);
+  }
+  return shared ? launch_one<double, LR, MAXT, ADJ, true>(L)
+                : launch_one<double, LR, MAXT, ADJ, false>(L);
 }
 }  // namespace
 
