@@ -1523,8 +1523,10 @@ int forward_impl(const qs_circuit* c, int dtype, int64_t B, const void* params,
   const int path = pick_path(*c, dtype, flags, &shape, count_slots(*c, ps), false,
                              tuned ? &tv : nullptr, ckpt_gates, n_ckpt);
   if (path < 0) return path;
-  // The fused engine encodes while it loads when x is in the state's precision.
-  const bool fuse_enc = enc && path == QS_PATH_FUSED && (enc->x_is_f64 != 0) == (dtype == QS_C128);
+  // The fused engine encodes while it loads when x is in the state's precision
+  // and the launch stages whole amplitudes.
+  const bool fuse_enc = enc && path == QS_PATH_FUSED && shape.half == 0 &&
+                        (enc->x_is_f64 != 0) == (dtype == QS_C128);
   if (!fuse_enc && (rc = encode_first(enc, dtype, c->n_qubits, B, state, stream)) != QS_OK)
     return rc;
   if (path == QS_PATH_PLAIN) {

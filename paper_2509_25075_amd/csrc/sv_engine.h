@@ -1226,7 +1226,10 @@ __device__ __forceinline__ void forward_body(const Args<real>& A, unsigned char*
   setup(C, A, smem, false, blk);
 
   St<real, R> x;
-  C.load_state(x, A.state, rlay(A, 0), !FLY && A.x_in != nullptr);
+  // (one-component staging keeps both components live through its passes;
+  // an encoding branch there doubles the registers, so such launches get an
+  // encoded state instead)
+  C.load_state(x, A.state, rlay(A, 0), !FLY && !HALF && A.x_in != nullptr);
   const int nseg = A.nseg;
   const QS_K int32_t* seg_begin = kc(A.seg_begin);
   for (int s = 0; s < nseg; ++s) {

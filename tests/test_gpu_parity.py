@@ -583,6 +583,14 @@ def test_forward_amplitude_vs_oracle(n, dtype, xbits):
     np.testing.assert_allclose(z.cpu().numpy()[keep], O.expz(psiG), atol=tol["z"])
 
 
+@pytest.mark.parametrize("n", [4, 10, 13])
+def test_forward_amplitude_with_one_component_staging(n, half_staging):
+    """Launches that stage one state component at a time get an encoded
+    state (the encoding kernel, then the sweep) instead of encoding while
+    they load: the same results."""
+    test_forward_amplitude_vs_oracle(n, "c64", 32)
+
+
 def test_forward_amplitude_with_checkpoints_matches_encode_then_forward():
     """With checkpoints the fused forward stores the same states as qs_encode
     followed by qs_forward, and ends in the same final state."""
