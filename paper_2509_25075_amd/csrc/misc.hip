@@ -464,31 +464,32 @@ unsigned grid_for(int64_t n) {
 
 int ok() { return hipGetLastError() == hipSuccess ? QS_OK : QS_ERR_LAUNCH; }
 
-// Mean-squared error on qubit q's readout: every workgroup writes its share
-// of the upstream gradient rows (2/B)(z_b - y_b) e_q; workgroup 0 also sums
-// the squared residuals, each thread over a fixed stride of rows and then
-// the workgroup in a fixed order, so the loss is bitwise reproducible.
+// Mean-squared error on qubit q's readout. Workgroup 0 sums the squared
+// residuals, each thread over a fixed stride of rows (their loads in flight
+// together) and then the workgroup in a fixed order, so the loss is bitwise
+// reproducible; the other workgroups write the upstream gradient rows
+// (2/B)(z_b - y_b) e_q, one element per thread.
 constexpr int kLossBlock = 1024;
 __global__ void __launch_bounds__(kLossBlock)
 loss_mse_z(int n, int64_t B, int q, const double* expz, const double* y, double* dexpz,
            double* loss) {
   __shared__ double sh[kLossBlock / 64];
   const double inv_b = B > 0 ? 1.0 / (double)B : 0.0;
-  if (dexpz != nullptr) {
+  if (blockIdx.x > 0) {
+    if (dexpz == nullptr) return;
     // row-major [B][n]: element i is row i / n, column i % n (32-bit
     // division while the index fits, which it does for any batch in HBM)
     const int64_t total = B * n;
     const bool small = total < (1ll << 31);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i = (int64_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)(gridDim.x - 1) * blockDim.x) {
       const int64_t b = small ? (int64_t)((uint32_t)i / (uint32_t)n) : i / n;
       const int k = (int)(i - b * n);
       dexpz[i] = k == q ? 2.0 * inv_b * (expz[b * n + q] - y[b]) : 0.0;
     }
+    return;
   }
-  if (blockIdx.x != 0 || loss == nullptr) return;
-  // Rows tid, tid + T, ... of this thread, added in that order; the loads of
-  // eight rows are in flight together.
+  if (loss == nullptr) return;
   double s = 0;
   const int64_t T = blockDim.x;
   for (int64_t b0 = threadIdx.x; b0 < B; b0 += 8 * T) {
@@ -510,6 +511,7 @@ loss_mse_z(int n, int64_t B, int q, const double* expz, const double* y, double*
     loss[0] = t * inv_b;
   }
 }
+
 
 }  // namespace
 
@@ -613,11 +615,11 @@ int launch_fill_f64(double* p, int64_t n, void* stream) {
 int launch_loss_mse_z(int n, int64_t B, int q, const double* expz, const double* y,
                       double* dexpz, double* loss, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
-  int64_t g = (B * n + kLossBlock * 4 - 1) / (kLossBlock * 4);
-  if (g < 1) g = 1;
-  if (g > 1024) g = 1024;
-  hipLaunchKernelGGL(loss_mse_z, dim3((unsigned)g), kLossBlock, 0, st, n, B, q, expz, y,
-                     dexpz, loss);
+  // workgroup 0: the loss; the others: one gradient element per thread
+  int64_t g = (B * n + kLossBlock - 1) / kLossBlock;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(loss_mse_z, dim3((unsigned)(g + 1)), kLossBlock, 0, st, n, B, q, expz,
+                     y, dexpz, loss);
   return ok();
 }
 
