@@ -492,15 +492,16 @@ loss_mse_z(int n, int64_t B, int q, const double* expz, const double* y, double*
   if (loss == nullptr) return;
   double s = 0;
   const int64_t T = blockDim.x;
-  for (int64_t b0 = threadIdx.x; b0 < B; b0 += 8 * T) {
-    double r[8];
+  constexpr int kRows = 32;  // rows of a thread whose loads are in flight together
+  for (int64_t b0 = threadIdx.x; b0 < B; b0 += kRows * T) {
+    double r[kRows];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < kRows; ++u) {
       const int64_t b = b0 + u * T;
       r[u] = b < B ? expz[b * n + q] - y[b] : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) s += r[u] * r[u];
+    for (int u = 0; u < kRows; ++u) s += r[u] * r[u];
   }
   for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
