@@ -99,6 +99,26 @@ def test_random_circuit_c128(n, path):
     _run_expz_case(c, "c128", path, 11 if n <= 9 else 3, seed=n)
 
 
+# Circuits whose every block is RY then RZ run the adjoint's gate-at-a-time
+# pass (register tiles 2^4 and 2^5 in complex64, 2^4 in complex128); the
+# builders give such circuits (re-uploading adds features to the RY angles).
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("kind,n", [("ring", 1), ("ring", 3), ("ring", 5), ("ring", 9),
+                                    ("ring", 12), ("ring", 14), ("chain", 7), ("chain", 11),
+                                    ("reupload", 6), ("reupload", 10), ("ring", 16)])
+def test_ry_rz_circuits(kind, n, dtype):
+    if kind == "ring":
+        c = C.hea_ry_rz_ring(n, 3)
+    elif kind == "chain":
+        c = C.ry_rz_chain(n, 3)
+    else:
+        c = C.reupload_ry_rz_chain(n, 3, 3)
+    B = 21 if n <= 10 else 3
+    _run_expz_case(c, dtype, "auto", B, seed=1800 + n)
+    if n <= 13:
+        _run_expz_case(c, dtype, "auto", B, seed=1900 + n, per_sample=True)
+
+
 @pytest.mark.parametrize("path", ["fused", "plain"])
 @pytest.mark.parametrize("n", [2, 6, 10, 13])
 def test_per_sample_params(n, path):
