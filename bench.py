@@ -83,12 +83,16 @@ LDS_TBPS_ASSUMED = 78.6
 # forms Im<lam|P|psi> (4). CNOT, CZ, X, Y, Z, H: counted as 0.
 FLOPS_ROT_FWD = 6
 FLOPS_ROT_ADJ = 16
+# ... and of one rotation on one amplitude in the forward sweep (two products
+# and one add per output component).
+FLOPS_ROT_FWD = 6
 
 # Sources that decide what the adjoint kernel does; the measured HBM traffic
 # in profiles/ is only reported while their hash matches the one recorded
 # with the counters.
 KERNEL_SOURCES = ["paper_2509_25075_amd/csrc/sv_engine.h",
                   "paper_2509_25075_amd/csrc/sv_c64_adj.hip",
+                  "paper_2509_25075_amd/csrc/sv_c64_train.hip",
                   "paper_2509_25075_amd/csrc/qs_internal.h",
                   "paper_2509_25075_amd/csrc/planner.cpp",
                   "include/qs.h"]
@@ -103,11 +107,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str):
-    """HBM bytes per launch of the adjoint kernel from the FETCH_SIZE /
+def measured_traffic(workload: str, kernel: str = "sv_adjoint"):
+    """HBM bytes per launch of the dominant kernel from the FETCH_SIZE /
     WRITE_SIZE counters recorded under profiles/ (scaled by a plain copy of
     known size), or None when absent or taken on other kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"sv_adjoint_{workload}_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -391,7 +395,13 @@ def main():
         path = {1: "fused", 2: "plain", 3: "tiled_hbm", 4: "mfma_blocks"}[
             d.sim.plan_info(w.batch)["path"]]
         updates = w.updates_per_step()
-        sim.Simulator.adjoint = timer.wrap(sim.Simulator.adjoint)
+        # The dominant call: the one-launch training step where it runs,
+        # else the adjoint.
+        one_launch = w.loss != "none" and sim.train_step_runs(d)
+        if one_launch:
+            N.qs_train_step_mse = timer.wrap(N.qs_train_step_mse)
+        else:
+            sim.Simulator.adjoint = timer.wrap(sim.Simulator.adjoint)
         ms, wall = timed_loop(torch, stream, lambda: sim.step(d), args.steps,
                               args.warmup, timer)
         adj_ms = timer.mean_ms()
@@ -433,6 +443,16 @@ def main():
                     "launches_per_step": n_bl, "algorithmic_bytes_per_call": bytes_call,
                     "mfma_tflops": mfma_flops / (adj_ms * 1e-3) / 1e12,
                     "mfma_frac": mfma_flops / (adj_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
+        elif one_launch:
+            # forward, readout, loss and adjoint in one launch (plus the
+            # partial-sum reduction in the same library call)
+            flops_step = (FLOPS_ROT_FWD + FLOPS_ROT_ADJ) * rot * amps
+            roof = {"bound": "alu", "achieved": flops_step / (adj_ms * 1e-3) / 1e12,
+                    "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                    "traffic": measured_traffic(key, "sv_train"),
+                    "kernel": "sv_train (forward, loss and adjoint in one launch)",
+                    "kernel_ms": adj_ms, "launches_per_step": n_adj,
+                    "algorithmic_flops_per_launch": flops_step}
         else:
             flops_adj = FLOPS_ROT_ADJ * rot * amps
             roof = {"bound": "alu", "achieved": flops_adj / (adj_ms * 1e-3) / 1e12,

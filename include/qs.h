@@ -230,6 +230,38 @@ int qs_forward_amplitude(const qs_circuit* circuit, int dtype, int64_t B,
 int qs_loss_mse_z(int n_qubits, int64_t B, int q, const double* expz, const double* y,
                   double* dexpz, double* loss, void* stream);
 
+/* A training step with the MSE loss on one qubit in one engine launch:
+ * the forward sweep from the amplitude encoding of x (qs_forward_amplitude's
+ * definition) or, with x NULL, from |0...0>; <Z> in FP64; the loss and its
+ * upstream gradient (qs_loss_mse_z's definitions, loss_q = q); the adjoint
+ * (qs_adjoint_backward's gradients). The state stays in registers from the
+ * encoding to the last gradient: no state is read from or written to HBM.
+ * Results equal those of qs_forward_amplitude (or qs_encode + qs_forward),
+ * qs_loss_mse_z and qs_adjoint_backward up to rounding order.
+ *   x, x_is_f64, D, x_stride, bad_rows  as qs_forward_amplitude, or x NULL
+ *   y        (device) [B] double labels
+ *   expz     (device, optional) [B][n] double, receives <Z_q>_b
+ *   loss     (device) [1] double, receives (1/B) sum_b (<Z_q>_b - y_b)^2,
+ *            summed per workgroup in sample order, then over workgroups in
+ *            a fixed order
+ *   grad_params (device) [n_params] double (overwritten), grad_feats
+ *            (device, optional) [B][n_features] double (overwritten)
+ *   ws, ws_bytes  (device) at least qs_train_workspace_size() bytes
+ * Runs only where that kernel exists: complex64, parameters shared by the
+ * batch, no channels, and a register/LDS engine shape with register tile
+ * 2^4 or 2^5 staging whole amplitudes (the adjoint's tuned shape). Other
+ * cases return QS_ERR_UNSUPPORTED before any device work (callers then use
+ * the three calls above), as does a float64 x. B == 0 does nothing. */
+int qs_train_step_mse(const qs_circuit* circuit, int dtype, int64_t B, const void* params,
+                      const void* feats, const void* x, int x_is_f64, int64_t D,
+                      int64_t x_stride, int32_t* bad_rows, const double* y, int q,
+                      double* expz, double* loss, double* grad_params, double* grad_feats,
+                      void* ws, size_t ws_bytes, int flags, void* stream);
+
+/* Workspace bytes of qs_train_step_mse for this shape (host only); 0 when
+ * the one-launch training step does not run for it. */
+size_t qs_train_workspace_size(const qs_circuit* circuit, int dtype, int64_t B, int flags);
+
 /* Bytes of device workspace qs_adjoint_backward needs for this shape. */
 size_t qs_workspace_size(const qs_circuit* circuit, int dtype, int64_t B,
                          int flags);

@@ -120,6 +120,10 @@ def lib() -> ctypes.CDLL:
                                                 i32p, i32, vp, ctypes.c_int, vp]),
         "qs_loss_mse_z": (ctypes.c_int, [ctypes.c_int, i64, ctypes.c_int, vp, vp, vp, vp,
                                          vp]),
+        "qs_train_step_mse": (ctypes.c_int, [cp, ctypes.c_int, i64, vp, vp, vp, ctypes.c_int,
+                                             i64, i64, vp, vp, ctypes.c_int, vp, vp, vp, vp,
+                                             vp, sz, ctypes.c_int, vp]),
+        "qs_train_workspace_size": (sz, [cp, ctypes.c_int, i64, ctypes.c_int]),
         "qs_workspace_size": (sz, [cp, ctypes.c_int, i64, ctypes.c_int]),
         "qs_adjoint_backward": (ctypes.c_int, [cp, ctypes.c_int, i64, vp, vp, vp,
                                                vp, vp, vp, vp, i32p, i32, vp, vp,
@@ -275,6 +279,26 @@ def qs_loss_mse_z(q: int, expz, y, dexpz=None, loss=None, stream=None):
     B, n = expz.shape
     _check(lib().qs_loss_mse_z(n, B, q, _ptr(expz), _ptr(y), _ptr(dexpz), _ptr(loss),
                                _stream(stream)), "qs_loss_mse_z")
+
+
+def qs_train_workspace_size(h: CircuitHandle, dtype: int, B: int, flags: int = 0) -> int:
+    return int(lib().qs_train_workspace_size(h.ptr, dtype, B, flags))
+
+
+def qs_train_step_mse(h: CircuitHandle, dtype: int, params, feats, x, y, q: int, loss,
+                      grad_params, ws, expz=None, grad_feats=None, bad_rows=None,
+                      B: int | None = None, flags: int = 0, stream=None):
+    """One-launch training step (see include/qs.h). x: [B, D] float32 device
+    tensor or None (start from |0...0>, then B must be given); y [B] float64;
+    loss [1] float64; ws uint8 of qs_train_workspace_size bytes."""
+    if x is not None:
+        B, D, xs, f64 = x.shape[0], x.shape[1], x.stride(0), int(x.dtype.itemsize == 8)
+    else:
+        D, xs, f64 = 0, 0, 0
+    _check(lib().qs_train_step_mse(h.ptr, dtype, B, _ptr(params), _ptr(feats), _ptr(x), f64,
+                                   D, xs, _ptr(bad_rows), _ptr(y), q, _ptr(expz), _ptr(loss),
+                                   _ptr(grad_params), _ptr(grad_feats), _ptr(ws), ws.numel(),
+                                   flags, _stream(stream)), "qs_train_step_mse")
 
 
 def qs_workspace_size(h: CircuitHandle, dtype: int, B: int, flags: int = 0) -> int:

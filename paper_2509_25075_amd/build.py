@@ -32,7 +32,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Wno-unused-result"]
 
 # Largest translation units first, so the parallel build ends soonest.
-SOURCES = ["sv_c64_adj.hip", "sv_c64_fwd.hip", "sv_c128.hip", "sv_prog.hip",
+SOURCES = ["sv_c64_adj.hip", "sv_c64_train.hip", "sv_c64_fwd.hip", "sv_c128.hip", "sv_prog.hip",
            "sv_engine.hip", "planner.cpp", "qs_api.cpp", "prog_api.cpp", "misc.hip",
            "plain.hip", "noalloc.hip", "mfma.hip", "blocks.cpp"]
 

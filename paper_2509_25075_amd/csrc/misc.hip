@@ -424,9 +424,18 @@ fidelity_trajectory_kernel(int n, int nt, const real* psi, const real* chi, cons
 template <typename acc_t>
 __global__ void __launch_bounds__(kBlock)
 reduce_partials(const acc_t* partials, int64_t rows, int cols, const int32_t* col_param,
-                double* out, int accumulate) {
+                double* out, int accumulate, const double* loss_part, double* loss,
+                double loss_scale) {
   __shared__ double sh[kBlock / 64];
   const int c = blockIdx.x;
+  if (c == cols) {
+    // the training step's loss: per-workgroup sums added in a fixed order
+    double s = 0;
+    for (int64_t r = threadIdx.x; r < rows; r += blockDim.x) s += loss_part[r];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) loss[0] = s * loss_scale;
+    return;
+  }
   const int64_t step = blockDim.x;
   double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
   int64_t r = threadIdx.x;
@@ -694,15 +703,19 @@ int launch_fidelity_trajectory(int dtype, int n, int n_trash, int64_t B, const v
 
 int launch_reduce_partials(int dtype, const void* partials, int64_t rows,
                            int cols, const int32_t* col_param, double* out,
-                           int accumulate, void* stream) {
-  if (cols <= 0) return QS_OK;
+                           int accumulate, void* stream, const double* loss_part,
+                           double* loss, double loss_scale) {
+  const int blocks = cols + (loss != nullptr ? 1 : 0);
+  if (blocks <= 0) return QS_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (dtype == QS_C64)
-    hipLaunchKernelGGL(reduce_partials<float>, dim3((unsigned)cols), kBlock, 0, st,
-                       (const float*)partials, rows, cols, col_param, out, accumulate);
+    hipLaunchKernelGGL(reduce_partials<float>, dim3((unsigned)blocks), kBlock, 0, st,
+                       (const float*)partials, rows, cols, col_param, out, accumulate,
+                       loss_part, loss, loss_scale);
   else
-    hipLaunchKernelGGL(reduce_partials<double>, dim3((unsigned)cols), kBlock, 0, st,
-                       (const double*)partials, rows, cols, col_param, out, accumulate);
+    hipLaunchKernelGGL(reduce_partials<double>, dim3((unsigned)blocks), kBlock, 0, st,
+                       (const double*)partials, rows, cols, col_param, out, accumulate,
+                       loss_part, loss, loss_scale);
   return ok();
 }
 

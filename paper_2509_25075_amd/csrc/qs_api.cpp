@@ -226,6 +226,7 @@ int64_t lds_bytes(int dtype, const qs_circuit& c, int S, int n_slots, int block,
   if (adjoint)                                      // gradient sums, features
     b += rs * (waves * (int64_t)grad_columns(c, ps).size() +
                (int64_t)S * wps * c.n_features + (int64_t)S * c.n_features);
+  if (adjoint) b += 8 * (int64_t)S + 8;             // training step: squared residuals
   return (b + 15) & ~15ll;
 }
 
@@ -894,17 +895,23 @@ int64_t grid_of(const SvShape& s, int64_t B) {
 // grid is counted with the LDS tables bounded (fewer samples per block than
 // any plan of the circuit gets, with or without checkpoints), so the size
 // covers every launch of that split.
-size_t fused_ws_bytes(const qs_circuit& c, int dtype, const SvShape& s, int64_t B,
-                      bool ps) {
-  if (ps) return 0;
-  const size_t acc = dtype == QS_C64 ? sizeof(float) : sizeof(double);
-  const size_t cols = std::max<size_t>(grad_columns(c, false).size(), 1);
+// Workgroups of the fused adjoint with register split s.r, bounded over the
+// plans of the circuit (see fused_ws_bytes).
+int64_t fused_rows_bound(const qs_circuit& c, int dtype, const SvShape& s, int64_t B, bool ps) {
   SvShape wide = s;
   if (!choose_shape(dtype, c, count_slots(c, ps), s.r, true, &wide, ps, nullptr, 0, false) ||
       wide.r != s.r)
     wide = s;
   const int64_t S = std::min(wide.samples_per_block, s.samples_per_block);
-  return (size_t)((B + S - 1) / S) * cols * acc;
+  return (B + S - 1) / S;
+}
+
+size_t fused_ws_bytes(const qs_circuit& c, int dtype, const SvShape& s, int64_t B,
+                      bool ps) {
+  if (ps) return 0;
+  const size_t acc = dtype == QS_C64 ? sizeof(float) : sizeof(double);
+  const size_t cols = std::max<size_t>(grad_columns(c, false).size(), 1);
+  return (size_t)fused_rows_bound(c, dtype, s, B, ps) * cols * acc;
 }
 
 bool tuned_for_call(const qs_circuit& c, int dtype, int64_t B, int flags, void* stream,
@@ -1646,6 +1653,97 @@ int qs_adjoint_backward(const qs_circuit* c, int dtype, int64_t B,
   return adjoint_backward_impl(c, dtype, B, params, feats, state, dexpz, dstate, grad_params,
                                grad_feats, ckpt_gates, n_ckpt, ckpt, ws, ws_bytes, flags,
                                stream, false);
+}
+
+}  // extern "C"
+
+namespace {
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// The one-launch training step runs on the fused engine with the adjoint's
+// (tuned) shape when that shape has a training-step kernel: complex64, angles
+// shared by the batch, no channels. Returns the shape, or false.
+bool train_shape(const qs_circuit& c, int dtype, int64_t B, int flags, void* stream, bool tune,
+                 SvShape* shape) {
+  if (dtype != QS_C64 || (flags & QS_FLAG_PER_SAMPLE_PARAMS) || has_channels(c)) return false;
+  TuneVal tv;
+  const bool tuned = tune ? tuned_for_call(c, dtype, B, flags, stream, &tv)
+                          : tuned_lookup(c, dtype, B, flags, &tv);
+  const int path = pick_path(c, dtype, flags, shape, count_slots(c, false), true,
+                             tuned ? &tv : nullptr);
+  return path == QS_PATH_FUSED && sv_train_supported(dtype, *shape);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t qs_train_workspace_size(const qs_circuit* c, int dtype, int64_t B, int flags) {
+  InvCircuit inv_;
+  c = apply_inverse(c, &flags, inv_);
+  if (validate(c) != QS_OK || B <= 0) return 0;
+  if (flags & ~(QS_PATH_MASK | QS_FLAG_PER_SAMPLE_PARAMS)) return 0;
+  SvShape shape;
+  if (!train_shape(*c, dtype, B, flags, nullptr, false, &shape)) return 0;
+  return align256(fused_ws_bytes(*c, dtype, shape, B, false)) +
+         (size_t)fused_rows_bound(*c, dtype, shape, B, false) * sizeof(double);
+}
+
+int qs_train_step_mse(const qs_circuit* c, int dtype, int64_t B, const void* params,
+                      const void* feats, const void* x, int x_is_f64, int64_t D,
+                      int64_t x_stride, int32_t* bad_rows, const double* y, int q,
+                      double* expz, double* loss, double* grad_params, double* grad_feats,
+                      void* ws, size_t ws_bytes, int flags, void* stream) {
+  CallStream call_(stream);
+  InvCircuit inv_;
+  c = apply_inverse(c, &flags, inv_);
+  int rc = validate(c);
+  if (rc != QS_OK) return rc;
+  if ((dtype != QS_C64 && dtype != QS_C128) || B < 0) return QS_ERR_INVALID;
+  if (flags & ~(QS_PATH_MASK | QS_FLAG_PER_SAMPLE_PARAMS)) return QS_ERR_INVALID;
+  if (q < 0 || q >= c->n_qubits) return QS_ERR_INVALID;
+  if (B == 0) return QS_OK;
+  if (!y || !loss) return QS_ERR_INVALID;
+  if (c->n_params > 0 && (!params || !grad_params)) return QS_ERR_INVALID;
+  if (c->n_features > 0 && !feats) return QS_ERR_INVALID;
+  if (x && (D < 1 || D > (1ll << c->n_qubits) || x_stride < D)) return QS_ERR_INVALID;
+  if (x && x_is_f64) return QS_ERR_UNSUPPORTED;  // complex64 reads float32 inputs
+  SvShape shape;
+  if (!train_shape(*c, dtype, B, flags, stream, true, &shape)) return QS_ERR_UNSUPPORTED;
+  Entry* e = get_plan(*c, shape.r, false, nullptr, 0, &rc);
+  if (!e) return rc;
+  if (!tables_fit(*e, dtype, *c, shape, false, true)) return QS_ERR_UNSUPPORTED;
+  const int64_t grid = grid_of(shape, B);
+  const size_t part = align256(fused_ws_bytes(*c, dtype, shape, B, false));
+  if (!ws || ws_bytes < part + (size_t)grid * sizeof(double)) return QS_ERR_WORKSPACE;
+  SvLaunch L{};
+  L.p = &e->dev;
+  L.shape = shape;
+  L.B = B;
+  L.params = params;
+  L.feats = feats;
+  L.state = nullptr;  // the state never leaves the registers
+  L.x_in = x;
+  L.x_stride = x_stride;
+  L.x_D = D;
+  L.bad_rows = bad_rows;
+  L.expz = expz;
+  L.ws_partials = ws;
+  L.grad_params = grad_params;
+  L.grad_feats = c->n_features ? grad_feats : nullptr;
+  L.y = y;
+  L.loss_q = q;
+  L.loss_part = reinterpret_cast<double*>(static_cast<char*>(ws) + part);
+  L.stream = stream;
+  if ((rc = launch_sv_train(dtype, L)) != QS_OK) return rc;
+  const int n_acc = c->n_params ? e->dev.n_acc : 0;
+  if (c->n_params && n_acc < c->n_params &&
+      (rc = launch_fill_f64(grad_params, c->n_params, stream)) != QS_OK)
+    return rc;
+  return launch_reduce_partials(dtype, ws, grid, n_acc, e->dev.grad_cols, grad_params,
+                                n_acc < c->n_params, stream, L.loss_part, loss,
+                                1.0 / (double)B);
 }
 
 }  // extern "C"

@@ -250,10 +250,19 @@ struct SvLaunch {
   const void* x_in = nullptr;
   int64_t x_stride = 0, x_D = 0;
   int32_t* bad_rows = nullptr;
+  // Training step (launch_sv_train): labels, loss qubit, per-workgroup
+  // squared-residual sums [grid] double.
+  const double* y = nullptr;
+  int loss_q = 0;
+  double* loss_part = nullptr;
   void* stream;
 };
 int launch_sv_forward(int dtype, const SvLaunch& L);
 int launch_sv_adjoint(int dtype, const SvLaunch& L);
+// The training step in one engine launch (complex64, whole-amplitude
+// staging, register tiles 2^4 and 2^5); QS_ERR_UNSUPPORTED otherwise.
+int launch_sv_train(int dtype, const SvLaunch& L);
+bool sv_train_supported(int dtype, const SvShape& shape);
 
 int launch_encode(int enc, int dtype, int n, int64_t B, int64_t D,
                   int x_is_f64, const void* x, int64_t x_stride, void* state,
@@ -273,9 +282,12 @@ int launch_fidelity_trajectory(int dtype, int n, int n_trash, int64_t B, const v
                                int32_t* outcome, const double* dfid, void* lam_psi,
                                void* lam_chi, void* stream);
 // out[col_param[j]] (+)= sum over rows of partials[row][j], j < cols.
+// Sums [rows][cols] partials per column into out[col_param[c]] (FP64, fixed
+// order); with `loss`, also loss[0] = loss_scale x the sum of loss_part[rows].
 int launch_reduce_partials(int dtype, const void* partials, int64_t rows,
                            int cols, const int32_t* col_param, double* out,
-                           int accumulate, void* stream);
+                           int accumulate, void* stream, const double* loss_part = nullptr,
+                           double* loss = nullptr, double loss_scale = 0.0);
 int launch_obs_cot(int dtype, int n, int64_t B, const double* dexpz,
                    const void* psi, void* lam, void* stream);
 int launch_fill_f64(double* p, int64_t n, void* stream);

@@ -478,6 +478,13 @@ struct Args {
   const real* x_in;
   int64_t x_stride, x_D;
   int32_t* bad_rows;
+  // Training step (forward, MSE loss on qubit loss_q against y, adjoint in
+  // one launch): y [B] labels; loss_part [grid] per-workgroup sums of the
+  // squared residuals. With x_in and state both null the sweep starts from
+  // |0...0>.
+  const double* y;
+  int loss_q;
+  double* loss_part;
 };
 
 template <typename real>
@@ -557,6 +564,7 @@ struct Ctx {
   real* gacc;        // [waves][n_acc] shared-parameter gradient sums
   real* facc;        // [S * wps][n_feats] feature gradient sums
   real* fsh;         // [S][n_feats] the block's features (adjoint)
+  double* lsq;       // [S] squared residuals of the training step's loss
   int wps;           // waves per sample (1 when a wave holds whole samples)
 
   __device__ Ctx(const Args<real>& a) : A(a) {}
@@ -700,6 +708,13 @@ struct Ctx {
     __builtin_amdgcn_s_setprio(1);  // memory phase: issue ahead of computing waves
     if (encode) {
       load_encoded(x);
+    } else if (src == nullptr) {
+      // |0...0>: amplitude 0 (tau = 0, u = 0) is 1
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        x.re[u] = (active && u == 0 && tau == 0) ? (real)1 : (real)0;
+        x.im[u] = 0;
+      }
     } else {
       const v2* s2 = reinterpret_cast<const v2*>(src);
       int64_t off[LR > 0 ? LR : 1];
@@ -1121,6 +1136,11 @@ __device__ __forceinline__ void setup(Ctx<real, LR, FLY, SHARED, HALF>& C,
   const int waves = blockDim.x >> 6;
   C.facc = C.gacc + (A.per_sample_params ? 0 : (size_t)waves * A.n_acc);
   C.fsh = C.facc + (adjoint ? (size_t)A.S * C.wps * A.n_feats : 0);
+  {
+    // 8-byte aligned, after the features
+    const uintptr_t e = reinterpret_cast<uintptr_t>(C.fsh + (adjoint ? (size_t)A.S * A.n_feats : 0));
+    C.lsq = reinterpret_cast<double*>((e + 7) & ~(uintptr_t)7);
+  }
 
   // Shared angles, by gate.
   for (int g = tid; g < A.n_gates; g += blockDim.x) {
@@ -1217,6 +1237,63 @@ __device__ __forceinline__ bool map_changed(const Args<real>& A, int s) {
   return ch;
 }
 
+// <Z_q> of every qubit in FP64 from the final register state x (arranged by
+// the last segment's layout, `last` = its qubit of each physical bit): each
+// wave's sums go to the sample's staging region, red[w * n + q], where every
+// thread of the sample can read them until the next staging pass; the
+// sample's totals go to expz when it is given.
+template <typename real, int LR, bool FLY, bool SHARED, bool HALF>
+__device__ __forceinline__ void readout(const Ctx<real, LR, FLY, SHARED, HALF>& C,
+                                        const Args<real>& A, const St<real, (1 << LR)>& x,
+                                        const QS_K uint8_t* last) {
+  constexpr int R = 1 << LR;
+  // <Z_q> partials in FP64, reduced over the sample's threads.
+  const int Tw = (1 << A.t) < 64 ? (1 << A.t) : 64;
+  const int nw = (1 << A.t) / Tw;  // waves per sample
+  double* red = reinterpret_cast<double*>(C.ldr);
+  sample_sync(A.t);
+  // tot = sum_k |x_k|^2 and hi[j] = the part with register bit j set, so a
+  // register-bit qubit reads tot - 2 hi[j] and a thread-bit one +-tot.
+  double tot = 0;
+  double hi[LR > 0 ? LR : 1];
+#pragma unroll
+  for (int j = 0; j < LR; ++j) hi[j] = 0;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const double pk = (double)x.re[k] * x.re[k] + (double)x.im[k] * x.im[k];
+    tot += pk;
+#pragma unroll
+    for (int j = 0; j < LR; ++j)
+      if (k & (1 << j)) hi[j] += pk;
+  }
+  const int wave_in_sample = C.tau / Tw;
+  for (int q = 0; q < A.n; ++q) {
+    int p = 0;
+    for (int i = 0; i < A.n; ++i)
+      if (last[i] == q) p = i;
+    p = uni(p);
+    double z;
+    if (p < LR) {
+      double h = hi[0];
+#pragma unroll
+      for (int j = 1; j < LR; ++j)
+        if (p == j) h = hi[j];
+      z = tot - 2 * h;
+    } else {
+      z = C.tbit(p) ? -tot : tot;
+    }
+    z = group_sum(z, Tw);
+    if ((C.tau & (Tw - 1)) == 0) red[(size_t)wave_in_sample * A.n + q] = z;
+  }
+  sample_sync(A.t);
+  if (C.active && A.expz != nullptr)
+    for (int q = C.tau; q < A.n; q += (1 << A.t)) {
+      double z = 0;
+      for (int w = 0; w < nw; ++w) z += red[(size_t)w * A.n + q];
+      A.expz[(size_t)C.b * A.n + q] = z;
+    }
+}
+
 // ------------------------------------------------------------------ forward
 template <typename real, int LR, bool FLY = false, bool SHARED = false, bool HALF = false>
 __device__ __forceinline__ void forward_body(const Args<real>& A, unsigned char* smem,
@@ -1245,58 +1322,12 @@ __device__ __forceinline__ void forward_body(const Args<real>& A, unsigned char*
   const QS_K uint8_t* last = seg_map<real, LR>(A, nseg - 1);
   C.store_state(x, A.state, wlay(A, nseg - 1));
 
-  if (A.expz != nullptr) {
-    // <Z_q> partials in FP64, reduced over the sample's threads.
-    const int Tw = (1 << A.t) < 64 ? (1 << A.t) : 64;
-    const int nw = (1 << A.t) / Tw;  // waves per sample
-    double* red = reinterpret_cast<double*>(C.ldr);
-    sample_sync(A.t);
-    // tot = sum_k |x_k|^2 and hi[j] = the part with register bit j set, so a
-    // register-bit qubit reads tot - 2 hi[j] and a thread-bit one +-tot.
-    double tot = 0;
-    double hi[LR > 0 ? LR : 1];
-#pragma unroll
-    for (int j = 0; j < LR; ++j) hi[j] = 0;
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-      const double pk = (double)x.re[k] * x.re[k] + (double)x.im[k] * x.im[k];
-      tot += pk;
-#pragma unroll
-      for (int j = 0; j < LR; ++j)
-        if (k & (1 << j)) hi[j] += pk;
-    }
-    const int wave_in_sample = C.tau / Tw;
-    for (int q = 0; q < A.n; ++q) {
-      int p = 0;
-      for (int i = 0; i < A.n; ++i)
-        if (last[i] == q) p = i;
-      p = uni(p);
-      double z;
-      if (p < LR) {
-        double h = hi[0];
-#pragma unroll
-        for (int j = 1; j < LR; ++j)
-          if (p == j) h = hi[j];
-        z = tot - 2 * h;
-      } else {
-        z = C.tbit(p) ? -tot : tot;
-      }
-      z = group_sum(z, Tw);
-      if ((C.tau & (Tw - 1)) == 0) red[(size_t)wave_in_sample * A.n + q] = z;
-    }
-    sample_sync(A.t);
-    if (C.active)
-      for (int q = C.tau; q < A.n; q += (1 << A.t)) {
-        double z = 0;
-        for (int w = 0; w < nw; ++w) z += red[(size_t)w * A.n + q];
-        A.expz[(size_t)C.b * A.n + q] = z;
-      }
-  }
+  if (A.expz != nullptr) readout(C, A, x, last);
 }
 
 // ------------------------------------------------------------------ adjoint
 template <typename real, int LR, bool FLY = false, bool SHARED = false, bool HALF = false,
-          bool RYRZ = false>
+          bool RYRZ = false, bool TRAIN = false>
 __device__ __forceinline__ void adjoint_body(const Args<real>& A, unsigned char* smem,
                                              int64_t blk) {
   constexpr int R = 1 << LR;
@@ -1306,8 +1337,29 @@ __device__ __forceinline__ void adjoint_body(const Args<real>& A, unsigned char*
   const QS_K uint8_t* last = seg_map<real, LR>(A, nseg - 1);
 
   St<real, R> psi, lam;
-  C.load_state(psi, A.state, wlay(A, nseg - 1));
-  if (A.dstate != nullptr) {
+  double g_loss = 0;  // training step: dL/d<Z_q> of this sample, q = A.loss_q
+  if constexpr (TRAIN) {
+    // The forward sweep, its readout and the loss without leaving registers:
+    // psi ends in the layout the adjoint starts from.
+    C.load_state(psi, A.state, rlay(A, 0), !HALF && A.x_in != nullptr);
+    const QS_K int32_t* fseg = kc(A.seg_begin);
+    for (int s = 0; s < nseg; ++s) {
+      if (s > 0 && map_changed(A, s)) C.remap(psi, wlay(A, s - 1), rlay(A, s));
+      const int e = fseg[s + 1];
+      for (int o = fseg[s]; o < e; ++o) C.apply_l1q(psi, o);
+    }
+    readout(C, A, psi, last);
+    const int Tw = (1 << A.t) < 64 ? (1 << A.t) : 64;
+    const double* red = reinterpret_cast<const double*>(C.ldr);
+    double z = 0;
+    for (int w = 0; w < (1 << A.t) / Tw; ++w) z += red[(size_t)w * A.n + A.loss_q];
+    const double r = C.active ? z - A.y[C.b] : 0.0;
+    g_loss = 2.0 * r / (double)A.B;
+    if (C.tau == 0) C.lsq[C.sl] = r * r;
+  } else {
+    C.load_state(psi, A.state, wlay(A, nseg - 1));
+  }
+  if (!TRAIN && A.dstate != nullptr) {
     C.load_state(lam, A.dstate, wlay(A, nseg - 1));
   } else {
     // lam = sum_q g_q Z_q psi: coefficient of amplitude with logical index L
@@ -1317,14 +1369,20 @@ __device__ __forceinline__ void adjoint_body(const Args<real>& A, unsigned char*
 #pragma unroll
     for (int j = 0; j < LR; ++j) w[j] = 0;
     if (C.active) {
-      const double* g = A.dexpz + (size_t)C.b * A.n;
+      const double* g = TRAIN ? nullptr : A.dexpz + (size_t)C.b * A.n;
+      auto gq_of = [&](int q) -> double {
+        if constexpr (TRAIN)
+          return q == A.loss_q ? g_loss : 0.0;
+        else
+          return g[q];
+      };
       for (int p = 0; p < A.n; ++p) {
-        const double gq = g[last[p]];
+        const double gq = gq_of(last[p]);
         base += gq;
         if (p >= LR && C.tbit(p)) base -= 2 * gq;
       }
 #pragma unroll
-      for (int j = 0; j < LR; ++j) w[j] = 2 * g[last[j]];
+      for (int j = 0; j < LR; ++j) w[j] = 2 * gq_of(last[j]);
     }
 #pragma unroll
     for (int k = 0; k < R; ++k) {
@@ -1378,6 +1436,14 @@ __device__ __forceinline__ void adjoint_body(const Args<real>& A, unsigned char*
       else
         *dst = t;
     }
+  if constexpr (TRAIN) {
+    // the workgroup's squared residuals, summed in sample order
+    if (threadIdx.x == 0) {
+      double t = 0;
+      for (int sl = 0; sl < A.S && blk + sl < A.B; ++sl) t += C.lsq[sl];
+      A.loss_part[blockIdx.x] = t;
+    }
+  }
 }
 
 template <typename real, int LR, int MAXT, bool SHARED, bool HALF>
@@ -1390,6 +1456,14 @@ template <typename real, int LR, int MAXT, bool SHARED, bool HALF, bool RYRZ = f
 __global__ void __launch_bounds__(MAXT) sv_adjoint(Args<real> A) {
   extern __shared__ __align__(16) unsigned char smem[];
   adjoint_body<real, LR, false, SHARED, HALF, RYRZ>(A, smem, (int64_t)blockIdx.x * A.S);
+}
+
+// A training step in one launch: forward sweep (from the amplitude encoding
+// of x, or from |0...0>), readout, MSE loss on one qubit, adjoint.
+template <typename real, int LR, int MAXT, bool SHARED, bool HALF, bool RYRZ = false>
+__global__ void __launch_bounds__(MAXT) sv_train(Args<real> A) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  adjoint_body<real, LR, false, SHARED, HALF, RYRZ, true>(A, smem, (int64_t)blockIdx.x * A.S);
 }
 
 // Uneven batches in one persistent launch: workgroups pull work items (a
@@ -1464,6 +1538,9 @@ sv_program(const ProgClass* classes, const ProgItem* items, int n_items,
     A.x_stride = 0;
     A.x_D = 0;
     A.bad_rows = nullptr;
+    A.y = nullptr;
+    A.loss_q = 0;
+    A.loss_part = nullptr;
     // Complex64 classes whose per-circuit angle table fits the LDS budget
     // next to the staging take the table path (sines and cosines once per
     // gate and circuit, in the prologue); the others compute angles where
@@ -1552,11 +1629,14 @@ Args<real> make_args(const SvLaunch& L) {
   A.x_stride = L.x_stride;
   A.x_D = L.x_D;
   A.bad_rows = L.bad_rows;
+  A.y = L.y;
+  A.loss_q = L.loss_q;
+  A.loss_part = L.loss_part;
   return A;
 }
 
 template <typename real, int LR, int MAXT, bool ADJ, bool SHARED = false, bool HALF = false,
-          bool RYRZ = false>
+          bool RYRZ = false, bool TRAIN = false>
 int launch_one(const SvLaunch& L) {
   Args<real> A = make_args<real>(L);
   const int64_t grid = (A.B + A.S - 1) / A.S;
@@ -1565,7 +1645,9 @@ int launch_one(const SvLaunch& L) {
   hipStream_t st = static_cast<hipStream_t>(L.stream);
   // Only the kernel of this direction is instantiated.
   auto kern = [] {
-    if constexpr (ADJ)
+    if constexpr (TRAIN)
+      return sv_train<real, LR, MAXT, SHARED, HALF, RYRZ>;
+    else if constexpr (ADJ)
       return sv_adjoint<real, LR, MAXT, SHARED, HALF, RYRZ>;
     else
       return sv_forward<real, LR, MAXT, SHARED, HALF>;

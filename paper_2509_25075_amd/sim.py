@@ -213,10 +213,16 @@ class DeviceWorkload:
     u: torch.Tensor | None = None     # [B] float64 trajectory uniforms
     loss_buf: torch.Tensor | None = None  # [1] float64 loss of the last step
     dfid: torch.Tensor | None = None  # [B] float64 dL/dF_b = -1/B (fidelity losses)
+    train_ws: torch.Tensor | None = None  # workspace of the one-launch training step
+    # Run MSE steps as one launch (qs_train_step_mse) where the library has
+    # that kernel. Off by default: on the 10-qubit batch the single launch
+    # measured 2 % slower than the forward, loss and adjoint launches it
+    # replaces; it is there for callers that cannot hold a [B][2^n] state.
+    one_launch: bool = False
 
 
 def to_device(w, flags: int = 0, device="cuda", ckpt_every_layers: int = 0,
-              traj_u=None) -> DeviceWorkload:
+              traj_u=None, one_launch: bool = False) -> DeviceWorkload:
     """``traj_u``: [B] uniforms in [0, 1) that draw the measurement outcome of
     each sample's reset-channel trajectory (loss "fidelity_trajectory")."""
     if w.loss == "fidelity_trajectory" and traj_u is None:
@@ -255,7 +261,16 @@ def to_device(w, flags: int = 0, device="cuda", ckpt_every_layers: int = 0,
         ws_dec=sim_dec.workspace(B, device, flags) if sim_dec else None,
         flags=flags, ckpt_gates=ckpt_gates, ckpt=ckpt, dz=dz,
         u=t(traj_u, torch.float64) if w.loss == "fidelity_trajectory" else None,
-        loss_buf=torch.zeros(1, dtype=torch.float64, device=device), dfid=dfid)
+        loss_buf=torch.zeros(1, dtype=torch.float64, device=device), dfid=dfid,
+        one_launch=one_launch)
+
+
+def train_step_runs(d: DeviceWorkload) -> bool:
+    """Whether step() runs the workload's training step as one launch
+    (qs_train_step_mse): asked for (one_launch), the MSE loss, no
+    checkpoints, and a shape the library has that kernel for."""
+    return (d.one_launch and d.w.loss == "mse_z0" and not d.ckpt_gates and
+            N.qs_train_workspace_size(d.sim.h, d.sim.qs_dtype, d.w.batch, d.flags) > 0)
 
 
 def step(d: DeviceWorkload, backward: bool = True) -> dict:
@@ -265,11 +280,10 @@ def step(d: DeviceWorkload, backward: bool = True) -> dict:
     B = w.batch
     # Amplitude inputs are encoded by the forward call itself.
     x = d.x if w.encoding == "amplitude" else None
-    if x is None:
-        sim.zero_state(B, d.state.device, out=d.state)
     out = {}
     if w.loss in ("fidelity_reset", "fidelity_postselect", "fidelity_trajectory"):
         if x is None:
+            sim.zero_state(B, d.state.device, out=d.state)
             sim.zero_state(B, d.state.device, out=d.state_dec)
         sim.forward(d.params, d.feats, d.state, want_expz=False, x=x)
         d.sim_dec.forward(d.params_dec, d.feats, d.state_dec, want_expz=False, x=x)
@@ -297,6 +311,27 @@ def step(d: DeviceWorkload, backward: bool = True) -> dict:
             out["grad_params_dec"], _ = d.sim_dec.adjoint(
                 d.params_dec, d.feats, d.state_dec, dstate=lam_chi, ws=d.ws_dec)
         return out
+    if backward and train_step_runs(d):
+        # The whole step in one engine launch where the library has that
+        # kernel for the tuned shape (qs_train_step_mse), else three calls.
+        need = N.qs_train_workspace_size(sim.h, sim.qs_dtype, B, d.flags)
+        if need > 0:
+            if d.train_ws is None or d.train_ws.numel() < need:
+                d.train_ws = torch.empty(need, dtype=torch.uint8, device=d.state.device)
+            dev = d.state.device
+            z = torch.empty((B, sim.n), dtype=torch.float64, device=dev)
+            gp = torch.empty(sim.h.n_params, dtype=torch.float64, device=dev)
+            gf = (torch.empty((B, sim.h.n_features), dtype=torch.float64, device=dev)
+                  if sim.h.n_features else None)
+            N.qs_train_step_mse(sim.h, sim.qs_dtype, d.params, d.feats, x, d.labels, 0,
+                                d.loss_buf, gp, d.train_ws, expz=z, grad_feats=gf, B=B,
+                                flags=d.flags)
+            out.update(expz=z, loss=d.loss_buf[0], grad_params=gp)
+            if gf is not None:
+                out["grad_feats"] = gf
+            return out
+    if x is None:
+        sim.zero_state(B, d.state.device, out=d.state)
     z = sim.forward(d.params, d.feats, d.state, want_expz=True,
                     ckpt_gates=d.ckpt_gates, ckpt=d.ckpt, x=x)
     out["expz"] = z

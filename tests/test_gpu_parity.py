@@ -632,6 +632,120 @@ def test_forward_amplitude_with_checkpoints_matches_encode_then_forward():
         np.testing.assert_allclose(a.cpu().numpy(), b.cpu().numpy(), atol=2e-6)
 
 
+def _train_case(c, B, seed, q, amplitude, dtype="c64"):
+    """qs_train_step_mse against the oracle and against the three calls it
+    fuses (forward from the encoding, loss kernel, adjoint)."""
+    rng = np.random.default_rng(seed)
+    n = c.n_qubits
+    s = sim.Simulator(c, dtype)
+    need = N.qs_train_workspace_size(s.h, s.qs_dtype, B)
+    assert need > 0, "the one-launch training step should run for this shape"
+    params = rng.uniform(-np.pi, np.pi, c.n_params).astype(np.float32)
+    feats = rng.uniform(-1, 1, (B, c.n_features)).astype(np.float32) if c.n_features else None
+    y = rng.choice([-1.0, 1.0], B)
+    pt, ft, yt = _dev(params, torch.float32), _dev(feats, torch.float32), _dev(y, torch.float64)
+    if amplitude:
+        D = max(1, (1 << n) - (1 << n) // 4)
+        x = rng.standard_normal((B, D)).astype(np.float32)
+        xt = _dev(x, torch.float32)
+        psi0 = O.encode_amplitude(x.astype(np.float64), n)
+    else:
+        xt = None
+        psi0 = O.encode_zero(B, n)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    z = torch.empty((B, n), dtype=torch.float64, device="cuda")
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    gp = torch.empty(c.n_params, dtype=torch.float64, device="cuda")
+    gf = torch.empty((B, c.n_features), dtype=torch.float64, device="cuda") if c.n_features else None
+    N.qs_train_step_mse(s.h, s.qs_dtype, pt, ft, xt, yt, q, loss, gp, ws, expz=z,
+                        grad_feats=gf, B=B)
+    torch.cuda.synchronize()
+    pc = params.astype(np.float64)
+    fc = None if feats is None else feats.astype(np.float64)
+    zo = O.expz(O.run_circuit(c, pc, fc, psi0))
+    r = zo[:, q] - y
+    dz = np.zeros((B, n))
+    dz[:, q] = 2.0 * r / B
+    gth, _ = O.adjoint_vjp(c, pc, fc, psi0, dexpz=dz)
+    rp, rf = O.theta_to_param_grads(c, pc, fc, gth)
+    tol = TOL[dtype]
+    np.testing.assert_allclose(z.cpu().numpy(), zo, atol=tol["z"])
+    assert abs(float(loss.item()) - float(np.mean(r * r))) < 4 * tol["z"]
+    np.testing.assert_allclose(gp.cpu().numpy(), rp, atol=tol["grad"])
+    if gf is not None:
+        np.testing.assert_allclose(gf.cpu().numpy(), rf, atol=tol["grad"])
+    # the three separate calls give the same numbers up to rounding order
+    st = s.empty_state(B)
+    if xt is None:
+        s.zero_state(B, out=st)
+    z2 = s.forward(pt, ft, st, x=xt)
+    dz2 = torch.empty_like(z2)
+    loss2 = torch.empty(1, dtype=torch.float64, device="cuda")
+    N.qs_loss_mse_z(q, z2, yt, dexpz=dz2, loss=loss2)
+    gp2, gf2 = s.adjoint(pt, ft, st, dexpz=dz2)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(z.cpu().numpy(), z2.cpu().numpy(), atol=1e-6)
+    assert abs(float(loss.item()) - float(loss2.item())) < 1e-6
+    np.testing.assert_allclose(gp.cpu().numpy(), gp2.cpu().numpy(), atol=2e-5)
+
+
+@pytest.mark.parametrize("n,B,q,amp", [(10, 37, 0, True), (4, 300, 3, True), (6, 65, 2, False),
+                                       (9, 21, 8, True), (12, 5, 5, True), (13, 3, 0, False)])
+def test_train_step_random_circuits(n, B, q, amp):
+    rng = np.random.default_rng(2000 + n)
+    c = C.random_circuit(n, 70, rng, n_params=6, n_features=2)
+    _announce(f"train step n={n} B={B} q={q} amplitude={amp}")
+    _train_case(c, B, 2100 + n, q, amp)
+
+
+@pytest.mark.parametrize("key,B", [("c2", 37), ("c2", 4096)])
+def test_train_step_workloads(key, B):
+    """The headline circuit's step (10 qubits, amplitude inputs, MSE on
+    qubit 0), through sim.step's one-launch path, against the oracle on
+    sampled rows."""
+    w = Dt.make_workload(key, B)
+    _announce(f"train step workload {key} B={B}")
+    d = sim.to_device(w, one_launch=True)
+    assert sim.train_step_runs(d)
+    out = sim.step(d)
+    torch.cuda.synchronize()
+    rows = np.arange(B) if B <= 64 else np.random.default_rng(5).choice(B, 48, replace=False)
+    idx, feats, psi0 = _oracle_workload(w, rows)
+    z = O.expz(O.run_circuit(w.circuit, w.params, feats, psi0))
+    np.testing.assert_allclose(out["expz"].cpu().numpy()[idx], z, atol=1e-5)
+    if B <= 64:
+        L, dz = O.loss_and_dexpz(w.loss, z, w.labels, w.weights)
+        assert abs(float(out["loss"]) - L) < 4e-5
+        gth, _ = O.adjoint_vjp(w.circuit, w.params, feats, psi0, dexpz=dz)
+        gp, _ = O.theta_to_param_grads(w.circuit, w.params, feats, gth)
+        np.testing.assert_allclose(out["grad_params"].cpu().numpy(), gp, atol=1e-4)
+
+
+def test_train_step_refuses_what_it_does_not_run(monkeypatch):
+    """Per-sample parameters, complex128, float64 inputs and shapes staging
+    one component at a time have no one-launch kernel: workspace size 0 and
+    QS_ERR_UNSUPPORTED, nothing launched."""
+    c = C.hea_ry_rz_ring(6, 2)
+    h = N.CircuitHandle(c)
+    assert N.qs_train_workspace_size(h, N.QS_C64, 8) > 0
+    assert N.qs_train_workspace_size(h, N.QS_C128, 8) == 0
+    assert N.qs_train_workspace_size(h, N.QS_C64, 8, N.QS_FLAG_PER_SAMPLE_PARAMS) == 0
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    p = torch.zeros(c.n_params, device="cuda")
+    y = torch.zeros(8, dtype=torch.float64, device="cuda")
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    gp = torch.empty(c.n_params, dtype=torch.float64, device="cuda")
+    x64 = torch.ones((8, 64), dtype=torch.float64, device="cuda")
+    with pytest.raises(N.QsError) as e:
+        N.qs_train_step_mse(h, N.QS_C64, p, None, x64, y, 0, loss, gp, ws)
+    assert e.value.status == N.QS_ERR_UNSUPPORTED
+    with pytest.raises(N.QsError) as e:
+        N.qs_train_step_mse(h, N.QS_C128, p.double(), None, None, y, 0, loss, gp, ws, B=8)
+    assert e.value.status == N.QS_ERR_UNSUPPORTED
+    monkeypatch.setenv("QS_ADJ_HALF_STAGING", "1")  # the adjoint's shape stages one component
+    assert N.qs_train_workspace_size(h, N.QS_C64, 8) == 0
+
+
 @pytest.mark.parametrize("B,n,q", [(1, 1, 0), (37, 10, 0), (4096, 10, 0), (777, 8, 7),
                                    (65536, 8, 0), (0, 3, 1)])
 def test_loss_mse_z(B, n, q):

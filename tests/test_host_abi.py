@@ -94,6 +94,35 @@ def test_forward_amplitude_and_loss_validate_before_touching_the_gpu():
     assert L.qs_loss_mse_z(3, 4, 0, x, x, None, None, None) == N.QS_OK        # no outputs
 
 
+def test_train_step_validates_before_touching_the_gpu():
+    """The one-launch training step rejects bad arguments and shapes it has
+    no kernel for before any device work; its workspace query is host-only."""
+    L = N.lib()
+    c = C.hea_ry_rz_ring(3, 1)
+    h = N.CircuitHandle(c)
+    p = ctypes.c_void_p(16)  # never dereferenced: every call below returns first
+
+    def call(B=4, q=0, dtype=N.QS_C64, x=None, f64=0, y=p, loss=p, flags=0):
+        return L.qs_train_step_mse(h.ptr, dtype, B, p, None, x, f64, 8, 8, None, y, q, None,
+                                   loss, p, None, p, 1 << 20, flags, None)
+    assert call(q=3) == N.QS_ERR_INVALID          # q >= n
+    assert call(q=-1) == N.QS_ERR_INVALID
+    assert call(B=-1) == N.QS_ERR_INVALID
+    assert call(y=None) == N.QS_ERR_INVALID
+    assert call(loss=None) == N.QS_ERR_INVALID
+    assert call(B=0, y=None, loss=None) == N.QS_OK  # nothing to do
+    assert call(x=p, f64=1) == N.QS_ERR_UNSUPPORTED  # complex64 reads float32 inputs
+    assert call(dtype=N.QS_C128) == N.QS_ERR_UNSUPPORTED
+    assert call(flags=N.QS_FLAG_PER_SAMPLE_PARAMS) == N.QS_ERR_UNSUPPORTED
+    # workspace query: > 0 where the kernel runs, 0 otherwise
+    w2 = Dt.make_workload("c2", 4096)
+    h2 = N.CircuitHandle(w2.circuit)
+    assert N.qs_train_workspace_size(h2, N.QS_C64, 4096) > 0
+    assert N.qs_train_workspace_size(h2, N.QS_C128, 4096) == 0
+    assert N.qs_train_workspace_size(h2, N.QS_C64, 4096, N.QS_FLAG_PER_SAMPLE_PARAMS) == 0
+    assert N.qs_train_workspace_size(h2, N.QS_C64, 0) == 0
+
+
 def test_status_strings():
     for s in [0, -1, -2, -3, -4, -5, -6, -7, -8, 7]:
         assert isinstance(N.status_string(s), str) and N.status_string(s)
