@@ -568,6 +568,12 @@ struct Ctx {
   int wps;           // waves per sample (1 when a wave holds whole samples)
 
   __device__ Ctx(const Args<real>& a) : A(a) {}
+  // The same context over another reference to the launch's arguments.
+  __device__ Ctx(const Args<real>& a, const Ctx& o)
+      : A(a), tau(o.tau), sl(o.sl), b(o.b), row(o.row), base(o.base), dep_tau(o.dep_tau),
+        active(o.active), ldr(o.ldr), lds(o.lds), salt(o.salt), ang_sh(o.ang_sh),
+        ang_ps(o.ang_ps), fu_sh(o.fu_sh), gen_sh(o.gen_sh), gacc(o.gacc), facc(o.facc),
+        fsh(o.fsh), lsq(o.lsq), wps(o.wps) {}
 
   __device__ __forceinline__ bool tbit(int p) const {
     return (tau >> (p - LR)) & 1;
@@ -1325,9 +1331,69 @@ __device__ __forceinline__ void forward_body(const Args<real>& A, unsigned char*
   if (A.expz != nullptr) readout(C, A, x, last);
 }
 
+// The adjoint's reverse sweep from (psi, lam) at the circuit's end, and the
+// flush of its gradient sums.
+template <typename real, int LR, bool FLY, bool SHARED, bool HALF, bool RYRZ, bool TRAIN>
+__device__ __forceinline__ void adjoint_sweep(const Args<real>& A,
+                                              Ctx<real, LR, FLY, SHARED, HALF>& C,
+                                              St<real, (1 << LR)>& psi, St<real, (1 << LR)>& lam,
+                                              int64_t blk) {
+  const int nseg = A.nseg;
+  const int Tw = (1 << A.t) < 64 ? (1 << A.t) : 64;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const QS_K int32_t* seg_begin = kc(A.seg_begin);
+  for (int s = nseg - 1; s >= 0; --s) {
+    const int ck = kc(A.seg_ckpt)[s];
+    if (ck >= 0 && A.ckpt != nullptr)  // re-anchor psi to the stored state
+      C.load_state(psi, A.ckpt + (size_t)ck * A.B * (2ull << A.n), wlay(A, s));
+    const int beg = seg_begin[s];
+    for (int o = seg_begin[s + 1] - 1; o >= beg; --o)
+      C.template adjoint_l1q<RYRZ>(psi, lam, o, lane, wave, Tw);
+    if (s > 0 && map_changed(A, s)) {
+      C.remap(psi, rlay(A, s), wlay(A, s - 1));
+      C.remap(lam, rlay(A, s), wlay(A, s - 1));
+    }
+  }
+  if (A.out_psi != nullptr) C.store_state(psi, A.out_psi, rlay(A, 0));
+  if (A.out_lam != nullptr) C.store_state(lam, A.out_lam, rlay(A, 0));
+  __syncthreads();
+  const int waves = blockDim.x >> 6;
+  if (!A.per_sample_params)
+    for (int i = threadIdx.x; i < A.n_acc; i += blockDim.x) {
+      real t = 0;
+      for (int w = 0; w < waves; ++w) t += C.gacc[(size_t)w * A.n_acc + i];
+      A.ws_partials[(size_t)blockIdx.x * A.n_acc + i] = t;
+    }
+  if (A.grad_feats != nullptr)
+    for (int i = threadIdx.x; i < A.S * A.n_feats; i += blockDim.x) {
+      const int sl = i / A.n_feats, f = i % A.n_feats;
+      const int64_t bb = blk + sl;
+      if (bb >= A.B) continue;
+      real t = 0;
+      for (int w = 0; w < C.wps; ++w) t += C.facc[((size_t)sl * C.wps + w) * A.n_feats + f];
+      double* dst = &A.grad_feats[(size_t)(bb >> A.ob) * A.n_feats + f];
+      if (A.tile_q != nullptr)
+        atomicAdd(dst, (double)t);  // several tiles share a batch row
+      else if (A.accum_feats)
+        *dst += t;  // one writer per entry; earlier segments' sums are in place
+      else
+        *dst = t;
+    }
+  if constexpr (TRAIN) {
+    // the workgroup's squared residuals, summed in sample order
+    if (threadIdx.x == 0) {
+      double t = 0;
+      for (int sl = 0; sl < A.S && blk + sl < A.B; ++sl) t += C.lsq[sl];
+      A.loss_part[blockIdx.x] = t;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ adjoint
 template <typename real, int LR, bool FLY = false, bool SHARED = false, bool HALF = false,
-          bool RYRZ = false, bool TRAIN = false>
+          bool RYRZ = false, bool TRAIN = false,
+          bool KERNARG = false>
 __device__ __forceinline__ void adjoint_body(const Args<real>& A, unsigned char* smem,
                                              int64_t blk) {
   constexpr int R = 1 << LR;
@@ -1395,54 +1461,21 @@ __device__ __forceinline__ void adjoint_body(const Args<real>& A, unsigned char*
     }
   }
 
-  const int Tw = (1 << A.t) < 64 ? (1 << A.t) : 64;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const QS_K int32_t* seg_begin = kc(A.seg_begin);
-  for (int s = nseg - 1; s >= 0; --s) {
-    const int ck = kc(A.seg_ckpt)[s];
-    if (ck >= 0 && A.ckpt != nullptr)  // re-anchor psi to the stored state
-      C.load_state(psi, A.ckpt + (size_t)ck * A.B * (2ull << A.n), wlay(A, s));
-    const int beg = seg_begin[s];
-    for (int o = seg_begin[s + 1] - 1; o >= beg; --o)
-      C.template adjoint_l1q<RYRZ>(psi, lam, o, lane, wave, Tw);
-    if (s > 0 && map_changed(A, s)) {
-      C.remap(psi, rlay(A, s), wlay(A, s - 1));
-      C.remap(lam, rlay(A, s), wlay(A, s - 1));
-    }
-  }
-  if (A.out_psi != nullptr) C.store_state(psi, A.out_psi, rlay(A, 0));
-  if (A.out_lam != nullptr) C.store_state(lam, A.out_lam, rlay(A, 0));
-  __syncthreads();
-  const int waves = blockDim.x >> 6;
-  if (!A.per_sample_params)
-    for (int i = threadIdx.x; i < A.n_acc; i += blockDim.x) {
-      real t = 0;
-      for (int w = 0; w < waves; ++w) t += C.gacc[(size_t)w * A.n_acc + i];
-      A.ws_partials[(size_t)blockIdx.x * A.n_acc + i] = t;
-    }
-  if (A.grad_feats != nullptr)
-    for (int i = threadIdx.x; i < A.S * A.n_feats; i += blockDim.x) {
-      const int sl = i / A.n_feats, f = i % A.n_feats;
-      const int64_t bb = blk + sl;
-      if (bb >= A.B) continue;
-      real t = 0;
-      for (int w = 0; w < C.wps; ++w) t += C.facc[((size_t)sl * C.wps + w) * A.n_feats + f];
-      double* dst = &A.grad_feats[(size_t)(bb >> A.ob) * A.n_feats + f];
-      if (A.tile_q != nullptr)
-        atomicAdd(dst, (double)t);  // several tiles share a batch row
-      else if (A.accum_feats)
-        *dst += t;  // one writer per entry; earlier segments' sums are in place
-      else
-        *dst = t;
-    }
-  if constexpr (TRAIN) {
-    // the workgroup's squared residuals, summed in sample order
-    if (threadIdx.x == 0) {
-      double t = 0;
-      for (int sl = 0; sl < A.S && blk + sl < A.B; ++sl) t += C.lsq[sl];
-      A.loss_part[blockIdx.x] = t;
-    }
+  if constexpr (KERNARG) {
+    // The sweep reads the launch's arguments through an address the compiler
+    // cannot see through, so their loop invariants are loaded here rather
+    // than hoisted to the kernel's entry: the values of the training step's
+    // forward sweep then do not compete with them for scalar registers
+    // (without this the compiler spills scalars to vector lanes, 200 lane
+    // reads per op in the adjoint's loop). The plain adjoint does not take
+    // it: there it cut the spills too but ran 2-3 % slower.
+    const QS_K Args<real>* pa = (const QS_K Args<real>*)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(pa));
+    const Args<real>& A2 = *(const Args<real>*)(pa);
+    Ctx<real, LR, FLY, SHARED, HALF> C2(A2, C);
+    adjoint_sweep<real, LR, FLY, SHARED, HALF, RYRZ, TRAIN>(A2, C2, psi, lam, blk);
+  } else {
+    adjoint_sweep<real, LR, FLY, SHARED, HALF, RYRZ, TRAIN>(A, C, psi, lam, blk);
   }
 }
 
@@ -1463,7 +1496,8 @@ __global__ void __launch_bounds__(MAXT) sv_adjoint(Args<real> A) {
 template <typename real, int LR, int MAXT, bool SHARED, bool HALF, bool RYRZ = false>
 __global__ void __launch_bounds__(MAXT) sv_train(Args<real> A) {
   extern __shared__ __align__(16) unsigned char smem[];
-  adjoint_body<real, LR, false, SHARED, HALF, RYRZ, true>(A, smem, (int64_t)blockIdx.x * A.S);
+  adjoint_body<real, LR, false, SHARED, HALF, RYRZ, true, true>(A, smem,
+                                                               (int64_t)blockIdx.x * A.S);
 }
 
 // Uneven batches in one persistent launch: workgroups pull work items (a

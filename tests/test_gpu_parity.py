@@ -202,7 +202,9 @@ def _oracle_workload(w, rows=None):
 def test_workload_step_vs_oracle(key, B):
     w = Dt.make_workload(key, B)
     _announce(f"workload {key} B={B}")
-    d = sim.to_device(w)
+    # the separate forward, loss and adjoint launches (the one-launch step
+    # has tests of its own)
+    d = sim.to_device(w, one_launch=False)
     out = sim.step(d)
     torch.cuda.synchronize()
     idx, feats, psi0 = _oracle_workload(w)
@@ -701,11 +703,11 @@ def test_train_step_random_circuits(n, B, q, amp):
 @pytest.mark.parametrize("key,B", [("c2", 37), ("c2", 4096)])
 def test_train_step_workloads(key, B):
     """The headline circuit's step (10 qubits, amplitude inputs, MSE on
-    qubit 0), through sim.step's one-launch path, against the oracle on
-    sampled rows."""
+    qubit 0), through sim.step's default path (one launch), against the
+    oracle on sampled rows."""
     w = Dt.make_workload(key, B)
     _announce(f"train step workload {key} B={B}")
-    d = sim.to_device(w, one_launch=True)
+    d = sim.to_device(w)
     assert sim.train_step_runs(d)
     out = sim.step(d)
     torch.cuda.synchronize()
