@@ -376,6 +376,70 @@ void free_dev(SvDevPlan& d) {
   (void)hipFree(d.grad_cols);
 }
 
+// Salts of one-component staging. A lane's LDS slot for amplitude index L is
+// swz(L) ^ salt with swz(L) = L ^ (L >> 5 & 31) ^ (L >> 10 & 31), and its
+// bank the slot's low six bits (4-byte slots, 64 banks). Within one access
+// the lanes of a wave differ in their thread part (the XOR of the layout's
+// index masks of the thread bits set in tau) and their sample's salt, so
+// they hit 64 different banks exactly when the swizzled thread masks and the
+// salt vectors are linearly independent over GF(2) in those six bits. The
+// salt vectors are picked greedily to maximise that rank summed over every
+// layout the kernels stage under (each segment's read and write layouts and
+// the identity of the HBM transfers); ties keep the default vector.
+uint64_t half_salt_basis(const SvPlan& P) {
+  const int t = P.t;
+  if (t >= 6 || P.n > 16) return 0;
+  const uint32_t N = 1u << P.n;
+  auto swz6 = [](uint32_t L) { return (L ^ ((L >> 5) & 31u) ^ ((L >> 10) & 31u)) & 63u; };
+  std::vector<std::vector<uint32_t>> lays;
+  std::vector<uint32_t> id;
+  for (int i = 0; i < t; ++i) id.push_back(swz6(1u << i));
+  lays.push_back(id);
+  for (int s = 0; s < P.nseg(); ++s)
+    for (int h = 0; h < 2; ++h) {
+      std::vector<uint32_t> v;
+      for (int i = 0; i < t; ++i)
+        v.push_back(swz6(P.seg_lay[(size_t)s * kLayWords + h * kMapStride + P.r + i]));
+      lays.push_back(v);
+    }
+  auto rank = [](std::vector<uint32_t> v) {
+    int r = 0;
+    for (int bit = 5; bit >= 0; --bit) {
+      size_t k = r;
+      while (k < v.size() && !((v[k] >> bit) & 1)) ++k;
+      if (k == v.size()) continue;
+      std::swap(v[r], v[k]);
+      for (size_t j = 0; j < v.size(); ++j)
+        if (j != (size_t)r && ((v[j] >> bit) & 1)) v[j] ^= v[r];
+      ++r;
+    }
+    return r;
+  };
+  std::vector<uint32_t> basis;
+  uint64_t packed = 0;
+  for (int k = 0; k < 6 - t; ++k) {
+    const uint32_t dflt = (1u << (t + k)) & 63u & (N - 1);
+    uint32_t best = dflt;
+    long best_score = -1;
+    for (uint32_t c = 0; c < 64 && c < N; ++c) {
+      long sc = 0;
+      for (const auto& l : lays) {
+        std::vector<uint32_t> v = l;
+        v.insert(v.end(), basis.begin(), basis.end());
+        v.push_back(c);
+        sc += rank(v);
+      }
+      if (sc > best_score || (sc == best_score && c == dflt)) {
+        best_score = sc;
+        best = c;
+      }
+    }
+    basis.push_back(best);
+    packed |= (uint64_t)best << (6 * k);
+  }
+  return packed;
+}
+
 // Plans on the host and uploads once per (circuit, r, flags, device). The
 // upload is synchronous, so the first call for a circuit must not be inside
 // a stream capture; later calls only look the plan up.
@@ -417,6 +481,7 @@ Entry* get_plan(const qs_circuit& c, int r, bool ps, const int32_t* ck, int n_ck
   d.n_fu = P.n_fu;
   d.n_gen = P.n_gen;
   d.n_acc = (int)P.grad_cols.size();
+  d.salt_half = half_salt_basis(P);
   d.ryrz = d.n_blocks > 0;
   for (int b = 0; b < d.n_blocks && d.ryrz; ++b)
     d.ryrz = P.blk_begin[b + 1] - P.blk_begin[b] == 2 &&

@@ -209,6 +209,8 @@ struct SvDevPlan {
   int32_t* grad_cols;  // [n_acc] parameter of each gradient column
   int n_blocks, n_fu, n_acc, n_gen;
   int ryrz = 0;        // every block is RY then RZ (hardware-efficient layers)
+  // Salt vectors of one-component staging (packed six bits each), 0: none.
+  uint64_t salt_half = 0;
 };
 
 // Launch geometry of the engine for a plan.

@@ -128,6 +128,62 @@ __device__ __forceinline__ real group_sum(real v, int G) {
   return v;
 }
 
+// Reduce-scatter steps over paired rows: the swap moves the upper 32 lanes of
+// its first operand into the lower 32 of its second (and back), so lanes
+// 0-31 end with a's sum over the pair l, l ^ 32 and lanes 32-63 with b's;
+// the 16-lane form does the same with even rows taking a and odd rows b.
+__device__ __forceinline__ float swap32_sum(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b),
+                                                  false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap16_sum(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b),
+                                                  false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ double join64(unsigned lo, unsigned hi) {
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double swap32_sum(double a, double b) {
+  const unsigned long long ua = (unsigned long long)__double_as_longlong(a);
+  const unsigned long long ub = (unsigned long long)__double_as_longlong(b);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32),
+                                                   false, false);
+  return join64(lo[0], hi[0]) + join64(lo[1], hi[1]);
+}
+__device__ __forceinline__ double swap16_sum(double a, double b) {
+  const unsigned long long ua = (unsigned long long)__double_as_longlong(a);
+  const unsigned long long ub = (unsigned long long)__double_as_longlong(b);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32),
+                                                   false, false);
+  return join64(lo[0], hi[0]) + join64(lo[1], hi[1]);
+}
+
+// The wave sums of four per-lane values at once: each swap step halves the
+// values a lane carries while the paired lanes sum them, and the in-row
+// steps finish one value per row, so every lane of row k (lanes 16k to
+// 16k + 15) ends with the sum of v_k. Three swaps and four in-row steps,
+// against six steps for each value summed alone.
+template <typename real>
+__device__ __forceinline__ real rows_sum4(real v0, real v1, real v2, real v3) {
+  const real a = swap32_sum(v0, v2);  // lanes 0-31: v0, lanes 32-63: v2
+  const real b = swap32_sum(v1, v3);  // lanes 0-31: v1, lanes 32-63: v3
+  return group_sum(swap16_sum(a, b), 16);
+}
+
+// Lane `l`'s value (l uniform) on every lane.
+__device__ __forceinline__ float lane_value(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  return join64((unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l),
+                (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l));
+}
+
 // Plan data is read-only for the whole launch: reading it through the
 // constant address space lets uniform indices become scalar loads.
 #define QS_K __attribute__((address_space(4)))
@@ -485,6 +541,10 @@ struct Args {
   const double* y;
   int loss_q;
   double* loss_part;
+  // One-component staging: six-bit salt vectors of the samples of a wave
+  // (vector i for bit i of the sample's position in its wave), packed six
+  // bits each; 0: the default salts.
+  uint64_t salt_basis;
 };
 
 template <typename real>
@@ -566,6 +626,22 @@ struct Ctx {
   real* fsh;         // [S][n_feats] the block's features (adjoint)
   double* lsq;       // [S] squared residuals of the training step's loss
   int wps;           // waves per sample (1 when a wave holds whole samples)
+  // Complex64 adjoint, per-sample blocks with shared parameters and at most
+  // four features: the sample's features and this lane's running terms of
+  // their gradients, kept in registers (summed per sample once, at the end).
+  // (Named scalars, not arrays: an array indexed by a feature number ends up
+  // in scratch memory, and the whole context with it.)
+  real fx0 = 0, fx1 = 0, fx2 = 0, fx3 = 0;
+  real fg0 = 0, fg1 = 0, fg2 = 0, fg3 = 0;
+  __device__ __forceinline__ real fx_of(int k) const {
+    return k == 0 ? fx0 : k == 1 ? fx1 : k == 2 ? fx2 : fx3;
+  }
+  __device__ __forceinline__ void fg_add(int k, real d) {
+    if (k == 0) fg0 += d;
+    else if (k == 1) fg1 += d;
+    else if (k == 2) fg2 += d;
+    else fg3 += d;
+  }
 
   __device__ Ctx(const Args<real>& a) : A(a) {}
   // The same context over another reference to the launch's arguments.
@@ -573,7 +649,8 @@ struct Ctx {
       : A(a), tau(o.tau), sl(o.sl), b(o.b), row(o.row), base(o.base), dep_tau(o.dep_tau),
         active(o.active), ldr(o.ldr), lds(o.lds), salt(o.salt), ang_sh(o.ang_sh),
         ang_ps(o.ang_ps), fu_sh(o.fu_sh), gen_sh(o.gen_sh), gacc(o.gacc), facc(o.facc),
-        fsh(o.fsh), lsq(o.lsq), wps(o.wps) {}
+        fsh(o.fsh), lsq(o.lsq), wps(o.wps), fx0(o.fx0), fx1(o.fx1), fx2(o.fx2),
+        fx3(o.fx3), fg0(o.fg0), fg1(o.fg1), fg2(o.fg2), fg3(o.fg3) {}
 
   __device__ __forceinline__ bool tbit(int p) const {
     return (tau >> (p - LR)) & 1;
@@ -930,6 +1007,113 @@ struct Ctx {
       y.im[k] = flip_sign(y.im[k], bit);
     }
   }
+  // Shared parameters: gradient terms gathered per block and summed over the
+  // wave together. Slot k holds a per-lane term and up to two LDS columns
+  // (the weight's and the bias's when they take the same term) that receive
+  // its wave sum.
+  struct Terms {
+    real v[4] = {0, 0, 0, 0};
+    int cw[4] = {-1, -1, -1, -1}, cb[4] = {-1, -1, -1, -1};
+  };
+  // The per-lane terms of rotation `gt` into slots K (weight, and bias when
+  // it has no feature) and, with a feature, K + 1 (bias); its feature
+  // gradient, which is per sample, is summed here.
+  template <int K>
+  __device__ __forceinline__ void shared_terms(Terms& t, const BGate& gt, real part, int Tw) {
+    if (bg_kind(gt) > QS_OP_RZ) return;
+    const real scale = (real)gt.scale;
+    if (gt.feat < 0) {
+      t.v[K] = scale * part;
+      t.cw[K] = gt.col_w;
+      t.cb[K] = gt.col_b;
+      return;
+    }
+    if constexpr (K + 1 < 4) {
+      t.v[K + 1] = active ? scale * part : (real)0;
+      t.cw[K + 1] = gt.col_b;
+      t.cw[K] = gt.col_w;
+      const real w = gt.p_w >= 0 ? kc(A.params)[gt.p_w] : (real)1;
+      if constexpr (feat_regs) {
+        if (A.n_feats <= 4) {
+          t.v[K] = t.v[K + 1] * fx_of(gt.feat);
+          fg_add(gt.feat, scale * w * part);
+          return;
+        }
+      }
+      const real f = active ? fsh[(size_t)sl * A.n_feats + gt.feat] : (real)0;
+      t.v[K] = t.v[K + 1] * f;
+      const real gth = group_sum(part, Tw);
+      if ((tau & (Tw - 1)) == 0 && active)
+        atomicAdd(&facc[((size_t)sl * wps + (tau >> 6)) * A.n_feats + gt.feat],
+                  gth * scale * w);
+    }
+  }
+  static constexpr bool feat_regs = sizeof(real) == 4 && !SHARED;
+  // The register terms of the feature gradients, summed per sample into the
+  // LDS sums by each sample's (wave's) leader lane.
+  __device__ __forceinline__ void fold_feature_terms(int Tw) {
+    if constexpr (feat_regs) {
+      if (A.per_sample_params || A.n_feats == 0 || A.n_feats > 4) return;
+      const bool leader = (tau & (Tw - 1)) == 0 && active;
+      real* fa = facc + ((size_t)sl * wps + (tau >> 6)) * A.n_feats;
+      const real g0 = group_sum(fg0, Tw);
+      if (leader) fa[0] += g0;
+      if (A.n_feats > 1) {
+        const real g1 = group_sum(fg1, Tw);
+        if (leader) fa[1] += g1;
+      }
+      if (A.n_feats > 2) {
+        const real g2 = group_sum(fg2, Tw);
+        if (leader) fa[2] += g2;
+      }
+      if (A.n_feats > 3) {
+        const real g3 = group_sum(fg3, Tw);
+        if (leader) fa[3] += g3;
+      }
+    }
+  }
+  // The wave sums of the slots (the first two only when N == 2), added to
+  // this wave's LDS columns by lane 0, in slot order.
+  template <int N>
+  __device__ __forceinline__ void add_terms(const Terms& t, int lane, int wave) {
+    real s[4];
+    if constexpr (N == 2) {
+      // lanes 0-31 hold slot 0's sum, lanes 32-63 slot 1's
+      const real r = group_sum(swap32_sum(t.v[0], t.v[1]), 32);
+      s[0] = lane_value(r, 0);
+      s[1] = lane_value(r, 32);
+    } else {
+      const real r = rows_sum4(t.v[0], t.v[1], t.v[2], t.v[3]);
+      s[0] = lane_value(r, 0);
+      s[1] = lane_value(r, 16);
+      s[2] = lane_value(r, 32);
+      s[3] = lane_value(r, 48);
+    }
+    if (lane == 0) {
+      real* ga = gacc + (size_t)wave * A.n_acc;
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        if (t.cw[k] >= 0) atomicAdd(&ga[t.cw[k]], s[k]);
+        if (t.cb[k] >= 0) atomicAdd(&ga[t.cb[k]], s[k]);
+      }
+    }
+  }
+  // The gradient sums of a block's two rotations (shared parameters): one
+  // two-slot sum without features, else one four-slot sum.
+  __device__ __forceinline__ void accum2(const BGate& ga, real pa, const BGate& gb, real pb,
+                                         int lane, int wave, int Tw) {
+    Terms t;
+    if (ga.feat < 0 && gb.feat < 0) {
+      shared_terms<0>(t, ga, pa, Tw);
+      shared_terms<1>(t, gb, pb, Tw);
+      add_terms<2>(t, lane, wave);
+    } else {
+      shared_terms<0>(t, ga, pa, Tw);
+      shared_terms<2>(t, gb, pb, Tw);
+      add_terms<4>(t, lane, wave);
+    }
+  }
+
   // Adds this thread's partial dL/dtheta of the rotation with record `gt`
   // to the gradient sums: shared parameters through per-wave LDS slots,
   // per-sample parameter sets with FP64 atomics, features per sample. Each
@@ -1008,8 +1192,12 @@ struct Ctx {
         const G3<real> pg = ryrz_and_apply<j>(psi, lam, c0, s0, c1, s1);
         if (bid >= 0) {
           __builtin_amdgcn_s_setprio(1);
-          accum(g1, pg.z, lane, wave, Tw);
-          accum(g0, pg.y, lane, wave, Tw);
+          if (!A.per_sample_params) {
+            accum2(g0, pg.y, g1, pg.z, lane, wave, Tw);
+          } else {
+            accum(g1, pg.z, lane, wave, Tw);
+            accum(g0, pg.y, lane, wave, Tw);
+          }
           __builtin_amdgcn_s_setprio(0);
         }
       });
@@ -1063,8 +1251,32 @@ struct Ctx {
             m.conj_by(k1, c1, s1);
             p0 = k0 == QS_OP_RX ? m.dot(0, pg) : k0 == QS_OP_RY ? m.dot(1, pg) : m.dot(2, pg);
           }
-          if (k1 <= QS_OP_RZ) accum(g1, p1, lane, wave, Tw);
-          if (k0 <= QS_OP_RZ) accum(g0, p0, lane, wave, Tw);
+          if (!A.per_sample_params) {
+            accum2(g0, p0, g1, p1, lane, wave, Tw);
+          } else {
+            if (k1 <= QS_OP_RZ) accum(g1, p1, lane, wave, Tw);
+            if (k0 <= QS_OP_RZ) accum(g0, p0, lane, wave, Tw);
+          }
+        } else if (sizeof(real) == 8 && !A.per_sample_params && (SHARED || gen >= 0)) {
+          // Shared angles (so no features): one slot per rotation, four
+          // rotations per wave sum. Complex128 only: its FP64 sums take
+          // twice the lane moves, and there this measured 2 % faster (on
+          // the 10-qubit batch); complex64 ran 1.6 % slower with it.
+          for (int i0 = b0; i0 < b1; i0 += 4) {
+            Terms t;
+            static_for<4>([&](auto KC) QS_AI {
+              constexpr int k = decltype(KC)::value;
+              if (i0 + k < b1) {
+                const BGate gt = kload(A.blk_rec, i0 + k);
+                const real* e = gen_sh + 3 * (size_t)(gen + i0 + k - b0);
+                shared_terms<k>(t, gt, e[0] * pg.x + e[1] * pg.y + e[2] * pg.z, Tw);
+              }
+            });
+            if (b1 - i0 <= 2)
+              add_terms<2>(t, lane, wave);
+            else
+              add_terms<4>(t, lane, wave);
+          }
         } else if (SHARED || gen >= 0) {
           for (int i = b0; i < b1; ++i) {
             const BGate gt = kload(A.blk_rec, i);
@@ -1132,6 +1344,14 @@ __device__ __forceinline__ void setup(Ctx<real, LR, FLY, SHARED, HALF>& C,
   // a slot is a complex pair; with one component staged (4-byte slots) the
   // salt takes 64 values.
   C.salt = ((uint32_t)C.sl << A.t) & (HALF ? 63u : 31u) & (uint32_t)(N - 1);
+  if (HALF && A.salt_basis != 0 && A.t < 6) {
+    // the plan's salts: chosen on the host so that the lanes of a wave hit
+    // different banks under as many of the plan's layouts as possible
+    uint32_t sv = 0;
+    for (int i = 0; i < 6 - A.t; ++i)
+      if ((C.sl >> i) & 1) sv ^= (uint32_t)(A.salt_basis >> (6 * i)) & 63u;
+    C.salt = sv & (uint32_t)(N - 1);
+  }
   real* tail = st + (size_t)A.S * N * comps;
   C.ang_sh = tail;
   C.ang_ps = C.ang_sh + 2 * (size_t)A.n_gates;
@@ -1170,6 +1390,15 @@ __device__ __forceinline__ void setup(Ctx<real, LR, FLY, SHARED, HALF>& C,
     }
     C.ang_ps[2 * (size_t)i] = c;
     C.ang_ps[2 * (size_t)i + 1] = s;
+  }
+  if constexpr (sizeof(real) == 4 && !SHARED) {
+    if (adjoint && A.n_feats <= 4 && C.active) {
+      const real* fr = A.feats + (size_t)C.row * A.n_feats;
+      if (A.n_feats > 0) C.fx0 = fr[0];
+      if (A.n_feats > 1) C.fx1 = fr[1];
+      if (A.n_feats > 2) C.fx2 = fr[2];
+      if (A.n_feats > 3) C.fx3 = fr[3];
+    }
   }
   if (adjoint) {
     if (!A.per_sample_params)
@@ -1355,6 +1584,7 @@ __device__ __forceinline__ void adjoint_sweep(const Args<real>& A,
       C.remap(lam, rlay(A, s), wlay(A, s - 1));
     }
   }
+  C.fold_feature_terms(Tw);
   if (A.out_psi != nullptr) C.store_state(psi, A.out_psi, rlay(A, 0));
   if (A.out_lam != nullptr) C.store_state(lam, A.out_lam, rlay(A, 0));
   __syncthreads();
@@ -1575,6 +1805,7 @@ sv_program(const ProgClass* classes, const ProgItem* items, int n_items,
     A.y = nullptr;
     A.loss_q = 0;
     A.loss_part = nullptr;
+    A.salt_basis = 0;
     // Complex64 classes whose per-circuit angle table fits the LDS budget
     // next to the staging take the table path (sines and cosines once per
     // gate and circuit, in the prologue); the others compute angles where
@@ -1666,6 +1897,7 @@ Args<real> make_args(const SvLaunch& L) {
   A.y = L.y;
   A.loss_q = L.loss_q;
   A.loss_part = L.loss_part;
+  A.salt_basis = L.shape.half ? p.salt_half : 0;
   return A;
 }
 
