@@ -1114,6 +1114,25 @@ struct Ctx {
     }
   }
 
+  // Per-sample parameter sets, a sample spanning whole waves, no features:
+  // the wave sums of a block's two rotations in one reduce-scatter (lanes
+  // 0-31 end with the first, 32-63 with the second), added to the sample's
+  // parameter gradients by lane 0 of each wave.
+  __device__ __forceinline__ void accum2_rows(const BGate& ga, real pa, const BGate& gb,
+                                              real pb, int lane) {
+    const bool ra = bg_kind(ga) <= QS_OP_RZ, rb = bg_kind(gb) <= QS_OP_RZ;
+    const real r = group_sum(swap32_sum(ra ? (real)ga.scale * pa : (real)0,
+                                        rb ? (real)gb.scale * pb : (real)0), 32);
+    const real sa = lane_value(r, 0), sb = lane_value(r, 32);
+    if (lane == 0 && active) {
+      double* gp = A.grad_params + (size_t)row * A.n_params;
+      if (ra && ga.p_w >= 0) atomicAdd(&gp[ga.p_w], (double)sa);
+      if (ra && ga.p_b >= 0) atomicAdd(&gp[ga.p_b], (double)sa);
+      if (rb && gb.p_w >= 0) atomicAdd(&gp[gb.p_w], (double)sb);
+      if (rb && gb.p_b >= 0) atomicAdd(&gp[gb.p_b], (double)sb);
+    }
+  }
+
   // Adds this thread's partial dL/dtheta of the rotation with record `gt`
   // to the gradient sums: shared parameters through per-wave LDS slots,
   // per-sample parameter sets with FP64 atomics, features per sample. Each
@@ -1194,6 +1213,8 @@ struct Ctx {
           __builtin_amdgcn_s_setprio(1);
           if (!A.per_sample_params) {
             accum2(g0, pg.y, g1, pg.z, lane, wave, Tw);
+          } else if (Tw == 64 && g0.feat < 0 && g1.feat < 0) {
+            accum2_rows(g0, pg.y, g1, pg.z, lane);
           } else {
             accum(g1, pg.z, lane, wave, Tw);
             accum(g0, pg.y, lane, wave, Tw);
@@ -1253,6 +1274,8 @@ struct Ctx {
           }
           if (!A.per_sample_params) {
             accum2(g0, p0, g1, p1, lane, wave, Tw);
+          } else if (Tw == 64 && g0.feat < 0 && g1.feat < 0) {
+            accum2_rows(g0, p0, g1, p1, lane);
           } else {
             if (k1 <= QS_OP_RZ) accum(g1, p1, lane, wave, Tw);
             if (k0 <= QS_OP_RZ) accum(g0, p0, lane, wave, Tw);

@@ -119,6 +119,21 @@ def test_ry_rz_circuits(kind, n, dtype):
         _run_expz_case(c, dtype, "auto", B, seed=1900 + n, per_sample=True)
 
 
+# Feature gradients of complex64 per-sample blocks with at most four
+# features accumulate per lane in registers; with more they take the
+# per-gate LDS sums. Both, on random circuits (general and two-gate blocks)
+# and on re-uploading layers (the RY-then-RZ pass).
+@pytest.mark.parametrize("nf", [1, 4, 5, 7])
+@pytest.mark.parametrize("n", [4, 9, 12])
+def test_feature_counts(n, nf):
+    rng = np.random.default_rng(2300 + 10 * n + nf)
+    B = 17 if n <= 9 else 3
+    _announce(f"feature counts n={n} features={nf}")
+    _run_expz_case(C.random_circuit(n, 70, rng, n_params=6, n_features=nf), "c64", "fused", B,
+                   seed=n + nf)
+    _run_expz_case(C.reupload_ry_rz_chain(n, 2, nf), "c64", "auto", B, seed=n + 3 * nf)
+
+
 @pytest.mark.parametrize("path", ["fused", "plain"])
 @pytest.mark.parametrize("n", [2, 6, 10, 13])
 def test_per_sample_params(n, path):
@@ -698,6 +713,16 @@ def test_train_step_random_circuits(n, B, q, amp):
     c = C.random_circuit(n, 70, rng, n_params=6, n_features=2)
     _announce(f"train step n={n} B={B} q={q} amplitude={amp}")
     _train_case(c, B, 2100 + n, q, amp)
+
+
+@pytest.mark.parametrize("nf", [4, 6])
+def test_train_step_feature_counts(nf):
+    """The one-launch step with feature gradients in registers (four
+    features) and in LDS sums (six)."""
+    rng = np.random.default_rng(2400 + nf)
+    c = C.random_circuit(9, 60, rng, n_params=6, n_features=nf)
+    _announce(f"train step features={nf}")
+    _train_case(c, 29, 2500 + nf, 1, True)
 
 
 @pytest.mark.parametrize("key,B", [("c2", 37), ("c2", 4096)])
