@@ -376,45 +376,109 @@ void free_dev(SvDevPlan& d) {
   (void)hipFree(d.grad_cols);
 }
 
-// Salts of one-component staging. A lane's LDS slot for amplitude index L is
-// swz(L) ^ salt with swz(L) = L ^ (L >> 5 & 31) ^ (L >> 10 & 31), and its
-// bank the slot's low six bits (4-byte slots, 64 banks). Within one access
-// the lanes of a wave differ in their thread part (the XOR of the layout's
-// index masks of the thread bits set in tau) and their sample's salt, so
-// they hit 64 different banks exactly when the swizzled thread masks and the
-// salt vectors are linearly independent over GF(2) in those six bits. The
-// salt vectors are picked greedily to maximise that rank summed over every
-// layout the kernels stage under (each segment's read and write layouts and
-// the identity of the HBM transfers); ties keep the default vector.
-uint64_t half_salt_basis(const SvPlan& P) {
-  const int t = P.t;
-  if (t >= 6 || P.n > 16) return 0;
-  const uint32_t N = 1u << P.n;
-  auto swz6 = [](uint32_t L) { return (L ^ ((L >> 5) & 31u) ^ ((L >> 10) & 31u)) & 63u; };
+// GF(2) rank of bit vectors.
+int gf2_rank(std::vector<uint32_t> v) {
+  int r = 0;
+  for (int bit = 15; bit >= 0; --bit) {
+    size_t k = r;
+    while (k < v.size() && !((v[k] >> bit) & 1)) ++k;
+    if (k == v.size()) continue;
+    std::swap(v[r], v[k]);
+    for (size_t j = 0; j < v.size(); ++j)
+      if (j != (size_t)r && ((v[j] >> bit) & 1)) v[j] ^= v[r];
+    ++r;
+  }
+  return r;
+}
+
+// The LDS staging swizzle of a plan: slot(L) = L ^ (XOR of fold[b] over the
+// set bits b >= 5 of L), each fold[b] a five-bit pattern, so the map is a
+// bijection on a sample's slots and linear over GF(2). The LDS serves 128
+// bytes per pass: 32 lanes of 4-byte slots, 16 of 8-byte, 8 of 16-byte; a
+// pass is free of bank conflicts when the low p bits (p = 5, 4, 3) of its
+// lanes' slots differ, i.e. when the swizzled masks of the layout's first p
+// thread bits (with the salt vectors of samples sharing the pass) have full
+// rank in those bits. The folds are chosen by coordinate descent from the
+// fixed fold (bit b onto bit (b - 5) mod 5), maximising that rank summed
+// over every layout the kernels stage under, weighted toward 8-byte slots.
+struct StageSwizzle {
+  uint32_t fold[16] = {};
+  uint32_t apply(uint32_t L) const {
+    uint32_t x = L;
+    for (int b = 5; b < 16; ++b)
+      if ((L >> b) & 1) x ^= fold[b];
+    return x;
+  }
+};
+
+// The thread-bit masks of every staged layout: each segment's read and write
+// layouts and the HBM order (thread bit i on logical bit i).
+std::vector<std::vector<uint32_t>> staged_thread_masks(const SvPlan& P) {
   std::vector<std::vector<uint32_t>> lays;
   std::vector<uint32_t> id;
-  for (int i = 0; i < t; ++i) id.push_back(swz6(1u << i));
+  for (int i = 0; i < P.t; ++i) id.push_back(1u << i);
   lays.push_back(id);
   for (int s = 0; s < P.nseg(); ++s)
     for (int h = 0; h < 2; ++h) {
       std::vector<uint32_t> v;
-      for (int i = 0; i < t; ++i)
-        v.push_back(swz6(P.seg_lay[(size_t)s * kLayWords + h * kMapStride + P.r + i]));
+      for (int i = 0; i < P.t; ++i)
+        v.push_back(P.seg_lay[(size_t)s * kLayWords + h * kMapStride + P.r + i]);
       lays.push_back(v);
     }
-  auto rank = [](std::vector<uint32_t> v) {
-    int r = 0;
-    for (int bit = 5; bit >= 0; --bit) {
-      size_t k = r;
-      while (k < v.size() && !((v[k] >> bit) & 1)) ++k;
-      if (k == v.size()) continue;
-      std::swap(v[r], v[k]);
-      for (size_t j = 0; j < v.size(); ++j)
-        if (j != (size_t)r && ((v[j] >> bit) & 1)) v[j] ^= v[r];
-      ++r;
-    }
-    return r;
+  return lays;
+}
+
+StageSwizzle stage_swizzle(const SvPlan& P) {
+  StageSwizzle sw;
+  for (int b = 5; b < 15; ++b) sw.fold[b] = 1u << ((b - 5) % 5);
+  if (P.n <= 5) return sw;
+  const auto lays = staged_thread_masks(P);
+  const int t = P.t;
+  auto score = [&](const StageSwizzle& z) {
+    long sc = 0;
+    for (const auto& l : lays)
+      for (int p = 3; p <= 5; ++p) {
+        const uint32_t mask = (1u << p) - 1;
+        std::vector<uint32_t> v;
+        for (int i = 0; i < t && i < p; ++i) v.push_back(z.apply(l[i]) & mask);
+        for (int j = 0; t + j < p; ++j) v.push_back((1u << (t + j)) & mask);  // default salts
+        sc += (p == 4 ? 4 : p == 5 ? 2 : 1) * gf2_rank(v);
+      }
+    return sc;
   };
+  long best = score(sw);
+  for (int sweep = 0; sweep < 3; ++sweep) {
+    bool moved = false;
+    for (int b = 5; b < P.n; ++b) {
+      const uint32_t keep = sw.fold[b];
+      uint32_t arg = keep;
+      for (uint32_t c = 0; c < 32; ++c) {
+        sw.fold[b] = c;
+        const long sc = score(sw);
+        if (sc > best) {
+          best = sc;
+          arg = c;
+        }
+      }
+      sw.fold[b] = arg;
+      moved |= arg != keep;
+    }
+    if (!moved) break;
+  }
+  return sw;
+}
+
+// Salts of one-component staging (4-byte slots, 32 lanes per LDS pass). The
+// salt of the sample at position s within its wave is the XOR of basis
+// vectors for the set bits of s. The vectors of the samples sharing a pass
+// are picked greedily to maximise the rank of the swizzled thread masks and
+// salts in the slots' low five bits, summed over the staged layouts (then
+// the six-bit rank of the whole wave breaks ties; ties keep the default
+// vector). `lays` holds the swizzled thread masks.
+uint64_t half_salt_basis(const SvPlan& P, const std::vector<std::vector<uint32_t>>& lays) {
+  const int t = P.t;
+  if (t >= 6 || P.n > 16) return 0;
+  const uint32_t N = 1u << P.n;
   std::vector<uint32_t> basis;
   uint64_t packed = 0;
   for (int k = 0; k < 6 - t; ++k) {
@@ -424,10 +488,18 @@ uint64_t half_salt_basis(const SvPlan& P) {
     for (uint32_t c = 0; c < 64 && c < N; ++c) {
       long sc = 0;
       for (const auto& l : lays) {
-        std::vector<uint32_t> v = l;
-        v.insert(v.end(), basis.begin(), basis.end());
-        v.push_back(c);
-        sc += rank(v);
+        std::vector<uint32_t> v5, v6;
+        for (int i = 0; i < t; ++i) {
+          if (i < 5) v5.push_back(l[i] & 31u);
+          v6.push_back(l[i] & 63u);
+        }
+        for (size_t j = 0; j < basis.size(); ++j) {
+          if (t + (int)j < 5) v5.push_back(basis[j] & 31u);
+          v6.push_back(basis[j]);
+        }
+        if (t + k < 5) v5.push_back(c & 31u);
+        v6.push_back(c);
+        sc += 8 * gf2_rank(v5) + gf2_rank(v6);
       }
       if (sc > best_score || (sc == best_score && c == dflt)) {
         best_score = sc;
@@ -481,7 +553,19 @@ Entry* get_plan(const qs_circuit& c, int r, bool ps, const int32_t* ck, int n_ck
   d.n_fu = P.n_fu;
   d.n_gen = P.n_gen;
   d.n_acc = (int)P.grad_cols.size();
-  d.salt_half = half_salt_basis(P);
+  // Device layouts: every mask swizzled, plus the HBM-order row.
+  const StageSwizzle sw = stage_swizzle(P);
+  std::vector<uint16_t> lay_dev((size_t)(d.nseg + 1) * kLayWords, 0);
+  for (size_t i = 0; i < P.seg_lay.size(); ++i) lay_dev[i] = (uint16_t)sw.apply(P.seg_lay[i]);
+  uint16_t* hrow = &lay_dev[(size_t)d.nseg * kLayWords];
+  for (int j = 0; j < P.r; ++j) hrow[j] = (uint16_t)sw.apply(1u << (P.t + j));
+  for (int i = 0; i < P.t; ++i) hrow[P.r + i] = (uint16_t)sw.apply(1u << i);
+  {
+    auto lays = staged_thread_masks(P);
+    for (auto& l : lays)
+      for (auto& m : l) m = sw.apply(m);
+    d.salt_half = half_salt_basis(P, lays);
+  }
   d.ryrz = d.n_blocks > 0;
   for (int b = 0; b < d.n_blocks && d.ryrz; ++b)
     d.ryrz = P.blk_begin[b + 1] - P.blk_begin[b] == 2 &&
@@ -502,7 +586,7 @@ Entry* get_plan(const qs_circuit& c, int r, bool ps, const int32_t* ck, int n_ck
     b.scale = x.scale;
   }
   bool okk = upload(&d.seg_map, P.seg_map.data(), P.seg_map.size()) &&
-             upload(&d.seg_lay, P.seg_lay.data(), P.seg_lay.size()) &&
+             upload(&d.seg_lay, lay_dev.data(), lay_dev.size()) &&
              upload(&d.seg_begin, P.seg_begin.data(), P.seg_begin.size()) &&
              upload(&d.seg_ckpt, P.seg_ckpt.data(), P.seg_ckpt.size()) &&
              upload(&d.ops, P.ops.data(), P.ops.size()) &&

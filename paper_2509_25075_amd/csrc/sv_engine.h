@@ -25,9 +25,11 @@
 // output, dotted with the rotation's generator as conjugated by the block's
 // later gates.
 //
-// LDS slots are swizzled, slot(L) = L ^ fold5(L >> 5) ^ (per-sample salt),
-// which is linear over GF(2), so the address of amplitude k of a lane is
-// (per-lane part) XOR (uniform per-k part): one VALU op per access.
+// LDS slots are swizzled, slot(L) = L ^ fold(L >> 5) ^ (per-sample salt),
+// with fold a linear map into the low five bits chosen per plan on the host;
+// the plan's layout masks arrive already swizzled, so the address of
+// amplitude k of a lane is (per-lane part) XOR (uniform per-k part): one VALU
+// op per access.
 //
 // Gates: R_P(t) = exp(-i t P / 2) (Nielsen & Chuang sec. 4.2); the adjoint
 // step computes dL/dtheta = Im <lam|P|psi> and un-applies the gate from psi
@@ -222,10 +224,6 @@ __device__ __forceinline__ uint32_t opaque(uint32_t v) {
   return v;
 }
 
-// Slot swizzle inside a sample's LDS region (in complex elements).
-__device__ __forceinline__ uint32_t swz(uint32_t L) {
-  return L ^ ((L >> 5) & 31u) ^ ((L >> 10) & 31u);
-}
 
 // --------------------------------------------------------------- state ops
 // Amplitudes of one thread. The engine runs layer ops only, so every index
@@ -659,12 +657,17 @@ struct Ctx {
   // A layout `lay` gives, for each physical bit, the logical index mask it
   // contributes (a placement: one bit each; after folded CNOTs: any GF(2)
   // combination). Logical index bits of this thread's thread-bit part:
+  // The layout row of HBM transfers (register bit j on logical bit t + j,
+  // thread bit i on logical bit i), stored after the plan's segments.
+  __device__ __forceinline__ const QS_K uint16_t* hbm_lay() const {
+    return kc(A.seg_lay) + (size_t)A.nseg * kLayWords;
+  }
   __device__ __forceinline__ uint32_t lane_part(const QS_K uint16_t* lay) const {
     const uint32_t tb = opaque((uint32_t)tau);
     uint32_t L = 0;
     for (int i = 0; i < A.t; ++i)
       if ((tb >> i) & 1) L ^= lay[LR + i];
-    return swz(L) ^ salt;
+    return L ^ salt;  // the masks are swizzled slots already
   }
 
   // Staging writes and reads under a layout: component P of the state
@@ -675,7 +678,7 @@ struct Ctx {
     const uint32_t base = lane_part(lay);
     uint32_t m[LR > 0 ? LR : 1];
 #pragma unroll
-    for (int j = 0; j < LR; ++j) m[j] = swz(uni(lay[j]));
+    for (int j = 0; j < LR; ++j) m[j] = uni(lay[j]);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       uint32_t off = 0;
@@ -697,7 +700,7 @@ struct Ctx {
     const uint32_t base = lane_part(lay);
     uint32_t m[LR > 0 ? LR : 1];
 #pragma unroll
-    for (int j = 0; j < LR; ++j) m[j] = swz(uni(lay[j]));
+    for (int j = 0; j < LR; ++j) m[j] = uni(lay[j]);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       uint32_t off = 0;
@@ -817,13 +820,21 @@ struct Ctx {
         x.im[u] = v.y;
       }
     }
-    const uint32_t tb = opaque((uint32_t)tau);
+    // the staging order of HBM transfers: logical index tau + u T
+    const QS_K uint16_t* hl = hbm_lay();
+    const uint32_t hb = lane_part(hl);
+    uint32_t hm[LR > 0 ? LR : 1];
+#pragma unroll
+    for (int j = 0; j < LR; ++j) hm[j] = uni(hl[j]);
     static_for<kPasses>([&](auto PC) QS_AI {
       constexpr int P = decltype(PC)::value;
       sample_sync(A.t);
 #pragma unroll
       for (int u = 0; u < R; ++u) {
-        const uint32_t a = swz(tb + ((uint32_t)u << A.t)) ^ salt;
+        uint32_t a = hb;
+#pragma unroll
+        for (int j = 0; j < LR; ++j)
+          if (u & (1 << j)) a ^= hm[j];
         if constexpr (HALF) {
           ldr[a] = P ? x.im[u] : x.re[u];
         } else {
@@ -848,7 +859,11 @@ struct Ctx {
     hbm_offsets(off);
     const int64_t a0 = hbm_a0();
     constexpr int W = R < 8 ? R : 8;
-    const uint32_t tb = opaque((uint32_t)tau);
+    const QS_K uint16_t* hl = hbm_lay();
+    const uint32_t hb = lane_part(hl);
+    uint32_t hm[LR > 0 ? LR : 1];
+#pragma unroll
+    for (int j = 0; j < LR; ++j) hm[j] = uni(hl[j]);
     static_for<kPasses>([&](auto PC) QS_AI {
       constexpr int P = decltype(PC)::value;
       sample_sync(A.t);
@@ -861,7 +876,10 @@ struct Ctx {
           E v[W];
 #pragma unroll
           for (int w = 0; w < W; ++w) {
-            const uint32_t a = swz(tb + ((uint32_t)(u0 + w) << A.t)) ^ salt;
+            uint32_t a = hb;
+#pragma unroll
+            for (int j = 0; j < LR; ++j)
+              if ((u0 + w) & (1 << j)) a ^= hm[j];
             if constexpr (HALF) v[w] = ldr[a]; else v[w] = lds[a];
           }
 #pragma unroll
