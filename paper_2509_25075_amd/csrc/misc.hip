@@ -231,32 +231,38 @@ template <typename real>
 __global__ void __launch_bounds__(kBlock)
 fidelity_kernel(int n, int nt, const real* psi, const real* chi, double* fid,
                 const double* dfid, real* lam_psi, real* lam_chi) {
-  __shared__ double sh[kBlock / 64];
   __shared__ double cre[64], cim[64];
   const int64_t b = blockIdx.x;
   const int k = n - nt;
   const int64_t K = 1ll << k, M = 1ll << nt, N = 1ll << n;
   const real* p = psi + 2 * b * N;
   const real* c = chi + 2 * b * N;  // chi_0 = first K amplitudes
-  double F = 0;
-  for (int64_t m = 0; m < M; ++m) {
+  // c_m = <chi_0|psi_m>: one wave per trash outcome m at a time (the sum
+  // over j within the wave, no workgroup barrier per m)
+  const int lane = threadIdx.x & 63, waves = blockDim.x >> 6;
+  for (int64_t m = threadIdx.x >> 6; m < M; m += waves) {
     double ar = 0, ai = 0;
-    for (int64_t j = threadIdx.x; j < K; j += blockDim.x) {
+    for (int64_t j = lane; j < K; j += 64) {
       const double xr = c[2 * j], xi = c[2 * j + 1];
       const double yr = p[2 * (m * K + j)], yi = p[2 * (m * K + j) + 1];
       ar += xr * yr + xi * yi;  // conj(x) y
       ai += xr * yi - xi * yr;
     }
-    ar = block_sum(ar, sh);
-    ai = block_sum(ai, sh);
-    if (threadIdx.x == 0) {
+    for (int o = 32; o >= 1; o >>= 1) {
+      ar += __shfl_xor(ar, o);
+      ai += __shfl_xor(ai, o);
+    }
+    if (lane == 0) {
       cre[m] = ar;
       cim[m] = ai;
     }
-    F += ar * ar + ai * ai;
   }
   __syncthreads();
-  if (threadIdx.x == 0) fid[b] = F;
+  if (threadIdx.x == 0) {
+    double F = 0;
+    for (int64_t m = 0; m < M; ++m) F += cre[m] * cre[m] + cim[m] * cim[m];
+    fid[b] = F;
+  }
   if (dfid == nullptr) return;
   const double d = dfid[b];
   real* lp = lam_psi + 2 * b * N;
