@@ -318,9 +318,10 @@ std::unordered_map<Key, Entry*, KeyHash> g_cache;
 std::unordered_map<Key, qs_gate*, KeyHash> g_gate_cache;  // plain path
 
 Key make_key(const qs_circuit& c, int r, bool ps, const int32_t* ck, int n_ck,
-             int device) {
+             int device, bool fixed_fold = false) {
   Key k;
-  int32_t hdr[8] = {c.n_qubits, c.n_gates, c.n_params, c.n_features, r, ps, n_ck, device};
+  int32_t hdr[9] = {c.n_qubits, c.n_gates, c.n_params, c.n_features, r, ps, n_ck, device,
+                    fixed_fold};
   k.bytes.append(reinterpret_cast<const char*>(hdr), sizeof(hdr));
   if (c.n_gates)
     k.bytes.append(reinterpret_cast<const char*>(c.gates), sizeof(qs_gate) * c.n_gates);
@@ -428,10 +429,10 @@ std::vector<std::vector<uint32_t>> staged_thread_masks(const SvPlan& P) {
   return lays;
 }
 
-StageSwizzle stage_swizzle(const SvPlan& P) {
+StageSwizzle stage_swizzle(const SvPlan& P, bool fixed) {
   StageSwizzle sw;
   for (int b = 5; b < 15; ++b) sw.fold[b] = 1u << ((b - 5) % 5);
-  if (P.n <= 5) return sw;
+  if (P.n <= 5 || fixed) return sw;
   const auto lays = staged_thread_masks(P);
   const int t = P.t;
   auto score = [&](const StageSwizzle& z) {
@@ -516,10 +517,10 @@ uint64_t half_salt_basis(const SvPlan& P, const std::vector<std::vector<uint32_t
 // upload is synchronous, so the first call for a circuit must not be inside
 // a stream capture; later calls only look the plan up.
 Entry* get_plan(const qs_circuit& c, int r, bool ps, const int32_t* ck, int n_ck,
-                int* rc) {
+                int* rc, bool fixed_fold = false) {
   int device = 0;
   (void)hipGetDevice(&device);
-  Key key = make_key(c, r, ps, ck, n_ck, device);
+  Key key = make_key(c, r, ps, ck, n_ck, device, fixed_fold);
   std::lock_guard<std::mutex> lock(g_mu);
   auto it = g_cache.find(key);
   if (it != g_cache.end()) return it->second;
@@ -554,7 +555,7 @@ Entry* get_plan(const qs_circuit& c, int r, bool ps, const int32_t* ck, int n_ck
   d.n_gen = P.n_gen;
   d.n_acc = (int)P.grad_cols.size();
   // Device layouts: every mask swizzled, plus the HBM-order row.
-  const StageSwizzle sw = stage_swizzle(P);
+  const StageSwizzle sw = stage_swizzle(P, fixed_fold);
   std::vector<uint16_t> lay_dev((size_t)(d.nseg + 1) * kLayWords, 0);
   for (size_t i = 0; i < P.seg_lay.size(); ++i) lay_dev[i] = (uint16_t)sw.apply(P.seg_lay[i]);
   uint16_t* hrow = &lay_dev[(size_t)d.nseg * kLayWords];

@@ -663,12 +663,22 @@ struct Ctx {
     return kc(A.seg_lay) + (size_t)A.nseg * kLayWords;
   }
   __device__ __forceinline__ uint32_t lane_part(const QS_K uint16_t* lay) const {
+    // The row's 16 masks come in one scalar load (a loop over t reading one
+    // mask per step waited on a scalar load each time: at 7 to 9 thread bits
+    // that cost the adjoint 4-15 % of its time); thread bit i is entry
+    // LR + i, taken where bit i of tau is set (i < t).
     const uint32_t tb = opaque((uint32_t)tau);
+    const QS_K uint32_t* w = reinterpret_cast<const QS_K uint32_t*>(lay);
     uint32_t L = 0;
-    for (int i = 0; i < A.t; ++i)
-      if ((tb >> i) & 1) L ^= lay[LR + i];
+#pragma unroll
+    for (int i = 0; i < 16 - LR; ++i) {
+      const int e = LR + i;
+      const uint32_t m = (w[e >> 1] >> ((e & 1) * 16)) & 0xffffu;
+      if (i < A.t) L ^= m & (0u - ((tb >> i) & 1u));
+    }
     return L ^ salt;  // the masks are swizzled slots already
   }
+
 
   // Staging writes and reads under a layout: component P of the state
   // (HALF), or whole complex amplitudes (P ignored).
