@@ -665,16 +665,21 @@ struct Ctx {
   __device__ __forceinline__ uint32_t lane_part(const QS_K uint16_t* lay) const {
     // The row's 16 masks come in one scalar load (a loop over t reading one
     // mask per step waited on a scalar load each time: at 7 to 9 thread bits
-    // that cost the adjoint 4-15 % of its time); thread bit i is entry
-    // LR + i, taken where bit i of tau is set (i < t).
+    // that cost the adjoint 4-15 % of its time). Thread bit i is entry
+    // LR + i, taken where bit i of tau is set; tau < 2^t, so the bits from t
+    // up select nothing and need no test (a test per bit would put each load
+    // behind its own branch and wait).
     const uint32_t tb = opaque((uint32_t)tau);
     const QS_K uint32_t* w = reinterpret_cast<const QS_K uint32_t*>(lay);
+    uint32_t wv[kMapStride / 2];
+#pragma unroll
+    for (int k = 0; k < kMapStride / 2; ++k) wv[k] = w[k];
     uint32_t L = 0;
 #pragma unroll
     for (int i = 0; i < 16 - LR; ++i) {
       const int e = LR + i;
-      const uint32_t m = (w[e >> 1] >> ((e & 1) * 16)) & 0xffffu;
-      if (i < A.t) L ^= m & (0u - ((tb >> i) & 1u));
+      const uint32_t m = (wv[e >> 1] >> ((e & 1) * 16)) & 0xffffu;
+      L ^= m & (0u - ((tb >> i) & 1u));
     }
     return L ^ salt;  // the masks are swizzled slots already
   }
