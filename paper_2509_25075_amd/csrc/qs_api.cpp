@@ -567,7 +567,8 @@ Entry* get_plan(const qs_circuit& c, int r, bool ps, const int32_t* ck, int n_ck
       for (auto& m : l) m = sw.apply(m);
     d.salt_half = half_salt_basis(P, lays);
   }
-  d.ryrz = d.n_blocks > 0;
+  // (the RY-then-RZ pass also reads block b's records at 2 b)
+  d.ryrz = d.n_blocks > 0 && P.blk_begin[0] == 0;
   for (int b = 0; b < d.n_blocks && d.ryrz; ++b)
     d.ryrz = P.blk_begin[b + 1] - P.blk_begin[b] == 2 &&
              c.gates[P.blk_gates[P.blk_begin[b]]].op == QS_OP_RY &&

@@ -1235,9 +1235,10 @@ struct Ctx {
         BGate g0{}, g1{};
         real c0 = 1, s0 = 0, c1 = 1, s1 = 0;
         if (bid >= 0) {
-          const int b0 = kc(A.blk_begin)[bid];
-          g0 = kload(A.blk_rec, b0);
-          g1 = kload(A.blk_rec, b0 + 1);
+          // every block holds two gates, so block bid's records start at
+          // 2 bid (no scalar load of the block table to wait on)
+          g0 = kload(A.blk_rec, 2 * bid);
+          g1 = kload(A.blk_rec, 2 * bid + 1);
           gate_cs(g0, c0, s0);
           gate_cs(g1, c1, s1);
         }
