@@ -1775,7 +1775,12 @@ __global__ void __launch_bounds__(MAXT) sv_forward(Args<real> A) {
 template <typename real, int LR, int MAXT, bool SHARED, bool HALF, bool RYRZ = false>
 __global__ void __launch_bounds__(MAXT) sv_adjoint(Args<real> A) {
   extern __shared__ __align__(16) unsigned char smem[];
-  adjoint_body<real, LR, false, SHARED, HALF, RYRZ>(A, smem, (int64_t)blockIdx.x * A.S);
+  // The sweep re-reads its arguments (see adjoint_body) in the complex64
+  // RY-then-RZ kernels, where that measured faster (26-qubit tiled epochs
+  // -6 %, 8-qubit re-uploading batch -2 %); the complex64 fused-block
+  // adjoint ran 3 % slower with it, and complex128 gained nothing.
+  adjoint_body<real, LR, false, SHARED, HALF, RYRZ, false, RYRZ && sizeof(real) == 4>(
+      A, smem, (int64_t)blockIdx.x * A.S);
 }
 
 // A training step in one launch: forward sweep (from the amplitude encoding
